@@ -23,7 +23,8 @@ list) can be pinned against what the mathematics fixes:
    (at most ``ZERO_RETRY`` times in a row); the stopping test after step k is
    ||u_k|| ||v_k|| <= tol ||S_k||_F with the Frobenius norm of the running
    approximation S_k updated incrementally; the next pivot row is the first
-   index of max |u_k| over unused rows; at most ``max_rank`` terms.
+   index of max |u_k| over unused rows; at most min(max_rank, |alpha|, |beta|)
+   terms.
 3. Leaf factor K_L: dense diagonal blocks C_lambda = K(lambda, lambda) +
    sigma^2 I, factored by Cholesky; their inverses applied to the rows of
    every off-diagonal basis that covers the leaf (§3.2 pseudo-code; §3.3).
@@ -111,6 +112,10 @@ def aca(row, col, m: int, nb: int, tol: float, max_rank: int):
     """Cross approximation A ~ U V^T of an m x nb block given row(i) -> A[i, :]
     and col(j) -> A[:, j].  Returns (U (m x r), V (nb x r), capped)."""
     U, V = [], []
+    # a block never needs more terms than its size; only the user's cap counts as "capped"
+    full = min(m, nb)
+    user_cap = max_rank < full
+    max_rank = min(max_rank, full)
     if m == 0 or nb == 0 or max_rank <= 0:
         return np.zeros((m, 0)), np.zeros((nb, 0)), False
     used = np.zeros(m, dtype=bool)
@@ -144,7 +149,7 @@ def aca(row, col, m: int, nb: int, tol: float, max_rank: int):
         if math.sqrt(float(u @ u)) * math.sqrt(float(v @ v)) <= tol * math.sqrt(max(s2, 0.0)):
             break
         if len(U) >= max_rank:
-            capped = True
+            capped = user_cap
             break
         if used.all():
             break

@@ -1,0 +1,297 @@
+"""MI355X HODLR Gaussian-process likelihoods: Python binding of libhodlrgp.
+
+The names mirror the C ABI in ``include/hodlr.h``.  This module only marshals
+arguments (numpy arrays for the host entry points, torch device tensors or
+raw device pointers for the ``_dev`` entry points); every step of the
+factorization, log-det and solve runs in the library's HIP kernels.  There
+is no fallback: if the shared library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "HodlrError", "Opts", "Factor", "Plan", "lib", "hodlr_order", "hodlr_num_levels",
+    "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
+    "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
+    "FP64", "MIXED", "EXPORTED",
+]
+
+K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOCONV"}
+EXPORTED = [
+    "hodlr_order", "hodlr_num_levels", "hodlr_build", "hodlr_logdet", "hodlr_solve",
+    "gp_loglik", "hodlr_info", "hodlr_free", "hodlr_last_error", "hodlr_plan_create",
+    "hodlr_plan_destroy", "hodlr_plan_workspace_size", "gp_loglik_dev", "hodlr_matvec_dev",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhodlrgp.so")
+_lib = None
+MAX_LEVELS = 40
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("presorted", ctypes.c_int32)]
+
+    def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0):
+        super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
+                         int(presorted))
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("max_rank_used", ctypes.c_int32),
+                ("capped_blocks", ctypes.c_int32),
+                ("rank_max", ctypes.c_int32 * MAX_LEVELS),
+                ("rank_mean", ctypes.c_double * MAX_LEVELS),
+                ("device_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
+
+
+def lib():
+    """Load libhodlrgp.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhodlrgp.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading torch first makes this library bind to that runtime, so device
+    # pointers and streams from torch are valid here and one process never
+    # holds two HIP runtimes.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    st = ctypes.c_int
+    L.hodlr_last_error.restype = ctypes.c_char_p
+    L.hodlr_num_levels.restype = i32
+    L.hodlr_num_levels.argtypes = [i64, i32]
+    L.hodlr_order.restype = st
+    L.hodlr_order.argtypes = [dp, i64, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.hodlr_build.restype = st
+    L.hodlr_build.argtypes = [dp, i64, i32, ctypes.c_int, dp, ctypes.c_double, i32,
+                              ctypes.c_double, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.hodlr_logdet.restype = st
+    L.hodlr_logdet.argtypes = [vp, dp]
+    L.hodlr_solve.restype = st
+    L.hodlr_solve.argtypes = [vp, dp, dp, i64]
+    L.gp_loglik.restype = st
+    L.gp_loglik.argtypes = [dp, i64, i32, ctypes.c_int, dp, ctypes.c_double, dp, i32,
+                            ctypes.c_double, ctypes.POINTER(Opts), dp, dp, dp]
+    L.hodlr_info.restype = st
+    L.hodlr_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.hodlr_free.restype = None
+    L.hodlr_free.argtypes = [vp]
+    L.hodlr_plan_create.restype = st
+    L.hodlr_plan_create.argtypes = [i64, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.hodlr_plan_destroy.restype = None
+    L.hodlr_plan_destroy.argtypes = [vp]
+    L.hodlr_plan_workspace_size.restype = st
+    L.hodlr_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.gp_loglik_dev.restype = st
+    L.gp_loglik_dev.argtypes = [vp, vp, ctypes.c_int, dp, ctypes.c_double, vp, ctypes.c_double,
+                                vp, ctypes.c_size_t, vp, vp, vp]
+    L.hodlr_matvec_dev.restype = st
+    L.hodlr_matvec_dev.argtypes = [i64, i32, vp, ctypes.c_int, dp, ctypes.c_double, vp, vp, vp]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise HodlrError(status, lib().hodlr_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pts(x):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if x.ndim == 1:
+        x = x.reshape(-1, 1)
+    return x
+
+
+def _theta(theta):
+    return np.ascontiguousarray(np.asarray(theta, dtype=np.float64).ravel()[:2])
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address); None -> NULL."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def hodlr_num_levels(n: int, leaf: int) -> int:
+    return int(lib().hodlr_num_levels(int(n), int(leaf)))
+
+
+def hodlr_order(x, leaf: int) -> np.ndarray:
+    x = _pts(x)
+    n, dim = x.shape
+    perm = np.empty(n, dtype=np.int64)
+    _check(lib().hodlr_order(_dp(x), n, dim, int(leaf),
+                             perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return perm
+
+
+class Factor:
+    """Owning handle of a library factor (hodlr_build ... hodlr_free)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise HodlrError(1, "factor already freed")
+        return self._h
+
+    def logdet(self) -> float:
+        return hodlr_logdet(self)
+
+    def solve(self, y) -> np.ndarray:
+        return hodlr_solve(self, y)
+
+    def info(self) -> dict:
+        return hodlr_info(self)
+
+    def free(self):
+        if self._h:
+            lib().hodlr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hodlr_build(x, kernel: int, theta, sigma2: float, leaf: int, tol: float,
+                opts: Opts | None = None) -> Factor:
+    x = _pts(x)
+    n, dim = x.shape
+    th = _theta(theta)
+    h = ctypes.c_void_p()
+    _check(lib().hodlr_build(_dp(x), n, dim, int(kernel), _dp(th), float(sigma2), int(leaf),
+                             float(tol), ctypes.byref(opts) if opts is not None else None,
+                             ctypes.byref(h)))
+    return Factor(h.value)
+
+
+def hodlr_logdet(f: Factor) -> float:
+    out = ctypes.c_double()
+    _check(lib().hodlr_logdet(f.handle, ctypes.byref(out)))
+    return out.value
+
+
+def hodlr_solve(f: Factor, y) -> np.ndarray:
+    y = np.asarray(y, dtype=np.float64)
+    vec = y.ndim == 1
+    Y = np.asfortranarray(y.reshape(y.shape[0], -1))
+    X = np.empty_like(Y, order="F")
+    _check(lib().hodlr_solve(f.handle, _dp(Y), _dp(X), Y.shape[1]))
+    return X[:, 0].copy() if vec else X
+
+
+def gp_loglik(x, y, kernel: int, theta, sigma2: float, leaf: int, tol: float,
+              opts: Opts | None = None):
+    """Returns (loglik, logdet, quad)."""
+    x = _pts(x)
+    n, dim = x.shape
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
+    th = _theta(theta)
+    ll, ld, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().gp_loglik(_dp(x), n, dim, int(kernel), _dp(th), float(sigma2), _dp(y),
+                           int(leaf), float(tol),
+                           ctypes.byref(opts) if opts is not None else None,
+                           ctypes.byref(ll), ctypes.byref(ld), ctypes.byref(q)))
+    return ll.value, ld.value, q.value
+
+
+def hodlr_info(f: Factor) -> dict:
+    I = Info()
+    _check(lib().hodlr_info(f.handle, ctypes.byref(I)))
+    L = I.levels
+    return {"n": I.n, "dim": I.dim, "levels": L, "leaf_max": I.leaf_max,
+            "max_rank_used": I.max_rank_used, "capped_blocks": I.capped_blocks,
+            "rank_max": list(I.rank_max[:L]), "rank_mean": list(I.rank_mean[:L]),
+            "device_bytes": I.device_bytes, "precision": I.precision,
+            "refine_steps": I.refine_steps, "refine_residual": I.refine_residual}
+
+
+def hodlr_free(f: Factor):
+    f.free()
+
+
+class Plan:
+    """hodlr_plan_create / hodlr_plan_workspace_size / hodlr_plan_destroy."""
+
+    def __init__(self, n: int, dim: int, leaf: int, opts: Opts | None = None):
+        h = ctypes.c_void_p()
+        _check(lib().hodlr_plan_create(int(n), int(dim), int(leaf),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(h)))
+        self._h = h.value
+        self.n, self.dim, self.leaf = int(n), int(dim), int(leaf)
+        sz = ctypes.c_size_t()
+        _check(lib().hodlr_plan_workspace_size(self._h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            lib().hodlr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def gp_loglik_dev(plan: Plan, d_x, kernel: int, theta, sigma2: float, d_y, tol: float, work,
+                  work_bytes: int, stream, d_out, d_z=None):
+    """Device entry point; d_x / d_y / work / d_out / d_z are torch device
+    tensors (or raw addresses); stream is a torch stream, a raw handle, or None."""
+    th = _theta(theta)
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    _check(lib().gp_loglik_dev(plan.handle, _ptr(d_x), int(kernel), _dp(th), float(sigma2),
+                               _ptr(d_y), float(tol), _ptr(work), int(work_bytes), s,
+                               _ptr(d_out), _ptr(d_z)))
+
+
+def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d_v, d_out,
+                     stream=None):
+    th = _theta(theta)
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    _check(lib().hodlr_matvec_dev(int(n), int(dim), _ptr(d_x), int(kernel), _dp(th),
+                                  float(sigma2), _ptr(d_v), _ptr(d_out), s))

@@ -1,0 +1,499 @@
+// C ABI of libhodlrgp: argument checks, ordering, device memory for the
+// host-pointer entry points, and the order of the device stages.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace hodlr {
+void run_leaf_solve(Pipeline &P, double *z);
+void run_levels_apply(Pipeline &P);
+}  // namespace hodlr
+
+using namespace hodlr;
+
+namespace {
+
+thread_local std::string g_err;
+
+hodlr_status fail(hodlr_status st, const std::string &m)
+{
+    g_err = m;
+    return st;
+}
+
+template <typename F>
+hodlr_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const Error &e) {
+        return fail(e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(HODLR_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(HODLR_EDEVICE, "unexpected exception");
+    }
+}
+
+hodlr_opts default_opts()
+{
+    hodlr_opts o;
+    o.max_rank = 64;
+    o.precision = HODLR_FP64;
+    o.refine_tol = 1e-10;
+    o.max_refine = 8;
+    o.presorted = 0;
+    return o;
+}
+
+void check_sizes(int64_t n, int32_t dim, int32_t leaf)
+{
+    if (n < 1)
+        throw Error{HODLR_EINVAL, "n must be >= 1"};
+    if (dim < 1 || dim > 3)
+        throw Error{HODLR_EINVAL, "dim must be 1, 2 or 3"};
+    if (leaf < 1)
+        throw Error{HODLR_EINVAL, "leaf must be >= 1"};
+}
+
+void check_opts(const hodlr_opts &o)
+{
+    if (o.max_rank < 0 || o.max_rank > RMAX_ABS)
+        throw Error{HODLR_EINVAL, "max_rank must be in [0, " + std::to_string(RMAX_ABS) + "]"};
+    if (o.precision != HODLR_FP64 && o.precision != HODLR_MIXED)
+        throw Error{HODLR_EINVAL, "unknown precision"};
+    if (o.precision == HODLR_MIXED)
+        throw Error{HODLR_EINVAL, "mixed precision is not available in this build"};
+    if (!(o.refine_tol > 0.0) || !std::isfinite(o.refine_tol))
+        throw Error{HODLR_EINVAL, "refine_tol must be positive"};
+}
+
+void check_params(int k, const double theta[2], double sigma2, double tol)
+{
+    if (k < HODLR_K_SE || k > HODLR_K_CONST)
+        throw Error{HODLR_EINVAL, "unknown kernel"};
+    if (!theta)
+        throw Error{HODLR_EINVAL, "theta is NULL"};
+    if (!(theta[0] > 0.0) || !std::isfinite(theta[0]) || !(theta[1] > 0.0) ||
+        !std::isfinite(theta[1]))
+        throw Error{HODLR_EINVAL, "theta = {a, l} must be positive and finite"};
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
+        throw Error{HODLR_EINVAL, "sigma2 must be >= 0 and finite"};
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        throw Error{HODLR_EINVAL, "tol must be positive and finite"};
+}
+
+void check_finite(const double *v, int64_t m, const char *what)
+{
+    if (!v)
+        throw Error{HODLR_EINVAL, std::string(what) + " is NULL"};
+    for (int64_t i = 0; i < m; ++i)
+        if (!std::isfinite(v[i]))
+            throw Error{HODLR_EINVAL, std::string(what) + " has a NaN or Inf entry"};
+}
+
+// RAII device buffer
+struct DevBuf {
+    void *p = nullptr;
+    explicit DevBuf(size_t bytes)
+    {
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            p = nullptr;
+            throw Error{HODLR_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                          " bytes failed"};
+        }
+    }
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    void *release()
+    {
+        void *q = p;
+        p = nullptr;
+        return q;
+    }
+};
+
+// ordered, coordinate-major copy of caller points
+std::vector<double> ordered_soa(const double *x, int64_t n, int dim, const std::vector<int64_t> &perm)
+{
+    std::vector<double> xs((size_t)n * dim);
+    for (int d = 0; d < dim; ++d)
+        for (int64_t k = 0; k < n; ++k)
+            xs[(size_t)d * n + k] = x[perm[k] * dim + d];
+    return xs;
+}
+
+void make_columns(Pipeline &P)
+{
+    const Plan &p = *P.plan;
+    P.cols.assign(1, 0);
+    P.cnt.assign(p.L + 1, 1);
+    for (int j = 1; j <= p.L; ++j) {
+        for (int c = 0; c < P.rmax[j]; ++c)
+            P.cols.push_back((int)(p.cofa[j] + c));
+        P.cnt[j] = (int)P.cols.size();
+    }
+    HIP_TRY(hipMemcpyAsync(wsp<int>(P, P.lay.cols), P.cols.data(), sizeof(int) * P.cols.size(),
+                           hipMemcpyHostToDevice, P.stream));
+}
+
+int read_status(Pipeline &P)
+{
+    int st = 0;
+    HIP_TRY(hipMemcpyAsync(&st, wsp<int>(P, P.lay.status), sizeof(int), hipMemcpyDeviceToHost,
+                           P.stream));
+    HIP_TRY(hipStreamSynchronize(P.stream));
+    return st;
+}
+
+void raise_status(int st)
+{
+    if (st & DS_NOTSPD_LEAF)
+        throw Error{HODLR_ENOTSPD, "a leaf block is not positive definite"};
+    if (st & DS_NOTSPD_NODE)
+        throw Error{HODLR_ENOTSPD, "a coupling determinant is not positive"};
+}
+
+// compression, leaves, levels, finish: everything for one likelihood
+void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
+{
+    HIP_TRY(hipMemsetAsync(wsp<int>(P, P.lay.status), 0, 4 * sizeof(int), P.stream));
+    run_aca(P);
+    make_columns(P);
+    if (!d_y)
+        HIP_TRY(hipMemsetAsync(wsp<double>(P, P.lay.Xt), 0, sizeof(double) * P.plan->n, P.stream));
+    run_leaf_factor(P, d_y);
+    run_levels_factor(P);
+    run_finish(P, d_y, d_out);
+}
+
+}  // namespace
+
+struct hodlr_plan_s {
+    Plan plan;
+    Layout lay;
+    hodlr_opts opts;
+};
+
+struct hodlr_factor_s {
+    Plan plan;
+    Layout lay;
+    hodlr_opts opts;
+    void *ws = nullptr;
+    double *dx = nullptr;
+    std::vector<int64_t> perm;
+    KParams kp;
+    double tol = 0;
+    double logdet = 0;
+    std::vector<int> rmax, cols, cnt, ranks;
+    int capped = 0;
+    int device = 0;
+    ~hodlr_factor_s()
+    {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        if (ws)
+            (void)hipFree(ws);
+        if (dx)
+            (void)hipFree(dx);
+        plan_release(plan);
+        (void)hipSetDevice(cur);
+    }
+};
+
+extern "C" {
+
+const char *hodlr_last_error(void) { return g_err.c_str(); }
+
+int32_t hodlr_num_levels(int64_t n, int32_t leaf) { return num_levels(n, leaf); }
+
+hodlr_status hodlr_order(const double *x, int64_t n, int32_t dim, int32_t leaf, int64_t *perm)
+{
+    return guarded([&]() {
+        check_sizes(n, dim, leaf);
+        check_finite(x, n * dim, "x");
+        if (!perm)
+            throw Error{HODLR_EINVAL, "perm is NULL"};
+        order_points(x, n, dim, leaf, perm);
+        return HODLR_OK;
+    });
+}
+
+hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
+                         const double theta[2], double sigma2, int32_t leaf, double tol,
+                         const hodlr_opts *opts, hodlr_factor *out)
+{
+    return guarded([&]() {
+        hodlr_opts o = opts ? *opts : default_opts();
+        check_sizes(n, dim, leaf);
+        check_opts(o);
+        check_params(k, theta, sigma2, tol);
+        check_finite(x, n * dim, "x");
+        if (!out)
+            throw Error{HODLR_EINVAL, "out is NULL"};
+        auto f = std::make_unique<hodlr_factor_s>();
+        HIP_TRY(hipGetDevice(&f->device));
+        f->opts = o;
+        f->perm.resize(n);
+        if (o.presorted)
+            for (int64_t i = 0; i < n; ++i)
+                f->perm[i] = i;
+        else
+            order_points(x, n, dim, leaf, f->perm.data());
+        plan_build(f->plan, n, dim, leaf, &o);
+        plan_upload(f->plan);
+        f->lay = make_layout(f->plan, true);
+        DevBuf ws(f->lay.total), dxb(sizeof(double) * n * dim);
+        std::vector<double> xs = ordered_soa(x, n, dim, f->perm);
+        HIP_TRY(hipMemcpy(dxb.p, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
+        Pipeline P;
+        P.plan = &f->plan;
+        P.lay = f->lay;
+        P.ws = (char *)ws.p;
+        P.stream = nullptr;
+        P.x = (const double *)dxb.p;
+        P.kp = make_kparams(k, dim, theta, sigma2);
+        P.tol = tol;
+        double *d_out = wsp<double>(P, P.lay.out);
+        factor_pipeline(P, nullptr, d_out);
+        double hout[8];
+        HIP_TRY(hipMemcpyAsync(hout, d_out, sizeof(double) * 8, hipMemcpyDeviceToHost, P.stream));
+        raise_status(read_status(P));
+        f->logdet = hout[1];
+        f->kp = P.kp;
+        f->tol = tol;
+        f->rmax = P.rmax;
+        f->cols = P.cols;
+        f->cnt = P.cnt;
+        f->ranks = P.ranks;
+        f->capped = P.capped;
+        f->ws = ws.release();
+        f->dx = (double *)dxb.release();
+        *out = f.release();
+        return HODLR_OK;
+    });
+}
+
+hodlr_status hodlr_logdet(hodlr_factor f, double *logdet)
+{
+    if (!f || !logdet)
+        return fail(HODLR_EINVAL, "NULL argument");
+    *logdet = f->logdet;
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrhs)
+{
+    return guarded([&]() {
+        if (!f || !y || !x || nrhs < 0)
+            throw Error{HODLR_EINVAL, "bad argument"};
+        const int64_t n = f->plan.n;
+        check_finite(y, n * nrhs, "y");
+        HIP_TRY(hipSetDevice(f->device));
+        Pipeline P;
+        P.plan = &f->plan;
+        P.lay = f->lay;
+        P.ws = (char *)f->ws;
+        P.stream = nullptr;
+        P.x = f->dx;
+        P.kp = f->kp;
+        P.tol = f->tol;
+        P.rmax = f->rmax;
+        P.cols = f->cols;
+        P.cnt = f->cnt;
+        P.ranks = f->ranks;
+        double *z = wsp<double>(P, P.lay.Xt);   // column 0 carries the vector
+        std::vector<double> buf(n), res(n);
+        for (int64_t c = 0; c < nrhs; ++c) {
+            const double *yc = y + c * n;
+            for (int64_t k = 0; k < n; ++k)
+                buf[k] = yc[f->perm[k]];
+            HIP_TRY(hipMemcpy(z, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+            run_leaf_solve(P, z);
+            run_levels_apply(P);
+            HIP_TRY(hipMemcpy(buf.data(), z, sizeof(double) * n, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < n; ++k)
+                res[f->perm[k]] = buf[k];
+            std::memcpy(x + c * n, res.data(), sizeof(double) * n);
+        }
+        return HODLR_OK;
+    });
+}
+
+hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
+                       const double theta[2], double sigma2, const double *y, int32_t leaf,
+                       double tol, const hodlr_opts *opts, double *loglik, double *logdet,
+                       double *quad)
+{
+    return guarded([&]() {
+        hodlr_opts o = opts ? *opts : default_opts();
+        check_sizes(n, dim, leaf);
+        check_opts(o);
+        check_params(k, theta, sigma2, tol);
+        check_finite(x, n * dim, "x");
+        check_finite(y, n, "y");
+        if (!loglik)
+            throw Error{HODLR_EINVAL, "loglik is NULL"};
+        std::vector<int64_t> perm(n);
+        if (o.presorted)
+            for (int64_t i = 0; i < n; ++i)
+                perm[i] = i;
+        else
+            order_points(x, n, dim, leaf, perm.data());
+        Plan plan;
+        plan_build(plan, n, dim, leaf, &o);
+        plan_upload(plan);
+        struct PlanGuard {
+            Plan &p;
+            ~PlanGuard() { plan_release(p); }
+        } pg{plan};
+        Layout lay = make_layout(plan, false);
+        DevBuf ws(lay.total), dxb(sizeof(double) * n * dim), dyb(sizeof(double) * n);
+        std::vector<double> xs = ordered_soa(x, n, dim, perm);
+        std::vector<double> ys(n);
+        for (int64_t i = 0; i < n; ++i)
+            ys[i] = y[perm[i]];
+        HIP_TRY(hipMemcpy(dxb.p, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(dyb.p, ys.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        Pipeline P;
+        P.plan = &plan;
+        P.lay = lay;
+        P.ws = (char *)ws.p;
+        P.stream = nullptr;
+        P.x = (const double *)dxb.p;
+        P.kp = make_kparams(k, dim, theta, sigma2);
+        P.tol = tol;
+        double *d_out = wsp<double>(P, lay.out);
+        factor_pipeline(P, (const double *)dyb.p, d_out);
+        double hout[8];
+        HIP_TRY(hipMemcpyAsync(hout, d_out, sizeof(double) * 8, hipMemcpyDeviceToHost, P.stream));
+        raise_status(read_status(P));
+        *loglik = hout[0];
+        if (logdet)
+            *logdet = hout[1];
+        if (quad)
+            *quad = hout[2];
+        return HODLR_OK;
+    });
+}
+
+hodlr_status hodlr_info(hodlr_factor f, hodlr_info_t *out)
+{
+    if (!f || !out)
+        return fail(HODLR_EINVAL, "NULL argument");
+    hodlr_info_t I;
+    std::memset(&I, 0, sizeof(I));
+    I.n = f->plan.n;
+    I.dim = f->plan.dim;
+    I.levels = f->plan.L;
+    I.leaf_max = f->plan.leafmax;
+    I.capped_blocks = f->capped;
+    I.precision = f->opts.precision;
+    for (int d = 0; d < f->plan.L && d < HODLR_MAX_LEVELS; ++d) {
+        int64_t h0 = f->plan.first_at(d), h1 = f->plan.first_at(d + 1);
+        int mx = 0;
+        double sum = 0;
+        for (int64_t h = h0; h < h1; ++h) {
+            mx = std::max(mx, f->ranks[h]);
+            sum += f->ranks[h];
+        }
+        I.rank_max[d] = mx;
+        I.rank_mean[d] = sum / (double)(h1 - h0);
+        I.max_rank_used = std::max(I.max_rank_used, mx);
+    }
+    I.device_bytes = (int64_t)f->lay.total + (int64_t)f->plan.dev_tables_bytes +
+                     (int64_t)sizeof(double) * f->plan.n * f->plan.dim;
+    *out = I;
+    return HODLR_OK;
+}
+
+void hodlr_free(hodlr_factor f) { delete f; }
+
+hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr_opts *opts,
+                               hodlr_plan *out)
+{
+    return guarded([&]() {
+        hodlr_opts o = opts ? *opts : default_opts();
+        check_sizes(n, dim, leaf);
+        check_opts(o);
+        if (!out)
+            throw Error{HODLR_EINVAL, "out is NULL"};
+        auto p = std::make_unique<hodlr_plan_s>();
+        p->opts = o;
+        plan_build(p->plan, n, dim, leaf, &o);
+        if (p->plan.leafmax > LEAF_LDS_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+        plan_upload(p->plan);
+        p->lay = make_layout(p->plan, false);
+        *out = p.release();
+        return HODLR_OK;
+    });
+}
+
+void hodlr_plan_destroy(hodlr_plan p)
+{
+    if (p) {
+        plan_release(p->plan);
+        delete p;
+    }
+}
+
+hodlr_status hodlr_plan_workspace_size(hodlr_plan p, size_t *bytes)
+{
+    if (!p || !bytes)
+        return fail(HODLR_EINVAL, "NULL argument");
+    *bytes = p->lay.total;
+    return HODLR_OK;
+}
+
+hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, const double theta[2],
+                           double sigma2, const double *d_y, double tol, void *d_work,
+                           size_t work_bytes, void *stream, double *d_out, double *d_z)
+{
+    return guarded([&]() {
+        if (!p || !d_x || !d_y || !d_work || !d_out)
+            throw Error{HODLR_EINVAL, "NULL argument"};
+        check_params(k, theta, sigma2, tol);
+        if (work_bytes < p->lay.total)
+            throw Error{HODLR_EINVAL, "workspace too small: need " + std::to_string(p->lay.total) +
+                                          " bytes"};
+        Pipeline P;
+        P.plan = &p->plan;
+        P.lay = p->lay;
+        P.ws = (char *)d_work;
+        P.stream = (hipStream_t)stream;
+        P.x = d_x;
+        P.kp = make_kparams(k, p->plan.dim, theta, sigma2);
+        P.tol = tol;
+        factor_pipeline(P, d_y, d_out);
+        if (d_z)
+            HIP_TRY(hipMemcpyAsync(d_z, wsp<double>(P, P.lay.Xt), sizeof(double) * p->plan.n,
+                                   hipMemcpyDeviceToDevice, P.stream));
+        raise_status(read_status(P));
+        return HODLR_OK;
+    });
+}
+
+hodlr_status hodlr_matvec_dev(int64_t n, int32_t dim, const double *d_x, hodlr_kernel k,
+                              const double theta[2], double sigma2, const double *d_v,
+                              double *d_out, void *stream)
+{
+    return guarded([&]() {
+        check_sizes(n, dim, 1);
+        check_params(k, theta, sigma2, 1.0);
+        if (!d_x || !d_v || !d_out)
+            throw Error{HODLR_EINVAL, "NULL argument"};
+        run_matvec(n, make_kparams(k, dim, theta, sigma2), d_x, d_v, d_out, (hipStream_t)stream);
+        return HODLR_OK;
+    });
+}
+
+}  // extern "C"

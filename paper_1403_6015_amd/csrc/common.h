@@ -1,0 +1,287 @@
+// Internal definitions shared by the HIP translation units of libhodlrgp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hodlr.h"
+
+namespace hodlr {
+
+// ------------------------------------------------------------- constants
+constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
+constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass
+constexpr int ACA_THREADS = 256;
+constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
+constexpr int LVL_ROWS = 512;     // minimum rows per level work-group
+constexpr int LVL_MAXCH = 256;    // at most this many work-groups per child per level
+constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored in LDS
+constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices live in LDS)
+// rows a block may try as pivots: every accepted term can follow ZERO_RETRY zero rows
+constexpr int USED_MAX = (RMAX_ABS + 1) * (ZERO_RETRY + 1) + 2;
+
+enum AcaDone { ACA_ACTIVE = 0, ACA_CONVERGED = 1, ACA_CAPPED = 2, ACA_EXHAUSTED = 3 };
+enum AcaPhase { PH_ROW = 0, PH_COL = 1 };
+
+// Per-block cross-approximation state (device resident).
+struct AcaState {
+    int k;          // terms accepted so far
+    int istar;      // current pivot row (local index in alpha)
+    int jstar;      // pivot column of the current term (local index in beta)
+    int done;       // AcaDone
+    int phase;      // AcaPhase: which pass acts next
+    int zeros;      // consecutive zero-pivot rows
+    int nused;      // rows used as pivots so far
+    int cap;        // min(max_rank, |alpha|, |beta|)
+    int usercap;    // 1 if cap came from max_rank (a hit counts as "capped")
+    int pad_;
+    double delta;   // pivot value of the current term
+    double v2;      // ||v_k||^2 of the current term
+    double s2;      // ||S_k||_F^2 running estimate
+};
+
+// One work-group's slice of a block or of a level.
+struct Chunk {
+    int node;       // heap index of the split node tau
+    int side;       // 0: rows of alpha (left child), 1: rows of beta (right child)
+    int64_t lo, hi; // global row range (tree order)
+    int part;       // partial-result slot (unique within its launch table)
+    int pad_;
+};
+
+// Kernel parameters: k(r) from r^2, with c the scale of the kernel:
+//   SE: a2 exp(-c r^2), c = 1/(2 l^2);  Matern-3/2: s = c r, a2 (1+s) e^{-s},
+//   c = sqrt(3)/l;  exponential: a2 exp(-c r), c = 1/l;  constant: a2.
+struct KParams {
+    int kind;
+    int dim;
+    double a2;
+    double c;
+    double sigma2;
+};
+
+inline KParams make_kparams(int kind, int dim, const double theta[2], double sigma2)
+{
+    KParams k;
+    k.kind = kind;
+    k.dim = dim;
+    k.a2 = theta[0] * theta[0];
+    double l = theta[1];
+    switch (kind) {
+    case HODLR_K_SE: k.c = 1.0 / (2.0 * l * l); break;
+    case HODLR_K_MATERN32: k.c = std::sqrt(3.0) / l; break;
+    case HODLR_K_EXP: k.c = 1.0 / l; break;
+    default: k.c = 0.0; break;
+    }
+    k.sigma2 = sigma2;
+    return k;
+}
+
+template <typename T>
+__device__ __forceinline__ T kfun_r2(int kind, T a2, T c, T r2)
+{
+    switch (kind) {
+    case HODLR_K_SE:
+        return a2 * exp(-c * r2);
+    case HODLR_K_MATERN32: {
+        T s = c * sqrt(r2);
+        return a2 * (T(1) + s) * exp(-s);
+    }
+    case HODLR_K_EXP:
+        return a2 * exp(-c * sqrt(r2));
+    default:
+        return a2;
+    }
+}
+
+// Squared distance between ordered points i and j; coordinates are
+// coordinate-major (x[d*n + i]).
+__device__ __forceinline__ double dist2(const double *__restrict__ x, int64_t n, int dim, int64_t i,
+                                        int64_t j)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        double t = x[d * n + i] - x[d * n + j];
+        r2 += t * t;
+    }
+    return r2;
+}
+
+__device__ __forceinline__ double kentry(const KParams &kp, const double *__restrict__ x, int64_t n,
+                                         int64_t i, int64_t j)
+{
+    return kfun_r2<double>(kp.kind, kp.a2, kp.c, dist2(x, n, kp.dim, i, j));
+}
+
+// ------------------------------------------------------- wave reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// argmax of |value| with ties to the smaller index
+__device__ __forceinline__ void wave_argmax(double &v, int64_t &idx)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int64_t oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
+
+// same, carrying a payload (the signed value at the winning index)
+__device__ __forceinline__ void wave_argmax_signed(double &v, int64_t &idx, double &pay)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int64_t oi = __shfl_xor(idx, off, 64);
+        double op = __shfl_xor(pay, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+            pay = op;
+        }
+    }
+}
+
+__device__ __forceinline__ double ld_coherent(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_coherent(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------- host helpers
+struct Error {
+    hodlr_status st;
+    std::string msg;
+};
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::hodlr::Error{HODLR_EDEVICE, std::string(#expr) + ": " +               \
+                                                    hipGetErrorString(e_)};               \
+    } while (0)
+
+// Status bits written by kernels into the workspace.
+enum DevStatus { DS_NOTSPD_LEAF = 1, DS_NOTSPD_NODE = 2, DS_NONFINITE = 4 };
+
+// ----------------------------------------------------------- the plan
+// Tree, per-depth column layout and launch tables for one (n, dim, leaf, cap).
+struct Plan {
+    int64_t n = 0;
+    int dim = 1;
+    int leaf = 1;
+    int L = 0;
+    int cap = 64;
+    int precision = HODLR_FP64;
+    double refine_tol = 1e-10;
+    int max_refine = 8;
+    int64_t nint = 0;    // internal (split) nodes 2^L - 1
+    int64_t nleaf = 1;   // 2^L
+    int leafmax = 0;
+    std::vector<int64_t> start, end;   // per heap node (2^(L+1) - 1)
+    std::vector<int> capj;             // per depth j = 1..L: columns reserved
+    std::vector<int64_t> cofa;         // per depth j: first column of the panel; [L+1] = total
+    int64_t ncol = 1;                  // columns of W / Xt (column 0 is the solve vector)
+    // ACA tables (all internal nodes)
+    std::vector<Chunk> aca_row, aca_col;
+    std::vector<int> aca_nrow, aca_ncol;   // per internal node: chunk counts
+    std::vector<int> aca_rowbase, aca_colbase;
+    int aca_pw = 0;                        // doubles per ACA partial record
+    // level tables: per depth d, chunks over rows of the children of depth-d nodes
+    std::vector<std::vector<Chunk>> lvl;
+    std::vector<std::vector<int>> lvl_nch;   // per depth, per node: chunks (both sides)
+    std::vector<std::vector<int>> lvl_base;  // per depth, per node: first partial slot
+    // device copies of the tables
+    void *dev_tables = nullptr;
+    size_t dev_tables_bytes = 0;
+    int64_t *d_start = nullptr, *d_end = nullptr;
+    Chunk *d_aca_row = nullptr, *d_aca_col = nullptr;
+    int *d_aca_nrow = nullptr, *d_aca_ncol = nullptr, *d_aca_rowbase = nullptr,
+        *d_aca_colbase = nullptr;
+    std::vector<Chunk *> d_lvl;
+    std::vector<int *> d_lvl_nch, d_lvl_base;
+    int device = 0;
+
+    int depth_of(int64_t h) const
+    {
+        int d = 0;
+        while (((int64_t)2 << d) - 1 <= h)
+            ++d;
+        return d;
+    }
+    int64_t first_at(int d) const { return ((int64_t)1 << d) - 1; }
+};
+
+// Workspace layout (byte offsets into one device buffer).
+struct Layout {
+    size_t W, Xt, G;
+    size_t aca_state, aca_used, aca_vdots, aca_part, aca_cnt, aca_active;
+    size_t rank, leaf_ld, node_ld;
+    size_t lvl_part, Tbuf, Sbuf, small;
+    size_t dot_part, out, status, cols, misc;
+    size_t total;
+    int64_t small_stride;   // doubles per internal node in the small-factor store
+    int64_t T_stride;       // doubles per node in Tbuf/Sbuf
+    int64_t lvl_part_cap;   // doubles in lvl_part
+    bool store_leaf;
+};
+
+Layout make_layout(const Plan &p, bool store_leaf);
+
+// Build the plan (host); upload tables to the current device.
+void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts);
+void plan_upload(Plan &p);
+void plan_release(Plan &p);
+
+// k-d / sort ordering of caller points (point-major) -> perm
+void order_points(const double *x, int64_t n, int dim, int leaf, int64_t *perm);
+int num_levels(int64_t n, int leaf);
+
+// ------------------------------------------------------ device pipeline
+struct Pipeline {
+    const Plan *plan;
+    Layout lay;
+    char *ws;
+    hipStream_t stream;
+    const double *x;      // ordered, coordinate-major
+    KParams kp;
+    double tol;
+    // host-side results of the compression
+    std::vector<int> rmax;    // per depth j (1..L), used columns of the panel
+    std::vector<int> cols;    // used column indices, depth-ascending, cols[0] = 0
+    std::vector<int> cnt;     // cnt[d] = 1 + sum_{j<=d} rmax[j]
+    int capped = 0;
+    std::vector<int> ranks;   // per internal node
+};
+
+// Stages (implemented in the .hip files)
+void run_aca(Pipeline &P);                                   // fills W panels, ranks
+void run_leaf_factor(Pipeline &P, const double *y);          // leaves: G, log-dets, Xt
+void run_levels_factor(Pipeline &P);                         // coupling matrices, Xt, z
+void run_solve(Pipeline &P, double *z);                      // z := C^{-1} z using a built factor
+void run_finish(Pipeline &P, const double *y, double *d_out);  // log det, quad, loglik
+void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,
+                hipStream_t s);
+
+template <typename T>
+inline T *wsp(const Pipeline &P, size_t off)
+{
+    return reinterpret_cast<T *>(P.ws + off);
+}
+
+}  // namespace hodlr

@@ -1,0 +1,413 @@
+// Level stage: factor the block-diagonal low-rank updates of the identity
+// level by level from the leaves' parents to the root (§3.2).
+//
+// For a node tau with children alpha, beta and bases W (K(alpha,beta) ~
+// W_alpha W_beta^T), once the finer inverses are applied the diagonal block
+// of tau is diag(C_alpha, C_beta) (I + diag(W~_alpha, W~_beta) R) with
+// R = [[0, W_beta^T], [W_alpha^T, 0]] (the block low-rank update form of
+// §3.2).  Sherman-Morrison-Woodbury turns its inverse into the small coupling
+// matrix M = I + R diag(W~_alpha, W~_beta) = [[I, P], [Q, I]] with
+// P = W_beta^T W~_beta and Q = W_alpha^T W~_alpha, and Sylvester's theorem
+// (§4) gives det of the block as det M = det(I - Q P).
+//
+// Per level three launches:
+//   reduce  -- T = [W_beta^T X_beta; W_alpha^T X_alpha] over every column X
+//              still to be updated plus the child panel itself (which yields
+//              P and Q), as per-work-group partial sums (tall-skinny products
+//              through LDS tiles);
+//   solve   -- one work-group per node sums the partials, forms I - Q P,
+//              LU-factors it with partial pivoting in LDS, records its
+//              log-det, and solves M S = T for the remaining columns
+//              (s2 = (I - QP)^{-1} (t2 - Q t1), s1 = t1 - P s2);
+//   update  -- X_alpha -= W~_alpha S_top, X_beta -= W~_beta S_bottom.
+// The solve path reuses the three kernels on the single vector z with the
+// stored small factors.
+#include "common.h"
+
+namespace hodlr {
+
+constexpr int LV_THREADS = 256;
+constexpr int LV_RT = 64;    // rows per LDS tile
+constexpr int LV_CT = 32;    // columns per LDS tile
+constexpr int LV_CB = 32;    // right-hand sides per batch in the node solve
+
+struct LevelArgs {
+    int64_t n;
+    const double *W;
+    double *Xt;
+    const int *cols;
+    int ncnt;          // columns entering the reduction (prefix of cols)
+    int nrhs;          // columns updated (prefix of cols)
+    int64_t colW;      // first column of the child panel
+    int rstride;       // reserved rank of the child panel at run time
+    const int *rank;
+    const Chunk *chunks;
+    const int *nch, *base;
+    int64_t node0;
+    double *part;
+    double *Tbuf, *Sbuf;
+    int64_t tstride;
+    double *small;
+    int64_t sstride;
+    double *node_ld;
+    int *status;
+    int factor;        // 1: build the coupling factors; 0: apply stored ones
+};
+
+__global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A)
+{
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    __shared__ double sW[LV_RT][RMAX_ABS + 1];
+    __shared__ double sX[LV_RT][LV_CT + 1];
+    const int tid = threadIdx.x;
+    const int64_t n = A.n;
+    for (int c0 = 0; c0 < A.ncnt; c0 += LV_CT) {
+        const int nc = min(LV_CT, A.ncnt - c0);
+        const int nout = r * nc;
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            acc[q] = 0.0;
+        for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += LV_RT) {
+            const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
+            for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
+                int l = idx / LV_RT, i = idx % LV_RT;
+                sW[i][l] = (i < nr) ? A.W[(A.colW + l) * n + i0 + i] : 0.0;
+            }
+            for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
+                int c = idx / LV_RT, i = idx % LV_RT;
+                sX[i][c] = (i < nr) ? A.Xt[(int64_t)A.cols[c0 + c] * n + i0 + i] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int o = tid + q * LV_THREADS;
+                if (o < nout) {
+                    int l = o / nc, c = o % nc;
+                    double a = acc[q];
+                    for (int i = 0; i < LV_RT; ++i)
+                        a += sW[i][l] * sX[i][c];
+                    acc[q] = a;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int o = tid + q * LV_THREADS;
+            if (o < nout) {
+                int l = o / nc, c = o % nc;
+                A.part[((int64_t)ch.part * A.rstride + l) * A.ncnt + c0 + c] = acc[q];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
+{
+    const int64_t loc = blockIdx.x;
+    const int64_t h = A.node0 + loc;
+    const int r = A.rank[h];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (r == 0) {
+        if (A.factor && tid == 0)
+            A.node_ld[h] = 0.0;
+        return;
+    }
+    __shared__ double sP[RMAX_ABS][RMAX_ABS + 1];
+    __shared__ double sQ[RMAX_ABS][RMAX_ABS + 1];
+    __shared__ double sN[RMAX_ABS][RMAX_ABS + 1];
+    __shared__ double t1[RMAX_ABS][LV_CB + 1];
+    __shared__ double t2[RMAX_ABS][LV_CB + 1];
+    __shared__ int piv[RMAX_ABS];
+    __shared__ double red[4];
+    __shared__ int sbad;
+    const int nch = A.nch[loc], base = A.base[loc];
+    const int ncnt = A.ncnt, rs = A.rstride;
+    double *T = A.Tbuf + loc * A.tstride;
+    // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
+    for (int idx = tid; idx < 2 * r * ncnt; idx += LV_THREADS) {
+        int row2 = idx / ncnt, c = idx % ncnt;
+        int side = row2 < r ? 1 : 0;
+        int l = row2 < r ? row2 : row2 - r;
+        double acc = 0.0;
+        for (int q = base; q < base + nch; ++q)
+            if (A.chunks[q].side == side)
+                acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+        T[(int64_t)(side ? l : rs + l) * ncnt + c] = acc;
+    }
+    __threadfence_block();
+    __syncthreads();
+    double *sm = A.small + h * A.sstride;   // [N_LU r*r | P r*r | Q r*r | piv r]
+    if (A.factor) {
+        const int cp = A.nrhs;   // the child panel's columns follow the updated ones
+        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+            int i = idx / r, j = idx % r;
+            sP[i][j] = T[(int64_t)i * ncnt + cp + j];
+            sQ[i][j] = T[(int64_t)(rs + i) * ncnt + cp + j];
+        }
+        if (tid == 0)
+            sbad = 0;
+        __syncthreads();
+        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+            int i = idx / r, j = idx % r;
+            double a = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < r; ++k)
+                a -= sQ[i][k] * sP[k][j];
+            sN[i][j] = a;
+        }
+        __syncthreads();
+        // LU with partial pivoting (rows swapped in place)
+        for (int k = 0; k < r; ++k) {
+            if (tid == 0) {
+                int p = k;
+                double best = fabs(sN[k][k]);
+                for (int i = k + 1; i < r; ++i)
+                    if (fabs(sN[i][k]) > best) {
+                        best = fabs(sN[i][k]);
+                        p = i;
+                    }
+                piv[k] = p;
+                if (best == 0.0)
+                    sbad = 1;
+            }
+            __syncthreads();
+            int p = piv[k];
+            if (p != k)
+                for (int j = tid; j < r; j += LV_THREADS) {
+                    double a = sN[k][j];
+                    sN[k][j] = sN[p][j];
+                    sN[p][j] = a;
+                }
+            __syncthreads();
+            double pv = sN[k][k];
+            for (int i = k + 1 + tid; i < r; i += LV_THREADS)
+                if (pv != 0.0)
+                    sN[i][k] /= pv;
+            __syncthreads();
+            int tr = r - k - 1;
+            for (int idx = tid; idx < tr * tr; idx += LV_THREADS) {
+                int i = k + 1 + idx / tr, j = k + 1 + idx % tr;
+                sN[i][j] -= sN[i][k] * sN[k][j];
+            }
+            __syncthreads();
+        }
+        // log det M = log det(I - QP); it must be positive for an SPD C
+        double lg = 0.0;
+        int neg = 0;
+        for (int i = tid; i < r; i += LV_THREADS) {
+            double u = sN[i][i];
+            lg += log(fabs(u));
+            neg += (u < 0.0) ? 1 : 0;
+            neg += (piv[i] != i) ? 1 : 0;
+        }
+        lg = wave_sum(lg);
+        for (int off = 32; off > 0; off >>= 1)
+            neg += __shfl_xor(neg, off, 64);
+        if (lane == 0) {
+            red[wid] = lg;
+            if (neg & 1)
+                atomicOr(&sbad, 2);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = (red[0] + red[1]) + (red[2] + red[3]);
+            if (sbad) {
+                atomicOr(A.status, DS_NOTSPD_NODE);
+                v = __builtin_nan("");
+            }
+            A.node_ld[h] = v;
+        }
+        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+            int i = idx / r, j = idx % r;
+            sm[idx] = sN[i][j];
+            sm[r * r + idx] = sP[i][j];
+            sm[2 * r * r + idx] = sQ[i][j];
+        }
+        for (int i = tid; i < r; i += LV_THREADS)
+            sm[3 * r * r + i] = (double)piv[i];
+    } else {
+        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+            int i = idx / r, j = idx % r;
+            sN[i][j] = sm[idx];
+            sP[i][j] = sm[r * r + idx];
+            sQ[i][j] = sm[2 * r * r + idx];
+        }
+        for (int i = tid; i < r; i += LV_THREADS)
+            piv[i] = (int)sm[3 * r * r + i];
+    }
+    __syncthreads();
+    // S = M^{-1} T on the columns to update, in batches
+    double *S = A.Sbuf + loc * A.tstride;
+    const int nrhs = A.nrhs;
+    for (int c0 = 0; c0 < nrhs; c0 += LV_CB) {
+        const int nb = min(LV_CB, nrhs - c0);
+        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+            int i = idx / nb, c = idx % nb;
+            t1[i][c] = T[(int64_t)i * ncnt + c0 + c];
+        }
+        __syncthreads();
+        // t2 := t2 - Q t1, with the row permutation of the LU applied after
+        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+            int i = idx / nb, c = idx % nb;
+            double a = T[(int64_t)(rs + i) * ncnt + c0 + c];
+            for (int k = 0; k < r; ++k)
+                a -= sQ[i][k] * t1[k][c];
+            t2[i][c] = a;
+        }
+        __syncthreads();
+        if (tid < nb) {
+            int c = tid;
+            for (int k = 0; k < r; ++k) {
+                int p = piv[k];
+                if (p != k) {
+                    double a = t2[k][c];
+                    t2[k][c] = t2[p][c];
+                    t2[p][c] = a;
+                }
+            }
+            for (int i = 1; i < r; ++i) {
+                double a = t2[i][c];
+                for (int k = 0; k < i; ++k)
+                    a -= sN[i][k] * t2[k][c];
+                t2[i][c] = a;
+            }
+            for (int i = r - 1; i >= 0; --i) {
+                double a = t2[i][c];
+                for (int k = i + 1; k < r; ++k)
+                    a -= sN[i][k] * t2[k][c];
+                t2[i][c] = a / sN[i][i];
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+            int i = idx / nb, c = idx % nb;
+            double a = t1[i][c];
+            for (int k = 0; k < r; ++k)
+                a -= sP[i][k] * t2[k][c];
+            S[(int64_t)i * nrhs + c0 + c] = a;
+            S[(int64_t)(rs + i) * nrhs + c0 + c] = t2[i][c];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A)
+{
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    __shared__ double sWt[LV_RT][RMAX_ABS + 1];
+    __shared__ double sS[RMAX_ABS][LV_CT + 1];
+    const int tid = threadIdx.x;
+    const int64_t n = A.n;
+    const int64_t loc = ch.node - A.node0;
+    const double *S = A.Sbuf + loc * A.tstride;
+    const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
+    const int nrhs = A.nrhs;
+    for (int c0 = 0; c0 < nrhs; c0 += LV_CT) {
+        const int nc = min(LV_CT, nrhs - c0);
+        for (int idx = tid; idx < r * nc; idx += LV_THREADS) {
+            int l = idx / nc, c = idx % nc;
+            sS[l][c] = S[(int64_t)(rowoff + l) * nrhs + c0 + c];
+        }
+        for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += LV_RT) {
+            const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
+            for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
+                int l = idx / LV_RT, i = idx % LV_RT;
+                sWt[i][l] = (i < nr) ? A.Xt[(A.colW + l) * n + i0 + i] : 0.0;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
+                int c = idx / LV_RT, i = idx % LV_RT;
+                if (i < nr) {
+                    double *px = A.Xt + (int64_t)A.cols[c0 + c] * n + i0 + i;
+                    double a = *px;
+                    for (int l = 0; l < r; ++l)
+                        a -= sWt[i][l] * sS[l][c];
+                    *px = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+static LevelArgs level_args(Pipeline &P, int d)
+{
+    const Plan &p = *P.plan;
+    LevelArgs A;
+    A.n = p.n;
+    A.W = wsp<double>(P, P.lay.W);
+    A.Xt = wsp<double>(P, P.lay.Xt);
+    A.cols = wsp<int>(P, P.lay.cols);
+    A.colW = p.cofa[d + 1];
+    A.rstride = P.rmax[d + 1];
+    A.rank = wsp<int>(P, P.lay.rank);
+    A.chunks = p.d_lvl[d];
+    A.nch = p.d_lvl_nch[d];
+    A.base = p.d_lvl_base[d];
+    A.node0 = p.first_at(d);
+    A.part = wsp<double>(P, P.lay.lvl_part);
+    A.Tbuf = wsp<double>(P, P.lay.Tbuf);
+    A.Sbuf = wsp<double>(P, P.lay.Sbuf);
+    A.small = wsp<double>(P, P.lay.small);
+    A.sstride = P.lay.small_stride;
+    A.node_ld = wsp<double>(P, P.lay.node_ld);
+    A.status = wsp<int>(P, P.lay.status);
+    return A;
+}
+
+static void level_launch(Pipeline &P, int d, LevelArgs A)
+{
+    const Plan &p = *P.plan;
+    const unsigned nchunks = (unsigned)p.lvl[d].size();
+    const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
+    if (nchunks)
+        level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+    level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
+    if (nchunks && A.nrhs > 0)
+        level_update_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+    HIP_TRY(hipGetLastError());
+}
+
+void run_levels_factor(Pipeline &P)
+{
+    const Plan &p = *P.plan;
+    for (int d = p.L - 1; d >= 0; --d) {
+        LevelArgs A = level_args(P, d);
+        A.factor = 1;
+        A.ncnt = P.cnt[d + 1];
+        A.nrhs = P.cnt[d];
+        A.tstride = 2 * (int64_t)A.rstride * A.ncnt;
+        if (A.rstride == 0) {
+            // every block of this level has rank 0: coupling determinants are 1
+            const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
+            level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
+            HIP_TRY(hipGetLastError());
+            continue;
+        }
+        level_launch(P, d, A);
+    }
+}
+
+void run_levels_apply(Pipeline &P)
+{
+    const Plan &p = *P.plan;
+    for (int d = p.L - 1; d >= 0; --d) {
+        LevelArgs A = level_args(P, d);
+        if (A.rstride == 0)
+            continue;
+        A.factor = 0;
+        A.ncnt = 1;
+        A.nrhs = 1;
+        A.tstride = 2 * (int64_t)A.rstride;
+        level_launch(P, d, A);
+    }
+}
+
+}  // namespace hodlr

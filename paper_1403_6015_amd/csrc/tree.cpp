@@ -1,0 +1,299 @@
+// Host side of the tree: point ordering, node ranges, column layout of the
+// basis panels and the launch tables of the device stages.
+//
+// Ordering (§3 of the paper: points are sorted by a k-d tree, one dimension at
+// a time, and the resulting order makes matrix rows/columns correspond to
+// tree nodes).  The tree is count-based: a node of m consecutive points splits
+// into a left child of floor(m/2) points and a right child of the rest.  The
+// number of levels is the smallest L with every leaf holding at most `leaf`
+// points (the paper's kappa from the smallest block size p_max, §3.2).
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+namespace hodlr {
+
+int num_levels(int64_t n, int leaf)
+{
+    if (n < 1 || leaf < 1)
+        return 0;
+    int L = 0;
+    while (L < 62 && (n + ((int64_t)1 << L) - 1) / ((int64_t)1 << L) > leaf)
+        ++L;
+    return L;
+}
+
+void order_points(const double *x, int64_t n, int dim, int leaf, int64_t *perm)
+{
+    std::vector<int64_t> p(n);
+    std::iota(p.begin(), p.end(), 0);
+    auto by = [&](int c) {
+        return [&, c](int64_t a, int64_t b) {
+            double xa = x[a * dim + c], xb = x[b * dim + c];
+            return xa < xb || (xa == xb && a < b);
+        };
+    };
+    if (dim == 1) {
+        std::sort(p.begin(), p.end(), by(0));
+    } else {
+        int L = num_levels(n, leaf);
+        // depth-d nodes: recursive halving of [0, n)
+        std::vector<std::pair<int64_t, int64_t>> level{{0, n}};
+        for (int d = 0; d < L; ++d) {
+            int c = d % dim;
+            std::vector<std::pair<int64_t, int64_t>> next;
+            next.reserve(level.size() * 2);
+            for (auto [s, e] : level) {
+                std::sort(p.begin() + s, p.begin() + e, by(c));
+                int64_t m = s + (e - s) / 2;
+                next.push_back({s, m});
+                next.push_back({m, e});
+            }
+            level.swap(next);
+        }
+    }
+    std::memcpy(perm, p.data(), sizeof(int64_t) * (size_t)n);
+}
+
+static void make_chunks(int node, int side, int64_t lo, int64_t hi, int64_t size,
+                        std::vector<Chunk> &out, int &slot)
+{
+    for (int64_t a = lo; a < hi; a += size) {
+        Chunk c;
+        c.node = node;
+        c.side = side;
+        c.lo = a;
+        c.hi = std::min(hi, a + size);
+        c.part = slot++;
+        c.pad_ = 0;
+        out.push_back(c);
+    }
+}
+
+void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
+{
+    p.n = n;
+    p.dim = dim;
+    p.leaf = leaf;
+    p.L = num_levels(n, leaf);
+    p.cap = opts ? opts->max_rank : 64;
+    p.precision = opts ? opts->precision : HODLR_FP64;
+    p.refine_tol = (opts && opts->refine_tol > 0) ? opts->refine_tol : 1e-10;
+    p.max_refine = (opts && opts->max_refine > 0) ? opts->max_refine : 8;
+    const int L = p.L;
+    const int64_t nn = ((int64_t)2 << L) - 1;
+    p.nint = ((int64_t)1 << L) - 1;
+    p.nleaf = (int64_t)1 << L;
+    p.start.assign(nn, 0);
+    p.end.assign(nn, 0);
+    p.start[0] = 0;
+    p.end[0] = n;
+    for (int64_t h = 0; h < p.nint; ++h) {
+        int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
+        p.start[2 * h + 1] = s;
+        p.end[2 * h + 1] = m;
+        p.start[2 * h + 2] = m;
+        p.end[2 * h + 2] = e;
+    }
+    p.leafmax = 0;
+    for (int64_t h = p.nint; h < nn; ++h)
+        p.leafmax = std::max<int>(p.leafmax, (int)(p.end[h] - p.start[h]));
+
+    // columns reserved per depth j (bases of depth-j nodes, rank of the parent block)
+    p.capj.assign(L + 2, 0);
+    p.cofa.assign(L + 2, 0);
+    for (int j = 1; j <= L; ++j) {
+        int64_t best = 0;
+        for (int64_t h = p.first_at(j - 1); h < p.first_at(j); ++h) {
+            int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
+            best = std::max(best, std::min(m - s, e - m));
+        }
+        p.capj[j] = (int)std::min<int64_t>(p.cap, best);
+    }
+    p.cofa[1] = 1;
+    for (int j = 1; j <= L; ++j)
+        p.cofa[j + 1] = p.cofa[j] + p.capj[j];
+    p.ncol = (L >= 1) ? p.cofa[L + 1] : 1;
+
+    // cross-approximation tables: row passes sweep beta, column passes sweep alpha
+    p.aca_row.clear();
+    p.aca_col.clear();
+    p.aca_nrow.assign(p.nint, 0);
+    p.aca_ncol.assign(p.nint, 0);
+    p.aca_rowbase.assign(p.nint, 0);
+    p.aca_colbase.assign(p.nint, 0);
+    int rslot = 0, cslot = 0;
+    for (int64_t h = 0; h < p.nint; ++h) {
+        int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
+        if (m - s == 0 || e - m == 0 || p.cap == 0)
+            continue;
+        p.aca_rowbase[h] = rslot;
+        p.aca_colbase[h] = cslot;
+        make_chunks((int)h, 1, m, e, ACA_CHUNK, p.aca_row, rslot);
+        make_chunks((int)h, 0, s, m, ACA_CHUNK, p.aca_col, cslot);
+        p.aca_nrow[h] = rslot - p.aca_rowbase[h];
+        p.aca_ncol[h] = cslot - p.aca_colbase[h];
+    }
+    p.aca_pw = std::max(p.cap, 1) + 4;
+
+    // level tables: for depth d, chunks over the rows of each child of each node
+    p.lvl.assign(L, {});
+    p.lvl_nch.assign(L, {});
+    p.lvl_base.assign(L, {});
+    for (int d = 0; d < L; ++d) {
+        int slot = 0;
+        for (int64_t h = p.first_at(d); h < p.first_at(d + 1); ++h) {
+            p.lvl_base[d].push_back(slot);
+            int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
+            for (int side = 0; side < 2; ++side) {
+                int64_t lo = side ? m : s, hi = side ? e : m;
+                int64_t len = hi - lo;
+                int64_t csz = std::max<int64_t>(LVL_ROWS, (len + LVL_MAXCH - 1) / LVL_MAXCH);
+                csz = (csz + 63) / 64 * 64;
+                if (len > 0)
+                    make_chunks((int)h, side, lo, hi, csz, p.lvl[d], slot);
+            }
+            p.lvl_nch[d].push_back(slot - p.lvl_base[d].back());
+        }
+    }
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void plan_upload(Plan &p)
+{
+    HIP_TRY(hipGetDevice(&p.device));
+    const int L = p.L;
+    const int64_t nn = ((int64_t)2 << L) - 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    size_t o_start = take(sizeof(int64_t) * nn), o_end = take(sizeof(int64_t) * nn);
+    size_t o_ar = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_row.size()));
+    size_t o_ac = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_col.size()));
+    size_t o_nr = take(sizeof(int) * std::max<int64_t>(1, p.nint));
+    size_t o_nc = take(sizeof(int) * std::max<int64_t>(1, p.nint));
+    size_t o_rb = take(sizeof(int) * std::max<int64_t>(1, p.nint));
+    size_t o_cb = take(sizeof(int) * std::max<int64_t>(1, p.nint));
+    std::vector<size_t> o_l(L), o_ln(L), o_lb(L);
+    for (int d = 0; d < L; ++d) {
+        o_l[d] = take(sizeof(Chunk) * std::max<size_t>(1, p.lvl[d].size()));
+        o_ln[d] = take(sizeof(int) * p.lvl_nch[d].size());
+        o_lb[d] = take(sizeof(int) * p.lvl_base[d].size());
+    }
+    std::vector<char> host(off, 0);
+    auto put = [&](size_t o, const void *src, size_t bytes) {
+        if (bytes)
+            std::memcpy(host.data() + o, src, bytes);
+    };
+    put(o_start, p.start.data(), sizeof(int64_t) * nn);
+    put(o_end, p.end.data(), sizeof(int64_t) * nn);
+    put(o_ar, p.aca_row.data(), sizeof(Chunk) * p.aca_row.size());
+    put(o_ac, p.aca_col.data(), sizeof(Chunk) * p.aca_col.size());
+    put(o_nr, p.aca_nrow.data(), sizeof(int) * p.nint);
+    put(o_nc, p.aca_ncol.data(), sizeof(int) * p.nint);
+    put(o_rb, p.aca_rowbase.data(), sizeof(int) * p.nint);
+    put(o_cb, p.aca_colbase.data(), sizeof(int) * p.nint);
+    for (int d = 0; d < L; ++d) {
+        put(o_l[d], p.lvl[d].data(), sizeof(Chunk) * p.lvl[d].size());
+        put(o_ln[d], p.lvl_nch[d].data(), sizeof(int) * p.lvl_nch[d].size());
+        put(o_lb[d], p.lvl_base[d].data(), sizeof(int) * p.lvl_base[d].size());
+    }
+    void *dev = nullptr;
+    if (hipMalloc(&dev, std::max<size_t>(off, 256)) != hipSuccess)
+        throw Error{HODLR_ENOMEM, "device allocation of plan tables failed"};
+    if (hipMemcpy(dev, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dev);
+        throw Error{HODLR_EDEVICE, "upload of plan tables failed"};
+    }
+    char *b = (char *)dev;
+    p.dev_tables = dev;
+    p.dev_tables_bytes = off;
+    p.d_start = (int64_t *)(b + o_start);
+    p.d_end = (int64_t *)(b + o_end);
+    p.d_aca_row = (Chunk *)(b + o_ar);
+    p.d_aca_col = (Chunk *)(b + o_ac);
+    p.d_aca_nrow = (int *)(b + o_nr);
+    p.d_aca_ncol = (int *)(b + o_nc);
+    p.d_aca_rowbase = (int *)(b + o_rb);
+    p.d_aca_colbase = (int *)(b + o_cb);
+    p.d_lvl.resize(L);
+    p.d_lvl_nch.resize(L);
+    p.d_lvl_base.resize(L);
+    for (int d = 0; d < L; ++d) {
+        p.d_lvl[d] = (Chunk *)(b + o_l[d]);
+        p.d_lvl_nch[d] = (int *)(b + o_ln[d]);
+        p.d_lvl_base[d] = (int *)(b + o_lb[d]);
+    }
+}
+
+void plan_release(Plan &p)
+{
+    if (p.dev_tables) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p.device);
+        (void)hipFree(p.dev_tables);
+        (void)hipSetDevice(cur);
+    }
+    p.dev_tables = nullptr;
+}
+
+Layout make_layout(const Plan &p, bool store_leaf)
+{
+    Layout y{};
+    const int L = p.L;
+    const int64_t n = p.n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 8));
+        return o;
+    };
+    int capmax = 1;
+    for (int j = 1; j <= L; ++j)
+        capmax = std::max(capmax, p.capj[j]);
+    y.store_leaf = store_leaf;
+    y.W = take(sizeof(double) * (size_t)n * (size_t)p.ncol);
+    y.Xt = take(sizeof(double) * (size_t)n * (size_t)p.ncol);
+    int64_t lm = p.leafmax;
+    y.G = take(store_leaf ? sizeof(double) * (size_t)p.nleaf * (size_t)(lm * (lm + 1) / 2) : 8);
+    int64_t ni = std::max<int64_t>(p.nint, 1);
+    y.aca_state = take(sizeof(AcaState) * ni);
+    y.aca_used = take(sizeof(int) * ni * USED_MAX);
+    y.aca_vdots = take(sizeof(double) * ni * std::max(p.cap, 1));
+    y.aca_part = take(sizeof(double) * std::max(p.aca_row.size(), p.aca_col.size()) * p.aca_pw);
+    y.aca_cnt = take(sizeof(int) * ni);
+    y.aca_active = take(sizeof(int) * 4);
+    y.rank = take(sizeof(int) * ni);
+    y.leaf_ld = take(sizeof(double) * p.nleaf);
+    y.node_ld = take(sizeof(double) * ni);
+    // worst-case sizes from the reserved columns
+    int64_t lp = 1, tb = 1;
+    for (int d = 0; d < L; ++d) {
+        int64_t cntc = p.cofa[d + 2];           // columns 0 .. end of panel d+1
+        int64_t r = p.capj[d + 1];
+        lp = std::max<int64_t>(lp, (int64_t)p.lvl[d].size() * r * cntc);
+        tb = std::max<int64_t>(tb, (p.first_at(d + 1) - p.first_at(d)) * 2 * r * cntc);
+    }
+    y.lvl_part_cap = lp;
+    y.lvl_part = take(sizeof(double) * lp);
+    y.Tbuf = take(sizeof(double) * tb);
+    y.Sbuf = take(sizeof(double) * tb);
+    y.small_stride = 3 * (int64_t)capmax * capmax + capmax;
+    y.small = take(sizeof(double) * ni * y.small_stride);
+    y.dot_part = take(sizeof(double) * 1024);
+    y.out = take(sizeof(double) * 8);
+    y.status = take(sizeof(int) * 4);
+    y.cols = take(sizeof(int) * p.ncol);
+    y.misc = take(4096);
+    y.total = off;
+    return y;
+}
+
+}  // namespace hodlr
