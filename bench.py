@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""GP log-likelihoods per second on one MI355X.
+
+Workload (the benchmark configuration): n = 2^20 points t ~ U(0, 1000)
+sorted, Matern-3/2 kernel a = 1, l = 5, sigma^2 = 0.1, leaf 128, tolerance
+1e-10, y ~ N(0, 1).  One step = one full log-likelihood for the given
+hyperparameters: cross approximation of every off-diagonal block, leaf
+factorizations, level-by-level factorization, log-det and C^{-1} y, with the
+ordered points and y already resident in HBM.  The ordering of the points is
+amortized over hyperparameters and reported separately.
+
+Prints one JSON line.  Also reports, for the kernel that takes the most time,
+its achieved rate against MI355X's peak (live HIP-event timing inside the
+library, on the stream each kernel is launched on), and the dense FP64 oracle
+timed on the host cores on a bounded slice of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GP log-likelihoods/s (factor+logdet+solve) at n=2^20; mixed vs FP64 at 1e-8"
+PEAK = {"hbm": 8000.0, "alu_fp64": 78.6, "alu_fp32": 157.3}   # GB/s, TFLOP/s, TFLOP/s
+
+
+def kernel_model(n, leaf_sizes, r, cnt):
+    """Algorithmic FLOPs and HBM bytes per call for each kernel kind.
+
+    leaf_sizes: sizes of the leaves; r[j]: columns of the depth-j panel
+    (j = 1..L); cnt[d] = 1 + sum_{j<=d} r[j] (columns still updated at depth d
+    plus the right-hand side).  Bytes count each FP64 operand moved once.
+    """
+    L = len(cnt) - 1
+    m = np.asarray(leaf_sizes, dtype=np.float64)
+    out = {}
+    # leaves: Cholesky m^3/3, two triangular solves on cnt[L] columns
+    flops = float(np.sum(m ** 3 / 3.0 + 2.0 * m * m * cnt[L]))
+    byts = 8.0 * n * (2 * cnt[L])
+    out["leaf_factor"] = (flops, byts)
+    fr = br = fu = bu = 0.0
+    for d in range(L):
+        rr = r[d + 1]
+        fr += 2.0 * rr * cnt[d + 1] * n
+        br += 8.0 * n * (cnt[d + 1] + rr)
+        fu += 2.0 * rr * cnt[d] * n
+        bu += 8.0 * n * (2 * cnt[d] + rr)
+    out["level_reduce"] = (fr, br)
+    out["level_update"] = (fu, bu)
+    return out
+
+
+def cpu_baseline(sample_n: int):
+    """The dense FP64 oracle on the first-`sample_n`-points slice of the
+    workload (same density), extrapolated to n = 2^20 by the n^3 cost of a
+    dense Cholesky; also times the exact O(n) Kalman oracle at full size and
+    returns it for the accuracy check of the GPU result."""
+    import oracle
+    import workloads as wl
+    oracle.build(force=False)
+    p = wl.matern1d(sample_n)
+    t0 = time.perf_counter()
+    oracle.gp_dense(p.x, p.y, p.kernel, p.theta, p.sigma2)
+    dt = time.perf_counter() - t0
+    full = wl.matern1d()
+    t1 = time.perf_counter()
+    kf = oracle.kalman_matern32(full.x[:, 0], full.y, full.theta, full.sigma2, want_alpha=False)
+    dk = time.perf_counter() - t1
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    value = 1.0 / (dt * (float(1 << 20) / sample_n) ** 3)
+    base = {"value": value, "unit": "likelihoods/s", "cores": threads, "kind": "oracle",
+            "sample": "dense FP64 Cholesky oracle on n=%d (density-matched slice of the "
+                      "workload) took %.2f s on %d threads; value = 1/(t*(2^20/%d)^3), an n^3 "
+                      "extrapolation" % (sample_n, dt, threads, sample_n)}
+    return base, kf, dk
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=1 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1403_6015_amd as H
+    import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = wl.matern1d(args.n)
+    t0 = time.perf_counter()
+    perm = H.hodlr_order(p.x, p.leaf)
+    t_order = time.perf_counter() - t0
+    xs = p.x[perm]
+    ys = p.y[perm]
+    opts = H.Opts(max_rank=64)
+    plan = H.Plan(p.n, p.dim, p.leaf, opts)
+    d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
+    d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
+    work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+    z = torch.empty(p.n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                        plan.workspace_bytes, stream, out, z)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    H.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = H.profile_read()
+    H.profile_enable(False)
+    loglik, logdet, quad = out[:3].cpu().tolist()
+
+    # ranks for the algorithmic model (one untimed build on the same data)
+    f = H.hodlr_build(xs, p.kernel, p.theta, p.sigma2, p.leaf, p.tol,
+                      H.Opts(max_rank=64, presorted=1))
+    info = f.info()
+    f.free()
+    L = info["levels"]
+    r = [0] + [int(v) for v in info["rank_max"][:L]]
+    cnt = [1]
+    for j in range(1, L + 1):
+        cnt.append(cnt[-1] + r[j])
+    nl = 1 << L
+    leaf_sizes = np.diff(np.linspace(0, p.n, nl + 1).round()).astype(int) if L else [p.n]
+    model = kernel_model(p.n, leaf_sizes, r, cnt)
+
+    stages = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(stages, key=lambda k: stages[k][0])
+    dom_ms, dom_launches = stages[dom]
+    roofline = None
+    if dom in model:
+        flops, byts = model[dom]
+        per_call_s = dom_ms / 1e3 / args.steps
+        ai = flops / byts
+        if ai > PEAK["alu_fp64"] * 1e12 / (PEAK["hbm"] * 1e9):
+            ach = flops / per_call_s / 1e12
+            roofline = {"bound": "alu", "achieved": ach, "peak": PEAK["alu_fp64"], "unit": "TFLOP/s",
+                        "frac": ach / PEAK["alu_fp64"], "traffic": None, "kernel": dom,
+                        "dtype": "fp64", "avg_launch_ms": dom_ms / dom_launches,
+                        "algorithmic_per_call": {"flops": flops, "bytes": byts}}
+        else:
+            ach = byts / per_call_s / 1e9
+            roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+                        "frac": ach / PEAK["hbm"], "traffic": None, "kernel": dom,
+                        "avg_launch_ms": dom_ms / dom_launches,
+                        "algorithmic_per_call": {"flops": flops, "bytes": byts}}
+
+    res = {
+        "metric": METRIC, "value": args.steps / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "matern32_1d_n%d_leaf%d_tol%g" % (p.n, p.leaf, p.tol), "n": p.n,
+                   "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
+                   "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": "fp64",
+                   "levels": L, "rank_max": r[1:]},
+        "roofline": roofline,
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "stage_launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+        "ordering_s": t_order,
+        "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
+    }
+    if not args.no_cpu_baseline and args.n == 1 << 20:
+        base, kf, dk = cpu_baseline(args.cpu_sample_n)
+        res["cpu_baseline"] = base
+        res["oracle_check"] = {"kalman_logdet": kf["logdet"], "kalman_quad": kf["quad"],
+                               "logdet_rel_err": abs(logdet - kf["logdet"]) / abs(kf["logdet"]),
+                               "quad_rel_err": abs(quad - kf["quad"]) / abs(kf["quad"]),
+                               "kalman_seconds_1core": dk}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

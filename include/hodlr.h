@@ -176,6 +176,26 @@ hodlr_status hodlr_matvec_dev(int64_t n, int32_t dim, const double *d_x, hodlr_k
                               const double theta[2], double sigma2, const double *d_v,
                               double *d_out, void *stream);
 
+/* ------------------------------------------------------------ profiling */
+
+#define HODLR_PROF_STAGES 16
+
+/* Per-kernel timing with HIP events recorded on the stream each kernel is
+ * launched on (tracing aid; not part of the method).  Stage names are
+ * NUL-terminated; ms is the summed event time and launches the number of
+ * timed launches since the last reset.                                      */
+typedef struct {
+    int32_t nstages;
+    char name[HODLR_PROF_STAGES][32];
+    double ms[HODLR_PROF_STAGES];
+    int64_t launches[HODLR_PROF_STAGES];
+} hodlr_profile_t;
+
+/* on = 1 starts timing (and clears the counters), 0 stops.  Process-wide.  */
+hodlr_status hodlr_profile_enable(int32_t on);
+/* Copies the counters accumulated by completed calls.                      */
+hodlr_status hodlr_profile_read(hodlr_profile_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ __all__ = [
     "HodlrError", "Opts", "Factor", "Plan", "lib", "hodlr_order", "hodlr_num_levels",
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
-    "FP64", "MIXED", "EXPORTED",
+    "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
@@ -27,6 +27,7 @@ EXPORTED = [
     "hodlr_order", "hodlr_num_levels", "hodlr_build", "hodlr_logdet", "hodlr_solve",
     "gp_loglik", "hodlr_info", "hodlr_free", "hodlr_last_error", "hodlr_plan_create",
     "hodlr_plan_destroy", "hodlr_plan_workspace_size", "gp_loglik_dev", "hodlr_matvec_dev",
+    "hodlr_profile_enable", "hodlr_profile_read",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,6 +51,11 @@ class Opts(ctypes.Structure):
     def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0):
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
                          int(presorted))
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("nstages", ctypes.c_int32), ("name", (ctypes.c_char * 32) * 16),
+                ("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
 
 
 class Info(ctypes.Structure):
@@ -112,6 +118,10 @@ def lib():
                                 vp, ctypes.c_size_t, vp, vp, vp]
     L.hodlr_matvec_dev.restype = st
     L.hodlr_matvec_dev.argtypes = [i64, i32, vp, ctypes.c_int, dp, ctypes.c_double, vp, vp, vp]
+    L.hodlr_profile_enable.restype = st
+    L.hodlr_profile_enable.argtypes = [i32]
+    L.hodlr_profile_read.restype = st
+    L.hodlr_profile_read.argtypes = [ctypes.POINTER(Profile)]
     _lib = L
     return L
 
@@ -295,3 +305,15 @@ def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d
     s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
     _check(lib().hodlr_matvec_dev(int(n), int(dim), _ptr(d_x), int(kernel), _dp(th),
                                   float(sigma2), _ptr(d_v), _ptr(d_out), s))
+
+
+def profile_enable(on: bool = True):
+    """Start (and reset) or stop per-kernel HIP-event timing inside the library."""
+    _check(lib().hodlr_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel kind: (summed ms, launches)} for completed calls since the reset."""
+    P = Profile()
+    _check(lib().hodlr_profile_read(ctypes.byref(P)))
+    return {P.name[i].value.decode(): (P.ms[i], int(P.launches[i])) for i in range(P.nstages)}

@@ -1,25 +1,35 @@
 // Batched adaptive cross approximation (ACA) of every off-diagonal block
-// K(alpha, beta) of the tree, all levels at once (§3.1 of the paper: an
-// approximate partially pivoted LU that builds A ~ sum_k u_k v_k^T from rows
-// and columns of A, with a sub-sampled error estimate).
+// K(alpha, beta) of the tree (§3.1 of the paper: an approximate partially
+// pivoted LU that builds A ~ sum_k u_k v_k^T from rows and columns of A,
+// with a sub-sampled error estimate).  Entries are evaluated on the fly from
+// the ordered coordinates; u_k fills column k of the alpha rows and v_k
+// column k of the beta rows of the depth-(d+1) panel.
 //
-// Each ACA step is two launches over all blocks still active:
-//   row pass    -- residual row v = A(i*, :) - sum_l u_l(i*) v_l over beta,
-//                  written as column k of the beta rows of the depth-(d+1)
-//                  panel; the last work-group of a block picks the pivot
-//                  column j* (first max |v|) and records v.v_l;
-//   column pass -- u = (A(:, j*) - sum_l v_l(j*) u_l) / v(j*) over alpha,
-//                  written as column k of the alpha rows; the last
-//                  work-group updates ||S_k||_F^2, applies the stopping test
-//                  ||u|| ||v|| <= tol ||S_k||_F and picks the next pivot row
-//                  (first max |u| over unused rows).
-// A zero pivot marks the row used and retries the unused row nearest the
-// split; the first row is the one next to the split.  Entries are evaluated
-// on the fly from the ordered coordinates; a work-group handles ACA_CHUNK
-// consecutive indices, so the coordinate and panel accesses are coalesced.
+// One step of the method (same rules as the oracle's walk-through):
+//   v = A(i*, :) - sum_l u_l(i*) v_l;  j* = first argmax |v|;
+//   v(j*) == 0: mark i* used, retry with the unused row nearest the split;
+//   u = (A(:, j*) - sum_l v_l(j*) u_l) / v(j*);
+//   ||S||_F^2 += |u|^2 |v|^2 + 2 sum_l (u.u_l)(v.v_l);
+//   stop when |u| |v| <= tol ||S||_F or at the rank cap; otherwise the next
+//   pivot row is the first argmax |u| over unused rows.
+//
+// Two paths, no communication between work-groups inside a launch (on this
+// chip the L2 caches of the eight dies are not coherent, so intra-launch
+// hand-offs would need device-wide cache write-backs):
+//   * small blocks (both sides <= ACA_SMALL): one work-group runs the whole
+//     loop for one block, all blocks in a single launch;
+//   * large blocks: each step is a row pass and a column pass over all large
+//     blocks, every work-group covering ACA_CHUNK indices of one block.  Each
+//     pass first re-derives the pivot and the norms from the previous pass's
+//     per-work-group records (identically in every work-group of the block),
+//     so state only moves across launch boundaries (double-buffered).
 #include "common.h"
 
 namespace hodlr {
+
+constexpr int SM_EPT = ACA_SMALL / ACA_THREADS;   // entries per thread, small path
+
+enum BigPhase { BP_FRESH = 0, BP_ROWDONE = 1, BP_COLDONE = 2, BP_RETRY = 3 };
 
 struct AcaArgs {
     const double *x;
@@ -28,18 +38,8 @@ struct AcaArgs {
     double tol;
     double *W;
     const int64_t *start, *end;
-    const int64_t *cofa;   // device copy of column offsets per depth
-    AcaState *st;
-    int *used;
-    double *vdots;
-    int vstride;
-    double *part;
-    int pw;
-    int *cnt;
-    int *active;
-    const Chunk *chunks;
-    const int *nch;
-    const int *base;
+    const int64_t *cofa;
+    int cap;
 };
 
 __device__ __forceinline__ int depth_of_node(int64_t h)
@@ -47,264 +47,505 @@ __device__ __forceinline__ int depth_of_node(int64_t h)
     return 63 - __clzll((unsigned long long)(h + 1));
 }
 
-__global__ void aca_init_kernel(AcaArgs A, int64_t nint, int cap)
+__device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t bi)
 {
-    int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (h >= nint)
+    return v > bv || (v == bv && i < bi);
+}
+
+// block argmax (ties to the smaller index) carrying the signed value; every
+// thread returns the result
+__device__ void block_argmax(double &v, int64_t &i, double &sgn, double *rv, int64_t *ri,
+                             double *rs)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_argmax_signed(v, i, sgn);
+    if (lane == 0) {
+        rv[wid] = v;
+        ri[wid] = i;
+        rs[wid] = sgn;
+    }
+    __syncthreads();
+    v = rv[0];
+    i = ri[0];
+    sgn = rs[0];
+    for (int w = 1; w < ACA_THREADS / 64; ++w)
+        if (better(rv[w], ri[w], v, i)) {
+            v = rv[w];
+            i = ri[w];
+            sgn = rs[w];
+        }
+    __syncthreads();
+}
+
+__device__ double block_sum(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0)
+        red[wid] = v;
+    __syncthreads();
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------ small blocks
+struct SmallArgs {
+    AcaArgs a;
+    const int *nodes;   // internal nodes handled here
+    int *rank;
+    int *status;        // per node AcaDone
+};
+
+__global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
+{
+    const AcaArgs &A = S.a;
+    const int64_t h = S.nodes[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
+    const int64_t na = m - s, nb = e - m, n = A.n;
+    const int64_t col0 = A.cofa[depth_of_node(h) + 1];
+    double *__restrict__ W = A.W;
+    __shared__ double rv[4], rs[4], red[4];
+    __shared__ int64_t ri[4];
+    __shared__ double sfix[RMAX_ABS];
+    __shared__ double vdot[RMAX_ABS];
+    __shared__ unsigned char used[ACA_SMALL];
+    const int64_t full = na < nb ? na : nb;
+    const int cap = (int)(A.cap < full ? A.cap : full);
+    const bool usercap = A.cap < full;
+    for (int64_t i = tid; i < na; i += ACA_THREADS)
+        used[i] = 0;
+    __syncthreads();
+    int k = 0, zeros = 0, nused = 0, done = (cap <= 0) ? ACA_EXHAUSTED : ACA_ACTIVE;
+    int64_t istar = na - 1;
+    double s2 = 0.0;
+    double uv[SM_EPT];
+    while (done == ACA_ACTIVE) {
+        // residual row at i*
+        // (written by other threads of this work-group: read past the L1)
+        for (int l = tid; l < k; l += ACA_THREADS)
+            sfix[l] = ld_coherent(&W[(col0 + l) * n + s + istar]);
+        __syncthreads();
+        double bv = -1.0, bs = 0.0, sq = 0.0;
+        int64_t bi = INT64_MAX;
+#pragma unroll
+        for (int t = 0; t < SM_EPT; ++t) {
+            int64_t j = tid + (int64_t)t * ACA_THREADS;
+            uv[t] = 0.0;
+            if (j < nb) {
+                double a = kentry(A.kp, A.x, n, s + istar, m + j);
+                for (int l = 0; l < k; ++l)
+                    a -= sfix[l] * W[(col0 + l) * n + m + j];
+                W[(col0 + k) * n + m + j] = a;
+                uv[t] = a;
+                sq += a * a;
+                if (fabs(a) > bv) {
+                    bv = fabs(a);
+                    bs = a;
+                    bi = j;
+                }
+            }
+        }
+        block_argmax(bv, bi, bs, rv, ri, rs);
+        if (tid == 0)
+            used[istar] = 1;
+        ++nused;
+        __syncthreads();
+        if (bv == 0.0) {
+            ++zeros;
+            if (zeros > ZERO_RETRY || nused >= na) {
+                done = ACA_EXHAUSTED;
+            } else {
+                int64_t c = na - 1;
+                while (c >= 0 && used[c])
+                    --c;
+                istar = c;
+            }
+            continue;
+        }
+        zeros = 0;
+        const double v2 = block_sum(sq, red);
+        for (int l = 0; l < k; ++l) {
+            double d = 0.0;
+#pragma unroll
+            for (int t = 0; t < SM_EPT; ++t) {
+                int64_t j = tid + (int64_t)t * ACA_THREADS;
+                if (j < nb)
+                    d += uv[t] * W[(col0 + l) * n + m + j];
+            }
+            d = block_sum(d, red);
+            if (tid == 0)
+                vdot[l] = d;
+        }
+        // residual column at j*
+        const int64_t jstar = bi;
+        const double delta = bs;
+        for (int l = tid; l < k; l += ACA_THREADS)
+            sfix[l] = ld_coherent(&W[(col0 + l) * n + m + jstar]);
+        __syncthreads();
+        bv = -1.0;
+        bs = 0.0;
+        bi = INT64_MAX;
+        sq = 0.0;
+#pragma unroll
+        for (int t = 0; t < SM_EPT; ++t) {
+            int64_t i = tid + (int64_t)t * ACA_THREADS;
+            uv[t] = 0.0;
+            if (i < na) {
+                double a = kentry(A.kp, A.x, n, s + i, m + jstar);
+                for (int l = 0; l < k; ++l)
+                    a -= sfix[l] * W[(col0 + l) * n + s + i];
+                a = a / delta;
+                W[(col0 + k) * n + s + i] = a;
+                uv[t] = a;
+                sq += a * a;
+                if (!used[i] && fabs(a) > bv) {
+                    bv = fabs(a);
+                    bs = a;
+                    bi = i;
+                }
+            }
+        }
+        block_argmax(bv, bi, bs, rv, ri, rs);
+        const double u2 = block_sum(sq, red);
+        double cross = 0.0;
+        for (int l = 0; l < k; ++l) {
+            double d = 0.0;
+#pragma unroll
+            for (int t = 0; t < SM_EPT; ++t) {
+                int64_t i = tid + (int64_t)t * ACA_THREADS;
+                if (i < na)
+                    d += uv[t] * W[(col0 + l) * n + s + i];
+            }
+            d = block_sum(d, red);
+            cross += d * vdot[l];
+        }
+        s2 += u2 * v2 + 2.0 * cross;
+        k += 1;
+        if (sqrt(u2) * sqrt(v2) <= A.tol * sqrt(s2 > 0.0 ? s2 : 0.0))
+            done = ACA_CONVERGED;
+        else if (k >= cap)
+            done = usercap ? ACA_CAPPED : ACA_CONVERGED;
+        else if (nused >= na || bv < 0.0)
+            done = ACA_EXHAUSTED;
+        else
+            istar = bi;
+    }
+    if (tid == 0) {
+        S.rank[h] = k;
+        S.status[h] = done;
+    }
+}
+
+// ------------------------------------------------------------ large blocks
+struct BigArgs {
+    AcaArgs a;
+    const Chunk *chunks;      // this pass's chunks (rows of beta or of alpha)
+    const int *bnode;         // per big-block index: heap index
+    const int *pnch, *pbase;  // previous pass's records: count and first slot per big block
+    const int *cidx;          // per chunk: big-block index
+    const BigState *sin;
+    BigState *sout;
+    const double *pin;        // previous pass's records
+    double *pout;             // this pass's records
+    int pw;
+    int *used;                // per big block, USED_MAX rows
+    double *vdots;            // per big block, RMAX_ABS
+    int *ndone;
+};
+
+__global__ void aca_big_init_kernel(BigState *st, const int *bnode, int nbig, AcaArgs A)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbig)
         return;
+    int64_t h = bnode[b];
     int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
-    int64_t na = m - s, nb = e - m;
-    int64_t full = na < nb ? na : nb;
-    int c = (int)(cap < full ? cap : full);
-    AcaState t;
+    int64_t na = m - s, nb = e - m, full = na < nb ? na : nb;
+    BigState t;
     t.k = 0;
     t.istar = (int)(na - 1);
     t.jstar = 0;
-    t.done = (c <= 0) ? ACA_EXHAUSTED : ACA_ACTIVE;
-    t.phase = PH_ROW;
     t.zeros = 0;
     t.nused = 0;
-    t.cap = c;
-    t.usercap = (cap < full) ? 1 : 0;
+    t.cap = (int)(A.cap < full ? A.cap : full);
+    t.usercap = A.cap < full;
+    t.done = t.cap <= 0 ? ACA_EXHAUSTED : ACA_ACTIVE;
+    t.phase = BP_FRESH;
     t.pad_ = 0;
-    t.delta = 0.0;
-    t.v2 = 0.0;
-    t.s2 = 0.0;
-    A.st[h] = t;
-    A.cnt[h] = 0;
-    if (t.done == ACA_ACTIVE)
-        atomicAdd(A.active, 1);
+    t.delta = t.v2 = t.s2 = 0.0;
+    st[b] = t;
 }
 
-// block-wide reductions over 256 threads (4 waves)
-struct BlockRed {
-    double v[4];
-    int64_t i[4];
-};
+// Reduce the previous pass's records of one big block: slot 0 = max |value|
+// (over eligible indices), 1 = its index, 2 = squared norm, 3 = signed value,
+// 4 + l = dot with term l.  Every thread ends with the same results.
+__device__ void reduce_records(const double *rec, int nrec, int pw, int k, double *dots,
+                               double &bv, int64_t &bi, double &bs, double *rv, int64_t *ri,
+                               double *rs, double *red)
+{
+    const int tid = threadIdx.x;
+    for (int l = 0; l <= k; ++l) {
+        int slot = (l < k) ? 4 + l : 2;
+        double acc = 0.0;
+        for (int c = tid; c < nrec; c += ACA_THREADS)
+            acc += rec[(int64_t)c * pw + slot];
+        acc = block_sum(acc, red);
+        if (tid == 0)
+            dots[l] = acc;
+    }
+    bv = -1.0;
+    bs = 0.0;
+    bi = INT64_MAX;
+    for (int c = tid; c < nrec; c += ACA_THREADS) {
+        double v = rec[(int64_t)c * pw + 0];
+        double di = rec[(int64_t)c * pw + 1];
+        int64_t i = di < 0.0 ? INT64_MAX : (int64_t)di;
+        if (better(v, i, bv, bi)) {
+            bv = v;
+            bi = i;
+            bs = rec[(int64_t)c * pw + 3];
+        }
+    }
+    block_argmax(bv, bi, bs, rv, ri, rs);   // ends with a barrier: dots[] visible
+}
 
 template <bool ROW>
-__global__ __launch_bounds__(ACA_THREADS) void aca_pass_kernel(AcaArgs A)
+__global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 {
-    const Chunk ch = A.chunks[blockIdx.x];
-    const int h = ch.node;
+    const AcaArgs &A = B.a;
+    const Chunk ch = B.chunks[blockIdx.x];
+    const int b = B.cidx[blockIdx.x];
+    const int64_t h = B.bnode[b];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    __shared__ AcaState sst;
-    __shared__ double sfix[RMAX_ABS];        // u_l(i*) (row pass) or v_l(j*) (column pass)
-    __shared__ int sused[USED_MAX];
+    __shared__ double rv[4], rs[4], red[4];
+    __shared__ int64_t ri[4];
+    __shared__ double sfix[RMAX_ABS];
+    __shared__ double dots[RMAX_ABS + 1];
     __shared__ double sdot[4][RMAX_ABS + 1];
-    __shared__ BlockRed sred;
-    __shared__ double ssgn[4];
-    __shared__ int s_last;
-    if (tid == 0)
-        sst = A.st[h];
-    __syncthreads();
-    if (sst.done != ACA_ACTIVE || sst.phase != (ROW ? PH_ROW : PH_COL))
-        return;
-    const int k = sst.k;
+    __shared__ int sused[USED_MAX];
+    BigState t = B.sin[b];
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
-    const int64_t n = A.n;
+    const int64_t na = m - s, n = A.n;
+    const bool lead = ch.lo == (ROW ? m : s);   // the block's first chunk writes its state
     const int64_t col0 = A.cofa[depth_of_node(h) + 1];
     double *__restrict__ W = A.W;
-    // the fixed index this pass crosses: pivot row (row pass) or pivot column
-    const int64_t fix = ROW ? (s + sst.istar) : (m + sst.jstar);
+    int *used = B.used + (int64_t)b * USED_MAX;
+    const double *prec = B.pin + (int64_t)B.pbase[b] * B.pw;
+    const int pn = B.pnch[b];
+    if (t.done != ACA_ACTIVE) {
+        if (lead && tid == 0)
+            B.sout[b] = t;
+        return;
+    }
+    if (ROW) {
+        if (t.phase == BP_COLDONE) {
+            // finish the previous step from the column records
+            double bv, bs;
+            int64_t bi;
+            reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red);
+            double u2 = dots[t.k];
+            double cross = 0.0;
+            for (int l = 0; l < t.k; ++l)
+                cross += dots[l] * B.vdots[(int64_t)b * RMAX_ABS + l];
+            t.s2 += u2 * t.v2 + 2.0 * cross;
+            t.k += 1;
+            double s2 = t.s2 > 0.0 ? t.s2 : 0.0;
+            if (sqrt(u2) * sqrt(t.v2) <= A.tol * sqrt(s2))
+                t.done = ACA_CONVERGED;
+            else if (t.k >= t.cap)
+                t.done = t.usercap ? ACA_CAPPED : ACA_CONVERGED;
+            else if (t.nused >= na || t.nused >= USED_MAX || bv < 0.0)
+                t.done = ACA_EXHAUSTED;
+            else
+                t.istar = (int)(bi - s);
+            if (t.done != ACA_ACTIVE) {
+                if (lead && tid == 0) {
+                    B.sout[b] = t;
+                    atomicAdd(B.ndone, 1);
+                }
+                return;
+            }
+        }
+        // evaluate the residual row i*; the row becomes used
+        const int k = t.k;
+        const int64_t fix = s + t.istar;
+        for (int l = tid; l < k; l += ACA_THREADS)
+            sfix[l] = W[(col0 + l) * n + fix];
+        __syncthreads();
+        double val[ACA_EPT];
+        double bv = -1.0, bs = 0.0, sq = 0.0;
+        int64_t bi = INT64_MAX;
+#pragma unroll
+        for (int q = 0; q < ACA_EPT; ++q) {
+            int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+            val[q] = 0.0;
+            if (g < ch.hi) {
+                double a = kentry(A.kp, A.x, n, fix, g);
+                for (int l = 0; l < k; ++l)
+                    a -= sfix[l] * W[(col0 + l) * n + g];
+                W[(col0 + k) * n + g] = a;
+                val[q] = a;
+                sq += a * a;
+                if (fabs(a) > bv) {
+                    bv = fabs(a);
+                    bs = a;
+                    bi = g;
+                }
+            }
+        }
+        for (int l = 0; l < k; ++l) {
+            double d = 0.0;
+#pragma unroll
+            for (int q = 0; q < ACA_EPT; ++q) {
+                int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+                if (g < ch.hi)
+                    d += val[q] * W[(col0 + l) * n + g];
+            }
+            d = wave_sum(d);
+            if (lane == 0)
+                sdot[wid][l] = d;
+        }
+        sq = wave_sum(sq);
+        if (lane == 0)
+            sdot[wid][k] = sq;
+        block_argmax(bv, bi, bs, rv, ri, rs);
+        double *rec = B.pout + (int64_t)ch.part * B.pw;
+        if (tid == 0) {
+            rec[0] = bv;
+            rec[1] = (bi == INT64_MAX) ? -1.0 : (double)bi;
+            rec[2] = (sdot[0][k] + sdot[1][k]) + (sdot[2][k] + sdot[3][k]);
+            rec[3] = bs;
+        }
+        for (int l = tid; l < k; l += ACA_THREADS)
+            rec[4 + l] = (sdot[0][l] + sdot[1][l]) + (sdot[2][l] + sdot[3][l]);
+        if (lead && tid == 0) {
+            if (t.nused < USED_MAX)
+                used[t.nused] = t.istar;
+            t.nused += 1;
+            t.phase = BP_ROWDONE;
+            B.sout[b] = t;
+        }
+        return;
+    }
+    // ---- column pass: pick the pivot column from the row records
+    double bv, bs;
+    int64_t bi;
+    reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red);
+    const int nu = t.nused < USED_MAX ? t.nused : USED_MAX;
+    for (int q = tid; q < nu; q += ACA_THREADS)
+        sused[q] = used[q];
+    __syncthreads();
+    if (bv == 0.0) {
+        if (lead && tid == 0) {
+            t.zeros += 1;
+            if (t.zeros > ZERO_RETRY || t.nused >= na || t.nused >= USED_MAX) {
+                t.done = ACA_EXHAUSTED;
+                atomicAdd(B.ndone, 1);
+            } else {
+                int c = (int)na - 1;
+                for (; c >= 0; --c) {
+                    bool u = false;
+                    for (int q = 0; q < nu; ++q)
+                        u = u || (sused[q] == c);
+                    if (!u)
+                        break;
+                }
+                t.istar = c;
+                t.phase = BP_RETRY;
+            }
+            B.sout[b] = t;
+        }
+        return;
+    }
+    const int k = t.k;
+    t.zeros = 0;
+    t.jstar = (int)(bi - m);
+    t.delta = bs;
+    t.v2 = dots[k];
+    const int64_t fix = bi;
     for (int l = tid; l < k; l += ACA_THREADS)
         sfix[l] = W[(col0 + l) * n + fix];
-    if (!ROW)
-        for (int t = tid; t < sst.nused; t += ACA_THREADS)
-            sused[t] = A.used[(int64_t)h * USED_MAX + t];
     __syncthreads();
-    const double delta = sst.delta;
     double val[ACA_EPT];
-    double bestv = -1.0, bests = 0.0;
-    int64_t besti = INT64_MAX;
-    double sq = 0.0;
+    double cv = -1.0, cs = 0.0, sq = 0.0;
+    int64_t ci = INT64_MAX;
 #pragma unroll
-    for (int t = 0; t < ACA_EPT; ++t) {
-        int64_t g = ch.lo + tid + (int64_t)t * ACA_THREADS;
-        val[t] = 0.0;
+    for (int q = 0; q < ACA_EPT; ++q) {
+        int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+        val[q] = 0.0;
         if (g < ch.hi) {
-            double a = kentry(A.kp, A.x, n, ROW ? fix : g, ROW ? g : fix);
+            double a = kentry(A.kp, A.x, n, g, fix);
             for (int l = 0; l < k; ++l)
                 a -= sfix[l] * W[(col0 + l) * n + g];
-            if (!ROW)
-                a = a / delta;
+            a = a / t.delta;
             W[(col0 + k) * n + g] = a;
-            val[t] = a;
+            val[q] = a;
             sq += a * a;
-            bool eligible = true;
-            if (!ROW) {
-                int li = (int)(g - s);
-                for (int q = 0; q < sst.nused; ++q)
-                    eligible = eligible && (sused[q] != li);
-            }
-            double av = fabs(a);
-            if (eligible && av > bestv) {
-                bestv = av;
-                bests = a;
-                besti = g;
+            int li = (int)(g - s);
+            bool elig = true;
+            for (int p = 0; p < nu; ++p)
+                elig = elig && (sused[p] != li);
+            if (elig && fabs(a) > cv) {
+                cv = fabs(a);
+                cs = a;
+                ci = g;
             }
         }
     }
-    // dots with the earlier terms of the same side
     for (int l = 0; l < k; ++l) {
-        double dsum = 0.0;
+        double d = 0.0;
 #pragma unroll
-        for (int t = 0; t < ACA_EPT; ++t) {
-            int64_t g = ch.lo + tid + (int64_t)t * ACA_THREADS;
+        for (int q = 0; q < ACA_EPT; ++q) {
+            int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
             if (g < ch.hi)
-                dsum += val[t] * W[(col0 + l) * n + g];
+                d += val[q] * W[(col0 + l) * n + g];
         }
-        dsum = wave_sum(dsum);
+        d = wave_sum(d);
         if (lane == 0)
-            sdot[wid][l] = dsum;
+            sdot[wid][l] = d;
     }
     sq = wave_sum(sq);
     if (lane == 0)
         sdot[wid][k] = sq;
-    wave_argmax_signed(bestv, besti, bests);
-    if (lane == 0) {
-        sred.v[wid] = bestv;
-        sred.i[wid] = besti;
-        ssgn[wid] = bests;
-    }
-    __syncthreads();
-    double *rec = A.part + (int64_t)ch.part * A.pw;
+    block_argmax(cv, ci, cs, rv, ri, rs);
+    double *rec = B.pout + (int64_t)ch.part * B.pw;
     if (tid == 0) {
-        double bv = sred.v[0], bs = ssgn[0];
-        int64_t bi = sred.i[0];
-        for (int w = 1; w < 4; ++w)
-            if (sred.v[w] > bv || (sred.v[w] == bv && sred.i[w] < bi)) {
-                bv = sred.v[w];
-                bi = sred.i[w];
-                bs = ssgn[w];
-            }
-        rec[0] = bv;
-        rec[1] = (bi == INT64_MAX) ? -1.0 : (double)bi;
-        rec[2] = sdot[0][k] + sdot[1][k] + sdot[2][k] + sdot[3][k];
-        rec[3] = bs;
+        rec[0] = cv;
+        rec[1] = (ci == INT64_MAX) ? -1.0 : (double)ci;
+        rec[2] = (sdot[0][k] + sdot[1][k]) + (sdot[2][k] + sdot[3][k]);
+        rec[3] = cs;
     }
     for (int l = tid; l < k; l += ACA_THREADS)
-        rec[4 + l] = sdot[0][l] + sdot[1][l] + sdot[2][l] + sdot[3][l];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        int prev = atomicAdd(&A.cnt[h], 1);
-        s_last = (prev == A.nch[h] - 1);
-    }
-    __syncthreads();
-    if (!s_last)
-        return;
-    __threadfence();
-    // ---- the last work-group of this block combines the partial records
-    const int nch = A.nch[h];
-    const double *prt = A.part + (int64_t)A.base[h] * A.pw;
-    // dots (l < k) and the squared norm (slot k), one accumulator per thread
-    for (int l = tid; l <= k; l += ACA_THREADS) {
-        double acc = 0.0;
-        int slot = (l < k) ? 4 + l : 2;
-        for (int c = 0; c < nch; ++c)
-            acc += ld_coherent(prt + (int64_t)c * A.pw + slot);
-        sdot[0][l] = acc;
-    }
-    double bv = -1.0, sv = 0.0;
-    int64_t bi = INT64_MAX;
-    for (int c = tid; c < nch; c += ACA_THREADS) {
-        double v = ld_coherent(prt + (int64_t)c * A.pw + 0);
-        double di = ld_coherent(prt + (int64_t)c * A.pw + 1);
-        int64_t i = di < 0.0 ? INT64_MAX : (int64_t)di;
-        if (v > bv || (v == bv && i < bi)) {
-            bv = v;
-            bi = i;
-            sv = ld_coherent(prt + (int64_t)c * A.pw + 3);
-        }
-    }
-    wave_argmax_signed(bv, bi, sv);
-    __syncthreads();   // stage-1 readers of sred/ssgn are done
-    if (lane == 0) {
-        sred.v[wid] = bv;
-        sred.i[wid] = bi;
-        ssgn[wid] = sv;
-    }
-    __syncthreads();
-    if (tid != 0)
-        return;
-    bv = sred.v[0];
-    bi = sred.i[0];
-    sv = ssgn[0];
-    for (int w = 1; w < 4; ++w)
-        if (sred.v[w] > bv || (sred.v[w] == bv && sred.i[w] < bi)) {
-            bv = sred.v[w];
-            bi = sred.i[w];
-            sv = ssgn[w];
-        }
-    AcaState t = sst;
-    const int64_t na = m - s;
-    int *used = A.used + (int64_t)h * USED_MAX;
-    if (ROW) {
-        if (t.nused < USED_MAX)
-            used[t.nused] = t.istar;
-        t.nused += 1;
-        if (bv == 0.0) {
-            t.zeros += 1;
-            if (t.zeros > ZERO_RETRY || t.nused >= na || t.nused >= USED_MAX) {
-                t.done = ACA_EXHAUSTED;
-            } else {
-                // unused row nearest the split
-                int cand = (int)na - 1;
-                for (; cand >= 0; --cand) {
-                    bool u = false;
-                    for (int q = 0; q < t.nused; ++q)
-                        u = u || (used[q] == cand);
-                    if (!u)
-                        break;
-                }
-                t.istar = cand;
-            }
-        } else {
-            t.zeros = 0;
-            t.jstar = (int)(bi - m);
-            t.delta = sv;
-            t.v2 = sdot[0][k];
-            for (int l = 0; l < k; ++l)
-                A.vdots[(int64_t)h * A.vstride + l] = sdot[0][l];
-            t.phase = PH_COL;
-        }
-    } else {
-        double u2 = sdot[0][k];
-        double cross = 0.0;
+        rec[4 + l] = (sdot[0][l] + sdot[1][l]) + (sdot[2][l] + sdot[3][l]);
+    if (lead && tid == 0) {
         for (int l = 0; l < k; ++l)
-            cross += sdot[0][l] * A.vdots[(int64_t)h * A.vstride + l];
-        t.s2 += u2 * t.v2 + 2.0 * cross;
-        t.k = k + 1;
-        double s2 = t.s2 > 0.0 ? t.s2 : 0.0;
-        if (sqrt(u2) * sqrt(t.v2) <= A.tol * sqrt(s2)) {
-            t.done = ACA_CONVERGED;
-        } else if (t.k >= t.cap) {
-            t.done = t.usercap ? ACA_CAPPED : ACA_CONVERGED;
-        } else if (t.nused >= na || t.nused >= USED_MAX || bv < 0.0) {
-            t.done = ACA_EXHAUSTED;
-        } else {
-            t.istar = (int)(bi - s);
-            t.phase = PH_ROW;
-        }
+            B.vdots[(int64_t)b * RMAX_ABS + l] = dots[l];
+        t.phase = BP_COLDONE;
+        B.sout[b] = t;
     }
-    if (t.done != ACA_ACTIVE)
-        atomicSub(A.active, 1);
-    A.st[h] = t;
-    A.cnt[h] = 0;
+}
+
+__global__ void aca_big_finish_kernel(const BigState *st, const int *bnode, int nbig, int *rank,
+                                      int *status)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbig)
+        return;
+    rank[bnode[b]] = st[b].k;
+    status[bnode[b]] = st[b].done;
 }
 
 // ranks, per-depth maxima and the capped count
-__global__ void aca_stats_kernel(const AcaState *st, int64_t nint, int *rank, int *rmax,
+__global__ void aca_stats_kernel(const int *rank, const int *status, int64_t nint, int *rmax,
                                  int *capped)
 {
     int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (h >= nint)
         return;
-    AcaState t = st[h];
-    rank[h] = t.k;
-    atomicMax(&rmax[depth_of_node(h) + 1], t.k);
-    if (t.done == ACA_CAPPED)
+    atomicMax(&rmax[depth_of_node(h) + 1], rank[h]);
+    if (status[h] == ACA_CAPPED)
         atomicAdd(capped, 1);
 }
 
@@ -337,8 +578,9 @@ void run_aca(Pipeline &P)
         ~Guard() { (void)hipHostFree(p); }
     } g{pinned};
     int64_t *d_cofa = wsp<int64_t>(P, P.lay.misc);          // [0, 512): column offsets
-    int *d_rmax = wsp<int>(P, P.lay.misc + 512);             // [512, 768): rmax per depth
-    int *d_capped = wsp<int>(P, P.lay.misc + 768);
+    int *d_rmax = wsp<int>(P, P.lay.misc + 512);             // [512, 784): rmax per depth
+    int *d_capped = wsp<int>(P, P.lay.misc + 784);
+    int *d_ndone = wsp<int>(P, P.lay.misc + 1024);
     HIP_TRY(hipMemcpyAsync(d_cofa, p.cofa.data(), sizeof(int64_t) * p.cofa.size(),
                            hipMemcpyHostToDevice, s));
     AcaArgs A;
@@ -350,44 +592,94 @@ void run_aca(Pipeline &P)
     A.start = p.d_start;
     A.end = p.d_end;
     A.cofa = d_cofa;
-    A.st = wsp<AcaState>(P, P.lay.aca_state);
-    A.used = wsp<int>(P, P.lay.aca_used);
-    A.vdots = wsp<double>(P, P.lay.aca_vdots);
-    A.vstride = std::max(p.cap, 1);
-    A.part = wsp<double>(P, P.lay.aca_part);
-    A.pw = p.aca_pw;
-    A.cnt = wsp<int>(P, P.lay.aca_cnt);
-    A.active = wsp<int>(P, P.lay.aca_active);
-    HIP_TRY(hipMemsetAsync(A.active, 0, 4 * sizeof(int), s));
-    int nb = (int)((p.nint + 255) / 256);
-    aca_init_kernel<<<nb, 256, 0, s>>>(A, p.nint, p.cap);
-    HIP_TRY(hipGetLastError());
-    AcaArgs R = A, C = A;
-    R.chunks = p.d_aca_row;
-    R.nch = p.d_aca_nrow;
-    R.base = p.d_aca_rowbase;
-    C.chunks = p.d_aca_col;
-    C.nch = p.d_aca_ncol;
-    C.base = p.d_aca_colbase;
-    const int nrow = (int)p.aca_row.size(), ncol = (int)p.aca_col.size();
-    const int max_iter = (p.cap + 1) * (ZERO_RETRY + 2) + 4;
-    int it = 0;
-    for (; it < max_iter; ++it) {
-        if (nrow)
-            aca_pass_kernel<true><<<nrow, ACA_THREADS, 0, s>>>(R);
-        if (ncol)
-            aca_pass_kernel<false><<<ncol, ACA_THREADS, 0, s>>>(C);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(pinned, A.active, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (pinned[0] <= 0)
-            break;
-    }
-    if (it >= max_iter)
-        throw Error{HODLR_EDEVICE, "cross approximation did not terminate"};
+    A.cap = p.cap;
     int *rank = wsp<int>(P, P.lay.rank);
-    HIP_TRY(hipMemsetAsync(d_rmax, 0, 68 * sizeof(int), s));
-    aca_stats_kernel<<<nb, 256, 0, s>>>(A.st, p.nint, rank, d_rmax, d_capped);
+    int *status = wsp<int>(P, P.lay.aca_status);
+    HIP_TRY(hipMemsetAsync(d_ndone, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(d_capped, 0, sizeof(int), s));
+    // blocks with an empty side keep rank 0 and count as done
+    HIP_TRY(hipMemsetAsync(rank, 0, sizeof(int) * p.nint, s));
+    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int) * p.nint, s));
+    // small blocks: the whole loop per work-group, one launch
+    if (!p.aca_small.empty()) {
+        SmallArgs S;
+        S.a = A;
+        S.nodes = p.d_aca_small;
+        S.rank = rank;
+        S.status = status;
+        ProfScope ps(s, PS_ACA_SMALL);
+        aca_small_kernel<<<(unsigned)p.aca_small.size(), ACA_THREADS, 0, s>>>(S);
+        HIP_TRY(hipGetLastError());
+    }
+    const int nbig = (int)p.aca_big.size();
+    if (nbig > 0) {
+        BigState *st0 = wsp<BigState>(P, P.lay.aca_state);
+        BigState *st1 = st0 + nbig;
+        double *rrec = wsp<double>(P, P.lay.aca_part);
+        double *crec = rrec + (int64_t)p.aca_row.size() * p.aca_pw;
+        {
+            ProfScope ps(s, PS_ACA_MISC);
+            aca_big_init_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big, nbig, A);
+        }
+        BigArgs R, C;
+        R.a = C.a = A;
+        R.bnode = C.bnode = p.d_aca_big;
+        R.pw = C.pw = p.aca_pw;
+        R.used = C.used = wsp<int>(P, P.lay.aca_used);
+        R.vdots = C.vdots = wsp<double>(P, P.lay.aca_vdots);
+        R.ndone = C.ndone = d_ndone;
+        R.chunks = p.d_aca_row;   // rows of beta
+        R.cidx = p.d_aca_rowidx;
+        R.pnch = p.d_aca_ncol;    // previous pass = column records
+        R.pbase = p.d_aca_colbase;
+        R.sin = st0;
+        R.sout = st1;
+        R.pin = crec;
+        R.pout = rrec;
+        C.chunks = p.d_aca_col;   // rows of alpha
+        C.cidx = p.d_aca_colidx;
+        C.pnch = p.d_aca_nrow;
+        C.pbase = p.d_aca_rowbase;
+        C.sin = st1;
+        C.sout = st0;
+        C.pin = rrec;
+        C.pout = crec;
+        const int nrow = (int)p.aca_row.size(), ncol = (int)p.aca_col.size();
+        const int max_iter = (p.cap + 1) * (ZERO_RETRY + 2) + 4;
+        int it = 0;
+        for (; it < max_iter; ++it) {
+            {
+                ProfScope ps(s, PS_ACA_ROW);
+                aca_big_pass_kernel<true><<<nrow, ACA_THREADS, 0, s>>>(R);
+            }
+            {
+                ProfScope ps(s, PS_ACA_COL);
+                aca_big_pass_kernel<false><<<ncol, ACA_THREADS, 0, s>>>(C);
+            }
+            HIP_TRY(hipGetLastError());
+            // a converged block is counted by the row pass that absorbs its last
+            // column; poll every other step from the third on
+            if (it >= 2 && (it & 1) == 0) {
+                HIP_TRY(hipMemcpyAsync(pinned, d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (pinned[0] >= p.aca_big_active)
+                    break;
+            }
+        }
+        if (it >= max_iter)
+            throw Error{HODLR_EDEVICE, "cross approximation did not terminate"};
+        {
+            ProfScope ps(s, PS_ACA_MISC);
+            aca_big_finish_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big, nbig,
+                                                                     rank, status);
+        }
+    }
+    HIP_TRY(hipMemsetAsync(d_rmax, 0, 64 * sizeof(int), s));
+    int nb = (int)((p.nint + 255) / 256);
+    {
+        ProfScope ps(s, PS_ACA_MISC);
+        aca_stats_kernel<<<nb, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * (p.L + 2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(pinned + 48, d_capped, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -397,10 +689,10 @@ void run_aca(Pipeline &P)
         P.rmax[j] = pinned[j];
     P.capped = pinned[48];
     // zero the padding columns of every block below its panel's maximum rank
-    if (nrow)
-        aca_pad_kernel<<<nrow, 256, 0, s>>>(A.W, p.n, p.d_aca_row, rank, d_rmax, d_cofa);
-    if (ncol)
-        aca_pad_kernel<<<ncol, 256, 0, s>>>(A.W, p.n, p.d_aca_col, rank, d_rmax, d_cofa);
+    ProfScope ps(s, PS_ACA_MISC);
+    if (!p.pad_chunks.empty())
+        aca_pad_kernel<<<(unsigned)p.pad_chunks.size(), 256, 0, s>>>(A.W, p.n, p.d_pad_chunks,
+                                                                      rank, d_rmax, d_cofa);
     HIP_TRY(hipGetLastError());
 }
 

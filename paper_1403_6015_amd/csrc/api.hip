@@ -150,6 +150,7 @@ int read_status(Pipeline &P)
     HIP_TRY(hipMemcpyAsync(&st, wsp<int>(P, P.lay.status), sizeof(int), hipMemcpyDeviceToHost,
                            P.stream));
     HIP_TRY(hipStreamSynchronize(P.stream));
+    prof_collect();
     return st;
 }
 
@@ -320,6 +321,7 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
             run_leaf_solve(P, z);
             run_levels_apply(P);
             HIP_TRY(hipMemcpy(buf.data(), z, sizeof(double) * n, hipMemcpyDeviceToHost));
+            prof_collect();
             for (int64_t k = 0; k < n; ++k)
                 res[f->perm[k]] = buf[k];
             std::memcpy(x + c * n, res.data(), sizeof(double) * n);

@@ -14,7 +14,8 @@ namespace hodlr {
 
 // ------------------------------------------------------------- constants
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
-constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass
+constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (large blocks)
+constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
 constexpr int LVL_ROWS = 512;     // minimum rows per level work-group
@@ -25,19 +26,19 @@ constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices 
 constexpr int USED_MAX = (RMAX_ABS + 1) * (ZERO_RETRY + 1) + 2;
 
 enum AcaDone { ACA_ACTIVE = 0, ACA_CONVERGED = 1, ACA_CAPPED = 2, ACA_EXHAUSTED = 3 };
-enum AcaPhase { PH_ROW = 0, PH_COL = 1 };
 
-// Per-block cross-approximation state (device resident).
-struct AcaState {
+// Cross-approximation state of one large block (device resident, moved
+// between launches only).
+struct BigState {
     int k;          // terms accepted so far
     int istar;      // current pivot row (local index in alpha)
     int jstar;      // pivot column of the current term (local index in beta)
-    int done;       // AcaDone
-    int phase;      // AcaPhase: which pass acts next
     int zeros;      // consecutive zero-pivot rows
     int nused;      // rows used as pivots so far
     int cap;        // min(max_rank, |alpha|, |beta|)
     int usercap;    // 1 if cap came from max_rank (a hit counts as "capped")
+    int done;       // AcaDone
+    int phase;      // which pass results are pending
     int pad_;
     double delta;   // pivot value of the current term
     double v2;      // ||v_k||^2 of the current term
@@ -197,10 +198,15 @@ struct Plan {
     std::vector<int> capj;             // per depth j = 1..L: columns reserved
     std::vector<int64_t> cofa;         // per depth j: first column of the panel; [L+1] = total
     int64_t ncol = 1;                  // columns of W / Xt (column 0 is the solve vector)
-    // ACA tables (all internal nodes)
-    std::vector<Chunk> aca_row, aca_col;
-    std::vector<int> aca_nrow, aca_ncol;   // per internal node: chunk counts
+    // cross-approximation tables
+    std::vector<int> aca_small;            // heap indices of blocks done by one work-group
+    std::vector<int> aca_big;              // heap indices of multi-work-group blocks
+    int aca_big_active = 0;                // big blocks with a positive rank cap
+    std::vector<Chunk> aca_row, aca_col;   // big blocks: chunks over beta / alpha
+    std::vector<int> aca_rowidx, aca_colidx;   // per chunk: big-block index
+    std::vector<int> aca_nrow, aca_ncol;   // per big block: chunk counts
     std::vector<int> aca_rowbase, aca_colbase;
+    std::vector<Chunk> pad_chunks;         // all blocks, both sides
     int aca_pw = 0;                        // doubles per ACA partial record
     // level tables: per depth d, chunks over rows of the children of depth-d nodes
     std::vector<std::vector<Chunk>> lvl;
@@ -210,9 +216,10 @@ struct Plan {
     void *dev_tables = nullptr;
     size_t dev_tables_bytes = 0;
     int64_t *d_start = nullptr, *d_end = nullptr;
-    Chunk *d_aca_row = nullptr, *d_aca_col = nullptr;
+    Chunk *d_aca_row = nullptr, *d_aca_col = nullptr, *d_pad_chunks = nullptr;
     int *d_aca_nrow = nullptr, *d_aca_ncol = nullptr, *d_aca_rowbase = nullptr,
-        *d_aca_colbase = nullptr;
+        *d_aca_colbase = nullptr, *d_aca_small = nullptr, *d_aca_big = nullptr,
+        *d_aca_rowidx = nullptr, *d_aca_colidx = nullptr;
     std::vector<Chunk *> d_lvl;
     std::vector<int *> d_lvl_nch, d_lvl_base;
     int device = 0;
@@ -230,7 +237,7 @@ struct Plan {
 // Workspace layout (byte offsets into one device buffer).
 struct Layout {
     size_t W, Xt, G;
-    size_t aca_state, aca_used, aca_vdots, aca_part, aca_cnt, aca_active;
+    size_t aca_state, aca_used, aca_vdots, aca_part, aca_status;
     size_t rank, leaf_ld, node_ld;
     size_t lvl_part, Tbuf, Sbuf, small;
     size_t dot_part, out, status, cols, misc;
@@ -267,6 +274,32 @@ struct Pipeline {
     std::vector<int> cnt;     // cnt[d] = 1 + sum_{j<=d} rmax[j]
     int capped = 0;
     std::vector<int> ranks;   // per internal node
+};
+
+// ------------------------------------------------------------ profiling
+// Optional HIP-event timing of every launch, per kernel kind (tracing aid).
+enum ProfStage {
+    PS_ACA_ROW = 0, PS_ACA_COL, PS_ACA_SMALL, PS_ACA_MISC, PS_LEAF, PS_LEAF_SOLVE, PS_LVL_REDUCE, PS_LVL_SOLVE,
+    PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_COUNT
+};
+bool prof_on();
+int prof_begin(hipStream_t s);
+void prof_end(int slot, hipStream_t s, int stage);
+void prof_collect();   // after the stream has been synchronized
+struct ProfScope {
+    int slot;
+    hipStream_t s;
+    int stage;
+    ProfScope(hipStream_t s_, int st) : slot(-1), s(s_), stage(st)
+    {
+        if (prof_on())
+            slot = prof_begin(s);
+    }
+    ~ProfScope()
+    {
+        if (slot >= 0)
+            prof_end(slot, s, stage);
+    }
 };
 
 // Stages (implemented in the .hip files)

@@ -237,6 +237,7 @@ void run_leaf_factor(Pipeline &P, const double *y)
     A.y = y;
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
+    ProfScope ps(P.stream, PS_LEAF);
     leaf_factor_kernel<<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A);
     HIP_TRY(hipGetLastError());
 }
@@ -245,6 +246,7 @@ void run_leaf_solve(Pipeline &P, double *z)
 {
     const Plan &p = *P.plan;
     LeafArgs A = leaf_args(P);
+    ProfScope ps(P.stream, PS_LEAF_SOLVE);
     leaf_solve_kernel<<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, z);
     HIP_TRY(hipGetLastError());
 }

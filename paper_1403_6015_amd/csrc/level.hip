@@ -367,11 +367,18 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
     const Plan &p = *P.plan;
     const unsigned nchunks = (unsigned)p.lvl[d].size();
     const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
-    if (nchunks)
+    if (nchunks) {
+        ProfScope ps(P.stream, PS_LVL_REDUCE);
         level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
-    level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
-    if (nchunks && A.nrhs > 0)
+    }
+    {
+        ProfScope ps(P.stream, PS_LVL_SOLVE);
+        level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
+    }
+    if (nchunks && A.nrhs > 0) {
+        ProfScope ps(P.stream, PS_LVL_UPDATE);
         level_update_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+    }
     HIP_TRY(hipGetLastError());
 }
 
@@ -387,6 +394,7 @@ void run_levels_factor(Pipeline &P)
         if (A.rstride == 0) {
             // every block of this level has rank 0: coupling determinants are 1
             const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
+            ProfScope ps(P.stream, PS_LVL_SOLVE);
             level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
             HIP_TRY(hipGetLastError());
             continue;

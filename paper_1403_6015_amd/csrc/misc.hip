@@ -68,6 +68,7 @@ void run_finish(Pipeline &P, const double *y, double *d_out)
     const Plan &p = *P.plan;
     double *dpart = wsp<double>(P, P.lay.dot_part);
     int ndp = 0;
+    ProfScope ps(P.stream, PS_FINISH);
     if (y) {
         dot_partial_kernel<<<FIN_BLOCKS, 256, 0, P.stream>>>(y, wsp<double>(P, P.lay.Xt), p.n,
                                                               dpart);
@@ -119,6 +120,7 @@ void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, 
                 hipStream_t s)
 {
     unsigned blocks = (unsigned)((n + MV_T - 1) / MV_T);
+    ProfScope ps(s, PS_MATVEC);
     matvec_kernel<<<blocks, MV_T, 0, s>>>(n, kp, x, v, out);
     HIP_TRY(hipGetLastError());
 }

@@ -117,24 +117,45 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
         p.cofa[j + 1] = p.cofa[j] + p.capj[j];
     p.ncol = (L >= 1) ? p.cofa[L + 1] : 1;
 
-    // cross-approximation tables: row passes sweep beta, column passes sweep alpha
+    // cross-approximation tables: blocks whose sides fit ACA_SMALL run whole in
+    // one work-group; larger ones get per-pass chunks (row passes sweep beta,
+    // column passes sweep alpha)
+    p.aca_small.clear();
+    p.aca_big.clear();
     p.aca_row.clear();
     p.aca_col.clear();
-    p.aca_nrow.assign(p.nint, 0);
-    p.aca_ncol.assign(p.nint, 0);
-    p.aca_rowbase.assign(p.nint, 0);
-    p.aca_colbase.assign(p.nint, 0);
-    int rslot = 0, cslot = 0;
+    p.aca_rowidx.clear();
+    p.aca_colidx.clear();
+    p.aca_nrow.clear();
+    p.aca_ncol.clear();
+    p.aca_rowbase.clear();
+    p.aca_colbase.clear();
+    p.pad_chunks.clear();
+    p.aca_big_active = 0;
+    int rslot = 0, cslot = 0, pslot = 0;
     for (int64_t h = 0; h < p.nint; ++h) {
         int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
         if (m - s == 0 || e - m == 0 || p.cap == 0)
             continue;
-        p.aca_rowbase[h] = rslot;
-        p.aca_colbase[h] = cslot;
+        make_chunks((int)h, 0, s, m, 4096, p.pad_chunks, pslot);
+        make_chunks((int)h, 1, m, e, 4096, p.pad_chunks, pslot);
+        if (m - s <= ACA_SMALL && e - m <= ACA_SMALL) {
+            p.aca_small.push_back((int)h);
+            continue;
+        }
+        int b = (int)p.aca_big.size();
+        p.aca_big.push_back((int)h);
+        p.aca_big_active += 1;
+        p.aca_rowbase.push_back(rslot);
+        p.aca_colbase.push_back(cslot);
         make_chunks((int)h, 1, m, e, ACA_CHUNK, p.aca_row, rslot);
         make_chunks((int)h, 0, s, m, ACA_CHUNK, p.aca_col, cslot);
-        p.aca_nrow[h] = rslot - p.aca_rowbase[h];
-        p.aca_ncol[h] = cslot - p.aca_colbase[h];
+        p.aca_nrow.push_back(rslot - p.aca_rowbase.back());
+        p.aca_ncol.push_back(cslot - p.aca_colbase.back());
+        while ((int)p.aca_rowidx.size() < rslot)
+            p.aca_rowidx.push_back(b);
+        while ((int)p.aca_colidx.size() < cslot)
+            p.aca_colidx.push_back(b);
     }
     p.aca_pw = std::max(p.cap, 1) + 4;
 
@@ -176,10 +197,16 @@ void plan_upload(Plan &p)
     size_t o_start = take(sizeof(int64_t) * nn), o_end = take(sizeof(int64_t) * nn);
     size_t o_ar = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_row.size()));
     size_t o_ac = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_col.size()));
-    size_t o_nr = take(sizeof(int) * std::max<int64_t>(1, p.nint));
-    size_t o_nc = take(sizeof(int) * std::max<int64_t>(1, p.nint));
-    size_t o_rb = take(sizeof(int) * std::max<int64_t>(1, p.nint));
-    size_t o_cb = take(sizeof(int) * std::max<int64_t>(1, p.nint));
+    size_t o_pc = take(sizeof(Chunk) * std::max<size_t>(1, p.pad_chunks.size()));
+    const size_t nbig = std::max<size_t>(1, p.aca_big.size());
+    size_t o_nr = take(sizeof(int) * nbig);
+    size_t o_nc = take(sizeof(int) * nbig);
+    size_t o_rb = take(sizeof(int) * nbig);
+    size_t o_cb = take(sizeof(int) * nbig);
+    size_t o_bg = take(sizeof(int) * nbig);
+    size_t o_sm = take(sizeof(int) * std::max<size_t>(1, p.aca_small.size()));
+    size_t o_ri = take(sizeof(int) * std::max<size_t>(1, p.aca_rowidx.size()));
+    size_t o_ci = take(sizeof(int) * std::max<size_t>(1, p.aca_colidx.size()));
     std::vector<size_t> o_l(L), o_ln(L), o_lb(L);
     for (int d = 0; d < L; ++d) {
         o_l[d] = take(sizeof(Chunk) * std::max<size_t>(1, p.lvl[d].size()));
@@ -195,10 +222,15 @@ void plan_upload(Plan &p)
     put(o_end, p.end.data(), sizeof(int64_t) * nn);
     put(o_ar, p.aca_row.data(), sizeof(Chunk) * p.aca_row.size());
     put(o_ac, p.aca_col.data(), sizeof(Chunk) * p.aca_col.size());
-    put(o_nr, p.aca_nrow.data(), sizeof(int) * p.nint);
-    put(o_nc, p.aca_ncol.data(), sizeof(int) * p.nint);
-    put(o_rb, p.aca_rowbase.data(), sizeof(int) * p.nint);
-    put(o_cb, p.aca_colbase.data(), sizeof(int) * p.nint);
+    put(o_pc, p.pad_chunks.data(), sizeof(Chunk) * p.pad_chunks.size());
+    put(o_nr, p.aca_nrow.data(), sizeof(int) * p.aca_nrow.size());
+    put(o_nc, p.aca_ncol.data(), sizeof(int) * p.aca_ncol.size());
+    put(o_rb, p.aca_rowbase.data(), sizeof(int) * p.aca_rowbase.size());
+    put(o_cb, p.aca_colbase.data(), sizeof(int) * p.aca_colbase.size());
+    put(o_bg, p.aca_big.data(), sizeof(int) * p.aca_big.size());
+    put(o_sm, p.aca_small.data(), sizeof(int) * p.aca_small.size());
+    put(o_ri, p.aca_rowidx.data(), sizeof(int) * p.aca_rowidx.size());
+    put(o_ci, p.aca_colidx.data(), sizeof(int) * p.aca_colidx.size());
     for (int d = 0; d < L; ++d) {
         put(o_l[d], p.lvl[d].data(), sizeof(Chunk) * p.lvl[d].size());
         put(o_ln[d], p.lvl_nch[d].data(), sizeof(int) * p.lvl_nch[d].size());
@@ -222,6 +254,11 @@ void plan_upload(Plan &p)
     p.d_aca_ncol = (int *)(b + o_nc);
     p.d_aca_rowbase = (int *)(b + o_rb);
     p.d_aca_colbase = (int *)(b + o_cb);
+    p.d_pad_chunks = (Chunk *)(b + o_pc);
+    p.d_aca_big = (int *)(b + o_bg);
+    p.d_aca_small = (int *)(b + o_sm);
+    p.d_aca_rowidx = (int *)(b + o_ri);
+    p.d_aca_colidx = (int *)(b + o_ci);
     p.d_lvl.resize(L);
     p.d_lvl_nch.resize(L);
     p.d_lvl_base.resize(L);
@@ -264,12 +301,12 @@ Layout make_layout(const Plan &p, bool store_leaf)
     int64_t lm = p.leafmax;
     y.G = take(store_leaf ? sizeof(double) * (size_t)p.nleaf * (size_t)(lm * (lm + 1) / 2) : 8);
     int64_t ni = std::max<int64_t>(p.nint, 1);
-    y.aca_state = take(sizeof(AcaState) * ni);
-    y.aca_used = take(sizeof(int) * ni * USED_MAX);
-    y.aca_vdots = take(sizeof(double) * ni * std::max(p.cap, 1));
-    y.aca_part = take(sizeof(double) * std::max(p.aca_row.size(), p.aca_col.size()) * p.aca_pw);
-    y.aca_cnt = take(sizeof(int) * ni);
-    y.aca_active = take(sizeof(int) * 4);
+    int64_t nb = std::max<int64_t>((int64_t)p.aca_big.size(), 1);
+    y.aca_state = take(sizeof(BigState) * 2 * nb);
+    y.aca_used = take(sizeof(int) * nb * USED_MAX);
+    y.aca_vdots = take(sizeof(double) * nb * RMAX_ABS);
+    y.aca_part = take(sizeof(double) * (p.aca_row.size() + p.aca_col.size()) * p.aca_pw);
+    y.aca_status = take(sizeof(int) * ni);
     y.rank = take(sizeof(int) * ni);
     y.leaf_ld = take(sizeof(double) * p.nleaf);
     y.node_ld = take(sizeof(double) * ni);
