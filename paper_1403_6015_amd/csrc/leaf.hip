@@ -74,15 +74,153 @@ __device__ void leaf_trsm(const double *Ap, double *Xs, int m, int nb)
     }
 }
 
-__global__ __launch_bounds__(LEAF_THREADS) void leaf_factor_kernel(LeafArgs A)
+// ---------------------------------------------------------------------------
+// Blocked FP64 factorization on the matrix cores.  The leaf (padded to a
+// multiple of 16 with an identity block) is held in LDS as 16 x 16 tiles;
+// every tile product is four v_mfma_f64_16x16x4 instructions.
+//
+// MFMA operand layout (lane l, r = l % 16, q = l / 16, kb = 0..3, k = q + 4 kb):
+//   A operand A[r][k], B operand B[k][r]; result element t is D[q + 4 t][r].
+// Storage: factor tiles column-major, right-hand-side tiles row-major, both
+// with leading dimension TLD (17 doubles: conflict-free column accesses).
+// With that storage, "A = tile" and "B = tile^T" (factor tiles) or "B = tile"
+// (right-hand-side tiles) all read  ptr[k * TLD + r].
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TLD = 17;
+constexpr int TSZ = 16 * TLD;
+constexpr int NT_MAX = LEAF_LDS_MAX / 16;           // 8 row tiles
+constexpr int NTRI = NT_MAX * (NT_MAX + 1) / 2;     // 36 lower tiles
+constexpr int LEAF_MT = 256;                        // threads of the factor kernel
+constexpr int LEAF_MW = LEAF_MT / 64;               // its waves
+
+__device__ __forceinline__ int tix(int I, int K) { return I * (I + 1) / 2 + K; }
+
+// acc += op(A) * B, op(A) = A or A^T
+template <bool TA>
+__device__ __forceinline__ d4 tile_mma(const double *A, const double *B, d4 acc)
 {
-    __shared__ double Ap[LEAF_LDS_MAX * (LEAF_LDS_MAX + 1) / 2];
-    __shared__ double Xs[LEAF_LDS_MAX * (LEAF_XB + 1)];
-    __shared__ double xc[3][LEAF_LDS_MAX];
-    __shared__ double colj[LEAF_LDS_MAX];
-    __shared__ double red[4];
-    __shared__ int sfail;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int k = q + 4 * kb;
+        double a = TA ? A[r * TLD + k] : A[k * TLD + r];
+        double b = B[k * TLD + r];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double rdlane(double v, int lane)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Cholesky of one 16 x 16 diagonal tile (column-major in LDS); the tile is
+// overwritten with the inverse of its lower factor.  One wave.
+//   factor (Crout, column by column): lane i < 16 keeps row i of the factor in
+//     registers and writes each new entry to the tile, where later columns read
+//     it back with uniform-address (broadcast) LDS loads; the pivot of column j
+//     moves to all lanes with one read-lane;
+//   inverse: lane c < 16 computes column c of L^{-1} by forward substitution
+//     with the same broadcast reads of L.
+// If g is given, the factor's rows (global rows row0 + i < m) go to the packed
+// lower store.  Returns sum_i log L_ii (uniform) or NaN on a bad pivot.
+__device__ double diag_factor(double *T, double *g, int row0, int m)
+{
+    const int lane = threadIdx.x & 63;
+    const int ii = lane & 15;
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        a[c] = T[c * TLD + ii];
+    double ginv[16];
+    double mydiag = 1.0;   // L[ii][ii]
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double s0 = a[j], s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            double ljk = T[k * TLD + j];   // L[j][k], written by lane j at column k
+            if (k & 1)
+                s1 -= a[k] * ljk;
+            else
+                s0 -= a[k] * ljk;
+        }
+        const double sj = s0 + s1;
+        const double d = rdlane(sj, j);
+        bad = bad || !(d > 0.0);
+        const double gj = sqrt(d > 0.0 ? d : 1.0);
+        ginv[j] = 1.0 / gj;
+        a[j] = (ii == j) ? gj : sj * ginv[j];
+        mydiag = (ii == j) ? gj : mydiag;
+        if (lane < 16 && ii >= j)
+            T[j * TLD + ii] = a[j];
+    }
+    double lg = (lane < 16) ? log(mydiag) : 0.0;
+    lg += __shfl_xor(lg, 8, 64);
+    lg += __shfl_xor(lg, 4, 64);
+    lg += __shfl_xor(lg, 2, 64);
+    lg += __shfl_xor(lg, 1, 64);
+    lg = rdlane(lg, 0);
+    if (g && lane < 16) {
+        const int i = row0 + ii;
+        if (i < m) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c <= ii)
+                    g[tri(i) + row0 + c] = a[c];
+        }
+    }
+    // column ii of L^{-1}
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        double s0 = (i == ii) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            double lik = T[k * TLD + i];
+            if (k & 1)
+                s1 -= lik * x[k];
+            else
+                s0 -= lik * x[k];
+        }
+        x[i] = (s0 + s1) * ginv[i];
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            T[ii * TLD + i] = (i >= ii) ? x[i] : 0.0;
+    }
+    return bad ? __builtin_nan("") : lg;
+}
+
+// acc += op(A) * B with A in LDS (op = identity or transpose) and B a tile
+// held in registers in the MFMA result layout (element t = row q + 4t),
+// which is exactly the B-operand layout of the K-slice t.  NEG subtracts.
+template <bool TA, bool NEG>
+__device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int k = q + 4 * kb;
+        double a = TA ? A[r * TLD + k] : A[k * TLD + r];
+        if (NEG)
+            a = -a;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kb], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
+{
+    __shared__ double Gt[NTRI * TSZ];   // lower factor tiles; diagonal slots hold L_JJ^{-1}
+    __shared__ double s_lg;
+    const int tid = threadIdx.x, wid = tid >> 6;
+    const int l = tid & 63, r = l & 15, q = l >> 4;
     const int64_t b = blockIdx.x;
     const int64_t h = A.leaf0 + b;
     const int64_t s = A.start[h];
@@ -93,92 +231,166 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_factor_kernel(LeafArgs A)
             A.leaf_ld[b] = 0.0;
         return;
     }
-    for (int idx = tid; idx < m * A.kp.dim; idx += LEAF_THREADS) {
-        int d = idx / m, i = idx % m;
-        xc[d][i] = A.x[d * n + s + i];
+    const int nt = (m + 15) >> 4;
+    double *gout = A.G ? A.G + b * A.gstride : nullptr;
+    // C = K + sigma^2 I on the lower tiles, identity on the padding.  With
+    // 256 threads every thread owns the same element (rr, cc) of each tile,
+    // so it needs only 8 row and 8 column points.
+    static_assert(LEAF_MT == 256, "one tile element per thread");
+    const int rr = tid & 15, cc = tid >> 4;
+    double xr[3][NT_MAX], xk[3][NT_MAX];
+#pragma unroll
+    for (int I = 0; I < NT_MAX; ++I) {
+        int i = 16 * I + rr, k = 16 * I + cc;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xr[d][I] = (d < A.kp.dim && i < m) ? A.x[d * n + s + i] : 0.0;
+            xk[d][I] = (d < A.kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int I = 0; I < NT_MAX; ++I) {
+#pragma unroll
+        for (int K = 0; K <= I; ++K) {
+            if (I < nt) {
+                int i = 16 * I + rr, k = 16 * K + cc;
+                double v;
+                if (i < m && k < m) {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        double t = xr[d][I] - xk[d][K];
+                        r2 += t * t;
+                    }
+                    v = kfun_r2<double>(A.kp.kind, A.kp.a2, A.kp.c, r2);
+                    if (i == k)
+                        v += A.kp.sigma2;
+                } else {
+                    v = (i == k) ? 1.0 : 0.0;
+                }
+                Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
+            }
+        }
+    }
+    __syncthreads();
+    double lgsum = 0.0;   // wave 0 only
+    if (wid == 0)
+        lgsum += diag_factor(Gt, gout, 0, m);
+    __syncthreads();
+    for (int J = 0; J < nt; ++J) {
+        // panel: L_IJ = C_IJ L_JJ^{-T}
+        for (int I = J + 1 + wid; I < nt; I += LEAF_MW) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            double *T = Gt + tix(I, J) * TSZ;
+            acc = tile_mma<false>(T, Gt + tix(J, J) * TSZ, acc);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                T[r * TLD + q + 4 * t] = acc[t];
+        }
+        __syncthreads();
+        if (J + 1 < nt) {
+            // wave 0: next diagonal tile first (look-ahead), then factor it
+            if (wid == 0) {
+                double *T = Gt + tix(J + 1, J + 1) * TSZ;
+                const double *P = Gt + tix(J + 1, J) * TSZ;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                acc = tile_mma<false>(P, P, acc);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    T[r * TLD + q + 4 * t] -= acc[t];
+                lgsum += diag_factor(T, gout, 16 * (J + 1), m);
+            }
+            // remaining trailing tiles C_IK -= L_IJ L_KJ^T (J < K <= I), other waves first
+            const int Tn = nt - 1 - J;
+            const int ntask = Tn * (Tn + 1) / 2 - 1;
+            for (int task = (wid + LEAF_MW - 1) % LEAF_MW; task < ntask; task += LEAF_MW) {
+                int tt = task + 1;   // skip the look-ahead tile (I = K = J+1)
+                int I = 0;
+                while ((I + 1) * (I + 2) / 2 <= tt)
+                    ++I;
+                int K = tt - I * (I + 1) / 2;
+                I += J + 1;
+                K += J + 1;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                acc = tile_mma<false>(Gt + tix(I, J) * TSZ, Gt + tix(K, J) * TSZ, acc);
+                double *T = Gt + tix(I, K) * TSZ;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    T[r * TLD + q + 4 * t] -= acc[t];
+            }
+        }
+        __syncthreads();
     }
     if (tid == 0)
-        sfail = 0;
+        s_lg = lgsum;
     __syncthreads();
-    const int np = tri(m);
-    for (int idx = tid; idx < np; idx += LEAF_THREADS) {
-        int i = tri_row(idx), k = idx - tri(i);
-        double r2 = 0.0;
-        for (int d = 0; d < A.kp.dim; ++d) {
-            double t = xc[d][i] - xc[d][k];
-            r2 += t * t;
-        }
-        double v = kfun_r2<double>(A.kp.kind, A.kp.a2, A.kp.c, r2);
-        if (i == k)
-            v += A.kp.sigma2;
-        Ap[idx] = v;
-    }
-    __syncthreads();
-    // right-looking Cholesky in the packed lower triangle
-    for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            double d = Ap[tri(j) + j];
-            if (!(d > 0.0))
-                sfail = 1;
-            else
-                Ap[tri(j) + j] = sqrt(d);
-        }
-        __syncthreads();
-        if (sfail)
-            break;
-        double g = Ap[tri(j) + j];
-        for (int i = j + 1 + tid; i < m; i += LEAF_THREADS) {
-            double v = Ap[tri(i) + j] / g;
-            Ap[tri(i) + j] = v;
-            colj[i] = v;
-        }
-        __syncthreads();
-        for (int i = j + 1 + wid; i < m; i += 4) {
-            double ci = colj[i];
-            int base = tri(i);
-            for (int k = j + 1 + lane; k <= i; k += 64)
-                Ap[base + k] -= ci * colj[k];
-        }
-        __syncthreads();
-    }
-    if (sfail) {
+    const double lg = s_lg;
+    if (!(lg == lg)) {
         if (tid == 0) {
             atomicOr(A.status, DS_NOTSPD_LEAF);
             A.leaf_ld[b] = __builtin_nan("");
         }
         return;
     }
-    double lg = 0.0;
-    for (int i = tid; i < m; i += LEAF_THREADS)
-        lg += log(Ap[tri(i) + i]);
-    lg = wave_sum(lg);
-    if (lane == 0)
-        red[wid] = lg;
-    if (A.G) {
-        double *g = A.G + b * A.gstride;
-        for (int idx = tid; idx < np; idx += LEAF_THREADS)
-            g[idx] = Ap[idx];
-    }
-    __syncthreads();
     if (tid == 0)
-        A.leaf_ld[b] = 2.0 * ((red[0] + red[1]) + (red[2] + red[3]));
-    // C_lambda^{-1} on the leaf rows of every column of the list
-    for (int c0 = A.cbeg; c0 < A.ncols; c0 += LEAF_XB) {
-        int nb = min(LEAF_XB, A.ncols - c0);
-        for (int idx = tid; idx < nb * m; idx += LEAF_THREADS) {
-            int c = idx / m, i = idx % m;
-            int col = A.cols[c0 + c];
-            double v = (col == 0) ? A.y[s + i] : A.W[(int64_t)col * n + s + i];
-            Xs[i * (LEAF_XB + 1) + c] = v;
+        A.leaf_ld[b] = 2.0 * lg;
+    if (gout) {   // off-diagonal factor tiles (the diagonal ones went out in diag_factor)
+        for (int idx = tid; idx < tri(m); idx += LEAF_MT) {
+            int i = tri_row(idx), k = idx - tri(i);
+            if ((i >> 4) != (k >> 4))
+                gout[idx] = Gt[tix(i >> 4, k >> 4) * TSZ + (k & 15) * TLD + (i & 15)];
         }
-        __syncthreads();
-        leaf_trsm(Ap, Xs, m, nb);
-        for (int idx = tid; idx < nb * m; idx += LEAF_THREADS) {
-            int c = idx / m, i = idx % m;
-            int col = A.cols[c0 + c];
-            A.Xt[(int64_t)col * n + s + i] = Xs[i * (LEAF_XB + 1) + c];
+    }
+    // C_lambda^{-1} on every column of the list: each wave owns 16 columns in
+    // registers and runs both substitutions on its own
+    for (int c0 = A.cbeg + 16 * wid; c0 < A.ncols; c0 += 16 * LEAF_MW) {
+        const int nb = min(16, A.ncols - c0);
+        const int cr = c0 + r;
+        const double *src = nullptr;
+        if (r < nb) {
+            int col = A.cols[cr];
+            src = (col == 0) ? A.y + s : A.W + (int64_t)col * n + s;
         }
-        __syncthreads();
+        d4 X[NT_MAX];
+#pragma unroll
+        for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int i = 16 * I + q + 4 * t;
+                X[I][t] = (src && I < nt && i < m) ? src[i] : 0.0;
+            }
+#pragma unroll
+        for (int J = 0; J < NT_MAX; ++J) {
+            if (J < nt) {
+                d4 z = {0.0, 0.0, 0.0, 0.0};
+                X[J] = tile_mma_rb<false, false>(Gt + tix(J, J) * TSZ, X[J], z);
+#pragma unroll
+                for (int I = J + 1; I < NT_MAX; ++I)
+                    if (I < nt)
+                        X[I] = tile_mma_rb<false, true>(Gt + tix(I, J) * TSZ, X[J], X[I]);
+            }
+        }
+#pragma unroll
+        for (int J = NT_MAX - 1; J >= 0; --J) {
+            if (J < nt) {
+                d4 z = {0.0, 0.0, 0.0, 0.0};
+                X[J] = tile_mma_rb<true, false>(Gt + tix(J, J) * TSZ, X[J], z);
+#pragma unroll
+                for (int I = 0; I < J; ++I)
+                    X[I] = tile_mma_rb<true, true>(Gt + tix(J, I) * TSZ, X[J], X[I]);
+            }
+        }
+        if (r < nb) {
+            double *dst = A.Xt + (int64_t)A.cols[cr] * n + s;
+#pragma unroll
+            for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    int i = 16 * I + q + 4 * t;
+                    if (I < nt && i < m)
+                        dst[i] = X[I][t];
+                }
+        }
     }
 }
 
@@ -238,7 +450,7 @@ void run_leaf_factor(Pipeline &P, const double *y)
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
     ProfScope ps(P.stream, PS_LEAF);
-    leaf_factor_kernel<<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A);
+    leaf_factor_kernel<<<(unsigned)p.nleaf, LEAF_MT, 0, P.stream>>>(A);
     HIP_TRY(hipGetLastError());
 }
 
