@@ -18,8 +18,7 @@ constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (larg
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
-constexpr int LVL_ROWS = 512;     // minimum rows per level work-group
-constexpr int LVL_MAXCH = 256;    // at most this many work-groups per child per level
+constexpr int LVL_ROWS = 512;     // rows per level work-group
 constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored in LDS
 constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices live in LDS)
 // rows a block may try as pivots: every accepted term can follow ZERO_RETRY zero rows

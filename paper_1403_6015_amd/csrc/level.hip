@@ -106,6 +106,101 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A)
     }
 }
 
+// Small-rank variants (panel rank <= R, the usual case for 1-D kernels):
+// one wave per chunk for the reduction, the chunk's W rows kept in registers
+// and every column reduced across the wave; one thread per row for the
+// update, with S in LDS.  Both stream each X column once, coalesced.
+constexpr int LV_SROWS = LVL_ROWS / 64;   // rows per lane in the reduction
+
+template <int R>
+__global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
+{
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    const int lane = threadIdx.x;
+    const int64_t n = A.n;
+    double w[LV_SROWS][R];
+    bool ok[LV_SROWS];
+#pragma unroll
+    for (int t = 0; t < LV_SROWS; ++t) {
+        const int64_t i = ch.lo + lane + 64 * t;
+        ok[t] = i < ch.hi;
+#pragma unroll
+        for (int l = 0; l < R; ++l)
+            w[t][l] = (ok[t] && l < r) ? A.W[(A.colW + l) * n + i] : 0.0;
+    }
+    double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
+    constexpr int CU = 4;   // columns per iteration: more loads in flight
+    for (int c0 = 0; c0 < A.ncnt; c0 += CU) {
+        const double *xc[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            xc[u] = (c0 + u < A.ncnt) ? A.Xt + (int64_t)A.cols[c0 + u] * n : nullptr;
+        double acc[CU][R];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+            for (int l = 0; l < R; ++l)
+                acc[u][l] = 0.0;
+#pragma unroll
+        for (int t = 0; t < LV_SROWS; ++t) {
+            if (ok[t]) {
+#pragma unroll
+                for (int u = 0; u < CU; ++u) {
+                    const double x = xc[u] ? xc[u][ch.lo + lane + 64 * t] : 0.0;
+#pragma unroll
+                    for (int l = 0; l < R; ++l)
+                        acc[u][l] += w[t][l] * x;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+            for (int l = 0; l < R; ++l) {
+                double v = wave_sum(acc[u][l]);
+                if (lane == 0 && l < r && c0 + u < A.ncnt)
+                    rec[(int64_t)l * A.ncnt + c0 + u] = v;
+            }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArgs A, int smax)
+{
+    extern __shared__ double sS[];   // R x nrhs
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    const int64_t n = A.n;
+    const int64_t loc = ch.node - A.node0;
+    const double *S = A.Sbuf + loc * A.tstride;
+    const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
+    const int nrhs = A.nrhs;
+    for (int idx = threadIdx.x; idx < R * nrhs; idx += LV_THREADS) {
+        int l = idx / nrhs, c = idx % nrhs;
+        sS[idx] = (l < r) ? S[(int64_t)(rowoff + l) * nrhs + c] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += LV_THREADS) {
+        double w[R];
+#pragma unroll
+        for (int l = 0; l < R; ++l)
+            w[l] = (l < r) ? A.Xt[(A.colW + l) * n + i] : 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            double *px = A.Xt + (int64_t)A.cols[c] * n + i;
+            double a = *px;
+#pragma unroll
+            for (int l = 0; l < R; ++l)
+                a -= w[l] * sS[l * nrhs + c];
+            *px = a;
+        }
+    }
+}
+
 __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
 {
     const int64_t loc = blockIdx.x;
@@ -117,11 +212,16 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
             A.node_ld[h] = 0.0;
         return;
     }
-    __shared__ double sP[RMAX_ABS][RMAX_ABS + 1];
-    __shared__ double sQ[RMAX_ABS][RMAX_ABS + 1];
-    __shared__ double sN[RMAX_ABS][RMAX_ABS + 1];
-    __shared__ double t1[RMAX_ABS][LV_CB + 1];
-    __shared__ double t2[RMAX_ABS][LV_CB + 1];
+    // LDS sized by the panel's rank: P, Q, N (rs x (rs+1)) and two RHS batches
+    extern __shared__ double dyn[];
+    const int ldr = A.rstride + 1;
+    double *sPb = dyn, *sQb = dyn + A.rstride * ldr, *sNb = dyn + 2 * A.rstride * ldr;
+    double *t1b = dyn + 3 * A.rstride * ldr, *t2b = t1b + A.rstride * (LV_CB + 1);
+#define sP(i, j) sPb[(i) * ldr + (j)]
+#define sQ(i, j) sQb[(i) * ldr + (j)]
+#define sN(i, j) sNb[(i) * ldr + (j)]
+#define t1(i, c) t1b[(i) * (LV_CB + 1) + (c)]
+#define t2(i, c) t2b[(i) * (LV_CB + 1) + (c)]
     __shared__ int piv[RMAX_ABS];
     __shared__ double red[4];
     __shared__ int sbad;
@@ -129,15 +229,36 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
     const int ncnt = A.ncnt, rs = A.rstride;
     double *T = A.Tbuf + loc * A.tstride;
     // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
-    for (int idx = tid; idx < 2 * r * ncnt; idx += LV_THREADS) {
-        int row2 = idx / ncnt, c = idx % ncnt;
-        int side = row2 < r ? 1 : 0;
-        int l = row2 < r ? row2 : row2 - r;
-        double acc = 0.0;
-        for (int q = base; q < base + nch; ++q)
-            if (A.chunks[q].side == side)
-                acc += A.part[((int64_t)q * rs + l) * ncnt + c];
-        T[(int64_t)(side ? l : rs + l) * ncnt + c] = acc;
+    if (nch <= 16 || 2 * r * ncnt >= LV_THREADS) {
+        // enough outputs to keep every thread busy: one output per thread
+        for (int idx = tid; idx < 2 * r * ncnt; idx += LV_THREADS) {
+            int row2 = idx / ncnt, c = idx % ncnt;
+            int side = row2 < r ? 1 : 0;
+            int l = row2 < r ? row2 : row2 - r;
+            double acc = 0.0;
+            for (int q = base; q < base + nch; ++q)
+                if (A.chunks[q].side == side)
+                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+            T[(int64_t)(side ? l : rs + l) * ncnt + c] = acc;
+        }
+    } else {
+        // few outputs, many records: all threads split the records
+        for (int o = 0; o < 2 * r * ncnt; ++o) {
+            int row2 = o / ncnt, c = o % ncnt;
+            int side = row2 < r ? 1 : 0;
+            int l = row2 < r ? row2 : row2 - r;
+            double acc = 0.0;
+            for (int q = base + tid; q < base + nch; q += LV_THREADS)
+                if (A.chunks[q].side == side)
+                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+            acc = wave_sum(acc);
+            if (lane == 0)
+                red[wid] = acc;
+            __syncthreads();
+            if (tid == 0)
+                T[(int64_t)(side ? l : rs + l) * ncnt + c] = (red[0] + red[1]) + (red[2] + red[3]);
+            __syncthreads();
+        }
     }
     __threadfence_block();
     __syncthreads();
@@ -146,8 +267,8 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
         const int cp = A.nrhs;   // the child panel's columns follow the updated ones
         for (int idx = tid; idx < r * r; idx += LV_THREADS) {
             int i = idx / r, j = idx % r;
-            sP[i][j] = T[(int64_t)i * ncnt + cp + j];
-            sQ[i][j] = T[(int64_t)(rs + i) * ncnt + cp + j];
+            sP(i, j) = T[(int64_t)i * ncnt + cp + j];
+            sQ(i, j) = T[(int64_t)(rs + i) * ncnt + cp + j];
         }
         if (tid == 0)
             sbad = 0;
@@ -156,18 +277,18 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
             int i = idx / r, j = idx % r;
             double a = (i == j) ? 1.0 : 0.0;
             for (int k = 0; k < r; ++k)
-                a -= sQ[i][k] * sP[k][j];
-            sN[i][j] = a;
+                a -= sQ(i, k) * sP(k, j);
+            sN(i, j) = a;
         }
         __syncthreads();
         // LU with partial pivoting (rows swapped in place)
         for (int k = 0; k < r; ++k) {
             if (tid == 0) {
                 int p = k;
-                double best = fabs(sN[k][k]);
+                double best = fabs(sN(k, k));
                 for (int i = k + 1; i < r; ++i)
-                    if (fabs(sN[i][k]) > best) {
-                        best = fabs(sN[i][k]);
+                    if (fabs(sN(i, k)) > best) {
+                        best = fabs(sN(i, k));
                         p = i;
                     }
                 piv[k] = p;
@@ -178,20 +299,20 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
             int p = piv[k];
             if (p != k)
                 for (int j = tid; j < r; j += LV_THREADS) {
-                    double a = sN[k][j];
-                    sN[k][j] = sN[p][j];
-                    sN[p][j] = a;
+                    double a = sN(k, j);
+                    sN(k, j) = sN(p, j);
+                    sN(p, j) = a;
                 }
             __syncthreads();
-            double pv = sN[k][k];
+            double pv = sN(k, k);
             for (int i = k + 1 + tid; i < r; i += LV_THREADS)
                 if (pv != 0.0)
-                    sN[i][k] /= pv;
+                    sN(i, k) /= pv;
             __syncthreads();
             int tr = r - k - 1;
             for (int idx = tid; idx < tr * tr; idx += LV_THREADS) {
                 int i = k + 1 + idx / tr, j = k + 1 + idx % tr;
-                sN[i][j] -= sN[i][k] * sN[k][j];
+                sN(i, j) -= sN(i, k) * sN(k, j);
             }
             __syncthreads();
         }
@@ -199,7 +320,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
         double lg = 0.0;
         int neg = 0;
         for (int i = tid; i < r; i += LV_THREADS) {
-            double u = sN[i][i];
+            double u = sN(i, i);
             lg += log(fabs(u));
             neg += (u < 0.0) ? 1 : 0;
             neg += (piv[i] != i) ? 1 : 0;
@@ -223,18 +344,18 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
         }
         for (int idx = tid; idx < r * r; idx += LV_THREADS) {
             int i = idx / r, j = idx % r;
-            sm[idx] = sN[i][j];
-            sm[r * r + idx] = sP[i][j];
-            sm[2 * r * r + idx] = sQ[i][j];
+            sm[idx] = sN(i, j);
+            sm[r * r + idx] = sP(i, j);
+            sm[2 * r * r + idx] = sQ(i, j);
         }
         for (int i = tid; i < r; i += LV_THREADS)
             sm[3 * r * r + i] = (double)piv[i];
     } else {
         for (int idx = tid; idx < r * r; idx += LV_THREADS) {
             int i = idx / r, j = idx % r;
-            sN[i][j] = sm[idx];
-            sP[i][j] = sm[r * r + idx];
-            sQ[i][j] = sm[2 * r * r + idx];
+            sN(i, j) = sm[idx];
+            sP(i, j) = sm[r * r + idx];
+            sQ(i, j) = sm[2 * r * r + idx];
         }
         for (int i = tid; i < r; i += LV_THREADS)
             piv[i] = (int)sm[3 * r * r + i];
@@ -247,7 +368,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
         const int nb = min(LV_CB, nrhs - c0);
         for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
             int i = idx / nb, c = idx % nb;
-            t1[i][c] = T[(int64_t)i * ncnt + c0 + c];
+            t1(i, c) = T[(int64_t)i * ncnt + c0 + c];
         }
         __syncthreads();
         // t2 := t2 - Q t1, with the row permutation of the LU applied after
@@ -255,8 +376,8 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
             int i = idx / nb, c = idx % nb;
             double a = T[(int64_t)(rs + i) * ncnt + c0 + c];
             for (int k = 0; k < r; ++k)
-                a -= sQ[i][k] * t1[k][c];
-            t2[i][c] = a;
+                a -= sQ(i, k) * t1(k, c);
+            t2(i, c) = a;
         }
         __syncthreads();
         if (tid < nb) {
@@ -264,36 +385,41 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
             for (int k = 0; k < r; ++k) {
                 int p = piv[k];
                 if (p != k) {
-                    double a = t2[k][c];
-                    t2[k][c] = t2[p][c];
-                    t2[p][c] = a;
+                    double a = t2(k, c);
+                    t2(k, c) = t2(p, c);
+                    t2(p, c) = a;
                 }
             }
             for (int i = 1; i < r; ++i) {
-                double a = t2[i][c];
+                double a = t2(i, c);
                 for (int k = 0; k < i; ++k)
-                    a -= sN[i][k] * t2[k][c];
-                t2[i][c] = a;
+                    a -= sN(i, k) * t2(k, c);
+                t2(i, c) = a;
             }
             for (int i = r - 1; i >= 0; --i) {
-                double a = t2[i][c];
+                double a = t2(i, c);
                 for (int k = i + 1; k < r; ++k)
-                    a -= sN[i][k] * t2[k][c];
-                t2[i][c] = a / sN[i][i];
+                    a -= sN(i, k) * t2(k, c);
+                t2(i, c) = a / sN(i, i);
             }
         }
         __syncthreads();
         for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
             int i = idx / nb, c = idx % nb;
-            double a = t1[i][c];
+            double a = t1(i, c);
             for (int k = 0; k < r; ++k)
-                a -= sP[i][k] * t2[k][c];
+                a -= sP(i, k) * t2(k, c);
             S[(int64_t)i * nrhs + c0 + c] = a;
-            S[(int64_t)(rs + i) * nrhs + c0 + c] = t2[i][c];
+            S[(int64_t)(rs + i) * nrhs + c0 + c] = t2(i, c);
         }
         __syncthreads();
     }
 }
+#undef sP
+#undef sQ
+#undef sN
+#undef t1
+#undef t2
 
 __global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A)
 {
@@ -337,6 +463,17 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A)
     }
 }
 
+static size_t solve_lds(int rs)
+{
+    static bool attr = false;   // allow the rank-64 size (about 134 KB) once per process
+    if (!attr) {
+        HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        attr = true;
+    }
+    return sizeof(double) * ((size_t)3 * rs * (rs + 1) + (size_t)2 * rs * (LV_CB + 1) + 1);
+}
+
 static LevelArgs level_args(Pipeline &P, int d)
 {
     const Plan &p = *P.plan;
@@ -367,17 +504,34 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
     const Plan &p = *P.plan;
     const unsigned nchunks = (unsigned)p.lvl[d].size();
     const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
+    const int R = A.rstride <= 2 ? 2 : A.rstride <= 4 ? 4 : A.rstride <= 8 ? 8 : 0;
+    const size_t sbytes = sizeof(double) * (size_t)R * A.nrhs;
+    const bool small_upd = R > 0 && sbytes <= 48 * 1024;
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
-        level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+        if (R == 2)
+            level_reduce_small_kernel<2><<<nchunks, 64, 0, P.stream>>>(A);
+        else if (R == 4)
+            level_reduce_small_kernel<4><<<nchunks, 64, 0, P.stream>>>(A);
+        else if (R == 8)
+            level_reduce_small_kernel<8><<<nchunks, 64, 0, P.stream>>>(A);
+        else
+            level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
-        level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
+        level_solve_kernel<<<nodes, LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
-        level_update_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+        if (small_upd && R == 2)
+            level_update_small_kernel<2><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+        else if (small_upd && R == 4)
+            level_update_small_kernel<4><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+        else if (small_upd && R == 8)
+            level_update_small_kernel<8><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+        else
+            level_update_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
     }
     HIP_TRY(hipGetLastError());
 }
@@ -395,7 +549,7 @@ void run_levels_factor(Pipeline &P)
             // every block of this level has rank 0: coupling determinants are 1
             const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
             ProfScope ps(P.stream, PS_LVL_SOLVE);
-            level_solve_kernel<<<nodes, LV_THREADS, 0, P.stream>>>(A);
+            level_solve_kernel<<<nodes, LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
             HIP_TRY(hipGetLastError());
             continue;
         }

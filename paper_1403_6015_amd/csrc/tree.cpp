@@ -171,8 +171,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
             for (int side = 0; side < 2; ++side) {
                 int64_t lo = side ? m : s, hi = side ? e : m;
                 int64_t len = hi - lo;
-                int64_t csz = std::max<int64_t>(LVL_ROWS, (len + LVL_MAXCH - 1) / LVL_MAXCH);
-                csz = (csz + 63) / 64 * 64;
+                const int64_t csz = LVL_ROWS;   // the small-rank kernels assume this
                 if (len > 0)
                     make_chunks((int)h, side, lo, hi, csz, p.lvl[d], slot);
             }
