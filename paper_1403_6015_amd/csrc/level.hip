@@ -111,6 +111,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A)
 // and every column reduced across the wave; one thread per row for the
 // update, with S in LDS.  Both stream each X column once, coalesced.
 constexpr int LV_SROWS = LVL_ROWS / 64;   // rows per lane in the reduction
+constexpr int LV_CGRP = 8;                 // columns per wave in the reduction
 
 template <int R>
 __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
@@ -133,11 +134,12 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
     }
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
     constexpr int CU = 4;   // columns per iteration: more loads in flight
-    for (int c0 = 0; c0 < A.ncnt; c0 += CU) {
+    const int cend = min(A.ncnt, (int)(blockIdx.y + 1) * LV_CGRP);
+    for (int c0 = blockIdx.y * LV_CGRP; c0 < cend; c0 += CU) {
         const double *xc[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
-            xc[u] = (c0 + u < A.ncnt) ? A.Xt + (int64_t)A.cols[c0 + u] * n : nullptr;
+            xc[u] = (c0 + u < cend) ? A.Xt + (int64_t)A.cols[c0 + u] * n : nullptr;
         double acc[CU][R];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
 #pragma unroll
             for (int l = 0; l < R; ++l) {
                 double v = wave_sum(acc[u][l]);
-                if (lane == 0 && l < r && c0 + u < A.ncnt)
+                if (lane == 0 && l < r && c0 + u < cend)
                     rec[(int64_t)l * A.ncnt + c0 + u] = v;
             }
     }
@@ -229,35 +231,32 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
     const int ncnt = A.ncnt, rs = A.rstride;
     double *T = A.Tbuf + loc * A.tstride;
     // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
-    if (nch <= 16 || 2 * r * ncnt >= LV_THREADS) {
-        // enough outputs to keep every thread busy: one output per thread
-        for (int idx = tid; idx < 2 * r * ncnt; idx += LV_THREADS) {
-            int row2 = idx / ncnt, c = idx % ncnt;
-            int side = row2 < r ? 1 : 0;
-            int l = row2 < r ? row2 : row2 - r;
+    {
+        // each output gets a power-of-two group of threads that splits the
+        // node's records; groups stay inside one wave for the final sum
+        const int nout = 2 * r * ncnt;
+        int G = 1;
+        while (G < 64 && G * 2 * nout <= LV_THREADS && G < nch)
+            G *= 2;
+        const int per = LV_THREADS / G;   // outputs per pass
+        const int sub = tid % G;
+        for (int o0 = 0; o0 < nout; o0 += per) {
+            const int o = o0 + tid / G;
             double acc = 0.0;
-            for (int q = base; q < base + nch; ++q)
-                if (A.chunks[q].side == side)
-                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
-            T[(int64_t)(side ? l : rs + l) * ncnt + c] = acc;
-        }
-    } else {
-        // few outputs, many records: all threads split the records
-        for (int o = 0; o < 2 * r * ncnt; ++o) {
-            int row2 = o / ncnt, c = o % ncnt;
-            int side = row2 < r ? 1 : 0;
-            int l = row2 < r ? row2 : row2 - r;
-            double acc = 0.0;
-            for (int q = base + tid; q < base + nch; q += LV_THREADS)
-                if (A.chunks[q].side == side)
-                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
-            acc = wave_sum(acc);
-            if (lane == 0)
-                red[wid] = acc;
-            __syncthreads();
-            if (tid == 0)
-                T[(int64_t)(side ? l : rs + l) * ncnt + c] = (red[0] + red[1]) + (red[2] + red[3]);
-            __syncthreads();
+            int side = 0, l = 0, c = 0;
+            if (o < nout) {
+                int row2 = o / ncnt;
+                c = o % ncnt;
+                side = row2 < r ? 1 : 0;
+                l = row2 < r ? row2 : row2 - r;
+                for (int q = base + sub; q < base + nch; q += G)
+                    if (A.chunks[q].side == side)
+                        acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+            }
+            for (int off = G / 2; off > 0; off >>= 1)
+                acc += __shfl_xor(acc, off, 64);
+            if (o < nout && sub == 0)
+                T[(int64_t)(side ? l : rs + l) * ncnt + c] = acc;
         }
     }
     __threadfence_block();
@@ -509,12 +508,13 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
     const bool small_upd = R > 0 && sbytes <= 48 * 1024;
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
+        const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP);
         if (R == 2)
-            level_reduce_small_kernel<2><<<nchunks, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<2><<<grid, 64, 0, P.stream>>>(A);
         else if (R == 4)
-            level_reduce_small_kernel<4><<<nchunks, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<4><<<grid, 64, 0, P.stream>>>(A);
         else if (R == 8)
-            level_reduce_small_kernel<8><<<nchunks, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<8><<<grid, 64, 0, P.stream>>>(A);
         else
             level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
     }
