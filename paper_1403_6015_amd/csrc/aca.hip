@@ -537,16 +537,28 @@ __global__ void aca_big_finish_kernel(const BigState *st, const int *bnode, int 
     status[bnode[b]] = st[b].done;
 }
 
-// ranks, per-depth maxima and the capped count
-__global__ void aca_stats_kernel(const int *rank, const int *status, int64_t nint, int *rmax,
-                                 int *capped)
+// ranks, per-depth maxima and the capped count: one work-group, LDS atomics
+__global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const int *status,
+                                                        int64_t nint, int *rmax, int *capped)
 {
-    int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (h >= nint)
-        return;
-    atomicMax(&rmax[depth_of_node(h) + 1], rank[h]);
-    if (status[h] == ACA_CAPPED)
-        atomicAdd(capped, 1);
+    __shared__ int smax[64];
+    __shared__ int scap;
+    if (threadIdx.x < 64)
+        smax[threadIdx.x] = 0;
+    if (threadIdx.x == 0)
+        scap = 0;
+    __syncthreads();
+    int mycap = 0;
+    for (int64_t h = threadIdx.x; h < nint; h += 256) {
+        atomicMax(&smax[depth_of_node(h) + 1], rank[h]);
+        mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
+    }
+    atomicAdd(&scap, mycap);
+    __syncthreads();
+    if (threadIdx.x < 64)
+        rmax[threadIdx.x] = smax[threadIdx.x];
+    if (threadIdx.x == 0)
+        *capped = scap;
 }
 
 // zero columns [rank, rmax) of the panel on the rows of each chunk's block
@@ -674,11 +686,9 @@ void run_aca(Pipeline &P)
                                                                      rank, status);
         }
     }
-    HIP_TRY(hipMemsetAsync(d_rmax, 0, 64 * sizeof(int), s));
-    int nb = (int)((p.nint + 255) / 256);
     {
         ProfScope ps(s, PS_ACA_MISC);
-        aca_stats_kernel<<<nb, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
+        aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * (p.L + 2), hipMemcpyDeviceToHost, s));
