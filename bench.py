@@ -91,6 +91,12 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--workload", default="matern1d",
+                    choices=["matern1d", "batched_theta"],
+                    help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
+                         "batched_theta: 256 hyperparameter settings on one shared n=65536 "
+                         "series per step, hipGraph replay")
+    ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -103,6 +109,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batched_theta":
+        return bench_batched(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -193,6 +201,47 @@ def main():
                                "logdet_rel_err": abs(logdet - kf["logdet"]) / abs(kf["logdet"]),
                                "quad_rel_err": abs(quad - kf["quad"]) / abs(kf["quad"]),
                                "kalman_seconds_1core": dk}
+    print(json.dumps(res), flush=True)
+
+
+def bench_batched(args, torch, H, wl, dev):
+    """Many hyperparameter settings on one shared sorted series: n = 65536,
+    x ~ U(0, 10), Matern-3/2, theta log-uniform in the box of workloads.theta_box;
+    one step = one batched call (all items), captured stages replayed as a graph."""
+    n, m = 65536, args.batch
+    x, y, th = wl.batched_theta(m=m, n=n)
+    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16))
+    nb = plan.batch_workspace_bytes(m)
+    d_x = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    d_y = torch.from_numpy(y).to(dev)
+    d_p = torch.from_numpy(np.ascontiguousarray(th)).to(dev)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = torch.zeros((m, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+
+    def step():
+        H.gp_loglik_batch_dev(plan, d_x, H.K_MATERN32, d_p, m, d_y, 0, 1e-10, work, nb, stream,
+                              out, True)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    o = out.cpu().numpy()
+    res = {"metric": "GP log-likelihoods/s, batched hyperparameters (n=65536 shared series)",
+           "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "batched_theta_m%d_n%d" % (m, n), "n": n, "items": m,
+                      "kernel": "matern32", "leaf": 128, "tol": 1e-10, "max_rank": 16,
+                      "graph": True},
+           "finite_items": int(np.isfinite(o[:, 0]).sum())}
     print(json.dumps(res), flush=True)
 
 

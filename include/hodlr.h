@@ -169,6 +169,24 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
                            void *d_work, size_t work_bytes, void *stream, double *d_out,
                            double *d_z);
 
+/* Batched log-likelihoods (many hyperparameter settings on shared points):
+ * item b uses (a, l, sigma2) = d_params[3b .. 3b+2] (device memory) and the
+ * right-hand side d_y + b * y_stride (y_stride = 0 shares one y).  Every stage
+ * is one launch over all items; after the compression the library reads the
+ * batch-wide rank maxima once (one synchronization) to fix a common column
+ * layout, and with use_graph != 0 (and a non-NULL stream) the remaining stages
+ * run as a hipGraph captured once per layout and buffer set and replayed.
+ * d_out receives 3 doubles per item {loglik, logdet, quad}; an item whose
+ * factorization fails (non-positive pivot or coupling determinant, or
+ * non-positive parameters) gets NaNs and does not stop the batch.
+ * Workspace: hodlr_plan_batch_workspace_size(plan, nitems).  The call returns
+ * without synchronizing; results are ready when the stream is.             */
+hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes);
+hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
+                                 const double *d_params, int32_t nitems, const double *d_y,
+                                 int64_t y_stride, double tol, void *d_work, size_t work_bytes,
+                                 void *stream, double *d_out, int32_t use_graph);
+
 /* Exact FP64 product out = C v evaluated entry by entry on the device
  * (O(n^2), nothing stored): the operator used by iterative refinement and for
  * residual checks.  Same layout rules as gp_loglik_dev; no workspace.       */

@@ -17,7 +17,7 @@ __all__ = [
     "HodlrError", "Opts", "Factor", "Plan", "lib", "hodlr_order", "hodlr_num_levels",
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
-    "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read",
+    "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
@@ -27,7 +27,8 @@ EXPORTED = [
     "hodlr_order", "hodlr_num_levels", "hodlr_build", "hodlr_logdet", "hodlr_solve",
     "gp_loglik", "hodlr_info", "hodlr_free", "hodlr_last_error", "hodlr_plan_create",
     "hodlr_plan_destroy", "hodlr_plan_workspace_size", "gp_loglik_dev", "hodlr_matvec_dev",
-    "hodlr_profile_enable", "hodlr_profile_read",
+    "hodlr_profile_enable", "hodlr_profile_read", "hodlr_plan_batch_workspace_size",
+    "gp_loglik_batch_dev",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -118,6 +119,11 @@ def lib():
                                 vp, ctypes.c_size_t, vp, vp, vp]
     L.hodlr_matvec_dev.restype = st
     L.hodlr_matvec_dev.argtypes = [i64, i32, vp, ctypes.c_int, dp, ctypes.c_double, vp, vp, vp]
+    L.hodlr_plan_batch_workspace_size.restype = st
+    L.hodlr_plan_batch_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.gp_loglik_batch_dev.restype = st
+    L.gp_loglik_batch_dev.argtypes = [vp, vp, ctypes.c_int, vp, i32, vp, i64, ctypes.c_double, vp,
+                                      ctypes.c_size_t, vp, vp, i32]
     L.hodlr_profile_enable.restype = st
     L.hodlr_profile_enable.argtypes = [i32]
     L.hodlr_profile_read.restype = st
@@ -276,6 +282,11 @@ class Plan:
     def handle(self):
         return self._h
 
+    def batch_workspace_bytes(self, nitems: int) -> int:
+        sz = ctypes.c_size_t()
+        _check(lib().hodlr_plan_batch_workspace_size(self._h, int(nitems), ctypes.byref(sz)))
+        return int(sz.value)
+
     def destroy(self):
         if self._h:
             lib().hodlr_plan_destroy(self._h)
@@ -297,6 +308,16 @@ def gp_loglik_dev(plan: Plan, d_x, kernel: int, theta, sigma2: float, d_y, tol: 
     _check(lib().gp_loglik_dev(plan.handle, _ptr(d_x), int(kernel), _dp(th), float(sigma2),
                                _ptr(d_y), float(tol), _ptr(work), int(work_bytes), s,
                                _ptr(d_out), _ptr(d_z)))
+
+
+def gp_loglik_batch_dev(plan: Plan, d_x, kernel: int, d_params, nitems: int, d_y, y_stride: int,
+                        tol: float, work, work_bytes: int, stream, d_out, use_graph: bool = True):
+    """Batched device entry point: d_params is an (nitems, 3) device tensor of
+    (a, l, sigma^2); d_out receives (nitems, 3) {loglik, logdet, quad}."""
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    _check(lib().gp_loglik_batch_dev(plan.handle, _ptr(d_x), int(kernel), _ptr(d_params),
+                                     int(nitems), _ptr(d_y), int(y_stride), float(tol), _ptr(work),
+                                     int(work_bytes), s, _ptr(d_out), 1 if use_graph else 0))
 
 
 def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d_v, d_out,

@@ -238,6 +238,244 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
     }
 }
 
+// ------------------------------------------------------------ batched form
+// Whole cross approximation of one block (any size) in one work-group, for
+// every internal node of every batch item (item = blockIdx.z).  Used rows are
+// kept as a list in LDS; the dots with earlier terms re-read the panel
+// entries the same thread wrote.
+__global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, BatchArgs B, int *rank0,
+                                                               int *status0)
+{
+    const int it = blockIdx.z;
+    const int64_t h = blockIdx.x;
+    const int tid = threadIdx.x;
+    const KParams kp = item_kp(A0.kp, B, it);
+    double *__restrict__ W = ioff(A0.W, B, it);
+    int *rank = ioff(rank0, B, it);
+    int *status = ioff(status0, B, it);
+    const int64_t s = A0.start[h], e = A0.end[h], m = s + (e - s) / 2;
+    const int64_t na = m - s, nb = e - m, n = A0.n;
+    const int64_t col0 = A0.cofa[depth_of_node(h) + 1];
+    __shared__ double rv[4], rs[4], red[4];
+    __shared__ int64_t ri[4];
+    __shared__ double sfix[RMAX_ABS];
+    __shared__ double vdot[RMAX_ABS];
+    __shared__ int usedl[USED_MAX];
+    const int64_t full = na < nb ? na : nb;
+    const int cap = (int)(A0.cap < full ? A0.cap : full);
+    const bool usercap = A0.cap < full;
+    int k = 0, zeros = 0, nused = 0, done = (cap <= 0) ? ACA_EXHAUSTED : ACA_ACTIVE;
+    int64_t istar = na - 1;
+    double s2 = 0.0;
+    while (done == ACA_ACTIVE) {
+        for (int l = tid; l < k; l += ACA_THREADS)
+            sfix[l] = ld_coherent(&W[(col0 + l) * n + s + istar]);
+        __syncthreads();
+        double bv = -1.0, bs = 0.0, sq = 0.0;
+        int64_t bi = INT64_MAX;
+        for (int64_t j = tid; j < nb; j += ACA_THREADS) {
+            double a = kentry(kp, A0.x, n, s + istar, m + j);
+            for (int l = 0; l < k; ++l)
+                a -= sfix[l] * W[(col0 + l) * n + m + j];
+            W[(col0 + k) * n + m + j] = a;
+            sq += a * a;
+            if (fabs(a) > bv) {
+                bv = fabs(a);
+                bs = a;
+                bi = j;
+            }
+        }
+        block_argmax(bv, bi, bs, rv, ri, rs);
+        if (tid == 0 && nused < USED_MAX)
+            usedl[nused] = (int)istar;
+        ++nused;
+        __syncthreads();
+        if (bv == 0.0) {
+            ++zeros;
+            if (zeros > ZERO_RETRY || nused >= na || nused >= USED_MAX) {
+                done = ACA_EXHAUSTED;
+            } else {
+                int64_t c = na - 1;
+                for (; c >= 0; --c) {
+                    bool u = false;
+                    for (int q = 0; q < nused; ++q)
+                        u = u || (usedl[q] == c);
+                    if (!u)
+                        break;
+                }
+                istar = c;
+            }
+            continue;
+        }
+        zeros = 0;
+        const double v2 = block_sum(sq, red);
+        for (int l = 0; l < k; ++l) {
+            double d = 0.0;
+            for (int64_t j = tid; j < nb; j += ACA_THREADS)
+                d += W[(col0 + k) * n + m + j] * W[(col0 + l) * n + m + j];
+            d = block_sum(d, red);
+            if (tid == 0)
+                vdot[l] = d;
+        }
+        const int64_t jstar = bi;
+        const double delta = bs;
+        for (int l = tid; l < k; l += ACA_THREADS)
+            sfix[l] = ld_coherent(&W[(col0 + l) * n + m + jstar]);
+        __syncthreads();
+        bv = -1.0;
+        bs = 0.0;
+        bi = INT64_MAX;
+        sq = 0.0;
+        for (int64_t i = tid; i < na; i += ACA_THREADS) {
+            double a = kentry(kp, A0.x, n, s + i, m + jstar);
+            for (int l = 0; l < k; ++l)
+                a -= sfix[l] * W[(col0 + l) * n + s + i];
+            a = a / delta;
+            W[(col0 + k) * n + s + i] = a;
+            sq += a * a;
+            bool elig = true;
+            for (int q = 0; q < nused && q < USED_MAX; ++q)
+                elig = elig && (usedl[q] != (int)i);
+            if (elig && fabs(a) > bv) {
+                bv = fabs(a);
+                bs = a;
+                bi = i;
+            }
+        }
+        block_argmax(bv, bi, bs, rv, ri, rs);
+        const double u2 = block_sum(sq, red);
+        double cross = 0.0;
+        for (int l = 0; l < k; ++l) {
+            double d = 0.0;
+            for (int64_t i = tid; i < na; i += ACA_THREADS)
+                d += W[(col0 + k) * n + s + i] * W[(col0 + l) * n + s + i];
+            d = block_sum(d, red);
+            cross += d * vdot[l];
+        }
+        s2 += u2 * v2 + 2.0 * cross;
+        k += 1;
+        if (sqrt(u2) * sqrt(v2) <= A0.tol * sqrt(s2 > 0.0 ? s2 : 0.0))
+            done = ACA_CONVERGED;
+        else if (k >= cap)
+            done = usercap ? ACA_CAPPED : ACA_CONVERGED;
+        else if (nused >= na || nused >= USED_MAX || bv < 0.0)
+            done = ACA_EXHAUSTED;
+        else
+            istar = bi;
+    }
+    if (tid == 0) {
+        rank[h] = k;
+        status[h] = done;
+    }
+}
+
+// per item: rank maxima per depth (into the item's own area and, by atomic
+// maximum, into the batch-wide area of item 0) and the capped count
+__global__ __launch_bounds__(256) void aca_batch_stats_kernel(const int *rank0, const int *status0,
+                                                              int64_t nint, BatchArgs B, int *rmax0,
+                                                              int *capped0, int *rmax_all,
+                                                              int *capped_all)
+{
+    const int it = blockIdx.z;
+    const int *rank = ioff(rank0, B, it);
+    const int *status = ioff(status0, B, it);
+    int *rmax = ioff(rmax0, B, it);
+    int *capped = ioff(capped0, B, it);
+    __shared__ int smax[64];
+    __shared__ int scap;
+    if (threadIdx.x < 64)
+        smax[threadIdx.x] = 0;
+    if (threadIdx.x == 0)
+        scap = 0;
+    __syncthreads();
+    int mycap = 0;
+    for (int64_t h = threadIdx.x; h < nint; h += 256) {
+        atomicMax(&smax[depth_of_node(h) + 1], rank[h]);
+        mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
+    }
+    atomicAdd(&scap, mycap);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        rmax[threadIdx.x] = smax[threadIdx.x];
+        atomicMax(&rmax_all[threadIdx.x], smax[threadIdx.x]);
+    }
+    if (threadIdx.x == 0) {
+        *capped = scap;
+        atomicAdd(capped_all, scap);
+    }
+}
+
+// zero panel columns [rank, rmax_all) of every block of every item
+__global__ void aca_batch_pad_kernel(double *W0, int64_t n, const Chunk *chunks, const int *rank0,
+                                     const int *rmax_all, const int64_t *cofa, BatchArgs B)
+{
+    const int it = blockIdx.z;
+    double *W = ioff(W0, B, it);
+    const int *rank = ioff(rank0, B, it);
+    const Chunk ch = chunks[blockIdx.x];
+    int d = depth_of_node(ch.node);
+    int r0 = rank[ch.node], r1 = rmax_all[d + 1];
+    int64_t col0 = cofa[d + 1];
+    for (int c = r0; c < r1; ++c)
+        for (int64_t g = ch.lo + threadIdx.x; g < ch.hi; g += blockDim.x)
+            W[(col0 + c) * n + g] = 0.0;
+}
+
+// Batched compression: one launch for every block of every item, then the
+// batch-wide rank maxima (the common column layout) come back to the host.
+void run_aca_batched(Pipeline &P)
+{
+    const Plan &p = *P.plan;
+    hipStream_t s = P.stream;
+    P.rmax.assign(p.L + 2, 0);
+    P.ranks.clear();
+    P.capped = 0;
+    if (p.L == 0)
+        return;
+    int64_t *d_cofa = wsp<int64_t>(P, P.lay.misc);   // item 0 holds the shared copy
+    int *d_rmax = wsp<int>(P, P.lay.misc + 512);
+    int *d_capped = wsp<int>(P, P.lay.misc + 784);
+    int *d_rmax_all = wsp<int>(P, P.lay.misc + 1536);
+    int *d_capped_all = wsp<int>(P, P.lay.misc + 1536 + 256);
+    HIP_TRY(hipMemcpyAsync(d_cofa, p.cofa.data(), sizeof(int64_t) * p.cofa.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(d_rmax_all, 0, 320, s));
+    AcaArgs A;
+    A.x = P.x;
+    A.n = p.n;
+    A.kp = P.kp;
+    A.tol = P.tol;
+    A.W = wsp<double>(P, P.lay.W);
+    A.start = p.d_start;
+    A.end = p.d_end;
+    A.cofa = d_cofa;
+    A.cap = p.cap;
+    int *rank = wsp<int>(P, P.lay.rank);
+    int *status = wsp<int>(P, P.lay.aca_status);
+    {
+        ProfScope ps(s, PS_ACA_SMALL);
+        aca_block_kernel<<<dim3((unsigned)p.nint, 1, P.nitems), ACA_THREADS, 0, s>>>(A, P.batch, rank,
+                                                                                 status);
+    }
+    {
+        ProfScope ps(s, PS_ACA_MISC);
+        aca_batch_stats_kernel<<<dim3(1, 1, P.nitems), 256, 0, s>>>(
+            rank, status, p.nint, P.batch, d_rmax, d_capped, d_rmax_all, d_capped_all);
+    }
+    HIP_TRY(hipGetLastError());
+    int host[80];
+    HIP_TRY(hipMemcpyAsync(host, d_rmax_all, sizeof(int) * 65, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j <= p.L + 1 && j < 64; ++j)
+        P.rmax[j] = host[j];
+    P.capped = host[64];
+    ProfScope ps(s, PS_ACA_MISC);
+    if (!p.pad_chunks.empty())
+        aca_batch_pad_kernel<<<dim3((unsigned)p.pad_chunks.size(), 1, P.nitems), 256, 0, s>>>(
+            A.W, p.n, p.d_pad_chunks, rank, d_rmax_all, d_cofa, P.batch);
+    HIP_TRY(hipGetLastError());
+}
+
 // ------------------------------------------------------------ large blocks
 struct BigArgs {
     AcaArgs a;

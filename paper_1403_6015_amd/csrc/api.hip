@@ -9,6 +9,7 @@
 namespace hodlr {
 void run_leaf_solve(Pipeline &P, double *z);
 void run_levels_apply(Pipeline &P);
+void prime_level_attributes();
 }  // namespace hodlr
 
 using namespace hodlr;
@@ -177,11 +178,42 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
 
 }  // namespace
 
+// graph of the synchronization-free stages of a batched call, valid for one
+// column layout and one set of buffers
+struct BatchGraph {
+    std::vector<int> rmax;
+    const void *ws, *x, *y, *params, *out;
+    int64_t ystride;
+    void *stream;
+    int kind, nitems;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct hodlr_plan_s {
     Plan plan;
     Layout lay;
     hodlr_opts opts;
+    std::vector<BatchGraph> graphs;
+    ~hodlr_plan_s()
+    {
+        for (auto &g : graphs) {
+            if (g.exec)
+                (void)hipGraphExecDestroy(g.exec);
+            if (g.graph)
+                (void)hipGraphDestroy(g.graph);
+        }
+    }
 };
+
+namespace {
+__global__ void zero_status_kernel(int *status0, BatchArgs B)
+{
+    if (threadIdx.x == 0)
+        *ioff(status0, B, blockIdx.x) = 0;
+}
+size_t item_stride(const Layout &lay) { return (lay.total + 255) & ~(size_t)255; }
+}  // namespace
 
 struct hodlr_factor_s {
     Plan plan;
@@ -480,6 +512,112 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
             HIP_TRY(hipMemcpyAsync(d_z, wsp<double>(P, P.lay.Xt), sizeof(double) * p->plan.n,
                                    hipMemcpyDeviceToDevice, P.stream));
         raise_status(read_status(P));
+        return HODLR_OK;
+    });
+}
+
+hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes)
+{
+    if (!p || !bytes || nitems < 1)
+        return fail(HODLR_EINVAL, "bad argument");
+    *bytes = item_stride(p->lay) * (size_t)nitems;
+    return HODLR_OK;
+}
+
+hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
+                                 const double *d_params, int32_t nitems, const double *d_y,
+                                 int64_t y_stride, double tol, void *d_work, size_t work_bytes,
+                                 void *stream, double *d_out, int32_t use_graph)
+{
+    return guarded([&]() {
+        if (!p || !d_x || !d_params || !d_y || !d_work || !d_out || nitems < 1)
+            throw Error{HODLR_EINVAL, "bad argument"};
+        if (k < HODLR_K_SE || k > HODLR_K_CONST)
+            throw Error{HODLR_EINVAL, "unknown kernel"};
+        if (!(tol > 0.0) || !std::isfinite(tol))
+            throw Error{HODLR_EINVAL, "tol must be positive and finite"};
+        if (y_stride < 0)
+            throw Error{HODLR_EINVAL, "y_stride must be >= 0"};
+        const size_t istride = item_stride(p->lay);
+        if (work_bytes < istride * (size_t)nitems)
+            throw Error{HODLR_EINVAL, "workspace too small: need " +
+                                          std::to_string(istride * (size_t)nitems) + " bytes"};
+        if (p->plan.leafmax > LEAF_LDS_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+        Pipeline P;
+        P.plan = &p->plan;
+        P.lay = p->lay;
+        P.ws = (char *)d_work;
+        P.stream = (hipStream_t)stream;
+        P.x = d_x;
+        const double one[2] = {1.0, 1.0};
+        P.kp = make_kparams(k, p->plan.dim, one, 0.0);
+        P.tol = tol;
+        P.nitems = nitems;
+        P.batch.istride = (int64_t)istride;
+        P.batch.params = d_params;
+        P.batch.ystride = y_stride;
+        zero_status_kernel<<<nitems, 64, 0, P.stream>>>(wsp<int>(P, P.lay.status), P.batch);
+        HIP_TRY(hipGetLastError());
+        run_aca_batched(P);
+        make_columns(P);
+        const bool graph = use_graph && stream != nullptr;
+        if (!graph) {
+            run_leaf_factor(P, d_y);
+            run_levels_factor(P);
+            run_finish(P, d_y, d_out, 3);
+            return HODLR_OK;
+        }
+        BatchGraph *hit = nullptr;
+        for (auto &g : p->graphs)
+            if (g.rmax == P.rmax && g.ws == d_work && g.x == d_x && g.y == d_y &&
+                g.params == d_params && g.out == d_out && g.ystride == y_stride &&
+                g.stream == stream && g.kind == (int)k && g.nitems == nitems) {
+                hit = &g;
+                break;
+            }
+        if (!hit) {
+            prime_level_attributes();
+            BatchGraph g;
+            g.rmax = P.rmax;
+            g.ws = d_work;
+            g.x = d_x;
+            g.y = d_y;
+            g.params = d_params;
+            g.out = d_out;
+            g.ystride = y_stride;
+            g.stream = stream;
+            g.kind = (int)k;
+            g.nitems = nitems;
+            prof_suspend(true);
+            hipError_t e = hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                try {
+                    run_leaf_factor(P, d_y);
+                    run_levels_factor(P);
+                    run_finish(P, d_y, d_out, 3);
+                } catch (...) {
+                    hipGraph_t dead = nullptr;
+                    (void)hipStreamEndCapture(P.stream, &dead);
+                    if (dead)
+                        (void)hipGraphDestroy(dead);
+                    prof_suspend(false);
+                    throw;
+                }
+                e = hipStreamEndCapture(P.stream, &g.graph);
+            }
+            prof_suspend(false);
+            HIP_TRY(e);
+            HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+            if (p->graphs.size() >= 8) {   // small cache: drop the oldest
+                (void)hipGraphExecDestroy(p->graphs.front().exec);
+                (void)hipGraphDestroy(p->graphs.front().graph);
+                p->graphs.erase(p->graphs.begin());
+            }
+            p->graphs.push_back(g);
+            hit = &p->graphs.back();
+        }
+        HIP_TRY(hipGraphLaunch(hit->exec, P.stream));
         return HODLR_OK;
     });
 }

@@ -111,6 +111,36 @@ __device__ __forceinline__ double dist2(const double *__restrict__ x, int64_t n,
     return r2;
 }
 
+// ----------------------------------------------------------- batching
+// A batch of items shares one plan: item b's workspace starts b * istride
+// bytes after item 0's, its kernel parameters (a, l, sigma^2) are
+// params[3b .. 3b+2] when params is given, and its right-hand side starts
+// b * ystride doubles after item 0's.  Kernels take the item from blockIdx.z.
+struct BatchArgs {
+    int64_t istride = 0;
+    const double *params = nullptr;
+    int64_t ystride = 0;
+};
+
+template <typename T>
+__device__ __forceinline__ T *ioff(T *p, const BatchArgs &B, int item)
+{
+    return p ? (T *)((char *)p + B.istride * item) : p;
+}
+
+__device__ __forceinline__ KParams item_kp(KParams kp, const BatchArgs &B, int item)
+{
+    if (B.params) {
+        const double a = B.params[3 * item], l = B.params[3 * item + 1];
+        kp.a2 = a * a;
+        kp.c = (kp.kind == HODLR_K_SE) ? 1.0 / (2.0 * l * l)
+             : (kp.kind == HODLR_K_MATERN32) ? 1.7320508075688772 / l
+             : (kp.kind == HODLR_K_EXP) ? 1.0 / l : 0.0;
+        kp.sigma2 = B.params[3 * item + 2];
+    }
+    return kp;
+}
+
 __device__ __forceinline__ double kentry(const KParams &kp, const double *__restrict__ x, int64_t n,
                                          int64_t i, int64_t j)
 {
@@ -267,6 +297,9 @@ struct Pipeline {
     const double *x;      // ordered, coordinate-major
     KParams kp;
     double tol;
+    int nitems = 1;       // batch size (all items share the plan)
+    BatchArgs batch;      // istride = lay.total rounded, params per item
+    bool capturing = false;
     // host-side results of the compression
     std::vector<int> rmax;    // per depth j (1..L), used columns of the panel
     std::vector<int> cols;    // used column indices, depth-ascending, cols[0] = 0
@@ -282,6 +315,7 @@ enum ProfStage {
     PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_COUNT
 };
 bool prof_on();
+void prof_suspend(bool on);   // no event recording (e.g. while a stream is captured)
 int prof_begin(hipStream_t s);
 void prof_end(int slot, hipStream_t s, int stage);
 void prof_collect();   // after the stream has been synchronized
@@ -303,10 +337,11 @@ struct ProfScope {
 
 // Stages (implemented in the .hip files)
 void run_aca(Pipeline &P);                                   // fills W panels, ranks
+void run_aca_batched(Pipeline &P);                           // every block of every item
 void run_leaf_factor(Pipeline &P, const double *y);          // leaves: G, log-dets, Xt
 void run_levels_factor(Pipeline &P);                         // coupling matrices, Xt, z
 void run_solve(Pipeline &P, double *z);                      // z := C^{-1} z using a built factor
-void run_finish(Pipeline &P, const double *y, double *d_out);  // log det, quad, loglik
+void run_finish(Pipeline &P, const double *y, double *d_out, int ostride = 8);  // log det, quad, loglik
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,
                 hipStream_t s);
 

@@ -29,6 +29,7 @@ struct LeafArgs {
     int64_t gstride;
     double *leaf_ld;
     int *status;
+    BatchArgs B;
 };
 
 __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
@@ -221,6 +222,13 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     __shared__ double s_lg;
     const int tid = threadIdx.x, wid = tid >> 6;
     const int l = tid & 63, r = l & 15, q = l >> 4;
+    const int it = blockIdx.z;   // batch item
+    const KParams kp = item_kp(A.kp, A.B, it);
+    const double *__restrict__ Wsrc = ioff(A.W, A.B, it);
+    double *__restrict__ Xdst = ioff(A.Xt, A.B, it);
+    double *leaf_ld = ioff(A.leaf_ld, A.B, it);
+    int *status = ioff(A.status, A.B, it);
+    const double *ysrc = A.y ? A.y + it * A.B.ystride : nullptr;
     const int64_t b = blockIdx.x;
     const int64_t h = A.leaf0 + b;
     const int64_t s = A.start[h];
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     const int64_t n = A.n;
     if (m == 0) {
         if (tid == 0)
-            A.leaf_ld[b] = 0.0;
+            leaf_ld[b] = 0.0;
         return;
     }
     const int nt = (m + 15) >> 4;
@@ -244,8 +252,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         int i = 16 * I + rr, k = 16 * I + cc;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            xr[d][I] = (d < A.kp.dim && i < m) ? A.x[d * n + s + i] : 0.0;
-            xk[d][I] = (d < A.kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
+            xr[d][I] = (d < kp.dim && i < m) ? A.x[d * n + s + i] : 0.0;
+            xk[d][I] = (d < kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
         }
     }
 #pragma unroll
@@ -262,9 +270,9 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                         double t = xr[d][I] - xk[d][K];
                         r2 += t * t;
                     }
-                    v = kfun_r2<double>(A.kp.kind, A.kp.a2, A.kp.c, r2);
+                    v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
                     if (i == k)
-                        v += A.kp.sigma2;
+                        v += kp.sigma2;
                 } else {
                     v = (i == k) ? 1.0 : 0.0;
                 }
@@ -327,13 +335,13 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     const double lg = s_lg;
     if (!(lg == lg)) {
         if (tid == 0) {
-            atomicOr(A.status, DS_NOTSPD_LEAF);
-            A.leaf_ld[b] = __builtin_nan("");
+            atomicOr(status, DS_NOTSPD_LEAF);
+            leaf_ld[b] = __builtin_nan("");
         }
         return;
     }
     if (tid == 0)
-        A.leaf_ld[b] = 2.0 * lg;
+        leaf_ld[b] = 2.0 * lg;
     if (gout) {   // off-diagonal factor tiles (the diagonal ones went out in diag_factor)
         for (int idx = tid; idx < tri(m); idx += LEAF_MT) {
             int i = tri_row(idx), k = idx - tri(i);
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         const double *src = nullptr;
         if (r < nb) {
             int col = A.cols[cr];
-            src = (col == 0) ? A.y + s : A.W + (int64_t)col * n + s;
+            src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
         }
         d4 X[NT_MAX];
 #pragma unroll
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
             }
         }
         if (r < nb) {
-            double *dst = A.Xt + (int64_t)A.cols[cr] * n + s;
+            double *dst = Xdst + (int64_t)A.cols[cr] * n + s;
 #pragma unroll
             for (int I = 0; I < NT_MAX; ++I)
 #pragma unroll
@@ -437,6 +445,7 @@ static LeafArgs leaf_args(Pipeline &P)
     A.gstride = (int64_t)p.leafmax * (p.leafmax + 1) / 2;
     A.leaf_ld = wsp<double>(P, P.lay.leaf_ld);
     A.status = wsp<int>(P, P.lay.status);
+    A.B = P.batch;
     return A;
 }
 
@@ -450,7 +459,7 @@ void run_leaf_factor(Pipeline &P, const double *y)
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
     ProfScope ps(P.stream, PS_LEAF);
-    leaf_factor_kernel<<<(unsigned)p.nleaf, LEAF_MT, 0, P.stream>>>(A);
+    leaf_factor_kernel<<<dim3((unsigned)p.nleaf, 1, P.nitems), LEAF_MT, 0, P.stream>>>(A);
     HIP_TRY(hipGetLastError());
 }
 

@@ -52,10 +52,30 @@ struct LevelArgs {
     double *node_ld;
     int *status;
     int factor;        // 1: build the coupling factors; 0: apply stored ones
+    BatchArgs B;
 };
 
-__global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A)
+// this work-group's batch item: offset every per-item pointer
+__device__ __forceinline__ LevelArgs item_args(LevelArgs A)
 {
+    const int it = blockIdx.z;
+    if (it) {
+        A.W = ioff(A.W, A.B, it);
+        A.Xt = ioff(A.Xt, A.B, it);
+        A.rank = ioff(A.rank, A.B, it);
+        A.part = ioff(A.part, A.B, it);
+        A.Tbuf = ioff(A.Tbuf, A.B, it);
+        A.Sbuf = ioff(A.Sbuf, A.B, it);
+        A.small = ioff(A.small, A.B, it);
+        A.node_ld = ioff(A.node_ld, A.B, it);
+        A.status = ioff(A.status, A.B, it);
+    }
+    return A;
+}
+
+__global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -114,8 +134,9 @@ constexpr int LV_SROWS = LVL_ROWS / 64;   // rows per lane in the reduction
 constexpr int LV_CGRP = 8;                 // columns per wave in the reduction
 
 template <int R>
-__global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
+__global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
 {
+    const LevelArgs A = item_args(A0);
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -170,8 +191,9 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A)
 }
 
 template <int R>
-__global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArgs A, int smax)
+__global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArgs A0, int smax)
 {
+    const LevelArgs A = item_args(A0);
     extern __shared__ double sS[];   // R x nrhs
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
@@ -203,8 +225,9 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArg
     }
 }
 
-__global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
+__global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
 {
+    const LevelArgs A = item_args(A0);
     const int64_t loc = blockIdx.x;
     const int64_t h = A.node0 + loc;
     const int r = A.rank[h];
@@ -420,8 +443,9 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A)
 #undef t1
 #undef t2
 
-__global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A)
+__global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A0)
 {
+    const LevelArgs A = item_args(A0);
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -473,6 +497,9 @@ static size_t solve_lds(int rs)
     return sizeof(double) * ((size_t)3 * rs * (rs + 1) + (size_t)2 * rs * (LV_CB + 1) + 1);
 }
 
+// set once, outside any stream capture
+void prime_level_attributes() { (void)solve_lds(1); }
+
 static LevelArgs level_args(Pipeline &P, int d)
 {
     const Plan &p = *P.plan;
@@ -495,6 +522,7 @@ static LevelArgs level_args(Pipeline &P, int d)
     A.sstride = P.lay.small_stride;
     A.node_ld = wsp<double>(P, P.lay.node_ld);
     A.status = wsp<int>(P, P.lay.status);
+    A.B = P.batch;
     return A;
 }
 
@@ -508,7 +536,7 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
     const bool small_upd = R > 0 && sbytes <= 48 * 1024;
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
-        const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP);
+        const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP, P.nitems);
         if (R == 2)
             level_reduce_small_kernel<2><<<grid, 64, 0, P.stream>>>(A);
         else if (R == 4)
@@ -516,22 +544,22 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
         else if (R == 8)
             level_reduce_small_kernel<8><<<grid, 64, 0, P.stream>>>(A);
         else
-            level_reduce_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+            level_reduce_kernel<<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
-        level_solve_kernel<<<nodes, LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
+        level_solve_kernel<<<dim3(nodes, 1, P.nitems), LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
         if (small_upd && R == 2)
-            level_update_small_kernel<2><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<2><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else if (small_upd && R == 4)
-            level_update_small_kernel<4><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<4><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else if (small_upd && R == 8)
-            level_update_small_kernel<8><<<nchunks, LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<8><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else
-            level_update_kernel<<<nchunks, LV_THREADS, 0, P.stream>>>(A);
+            level_update_kernel<<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
     }
     HIP_TRY(hipGetLastError());
 }
@@ -549,7 +577,7 @@ void run_levels_factor(Pipeline &P)
             // every block of this level has rank 0: coupling determinants are 1
             const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
             ProfScope ps(P.stream, PS_LVL_SOLVE);
-            level_solve_kernel<<<nodes, LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
+            level_solve_kernel<<<dim3(nodes, 1, P.nitems), LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
             HIP_TRY(hipGetLastError());
             continue;
         }

@@ -12,8 +12,12 @@ namespace hodlr {
 constexpr int FIN_BLOCKS = 512;
 
 __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const double *b,
-                                                          int64_t n, double *part)
+                                                          int64_t n, double *part, BatchArgs B)
 {
+    const int it = blockIdx.z;
+    a += it * B.ystride;
+    b = ioff(b, B, it);
+    part = ioff(part, B, it);
     double s = 0.0;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         s += a[i] * b[i];
@@ -30,8 +34,13 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
 __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int64_t nleaf,
                                                      const double *node_ld, int64_t nint,
                                                      const double *dpart, int ndp, int64_t n,
-                                                     double *out)
+                                                     double *out, int ostride, BatchArgs B)
 {
+    const int it = blockIdx.z;
+    leaf_ld = ioff(leaf_ld, B, it);
+    node_ld = ioff(node_ld, B, it);
+    dpart = ioff(dpart, B, it);
+    out += (int64_t)it * ostride;
     __shared__ double red[3][4];
     double a = 0.0, b = 0.0, q = 0.0;
     for (int64_t i = threadIdx.x; i < nleaf; i += 256)
@@ -58,25 +67,27 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int6
         out[1] = ld;
         out[2] = qq;
         out[0] = -0.5 * qq - 0.5 * ld - 0.5 * (double)n * log(2.0 * M_PI);
-        out[3] = la;
-        out[4] = lb;
+        if (ostride >= 5) {
+            out[3] = la;
+            out[4] = lb;
+        }
     }
 }
 
-void run_finish(Pipeline &P, const double *y, double *d_out)
+void run_finish(Pipeline &P, const double *y, double *d_out, int ostride)
 {
     const Plan &p = *P.plan;
     double *dpart = wsp<double>(P, P.lay.dot_part);
     int ndp = 0;
     ProfScope ps(P.stream, PS_FINISH);
     if (y) {
-        dot_partial_kernel<<<FIN_BLOCKS, 256, 0, P.stream>>>(y, wsp<double>(P, P.lay.Xt), p.n,
-                                                              dpart);
+        dot_partial_kernel<<<dim3(FIN_BLOCKS, 1, P.nitems), 256, 0, P.stream>>>(
+            y, wsp<double>(P, P.lay.Xt), p.n, dpart, P.batch);
         ndp = FIN_BLOCKS;
     }
-    finish_kernel<<<1, 256, 0, P.stream>>>(wsp<double>(P, P.lay.leaf_ld), p.nleaf,
-                                           wsp<double>(P, P.lay.node_ld), p.nint, dpart, ndp,
-                                           p.n, d_out);
+    finish_kernel<<<dim3(1, 1, P.nitems), 256, 0, P.stream>>>(
+        wsp<double>(P, P.lay.leaf_ld), p.nleaf, wsp<double>(P, P.lay.node_ld), p.nint, dpart, ndp,
+        p.n, d_out, ostride, P.batch);
     HIP_TRY(hipGetLastError());
 }
 

@@ -46,7 +46,11 @@ hipEvent_t take(Prof &p)
 }
 }  // namespace
 
-bool prof_on() { return P().on.load(std::memory_order_relaxed); }
+thread_local bool t_suspended = false;
+
+bool prof_on() { return !t_suspended && P().on.load(std::memory_order_relaxed); }
+
+void prof_suspend(bool on) { t_suspended = on; }
 
 int prof_begin(hipStream_t s)
 {
