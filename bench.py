@@ -92,10 +92,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
-                    choices=["matern1d", "batched_theta"],
+                    choices=["matern1d", "batched_theta", "ragged"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
-                         "series per step, hipGraph replay")
+                         "series per step, hipGraph replay; ragged: 512 independent series "
+                         "with n log-uniform in [1024, 131072] per step")
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -111,6 +113,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "batched_theta":
         return bench_batched(args, torch, H, wl, dev)
+    if args.workload == "ragged":
+        return bench_ragged(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -241,6 +245,41 @@ def bench_batched(args, torch, H, wl, dev):
            "config": {"workload": "batched_theta_m%d_n%d" % (m, n), "n": n, "items": m,
                       "kernel": "matern32", "leaf": 128, "tol": 1e-10, "max_rank": 16,
                       "graph": True},
+           "finite_items": int(np.isfinite(o[:, 0]).sum())}
+    print(json.dumps(res), flush=True)
+
+
+def bench_ragged(args, torch, H, wl, dev):
+    """Many independent series of uneven size: 512 items, n log-uniform in
+    [1024, 131072], x ~ U(0, 10) sorted, y ~ N(0, 1), Matern-3/2, theta from
+    the box of workloads.theta_box.  One step = one gp_loglik_ragged call over
+    all items (host arrays in, host results out: the transfers of points and
+    observations are inside the timed region)."""
+    m = 512
+    xs, ys, th = wl.batched_ragged(m=m)
+    opts = H.Opts(max_rank=16)
+
+    def step():
+        return H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 128, 1e-10, opts, args.workers)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        o = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ntot = int(sum(len(x) for x in xs))
+    res = {"metric": "GP log-likelihoods/s, independent series of uneven size",
+           "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "ragged_m%d_n1024to131072" % m, "items": m,
+                      "total_points": ntot, "kernel": "matern32", "leaf": 128, "tol": 1e-10,
+                      "max_rank": 16, "workers": args.workers, "host_buffers": True},
+           "points_per_s": args.steps * ntot / elapsed,
            "finite_items": int(np.isfinite(o[:, 0]).sum())}
     print(json.dumps(res), flush=True)
 

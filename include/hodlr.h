@@ -187,6 +187,22 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
                                  int64_t y_stride, double tol, void *d_work, size_t work_bytes,
                                  void *stream, double *d_out, int32_t use_graph);
 
+/* Log-likelihoods (Eq. (1), as gp_loglik) of m independent problems of
+ * uneven size.  Item i has ns[i] points xs[i] (point-major ns[i]*dim host
+ * doubles, caller order), observations ys[i] (ns[i] host doubles) and
+ * hyperparameters {a, l, sigma2} = params[3i .. 3i+2]; dim, kernel, leaf,
+ * tol and opts are shared.  nworkers host threads (<= 0: 8) each own a
+ * stream and one device arena sized for the largest item, and take items
+ * largest first.  out receives 3 doubles per item {loglik, logdet, quad}; an
+ * item that is invalid or whose factorization fails gets NaNs and does not
+ * stop the others.  All pointers are host memory owned by the caller; the
+ * call returns when every item is done.  Errors: EINVAL (shared arguments),
+ * EDEVICE (the device failed; items not reached hold NaN or are untouched). */
+hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const double *const *xs,
+                              const double *const *ys, int32_t dim, hodlr_kernel k,
+                              const double *params, int32_t leaf, double tol,
+                              const hodlr_opts *opts, int32_t nworkers, double *out);
+
 /* Exact FP64 product out = C v evaluated entry by entry on the device
  * (O(n^2), nothing stored): the operator used by iterative refinement and for
  * residual checks.  Same layout rules as gp_loglik_dev; no workspace.       */

@@ -18,6 +18,7 @@ __all__ = [
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
     "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
+    "gp_loglik_ragged",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
@@ -28,7 +29,7 @@ EXPORTED = [
     "gp_loglik", "hodlr_info", "hodlr_free", "hodlr_last_error", "hodlr_plan_create",
     "hodlr_plan_destroy", "hodlr_plan_workspace_size", "gp_loglik_dev", "hodlr_matvec_dev",
     "hodlr_profile_enable", "hodlr_profile_read", "hodlr_plan_batch_workspace_size",
-    "gp_loglik_batch_dev",
+    "gp_loglik_batch_dev", "gp_loglik_ragged",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -124,6 +125,10 @@ def lib():
     L.gp_loglik_batch_dev.restype = st
     L.gp_loglik_batch_dev.argtypes = [vp, vp, ctypes.c_int, vp, i32, vp, i64, ctypes.c_double, vp,
                                       ctypes.c_size_t, vp, vp, i32]
+    L.gp_loglik_ragged.restype = st
+    L.gp_loglik_ragged.argtypes = [i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dp),
+                                   ctypes.POINTER(dp), i32, ctypes.c_int, dp, i32, ctypes.c_double,
+                                   ctypes.POINTER(Opts), i32, dp]
     L.hodlr_profile_enable.restype = st
     L.hodlr_profile_enable.argtypes = [i32]
     L.hodlr_profile_read.restype = st
@@ -318,6 +323,33 @@ def gp_loglik_batch_dev(plan: Plan, d_x, kernel: int, d_params, nitems: int, d_y
     _check(lib().gp_loglik_batch_dev(plan.handle, _ptr(d_x), int(kernel), _ptr(d_params),
                                      int(nitems), _ptr(d_y), int(y_stride), float(tol), _ptr(work),
                                      int(work_bytes), s, _ptr(d_out), 1 if use_graph else 0))
+
+
+def gp_loglik_ragged(xs, ys, kernel: int, params, leaf: int, tol: float,
+                     opts: Opts | None = None, nworkers: int = 8) -> np.ndarray:
+    """Log-likelihoods of independent problems of uneven size (host arrays).
+    xs[i]: (n_i, dim) or (n_i,) points; ys[i]: n_i observations; params:
+    (m, 3) rows (a, l, sigma^2).  Returns (m, 3) {loglik, logdet, quad}; NaN
+    rows mark items that failed."""
+    m = len(xs)
+    if len(ys) != m:
+        raise ValueError("xs and ys differ in length")
+    X = [_pts(x) for x in xs]
+    dim = X[0].shape[1] if m else 1
+    if any(x.shape[1] != dim for x in X):
+        raise ValueError("all items must share dim")
+    Y = [np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel()) for y in ys]
+    ns = np.array([x.shape[0] for x in X], dtype=np.int64)
+    P = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(m, 3))
+    dpt = ctypes.POINTER(ctypes.c_double)
+    xa = (dpt * m)(*[_dp(x) for x in X])
+    ya = (dpt * m)(*[_dp(y) for y in Y])
+    out = np.empty((m, 3), dtype=np.float64)
+    _check(lib().gp_loglik_ragged(m, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), xa, ya,
+                                  int(dim), int(kernel), _dp(P), int(leaf), float(tol),
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  int(nworkers), _dp(out)))
+    return out
 
 
 def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d_v, d_out,

@@ -812,6 +812,24 @@ __global__ void aca_pad_kernel(double *W, int64_t n, const Chunk *chunks, const 
             W[(col0 + c) * n + g] = 0.0;
 }
 
+// 64 pinned ints per host thread, allocated on first use and released when
+// the thread ends
+int *pinned_scratch()
+{
+    struct Buf {
+        int *p = nullptr;
+        ~Buf()
+        {
+            if (p)
+                (void)hipHostFree(p);
+        }
+    };
+    thread_local Buf buf;
+    if (!buf.p)
+        HIP_TRY(hipHostMalloc((void **)&buf.p, 64 * sizeof(int), hipHostMallocDefault));
+    return buf.p;
+}
+
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -821,12 +839,7 @@ void run_aca(Pipeline &P)
     P.capped = 0;
     if (p.L == 0)
         return;
-    int *pinned = nullptr;
-    HIP_TRY(hipHostMalloc((void **)&pinned, 64 * sizeof(int), hipHostMallocDefault));
-    struct Guard {
-        int *p;
-        ~Guard() { (void)hipHostFree(p); }
-    } g{pinned};
+    int *pinned = pinned_scratch();
     int64_t *d_cofa = wsp<int64_t>(P, P.lay.misc);          // [0, 512): column offsets
     int *d_rmax = wsp<int>(P, P.lay.misc + 512);             // [512, 784): rmax per depth
     int *d_capped = wsp<int>(P, P.lay.misc + 784);

@@ -131,6 +131,9 @@ std::vector<double> ordered_soa(const double *x, int64_t n, int dim, const std::
     return xs;
 }
 
+}  // namespace
+
+namespace hodlr {
 void make_columns(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -176,7 +179,7 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
     run_finish(P, d_y, d_out);
 }
 
-}  // namespace
+}  // namespace hodlr
 
 // graph of the synchronization-free stages of a batched call, valid for one
 // column layout and one set of buffers
@@ -637,3 +640,7 @@ hodlr_status hodlr_matvec_dev(int64_t n, int32_t dim, const double *d_x, hodlr_k
 }
 
 }  // extern "C"
+
+namespace hodlr {
+hodlr_status report(hodlr_status st, const std::string &msg) { return fail(st, msg); }
+}  // namespace hodlr

@@ -241,6 +241,11 @@ struct Plan {
     std::vector<std::vector<Chunk>> lvl;
     std::vector<std::vector<int>> lvl_nch;   // per depth, per node: chunks (both sides)
     std::vector<std::vector<int>> lvl_base;  // per depth, per node: first partial slot
+    // offsets of the device tables inside their image
+    struct TableOffsets {
+        size_t start, end, ar, ac, pc, nr, nc, rb, cb, bg, sm, ri, ci;
+        std::vector<size_t> l, ln, lb;
+    } tbl;
     // device copies of the tables
     void *dev_tables = nullptr;
     size_t dev_tables_bytes = 0;
@@ -283,6 +288,8 @@ Layout make_layout(const Plan &p, bool store_leaf);
 void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts);
 void plan_upload(Plan &p);
 void plan_release(Plan &p);
+size_t plan_image(Plan &p, std::vector<char> &host);   // table image + offsets
+void plan_bind(Plan &p, char *dev);                    // point the tables at dev
 
 // k-d / sort ordering of caller points (point-major) -> perm
 void order_points(const double *x, int64_t n, int dim, int leaf, int64_t *perm);
@@ -344,6 +351,11 @@ void run_solve(Pipeline &P, double *z);                      // z := C^{-1} z us
 void run_finish(Pipeline &P, const double *y, double *d_out, int ostride = 8);  // log det, quad, loglik
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,
                 hipStream_t s);
+void make_columns(Pipeline &P);                                // column list after compression
+int read_status(Pipeline &P);                                  // synchronizes the stream
+void raise_status(int st);
+void factor_pipeline(Pipeline &P, const double *d_y, double *d_out);
+int *pinned_scratch();                                         // per-thread pinned ints
 
 template <typename T>
 inline T *wsp(const Pipeline &P, size_t off)

@@ -182,9 +182,10 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-void plan_upload(Plan &p)
+// Host image of the plan's device tables; offsets are kept in the plan so
+// the same image can be bound to any device region (plan_bind).
+size_t plan_image(Plan &p, std::vector<char> &host)
 {
-    HIP_TRY(hipGetDevice(&p.device));
     const int L = p.L;
     const int64_t nn = ((int64_t)2 << L) - 1;
     size_t off = 0;
@@ -193,48 +194,86 @@ void plan_upload(Plan &p)
         off = align256(off + bytes);
         return o;
     };
-    size_t o_start = take(sizeof(int64_t) * nn), o_end = take(sizeof(int64_t) * nn);
-    size_t o_ar = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_row.size()));
-    size_t o_ac = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_col.size()));
-    size_t o_pc = take(sizeof(Chunk) * std::max<size_t>(1, p.pad_chunks.size()));
+    auto &o = p.tbl;
+    o.start = take(sizeof(int64_t) * nn);
+    o.end = take(sizeof(int64_t) * nn);
+    o.ar = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_row.size()));
+    o.ac = take(sizeof(Chunk) * std::max<size_t>(1, p.aca_col.size()));
+    o.pc = take(sizeof(Chunk) * std::max<size_t>(1, p.pad_chunks.size()));
     const size_t nbig = std::max<size_t>(1, p.aca_big.size());
-    size_t o_nr = take(sizeof(int) * nbig);
-    size_t o_nc = take(sizeof(int) * nbig);
-    size_t o_rb = take(sizeof(int) * nbig);
-    size_t o_cb = take(sizeof(int) * nbig);
-    size_t o_bg = take(sizeof(int) * nbig);
-    size_t o_sm = take(sizeof(int) * std::max<size_t>(1, p.aca_small.size()));
-    size_t o_ri = take(sizeof(int) * std::max<size_t>(1, p.aca_rowidx.size()));
-    size_t o_ci = take(sizeof(int) * std::max<size_t>(1, p.aca_colidx.size()));
-    std::vector<size_t> o_l(L), o_ln(L), o_lb(L);
+    o.nr = take(sizeof(int) * nbig);
+    o.nc = take(sizeof(int) * nbig);
+    o.rb = take(sizeof(int) * nbig);
+    o.cb = take(sizeof(int) * nbig);
+    o.bg = take(sizeof(int) * nbig);
+    o.sm = take(sizeof(int) * std::max<size_t>(1, p.aca_small.size()));
+    o.ri = take(sizeof(int) * std::max<size_t>(1, p.aca_rowidx.size()));
+    o.ci = take(sizeof(int) * std::max<size_t>(1, p.aca_colidx.size()));
+    o.l.assign(L, 0);
+    o.ln.assign(L, 0);
+    o.lb.assign(L, 0);
     for (int d = 0; d < L; ++d) {
-        o_l[d] = take(sizeof(Chunk) * std::max<size_t>(1, p.lvl[d].size()));
-        o_ln[d] = take(sizeof(int) * p.lvl_nch[d].size());
-        o_lb[d] = take(sizeof(int) * p.lvl_base[d].size());
+        o.l[d] = take(sizeof(Chunk) * std::max<size_t>(1, p.lvl[d].size()));
+        o.ln[d] = take(sizeof(int) * p.lvl_nch[d].size());
+        o.lb[d] = take(sizeof(int) * p.lvl_base[d].size());
     }
-    std::vector<char> host(off, 0);
-    auto put = [&](size_t o, const void *src, size_t bytes) {
+    host.assign(off, 0);
+    auto put = [&](size_t at, const void *src, size_t bytes) {
         if (bytes)
-            std::memcpy(host.data() + o, src, bytes);
+            std::memcpy(host.data() + at, src, bytes);
     };
-    put(o_start, p.start.data(), sizeof(int64_t) * nn);
-    put(o_end, p.end.data(), sizeof(int64_t) * nn);
-    put(o_ar, p.aca_row.data(), sizeof(Chunk) * p.aca_row.size());
-    put(o_ac, p.aca_col.data(), sizeof(Chunk) * p.aca_col.size());
-    put(o_pc, p.pad_chunks.data(), sizeof(Chunk) * p.pad_chunks.size());
-    put(o_nr, p.aca_nrow.data(), sizeof(int) * p.aca_nrow.size());
-    put(o_nc, p.aca_ncol.data(), sizeof(int) * p.aca_ncol.size());
-    put(o_rb, p.aca_rowbase.data(), sizeof(int) * p.aca_rowbase.size());
-    put(o_cb, p.aca_colbase.data(), sizeof(int) * p.aca_colbase.size());
-    put(o_bg, p.aca_big.data(), sizeof(int) * p.aca_big.size());
-    put(o_sm, p.aca_small.data(), sizeof(int) * p.aca_small.size());
-    put(o_ri, p.aca_rowidx.data(), sizeof(int) * p.aca_rowidx.size());
-    put(o_ci, p.aca_colidx.data(), sizeof(int) * p.aca_colidx.size());
+    put(o.start, p.start.data(), sizeof(int64_t) * nn);
+    put(o.end, p.end.data(), sizeof(int64_t) * nn);
+    put(o.ar, p.aca_row.data(), sizeof(Chunk) * p.aca_row.size());
+    put(o.ac, p.aca_col.data(), sizeof(Chunk) * p.aca_col.size());
+    put(o.pc, p.pad_chunks.data(), sizeof(Chunk) * p.pad_chunks.size());
+    put(o.nr, p.aca_nrow.data(), sizeof(int) * p.aca_nrow.size());
+    put(o.nc, p.aca_ncol.data(), sizeof(int) * p.aca_ncol.size());
+    put(o.rb, p.aca_rowbase.data(), sizeof(int) * p.aca_rowbase.size());
+    put(o.cb, p.aca_colbase.data(), sizeof(int) * p.aca_colbase.size());
+    put(o.bg, p.aca_big.data(), sizeof(int) * p.aca_big.size());
+    put(o.sm, p.aca_small.data(), sizeof(int) * p.aca_small.size());
+    put(o.ri, p.aca_rowidx.data(), sizeof(int) * p.aca_rowidx.size());
+    put(o.ci, p.aca_colidx.data(), sizeof(int) * p.aca_colidx.size());
     for (int d = 0; d < L; ++d) {
-        put(o_l[d], p.lvl[d].data(), sizeof(Chunk) * p.lvl[d].size());
-        put(o_ln[d], p.lvl_nch[d].data(), sizeof(int) * p.lvl_nch[d].size());
-        put(o_lb[d], p.lvl_base[d].data(), sizeof(int) * p.lvl_base[d].size());
+        put(o.l[d], p.lvl[d].data(), sizeof(Chunk) * p.lvl[d].size());
+        put(o.ln[d], p.lvl_nch[d].data(), sizeof(int) * p.lvl_nch[d].size());
+        put(o.lb[d], p.lvl_base[d].data(), sizeof(int) * p.lvl_base[d].size());
     }
+    return off;
+}
+
+void plan_bind(Plan &p, char *b)
+{
+    const auto &o = p.tbl;
+    p.d_start = (int64_t *)(b + o.start);
+    p.d_end = (int64_t *)(b + o.end);
+    p.d_aca_row = (Chunk *)(b + o.ar);
+    p.d_aca_col = (Chunk *)(b + o.ac);
+    p.d_pad_chunks = (Chunk *)(b + o.pc);
+    p.d_aca_nrow = (int *)(b + o.nr);
+    p.d_aca_ncol = (int *)(b + o.nc);
+    p.d_aca_rowbase = (int *)(b + o.rb);
+    p.d_aca_colbase = (int *)(b + o.cb);
+    p.d_aca_big = (int *)(b + o.bg);
+    p.d_aca_small = (int *)(b + o.sm);
+    p.d_aca_rowidx = (int *)(b + o.ri);
+    p.d_aca_colidx = (int *)(b + o.ci);
+    p.d_lvl.resize(p.L);
+    p.d_lvl_nch.resize(p.L);
+    p.d_lvl_base.resize(p.L);
+    for (int d = 0; d < p.L; ++d) {
+        p.d_lvl[d] = (Chunk *)(b + o.l[d]);
+        p.d_lvl_nch[d] = (int *)(b + o.ln[d]);
+        p.d_lvl_base[d] = (int *)(b + o.lb[d]);
+    }
+}
+
+void plan_upload(Plan &p)
+{
+    HIP_TRY(hipGetDevice(&p.device));
+    std::vector<char> host;
+    size_t off = plan_image(p, host);
     void *dev = nullptr;
     if (hipMalloc(&dev, std::max<size_t>(off, 256)) != hipSuccess)
         throw Error{HODLR_ENOMEM, "device allocation of plan tables failed"};
@@ -242,30 +281,9 @@ void plan_upload(Plan &p)
         (void)hipFree(dev);
         throw Error{HODLR_EDEVICE, "upload of plan tables failed"};
     }
-    char *b = (char *)dev;
     p.dev_tables = dev;
     p.dev_tables_bytes = off;
-    p.d_start = (int64_t *)(b + o_start);
-    p.d_end = (int64_t *)(b + o_end);
-    p.d_aca_row = (Chunk *)(b + o_ar);
-    p.d_aca_col = (Chunk *)(b + o_ac);
-    p.d_aca_nrow = (int *)(b + o_nr);
-    p.d_aca_ncol = (int *)(b + o_nc);
-    p.d_aca_rowbase = (int *)(b + o_rb);
-    p.d_aca_colbase = (int *)(b + o_cb);
-    p.d_pad_chunks = (Chunk *)(b + o_pc);
-    p.d_aca_big = (int *)(b + o_bg);
-    p.d_aca_small = (int *)(b + o_sm);
-    p.d_aca_rowidx = (int *)(b + o_ri);
-    p.d_aca_colidx = (int *)(b + o_ci);
-    p.d_lvl.resize(L);
-    p.d_lvl_nch.resize(L);
-    p.d_lvl_base.resize(L);
-    for (int d = 0; d < L; ++d) {
-        p.d_lvl[d] = (Chunk *)(b + o_l[d]);
-        p.d_lvl_nch[d] = (int *)(b + o_ln[d]);
-        p.d_lvl_base[d] = (int *)(b + o_lb[d]);
-    }
+    plan_bind(p, (char *)dev);
 }
 
 void plan_release(Plan &p)

@@ -1,0 +1,71 @@
+"""GPU parity of the uneven-size form: every item of a gp_loglik_ragged call
+equals the single gp_loglik call on the same problem and matches the exact
+Kalman oracle (Matern-3/2 in 1-D); failing or invalid items give NaN rows
+without disturbing the others."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1403_6015_amd as H
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+
+
+def _problems(m, nmin, nmax, extra_ns=()):
+    xs, ys, th = wl.batched_ragged(m=m, nmin=nmin, nmax=nmax)
+    for j, n in enumerate(extra_ns):
+        rng = np.random.default_rng(900 + j)
+        xs.append(np.sort(rng.uniform(0.0, 10.0, size=n)).reshape(-1, 1))
+        ys.append(rng.standard_normal(n))
+        th = np.vstack([th, th[j % len(th)]])
+    return xs, ys, th
+
+
+@pytest.mark.parametrize("nworkers", [1, 6])
+def test_ragged_items_equal_single_calls_and_kalman(nworkers):
+    xs, ys, th = _problems(20, 200, 20000, extra_ns=(1, 5, 128, 129, 257))
+    m = len(xs)
+    announce("ragged m=%d n=%s workers=%d" % (m, [len(x) for x in xs], nworkers))
+    opts = H.Opts(max_rank=32)
+    out = H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 64, 1e-10, opts, nworkers=nworkers)
+    assert out.shape == (m, 3)
+    for i in range(m):
+        a, ell, s2 = th[i]
+        ll, ld, q = H.gp_loglik(xs[i], ys[i], H.K_MATERN32, (a, ell), s2, 64, 1e-10, opts)
+        # same plan, same kernels, deterministic reductions
+        assert out[i, 0] == pytest.approx(ll, rel=1e-13, abs=1e-12), i
+        assert out[i, 1] == pytest.approx(ld, rel=1e-13, abs=1e-12), i
+        assert out[i, 2] == pytest.approx(q, rel=1e-13, abs=1e-12), i
+        kf = oracle.kalman_matern32(xs[i][:, 0], ys[i], (a, ell), s2, want_alpha=False)
+        assert abs(out[i, 1] - kf["logdet"]) <= 1e-10 * max(abs(kf["logdet"]), 1.0), i
+        assert abs(out[i, 0] - kf["loglik"]) <= 1e-9 * max(abs(kf["loglik"]), 1.0), i
+
+
+def test_ragged_failed_and_invalid_items_are_nan():
+    xs, ys, th = _problems(6, 300, 3000)
+    # item 1: all points equal, a = 1, no noise: C is the all-ones matrix and
+    # the second leaf pivot is exactly 1 - 1*1 = 0 (ENOTSPD when run alone)
+    xs[1] = np.full_like(xs[1], 5.0)
+    th = th.copy()
+    th[1] = (1.0, 0.7, 0.0)
+    # item 3: non-positive length scale
+    th[3, 1] = -1.0
+    announce("ragged failures m=%d" % len(xs))
+    out = H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 64, 1e-10, H.Opts(max_rank=32))
+    assert np.isnan(out[1]).all() and np.isnan(out[3]).all()
+    for i in (0, 2, 4, 5):
+        a, ell, s2 = th[i]
+        kf = oracle.kalman_matern32(xs[i][:, 0], ys[i], (a, ell), s2, want_alpha=False)
+        assert abs(out[i, 0] - kf["loglik"]) <= 1e-9 * max(abs(kf["loglik"]), 1.0), i
+
+
+def test_ragged_shared_argument_errors():
+    xs, ys, th = _problems(2, 100, 200)
+    with pytest.raises(H.HodlrError) as e:
+        H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 64, -1.0)
+    assert e.value.name == "EINVAL"
