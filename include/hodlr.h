@@ -210,6 +210,119 @@ hodlr_status hodlr_matvec_dev(int64_t n, int32_t dim, const double *d_x, hodlr_k
                               const double theta[2], double sigma2, const double *d_v,
                               double *d_out, void *stream);
 
+/* ------------------------------------------- surrogate of the likelihood */
+
+/* The paper's outer loop needs the likelihood at many hyperparameters (§1,
+ * Eq. (1), posterior over theta).  A small network l~(theta) screens
+ * proposals before the exact HODLR likelihood is paid for:
+ *   u = (log theta - mu_in) / sd_in;  h1 = tanh(W1 u + b1);
+ *   h2 = tanh(W2 h1 + b2);  o = W3 . h2 + b3;  l~ = mu_out + sd_out * o.
+ * Parameters: one flat vector of HODLR_MLP_NPARAM numbers in the order
+ * W1 (128 x 3, row = unit), b1 (128), W2 (128 x 128, row = output unit), b2,
+ * W3 (128), b3 (1).  The optimizer owns an FP32 master copy; products use a
+ * BF16 copy (uint16 bit patterns, round to nearest even) and accumulate in
+ * FP32.  log theta rows are (log a, log l, log sigma2), FP64, row-major. */
+#define HODLR_MLP_NPARAM 17153
+typedef struct {
+    float mu_in[3], sd_in[3]; /* input standardization (sd > 0)            */
+    float mu_out, sd_out;     /* output scale: l~ = mu_out + sd_out * o     */
+} hodlr_mlp_norm;
+
+/* Workspace bytes for a training or gradient call on `batch` samples.      */
+hodlr_status hodlr_mlp_workspace_size(int32_t batch, size_t *bytes);
+/* d_wbf16[p] = BF16(d_master[p]) for all parameters (device arrays).       */
+hodlr_status hodlr_mlp_cast_dev(const float *d_master, uint16_t *d_wbf16, void *stream);
+/* d_out[s] = l~(d_logtheta[3s .. 3s+2]) for s < batch (device memory).     */
+hodlr_status hodlr_mlp_forward_dev(const uint16_t *d_wbf16, const hodlr_mlp_norm *norm,
+                                   const double *d_logtheta, int32_t batch, double *d_out,
+                                   void *stream);
+/* Loss mean_s (o_s - (t_s - mu_out)/sd_out)^2 over the batch and its
+ * gradient with respect to the parameters (FP32, HODLR_MLP_NPARAM floats),
+ * evaluated with the BF16 weights.  d_loss (device float) may be NULL.     */
+hodlr_status hodlr_mlp_grad_dev(const uint16_t *d_wbf16, const hodlr_mlp_norm *norm,
+                                const double *d_logtheta, const double *d_target, int32_t batch,
+                                void *d_work, size_t work_bytes, float *d_grad, float *d_loss,
+                                void *stream);
+/* One training step: gradient as above, then Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, step number `step` >= 1 for the bias correction) on the master
+ * copy and moments d_m, d_v (FP32, zero before step 1), and the BF16 copy
+ * refreshed.  Sample s of the batch is row d_index[s] of d_logtheta and
+ * d_target (d_index NULL: row s).  Nothing is synchronized.
+ * Errors: EINVAL, EDEVICE.                                                  */
+hodlr_status hodlr_mlp_train_step_dev(float *d_master, uint16_t *d_wbf16, float *d_m, float *d_v,
+                                      int32_t step, float lr, const hodlr_mlp_norm *norm,
+                                      const double *d_logtheta, const double *d_target,
+                                      const int32_t *d_index, int32_t batch, void *d_work,
+                                      size_t work_bytes, float *d_loss, void *stream);
+/* `epochs` passes over n training pairs in minibatches of `batch` (the last
+ * one of an epoch may be smaller), epoch e visiting rows in the order
+ * d_perm[e*n .. e*n+n-1]; Adam step numbers start at step0.  d_loss_hist
+ * (nullable, device) receives one loss per minibatch.  The workspace must
+ * hold hodlr_mlp_workspace_size(batch).                                    */
+hodlr_status hodlr_mlp_fit_dev(float *d_master, uint16_t *d_wbf16, float *d_m, float *d_v,
+                               int32_t step0, float lr, const hodlr_mlp_norm *norm,
+                               const double *d_logtheta, const double *d_target, int32_t n,
+                               const int32_t *d_perm, int32_t epochs, int32_t batch, void *d_work,
+                               size_t work_bytes, float *d_loss_hist, void *stream);
+
+/* ------------------------------------------------------------- sampling */
+
+/* Random-walk Metropolis over log theta = (log a, log l, log sigma2) for the
+ * posterior exp(l(theta)) p(theta) that the paper's likelihood serves (§1,
+ * Eq. (1)), with a uniform prior on a box in log theta.  The delayed form
+ * (Christen and Fox, 2005) screens each proposal with the surrogate l~:
+ *   stage 1: survive if log u1 < l~(theta') - l~(theta);
+ *   stage 2: accept if log u2 < [l(theta') - l(theta)] - [l~(theta') - l~(theta)],
+ * which leaves the exact posterior invariant for any surrogate.  The plain
+ * form accepts if log u1 < l(theta') - l(theta).  Proposals leave the box
+ * rejected, with no likelihood evaluated.  Random numbers are inputs.
+ * Walker arrays are device memory: theta W x 3 row-major, lp and sur W.     */
+typedef struct {
+    int32_t walkers;    /* W in [1, 1024]                                  */
+    int32_t steps;      /* steps per call                                  */
+    double lo[3], hi[3];/* prior box in log theta                          */
+    double chol[9];     /* proposal theta' = theta + L eps, L row-major    */
+    int32_t init_state; /* 1: evaluate lp (and sur) at theta before step 1 */
+} hodlr_sampler_cfg;
+typedef struct {
+    int64_t proposals, survivors, exact_evals, accepted;
+} hodlr_sampler_stats;
+
+/* prop = theta + eps L^T row by row (chol: host, 9 doubles, row-major).     */
+hodlr_status hodlr_mh_propose_dev(int32_t w, const double *d_theta, const double chol[9],
+                                  const double *d_eps, double *d_prop, void *stream);
+/* Stage 1.  d_sur_prop NULL: plain form (box test only).  Writes slot[i]
+ * (position of walker i among the survivors, walker order, or -1), the
+ * survivor count (one int) and the survivors' (a, l, sigma2) = exp(prop)
+ * rows, ready for gp_loglik_batch_dev.  lo/hi: host arrays.                 */
+hodlr_status hodlr_da_screen_dev(int32_t w, const double *d_prop, const double lo[3],
+                                 const double hi[3], const double *d_sur, const double *d_sur_prop,
+                                 const double *d_u1, int32_t *d_slot, int32_t *d_count,
+                                 double *d_params, void *stream);
+/* Stage 2 (delayed != 0) or the plain decision, for walkers with a slot:
+ * d_exact holds rows {loglik, ...} (3 doubles) of the survivors in slot
+ * order; d_u is u2 (delayed) or u1 (plain).  Accepted walkers take prop, the
+ * exact value and (delayed) the surrogate value.  d_accepted nullable.      */
+hodlr_status hodlr_da_accept_dev(int32_t w, int32_t delayed, const int32_t *d_slot,
+                                 const double *d_exact, const double *d_u, const double *d_prop,
+                                 const double *d_sur_prop, double *d_theta, double *d_lp,
+                                 double *d_sur, int32_t *d_accepted, void *stream);
+/* Workspace of gp_sample_dev for W walkers on plan p.                      */
+hodlr_status hodlr_sampler_workspace_size(hodlr_plan p, int32_t walkers, size_t *bytes);
+/* cfg->steps steps of all walkers on the shared points d_x / observations
+ * d_y of plan p (kernel k, tolerance tol).  d_wbf16 non-NULL selects the
+ * delayed form with that network; NULL the plain form.  Step t uses
+ * d_eps[3Wt ..], d_u1[Wt ..], d_u2[Wt ..]; d_chain (nullable) receives theta
+ * after each step (steps x W x 3).  One host synchronization per step reads
+ * the survivor count.  stats (host, nullable) gets the tallies.
+ * Errors: EINVAL, EDEVICE; a failed exact evaluation rejects its move.     */
+hodlr_status gp_sample_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, const double *d_y,
+                           double tol, const uint16_t *d_wbf16, const hodlr_mlp_norm *norm,
+                           const hodlr_sampler_cfg *cfg, double *d_theta, double *d_lp,
+                           double *d_sur, const double *d_eps, const double *d_u1,
+                           const double *d_u2, void *d_work, size_t work_bytes, void *stream,
+                           double *d_chain, hodlr_sampler_stats *stats);
+
 /* ------------------------------------------------------------ profiling */
 
 #define HODLR_PROF_STAGES 16

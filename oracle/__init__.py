@@ -17,6 +17,10 @@ Contents
 * ``hodlr_ref``: the method's own steps (tree, cross approximation, leaf
   factorization, level-by-level Sherman-Morrison-Woodbury, Sylvester
   determinant, solve) in numpy, for pinning intermediate quantities.
+* ``mlp_ref``: the likelihood surrogate network (forward, gradient by the
+  chain rule, Adam) in FP64 numpy.
+* ``mcmc_ref``: plain and delayed-acceptance Metropolis decisions and an
+  effective-sample-size estimator, for the sampler of the paper's outer loop.
 """
 from __future__ import annotations
 

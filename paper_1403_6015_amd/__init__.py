@@ -18,7 +18,10 @@ __all__ = [
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
     "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
-    "gp_loglik_ragged",
+    "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
+    "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
+    "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
+    "gp_sample_dev",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
@@ -29,8 +32,12 @@ EXPORTED = [
     "gp_loglik", "hodlr_info", "hodlr_free", "hodlr_last_error", "hodlr_plan_create",
     "hodlr_plan_destroy", "hodlr_plan_workspace_size", "gp_loglik_dev", "hodlr_matvec_dev",
     "hodlr_profile_enable", "hodlr_profile_read", "hodlr_plan_batch_workspace_size",
-    "gp_loglik_batch_dev", "gp_loglik_ragged",
+    "gp_loglik_batch_dev", "gp_loglik_ragged", "hodlr_mlp_workspace_size", "hodlr_mlp_cast_dev",
+    "hodlr_mlp_forward_dev", "hodlr_mlp_grad_dev", "hodlr_mlp_train_step_dev",
+    "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
+    "hodlr_sampler_workspace_size", "gp_sample_dev",
 ]
+MLP_NPARAM = 17153
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhodlrgp.so")
@@ -68,6 +75,35 @@ class Info(ctypes.Structure):
                 ("rank_mean", ctypes.c_double * MAX_LEVELS),
                 ("device_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
+
+
+class MlpNorm(ctypes.Structure):
+    _fields_ = [("mu_in", ctypes.c_float * 3), ("sd_in", ctypes.c_float * 3),
+                ("mu_out", ctypes.c_float), ("sd_out", ctypes.c_float)]
+
+    def __init__(self, mu_in=(0.0, 0.0, 0.0), sd_in=(1.0, 1.0, 1.0), mu_out=0.0, sd_out=1.0):
+        super().__init__((ctypes.c_float * 3)(*mu_in), (ctypes.c_float * 3)(*sd_in),
+                         float(mu_out), float(sd_out))
+
+    def as_dict(self):
+        return {"mu_in": [float(v) for v in self.mu_in], "sd_in": [float(v) for v in self.sd_in],
+                "mu_out": float(self.mu_out), "sd_out": float(self.sd_out)}
+
+
+class SamplerCfg(ctypes.Structure):
+    _fields_ = [("walkers", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("chol", ctypes.c_double * 9), ("init_state", ctypes.c_int32)]
+
+    def __init__(self, walkers, steps, lo, hi, chol, init_state=1):
+        c = np.asarray(chol, dtype=np.float64).reshape(9)
+        super().__init__(int(walkers), int(steps), (ctypes.c_double * 3)(*lo),
+                         (ctypes.c_double * 3)(*hi), (ctypes.c_double * 9)(*c), int(init_state))
+
+
+class SamplerStats(ctypes.Structure):
+    _fields_ = [("proposals", ctypes.c_int64), ("survivors", ctypes.c_int64),
+                ("exact_evals", ctypes.c_int64), ("accepted", ctypes.c_int64)]
 
 
 def lib():
@@ -129,6 +165,37 @@ def lib():
     L.gp_loglik_ragged.argtypes = [i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dp),
                                    ctypes.POINTER(dp), i32, ctypes.c_int, dp, i32, ctypes.c_double,
                                    ctypes.POINTER(Opts), i32, dp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    nrm = ctypes.POINTER(MlpNorm)
+    f32 = ctypes.c_float
+    L.hodlr_mlp_workspace_size.restype = st
+    L.hodlr_mlp_workspace_size.argtypes = [i32, szp]
+    L.hodlr_mlp_cast_dev.restype = st
+    L.hodlr_mlp_cast_dev.argtypes = [vp, vp, vp]
+    L.hodlr_mlp_forward_dev.restype = st
+    L.hodlr_mlp_forward_dev.argtypes = [vp, nrm, vp, i32, vp, vp]
+    L.hodlr_mlp_grad_dev.restype = st
+    L.hodlr_mlp_grad_dev.argtypes = [vp, nrm, vp, vp, i32, vp, ctypes.c_size_t, vp, vp, vp]
+    L.hodlr_mlp_train_step_dev.restype = st
+    L.hodlr_mlp_train_step_dev.argtypes = [vp, vp, vp, vp, i32, f32, nrm, vp, vp, vp, i32, vp,
+                                           ctypes.c_size_t, vp, vp]
+    L.hodlr_mlp_fit_dev.restype = st
+    L.hodlr_mlp_fit_dev.argtypes = [vp, vp, vp, vp, i32, f32, nrm, vp, vp, i32, vp, i32, i32, vp,
+                                    ctypes.c_size_t, vp, vp]
+    L.hodlr_mh_propose_dev.restype = st
+    L.hodlr_mh_propose_dev.argtypes = [i32, vp, dp, vp, vp, vp]
+    L.hodlr_da_screen_dev.restype = st
+    L.hodlr_da_screen_dev.argtypes = [i32, vp, dp, dp, vp, vp, vp, vp, vp, vp, vp]
+    L.hodlr_da_accept_dev.restype = st
+    L.hodlr_da_accept_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.hodlr_sampler_workspace_size.restype = st
+    L.hodlr_sampler_workspace_size.argtypes = [vp, i32, szp]
+    L.gp_sample_dev.restype = st
+    L.gp_sample_dev.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_double, vp, nrm,
+                                ctypes.POINTER(SamplerCfg), vp, vp, vp, vp, vp, vp, vp,
+                                ctypes.c_size_t, vp, vp, ctypes.POINTER(SamplerStats)]
+    del fp
     L.hodlr_profile_enable.restype = st
     L.hodlr_profile_enable.argtypes = [i32]
     L.hodlr_profile_read.restype = st
@@ -350,6 +417,98 @@ def gp_loglik_ragged(xs, ys, kernel: int, params, leaf: int, tol: float,
                                   ctypes.byref(opts) if opts is not None else None,
                                   int(nworkers), _dp(out)))
     return out
+
+
+def _stream(stream):
+    return None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+
+
+def _host3(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.float64).ravel())
+
+
+def mlp_workspace_size(batch: int) -> int:
+    sz = ctypes.c_size_t()
+    _check(lib().hodlr_mlp_workspace_size(int(batch), ctypes.byref(sz)))
+    return int(sz.value)
+
+
+def mlp_cast_dev(d_master, d_wbf16, stream=None):
+    _check(lib().hodlr_mlp_cast_dev(_ptr(d_master), _ptr(d_wbf16), _stream(stream)))
+
+
+def mlp_forward_dev(d_wbf16, norm: MlpNorm, d_logtheta, batch: int, d_out, stream=None):
+    _check(lib().hodlr_mlp_forward_dev(_ptr(d_wbf16), ctypes.byref(norm), _ptr(d_logtheta),
+                                       int(batch), _ptr(d_out), _stream(stream)))
+
+
+def mlp_grad_dev(d_wbf16, norm: MlpNorm, d_logtheta, d_target, batch: int, work, work_bytes: int,
+                 d_grad, d_loss=None, stream=None):
+    _check(lib().hodlr_mlp_grad_dev(_ptr(d_wbf16), ctypes.byref(norm), _ptr(d_logtheta),
+                                    _ptr(d_target), int(batch), _ptr(work), int(work_bytes),
+                                    _ptr(d_grad), _ptr(d_loss), _stream(stream)))
+
+
+def mlp_train_step_dev(d_master, d_wbf16, d_m, d_v, step: int, lr: float, norm: MlpNorm,
+                       d_logtheta, d_target, batch: int, work, work_bytes: int, d_loss=None,
+                       stream=None, d_index=None):
+    _check(lib().hodlr_mlp_train_step_dev(_ptr(d_master), _ptr(d_wbf16), _ptr(d_m), _ptr(d_v),
+                                          int(step), float(lr), ctypes.byref(norm),
+                                          _ptr(d_logtheta), _ptr(d_target), _ptr(d_index),
+                                          int(batch), _ptr(work), int(work_bytes), _ptr(d_loss),
+                                          _stream(stream)))
+
+
+def mlp_fit_dev(d_master, d_wbf16, d_m, d_v, step0: int, lr: float, norm: MlpNorm, d_logtheta,
+                d_target, n: int, d_perm, epochs: int, batch: int, work, work_bytes: int,
+                d_loss_hist=None, stream=None):
+    _check(lib().hodlr_mlp_fit_dev(_ptr(d_master), _ptr(d_wbf16), _ptr(d_m), _ptr(d_v),
+                                   int(step0), float(lr), ctypes.byref(norm), _ptr(d_logtheta),
+                                   _ptr(d_target), int(n), _ptr(d_perm), int(epochs), int(batch),
+                                   _ptr(work), int(work_bytes), _ptr(d_loss_hist),
+                                   _stream(stream)))
+
+
+def mh_propose_dev(w: int, d_theta, chol, d_eps, d_prop, stream=None):
+    c = _host3(chol)
+    _check(lib().hodlr_mh_propose_dev(int(w), _ptr(d_theta), _dp(c), _ptr(d_eps), _ptr(d_prop),
+                                      _stream(stream)))
+
+
+def da_screen_dev(w: int, d_prop, lo, hi, d_sur, d_sur_prop, d_u1, d_slot, d_count, d_params,
+                  stream=None):
+    lo, hi = _host3(lo), _host3(hi)
+    _check(lib().hodlr_da_screen_dev(int(w), _ptr(d_prop), _dp(lo), _dp(hi), _ptr(d_sur),
+                                     _ptr(d_sur_prop), _ptr(d_u1), _ptr(d_slot), _ptr(d_count),
+                                     _ptr(d_params), _stream(stream)))
+
+
+def da_accept_dev(w: int, delayed: bool, d_slot, d_exact, d_u, d_prop, d_sur_prop, d_theta, d_lp,
+                  d_sur, d_accepted=None, stream=None):
+    _check(lib().hodlr_da_accept_dev(int(w), 1 if delayed else 0, _ptr(d_slot), _ptr(d_exact),
+                                     _ptr(d_u), _ptr(d_prop), _ptr(d_sur_prop), _ptr(d_theta),
+                                     _ptr(d_lp), _ptr(d_sur), _ptr(d_accepted), _stream(stream)))
+
+
+def sampler_workspace_size(plan: Plan, walkers: int) -> int:
+    sz = ctypes.c_size_t()
+    _check(lib().hodlr_sampler_workspace_size(plan.handle, int(walkers), ctypes.byref(sz)))
+    return int(sz.value)
+
+
+def gp_sample_dev(plan: Plan, d_x, kernel: int, d_y, tol: float, d_wbf16, norm, cfg: SamplerCfg,
+                  d_theta, d_lp, d_sur, d_eps, d_u1, d_u2, work, work_bytes: int, stream=None,
+                  d_chain=None) -> dict:
+    """Runs cfg.steps sampler steps (delayed form if d_wbf16 is given);
+    returns the tallies {proposals, survivors, exact_evals, accepted}."""
+    S = SamplerStats()
+    _check(lib().gp_sample_dev(plan.handle, _ptr(d_x), int(kernel), _ptr(d_y), float(tol),
+                               _ptr(d_wbf16), ctypes.byref(norm) if norm is not None else None,
+                               ctypes.byref(cfg), _ptr(d_theta), _ptr(d_lp), _ptr(d_sur),
+                               _ptr(d_eps), _ptr(d_u1), _ptr(d_u2), _ptr(work), int(work_bytes),
+                               _stream(stream), _ptr(d_chain), ctypes.byref(S)))
+    return {"proposals": S.proposals, "survivors": S.survivors, "exact_evals": S.exact_evals,
+            "accepted": S.accepted}
 
 
 def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d_v, d_out,

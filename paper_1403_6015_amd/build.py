@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhodlrgp.so")
-SOURCES = ["tree.cpp", "prof.cpp", "aca.hip", "leaf.hip", "level.hip", "misc.hip", "api.hip", "ragged.hip"]
+SOURCES = ["tree.cpp", "prof.cpp", "aca.hip", "leaf.hip", "level.hip", "misc.hip", "api.hip", "ragged.hip",
+           "mlp.hip", "sampler.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
