@@ -92,11 +92,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
-                    choices=["matern1d", "batched_theta", "ragged"],
+                    choices=["matern1d", "batched_theta", "ragged", "learned"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
-                         "with n log-uniform in [1024, 131072] per step")
+                         "with n log-uniform in [1024, 131072] per step; learned: surrogate-"
+                         "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18")
+    ap.add_argument("--mcmc-steps", type=int, default=300)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
@@ -115,6 +117,8 @@ def main():
         return bench_batched(args, torch, H, wl, dev)
     if args.workload == "ragged":
         return bench_ragged(args, torch, H, wl, dev)
+    if args.workload == "learned":
+        return bench_learned(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -281,6 +285,72 @@ def bench_ragged(args, torch, H, wl, dev):
                       "max_rank": 16, "workers": args.workers, "host_buffers": True},
            "points_per_s": args.steps * ntot / elapsed,
            "finite_items": int(np.isfinite(o[:, 0]).sum())}
+    print(json.dumps(res), flush=True)
+
+
+def bench_learned(args, torch, H, wl, dev):
+    """Surrogate-screened sampling of log theta for n = 2^18 Matern-3/2 data
+    drawn at theta = (1, 5, 0.1): Laplace scale from exact likelihoods,
+    20000 exact training likelihoods around the mode, device training, then
+    64 walkers of plain and of delayed-acceptance Metropolis with the same
+    proposal; value = effective samples per second of the delayed form."""
+    from paper_1403_6015_amd import learned as LR
+    p = wl.learned(1 << 18)
+    gp = LR.ExactGP(p.x, p.y, kernel=p.kernel, leaf=p.leaf, tol=p.tol, max_rank=16, chunk=256)
+    t_true = np.log([p.theta[0], p.theta[1], p.sigma2])
+    t0 = time.perf_counter()
+    mode, cov = LR.laplace(gp, t_true, 0.05)
+    t_laplace = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    X, T = LR.training_set(gp, mode, cov, n=20000)
+    t_data = time.perf_counter() - t0
+    nval = 2000
+    sur = LR.Surrogate(seed=0)
+    t0 = time.perf_counter()
+    hist = sur.fit(X[nval:], T[nval:], epochs=150, batch=256, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    pred = sur.predict(X[:nval])
+    rmse = float(np.sqrt(np.mean((pred - T[:nval]) ** 2)))
+    rmse_bulk, nbulk = LR.bulk_rmse(pred, T[:nval], gp.loglik(mode[None])[0])
+    sd = np.sqrt(np.diag(cov))
+    lo, hi = mode - 12 * sd, mode + 12 * sd
+    W = 64
+    rng = np.random.default_rng(5)
+    start = mode + 2.0 * rng.standard_normal((W, 3)) @ np.linalg.cholesky(cov).T
+    start = np.clip(start, lo, hi)
+    chol = 2.38 / np.sqrt(3.0) * np.linalg.cholesky(cov)
+    steps, burn = args.mcmc_steps, args.mcmc_steps // 5
+    res_runs = {}
+    for name, s in (("plain", None), ("delayed", sur)):
+        chain, tal, secs = LR.sample(gp, start, chol, lo, hi, steps, surrogate=s, seed=7)
+        e = LR.chain_ess(chain, burn)
+        post = chain[burn:].reshape(-1, 3)
+        res_runs[name] = {"seconds": secs, "ess": e, "ess_per_s": e / secs,
+                          "exact_evals": tal["exact_evals"], "survivors": tal["survivors"],
+                          "accepted": tal["accepted"], "proposals": tal["proposals"],
+                          "acceptance": tal["accepted"] / tal["proposals"],
+                          "post_mean_log_theta": post.mean(axis=0).tolist(),
+                          "post_sd_log_theta": post.std(axis=0).tolist()}
+    da, pm = res_runs["delayed"], res_runs["plain"]
+    res = {"metric": "effective samples/s of surrogate-screened (delayed-acceptance) Metropolis",
+           "value": da["ess_per_s"], "unit": "effective samples/s", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": da["seconds"] / steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "learned_damh_n262144_w64", "n": p.n, "walkers": W,
+                      "kernel": "matern32", "theta_true": list(map(float, [p.theta[0], p.theta[1],
+                                                                           p.sigma2])),
+                      "training_pairs": int(len(T) - nval), "validation_pairs": nval,
+                      "network": "3-128-128-1 tanh, bf16 weights, fp32 accumulation",
+                      "burn_in": burn},
+           "gain_vs_plain_mh": da["ess_per_s"] / pm["ess_per_s"],
+           "plain_mh": pm, "delayed_acceptance": da,
+           "surrogate": {"validation_rmse_nats": rmse, "validation_rmse_bulk_nats": rmse_bulk,
+                         "validation_bulk_points": nbulk, "final_train_loss": float(hist[-50:].mean()),
+                         "train_seconds": t_train, "data_seconds": t_data,
+                         "laplace_seconds": t_laplace},
+           "laplace": {"mode_log_theta": mode.tolist(), "sd_log_theta": sd.tolist()},
+           "ess_per_s_including_training": da["ess"] / (da["seconds"] + t_train + t_data)}
     print(json.dumps(res), flush=True)
 
 
