@@ -72,14 +72,23 @@ enum { HODLR_FP64 = 0, HODLR_MIXED = 1 };
 typedef struct {
     int32_t max_rank;    /* per off-diagonal block rank cap (default 64); a hit cap is
                             counted in hodlr_info, not an error                       */
-    int32_t precision;   /* HODLR_FP64 (default) or HODLR_MIXED                        */
+    int32_t precision;   /* HODLR_FP64 (default) or HODLR_MIXED: the basis panels W, W~
+                            and the solve vector stored in FP32 (the compression and
+                            the panel updates compute in FP64 registers and round on
+                            store; compression tolerance at least 1e-6);
+                            leaf Cholesky factors, coupling-matrix LU and every log-det
+                            sum in FP64.  hodlr_solve and gp_loglik then refine against
+                            the exact FP64 product (hodlr_matvec_dev); gp_loglik_dev and
+                            the batched form return the unrefined quadratic form      */
     double refine_tol;   /* mixed form: stop at ||y - C x|| / ||y|| <= refine_tol
                             (default 1e-10)                                           */
     int32_t max_refine;  /* mixed form: at most this many refinement steps (default 8) */
     int32_t presorted;   /* 1: the points are already in tree order; skip ordering     */
 } hodlr_opts;          /* pass NULL for all defaults */
 
-typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; immutable after build */
+typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one
+                                                  solve at a time per factor (it uses the
+                                                  factor's own solve vector)           */
 typedef struct hodlr_plan_s *hodlr_plan;       /* opaque; tree + workspace layout */
 
 #define HODLR_MAX_LEVELS 40

@@ -7,7 +7,7 @@
 #include "common.h"
 
 namespace hodlr {
-void run_leaf_solve(Pipeline &P, double *z);
+void run_leaf_solve(Pipeline &P, void *z);
 void run_levels_apply(Pipeline &P);
 void prime_level_attributes();
 }  // namespace hodlr
@@ -65,8 +65,8 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "max_rank must be in [0, " + std::to_string(RMAX_ABS) + "]"};
     if (o.precision != HODLR_FP64 && o.precision != HODLR_MIXED)
         throw Error{HODLR_EINVAL, "unknown precision"};
-    if (o.precision == HODLR_MIXED)
-        throw Error{HODLR_EINVAL, "mixed precision is not available in this build"};
+    if (o.max_refine < 0)
+        throw Error{HODLR_EINVAL, "max_refine must be >= 0"};
     if (!(o.refine_tol > 0.0) || !std::isfinite(o.refine_tol))
         throw Error{HODLR_EINVAL, "refine_tol must be positive"};
 }
@@ -173,7 +173,7 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
     run_aca(P);
     make_columns(P);
     if (!d_y)
-        HIP_TRY(hipMemsetAsync(wsp<double>(P, P.lay.Xt), 0, sizeof(double) * P.plan->n, P.stream));
+        HIP_TRY(hipMemsetAsync(P.ws + P.lay.Xt, 0, P.plan->panel_bytes() * P.plan->n, P.stream));
     run_leaf_factor(P, d_y);
     run_levels_factor(P);
     run_finish(P, d_y, d_out);
@@ -231,6 +231,8 @@ struct hodlr_factor_s {
     std::vector<int> rmax, cols, cnt, ranks;
     int capped = 0;
     int device = 0;
+    int refine_steps = 0;          // largest refinement count of the last solve
+    double refine_residual = 0.0;  // largest final relative residual of the last solve
     ~hodlr_factor_s()
     {
         int cur = 0;
@@ -244,6 +246,76 @@ struct hodlr_factor_s {
         (void)hipSetDevice(cur);
     }
 };
+
+namespace {
+
+// Pipeline view of a stored factor
+Pipeline factor_pipeline_of(hodlr_factor_s *f)
+{
+    Pipeline P;
+    P.plan = &f->plan;
+    P.lay = f->lay;
+    P.ws = (char *)f->ws;
+    P.stream = nullptr;
+    P.x = f->dx;
+    P.kp = f->kp;
+    P.tol = f->tol;
+    P.rmax = f->rmax;
+    P.cols = f->cols;
+    P.cnt = f->cnt;
+    P.ranks = f->ranks;
+    return P;
+}
+
+struct Refined {
+    int steps;
+    double residual;   // ||y - C x|| / ||y||; -1 when not measured (FP64 factor)
+    bool converged;
+};
+
+// d_x = C^{-1} d_y in tree order (device FP64 vectors).  An FP64 factor
+// applies its inverse once.  A mixed factor refines: x_0 = H^{-1} y and
+// x_{k+1} = x_k + H^{-1} (y - C x_k), the residual from the exact FP64
+// product, until ||y - C x|| <= refine_tol ||y|| or max_refine corrections.
+Refined solve_tree(hodlr_factor_s *f, Pipeline &P, const double *d_y, double *d_x, double *d_r,
+                   double *d_cx, double *part)
+{
+    const int64_t n = f->plan.n;
+    const bool f32 = f->plan.f32();
+    void *z = P.ws + P.lay.Xt;   // column 0 of the panel carries the vector
+    hipStream_t s = P.stream;
+    if (!f32) {
+        HIP_TRY(hipMemcpyAsync(z, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        run_leaf_solve(P, z);
+        run_levels_apply(P);
+        HIP_TRY(hipMemcpyAsync(d_x, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        return {0, -1.0, true};
+    }
+    const double ynorm = std::sqrt(run_sumsq(d_y, n, part, s));
+    HIP_TRY(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
+    if (ynorm == 0.0)
+        return {0, 0.0, true};
+    HIP_TRY(hipMemcpyAsync(d_r, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double rnorm = ynorm;
+    for (int k = 0;; ++k) {
+        run_cast_scaled(d_r, 1.0 / rnorm, z, true, n, s);
+        run_leaf_solve(P, z);
+        run_levels_apply(P);
+        run_axpy(d_x, rnorm, z, true, n, s);
+        run_matvec(n, f->kp, f->dx, d_x, d_cx, s);
+        run_sub(d_y, d_cx, d_r, n, s);
+        rnorm = std::sqrt(run_sumsq(d_r, n, part, s));
+        const double rel = rnorm / ynorm;
+        if (!std::isfinite(rel))
+            return {k, rel, false};
+        if (rel <= f->plan.refine_tol)
+            return {k, rel, true};
+        if (k >= f->plan.max_refine)
+            return {k, rel, false};
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -334,33 +406,37 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
         const int64_t n = f->plan.n;
         check_finite(y, n * nrhs, "y");
         HIP_TRY(hipSetDevice(f->device));
-        Pipeline P;
-        P.plan = &f->plan;
-        P.lay = f->lay;
-        P.ws = (char *)f->ws;
-        P.stream = nullptr;
-        P.x = f->dx;
-        P.kp = f->kp;
-        P.tol = f->tol;
-        P.rmax = f->rmax;
-        P.cols = f->cols;
-        P.cnt = f->cnt;
-        P.ranks = f->ranks;
-        double *z = wsp<double>(P, P.lay.Xt);   // column 0 carries the vector
+        Pipeline P = factor_pipeline_of(f);
+        const bool f32 = f->plan.f32();
+        DevBuf dy(sizeof(double) * n), dx(sizeof(double) * n);
+        DevBuf dr(f32 ? sizeof(double) * n : 8), dcx(f32 ? sizeof(double) * n : 8),
+            part(sizeof(double) * 512);
         std::vector<double> buf(n), res(n);
+        int steps = 0;
+        double worst = f32 ? 0.0 : -1.0;
+        bool all_ok = true;
         for (int64_t c = 0; c < nrhs; ++c) {
             const double *yc = y + c * n;
             for (int64_t k = 0; k < n; ++k)
                 buf[k] = yc[f->perm[k]];
-            HIP_TRY(hipMemcpy(z, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-            run_leaf_solve(P, z);
-            run_levels_apply(P);
-            HIP_TRY(hipMemcpy(buf.data(), z, sizeof(double) * n, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(dy.p, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+            Refined r = solve_tree(f, P, (const double *)dy.p, (double *)dx.p, (double *)dr.p,
+                                   (double *)dcx.p, (double *)part.p);
+            HIP_TRY(hipMemcpy(buf.data(), dx.p, sizeof(double) * n, hipMemcpyDeviceToHost));
             prof_collect();
+            steps = std::max(steps, r.steps);
+            if (f32)
+                worst = std::max(worst, r.residual);
+            all_ok = all_ok && r.converged;
             for (int64_t k = 0; k < n; ++k)
                 res[f->perm[k]] = buf[k];
             std::memcpy(x + c * n, res.data(), sizeof(double) * n);
         }
+        f->refine_steps = steps;
+        f->refine_residual = worst;
+        if (!all_ok)
+            throw Error{HODLR_ENOCONV, "refinement did not reach refine_tol within max_refine "
+                                       "steps (the best iterate was written)"};
         return HODLR_OK;
     });
 }
@@ -379,6 +455,28 @@ hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
         check_finite(y, n, "y");
         if (!loglik)
             throw Error{HODLR_EINVAL, "loglik is NULL"};
+        if (o.precision == HODLR_MIXED) {
+            // factor once, then the refined solve for the quadratic form
+            hodlr_factor f = nullptr;
+            hodlr_status st = hodlr_build(x, n, dim, k, theta, sigma2, leaf, tol, &o, &f);
+            if (st != HODLR_OK)
+                return st;
+            std::unique_ptr<hodlr_factor_s> own(f);
+            std::vector<double> z(n);
+            st = hodlr_solve(f, y, z.data(), 1);
+            if (st != HODLR_OK && st != HODLR_ENOCONV)
+                return st;   // ENOCONV: the best iterate still gives the outputs
+            double q = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                q += y[i] * z[i];
+            const double ld = f->logdet;
+            *loglik = -0.5 * q - 0.5 * ld - 0.5 * (double)n * std::log(2.0 * M_PI);
+            if (logdet)
+                *logdet = ld;
+            if (quad)
+                *quad = q;
+            return st;
+        }
         std::vector<int64_t> perm(n);
         if (o.presorted)
             for (int64_t i = 0; i < n; ++i)
@@ -434,6 +532,8 @@ hodlr_status hodlr_info(hodlr_factor f, hodlr_info_t *out)
     I.leaf_max = f->plan.leafmax;
     I.capped_blocks = f->capped;
     I.precision = f->opts.precision;
+    I.refine_steps = f->refine_steps;
+    I.refine_residual = f->refine_residual;
     for (int d = 0; d < f->plan.L && d < HODLR_MAX_LEVELS; ++d) {
         int64_t h0 = f->plan.first_at(d), h1 = f->plan.first_at(d + 1);
         int mx = 0;
@@ -512,8 +612,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         P.tol = tol;
         factor_pipeline(P, d_y, d_out);
         if (d_z)
-            HIP_TRY(hipMemcpyAsync(d_z, wsp<double>(P, P.lay.Xt), sizeof(double) * p->plan.n,
-                                   hipMemcpyDeviceToDevice, P.stream));
+            run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
         raise_status(read_status(P));
         return HODLR_OK;
     });

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -16,6 +17,10 @@ namespace hodlr {
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
 constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (large blocks)
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
+// Smallest relative tolerance the FP32 cross approximation can meet: its
+// residual entries carry rounding noise near 1e-7 of the block, and a
+// tighter request would keep adding noise terms up to the rank cap.
+constexpr double ACA_TOL_F32 = 1e-6;
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
 constexpr int LVL_ROWS = 512;     // rows per level work-group
@@ -187,6 +192,10 @@ __device__ __forceinline__ double ld_coherent(const double *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ float ld_coherent(const float *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int ld_coherent(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -266,6 +275,9 @@ struct Plan {
         return d;
     }
     int64_t first_at(int d) const { return ((int64_t)1 << d) - 1; }
+    // the mixed form keeps the basis panels W, W~ (and the solve vector) in FP32
+    bool f32() const { return precision == HODLR_MIXED; }
+    size_t panel_bytes() const { return f32() ? sizeof(float) : sizeof(double); }
 };
 
 // Workspace layout (byte offsets into one device buffer).
@@ -349,6 +361,12 @@ void run_leaf_factor(Pipeline &P, const double *y);          // leaves: G, log-d
 void run_levels_factor(Pipeline &P);                         // coupling matrices, Xt, z
 void run_solve(Pipeline &P, double *z);                      // z := C^{-1} z using a built factor
 void run_finish(Pipeline &P, const double *y, double *d_out, int ostride = 8);  // log det, quad, loglik
+// refinement helpers (misc.hip); z is the panel-typed solve vector
+void run_cast_scaled(const double *r, double inv, void *z, bool f32, int64_t n, hipStream_t s);
+void run_axpy(double *x, double a, const void *z, bool f32, int64_t n, hipStream_t s);
+void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s);
+void run_sub(const double *y, const double *cx, double *r, int64_t n, hipStream_t s);
+double run_sumsq(const double *v, int64_t n, double *part, hipStream_t s);
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,
                 hipStream_t s);
 void make_columns(Pipeline &P);                                // column list after compression

@@ -20,8 +20,8 @@ struct LeafArgs {
     KParams kp;
     const int64_t *start, *end;
     int64_t leaf0;          // heap index of the first leaf
-    const double *W;        // original bases (source columns)
-    double *Xt;             // destination columns
+    const void *W;          // original bases (source columns; float in the mixed form)
+    void *Xt;               // destination columns (same type)
     const double *y;        // right-hand side for column 0 (nullable)
     const int *cols;
     int ncols, cbeg;
@@ -216,6 +216,7 @@ __device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
     return acc;
 }
 
+template <typename PT>
 __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 {
     __shared__ double Gt[NTRI * TSZ];   // lower factor tiles; diagonal slots hold L_JJ^{-1}
@@ -224,8 +225,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     const int l = tid & 63, r = l & 15, q = l >> 4;
     const int it = blockIdx.z;   // batch item
     const KParams kp = item_kp(A.kp, A.B, it);
-    const double *__restrict__ Wsrc = ioff(A.W, A.B, it);
-    double *__restrict__ Xdst = ioff(A.Xt, A.B, it);
+    const PT *__restrict__ Wsrc = ioff((const PT *)A.W, A.B, it);
+    PT *__restrict__ Xdst = ioff((PT *)A.Xt, A.B, it);
     double *leaf_ld = ioff(A.leaf_ld, A.B, it);
     int *status = ioff(A.status, A.B, it);
     const double *ysrc = A.y ? A.y + it * A.B.ystride : nullptr;
@@ -354,10 +355,14 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     for (int c0 = A.cbeg + 16 * wid; c0 < A.ncols; c0 += 16 * LEAF_MW) {
         const int nb = min(16, A.ncols - c0);
         const int cr = c0 + r;
-        const double *src = nullptr;
+        const double *srcy = nullptr;   // column 0: the FP64 right-hand side
+        const PT *src = nullptr;
         if (r < nb) {
             int col = A.cols[cr];
-            src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
+            if (col == 0)
+                srcy = ysrc + s;
+            else
+                src = Wsrc + (int64_t)col * n + s;
         }
         d4 X[NT_MAX];
 #pragma unroll
@@ -365,7 +370,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 int i = 16 * I + q + 4 * t;
-                X[I][t] = (src && I < nt && i < m) ? src[i] : 0.0;
+                X[I][t] = (I < nt && i < m) ? (srcy ? srcy[i] : src ? (double)src[i] : 0.0)
+                                            : 0.0;
             }
 #pragma unroll
         for (int J = 0; J < NT_MAX; ++J) {
@@ -389,21 +395,22 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
             }
         }
         if (r < nb) {
-            double *dst = Xdst + (int64_t)A.cols[cr] * n + s;
+            PT *dst = Xdst + (int64_t)A.cols[cr] * n + s;
 #pragma unroll
             for (int I = 0; I < NT_MAX; ++I)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     int i = 16 * I + q + 4 * t;
                     if (I < nt && i < m)
-                        dst[i] = X[I][t];
+                        dst[i] = (PT)X[I][t];
                 }
         }
     }
 }
 
 // z <- C_lambda^{-1} z on each leaf with the stored packed factors
-__global__ __launch_bounds__(LEAF_THREADS) void leaf_solve_kernel(LeafArgs A, double *z)
+template <typename PT>
+__global__ __launch_bounds__(LEAF_THREADS) void leaf_solve_kernel(LeafArgs A, PT *z)
 {
     __shared__ double Ap[LEAF_LDS_MAX * (LEAF_LDS_MAX + 1) / 2];
     __shared__ double Xs[LEAF_LDS_MAX * (LEAF_XB + 1)];
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_solve_kernel(LeafArgs A, do
     __syncthreads();
     leaf_trsm(Ap, Xs, m, 1);
     for (int i = tid; i < m; i += LEAF_THREADS)
-        z[s + i] = Xs[i * (LEAF_XB + 1)];
+        z[s + i] = (PT)Xs[i * (LEAF_XB + 1)];
 }
 
 static LeafArgs leaf_args(Pipeline &P)
@@ -435,8 +442,8 @@ static LeafArgs leaf_args(Pipeline &P)
     A.start = p.d_start;
     A.end = p.d_end;
     A.leaf0 = p.nint;
-    A.W = wsp<double>(P, P.lay.W);
-    A.Xt = wsp<double>(P, P.lay.Xt);
+    A.W = P.ws + P.lay.W;
+    A.Xt = P.ws + P.lay.Xt;
     A.y = nullptr;
     A.cols = wsp<int>(P, P.lay.cols);
     A.ncols = 0;
@@ -459,16 +466,23 @@ void run_leaf_factor(Pipeline &P, const double *y)
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
     ProfScope ps(P.stream, PS_LEAF);
-    leaf_factor_kernel<<<dim3((unsigned)p.nleaf, 1, P.nitems), LEAF_MT, 0, P.stream>>>(A);
+    const dim3 grid((unsigned)p.nleaf, 1, P.nitems);
+    if (p.f32())
+        leaf_factor_kernel<float><<<grid, LEAF_MT, 0, P.stream>>>(A);
+    else
+        leaf_factor_kernel<double><<<grid, LEAF_MT, 0, P.stream>>>(A);
     HIP_TRY(hipGetLastError());
 }
 
-void run_leaf_solve(Pipeline &P, double *z)
+void run_leaf_solve(Pipeline &P, void *z)
 {
     const Plan &p = *P.plan;
     LeafArgs A = leaf_args(P);
     ProfScope ps(P.stream, PS_LEAF_SOLVE);
-    leaf_solve_kernel<<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, z);
+    if (p.f32())
+        leaf_solve_kernel<float><<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, (float *)z);
+    else
+        leaf_solve_kernel<double><<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, (double *)z);
     HIP_TRY(hipGetLastError());
 }
 

@@ -33,8 +33,8 @@ constexpr int LV_CB = 32;    // right-hand sides per batch in the node solve
 
 struct LevelArgs {
     int64_t n;
-    const double *W;
-    double *Xt;
+    const void *W;     // panels: double, or float in the mixed form
+    void *Xt;
     const int *cols;
     int ncnt;          // columns entering the reduction (prefix of cols)
     int nrhs;          // columns updated (prefix of cols)
@@ -73,9 +73,12 @@ __device__ __forceinline__ LevelArgs item_args(LevelArgs A)
     return A;
 }
 
+template <typename PT>
 __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
+    const PT *__restrict__ Wp = (const PT *)A.W;
+    const PT *__restrict__ Xp = (const PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -95,11 +98,11 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
             const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
             for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
                 int l = idx / LV_RT, i = idx % LV_RT;
-                sW[i][l] = (i < nr) ? A.W[(A.colW + l) * n + i0 + i] : 0.0;
+                sW[i][l] = (i < nr) ? (double)Wp[(A.colW + l) * n + i0 + i] : 0.0;
             }
             for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
                 int c = idx / LV_RT, i = idx % LV_RT;
-                sX[i][c] = (i < nr) ? A.Xt[(int64_t)A.cols[c0 + c] * n + i0 + i] : 0.0;
+                sX[i][c] = (i < nr) ? (double)Xp[(int64_t)A.cols[c0 + c] * n + i0 + i] : 0.0;
             }
             __syncthreads();
 #pragma unroll
@@ -133,10 +136,12 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 constexpr int LV_SROWS = LVL_ROWS / 64;   // rows per lane in the reduction
 constexpr int LV_CGRP = 8;                 // columns per wave in the reduction
 
-template <int R>
+template <typename PT, int R>
 __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
+    const PT *__restrict__ Wp = (const PT *)A.W;
+    const PT *__restrict__ Xp = (const PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -151,16 +156,16 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
         ok[t] = i < ch.hi;
 #pragma unroll
         for (int l = 0; l < R; ++l)
-            w[t][l] = (ok[t] && l < r) ? A.W[(A.colW + l) * n + i] : 0.0;
+            w[t][l] = (ok[t] && l < r) ? (double)Wp[(A.colW + l) * n + i] : 0.0;
     }
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
     constexpr int CU = 4;   // columns per iteration: more loads in flight
     const int cend = min(A.ncnt, (int)(blockIdx.y + 1) * LV_CGRP);
     for (int c0 = blockIdx.y * LV_CGRP; c0 < cend; c0 += CU) {
-        const double *xc[CU];
+        const PT *xc[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
-            xc[u] = (c0 + u < cend) ? A.Xt + (int64_t)A.cols[c0 + u] * n : nullptr;
+            xc[u] = (c0 + u < cend) ? Xp + (int64_t)A.cols[c0 + u] * n : nullptr;
         double acc[CU][R];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
             if (ok[t]) {
 #pragma unroll
                 for (int u = 0; u < CU; ++u) {
-                    const double x = xc[u] ? xc[u][ch.lo + lane + 64 * t] : 0.0;
+                    const double x = xc[u] ? (double)xc[u][ch.lo + lane + 64 * t] : 0.0;
 #pragma unroll
                     for (int l = 0; l < R; ++l)
                         acc[u][l] += w[t][l] * x;
@@ -190,10 +195,11 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
     }
 }
 
-template <int R>
+template <typename PT, int R>
 __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArgs A0, int smax)
 {
     const LevelArgs A = item_args(A0);
+    PT *__restrict__ Xp = (PT *)A.Xt;
     extern __shared__ double sS[];   // R x nrhs
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
@@ -213,14 +219,14 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArg
         double w[R];
 #pragma unroll
         for (int l = 0; l < R; ++l)
-            w[l] = (l < r) ? A.Xt[(A.colW + l) * n + i] : 0.0;
+            w[l] = (l < r) ? (double)Xp[(A.colW + l) * n + i] : 0.0;
         for (int c = 0; c < nrhs; ++c) {
-            double *px = A.Xt + (int64_t)A.cols[c] * n + i;
+            PT *px = Xp + (int64_t)A.cols[c] * n + i;
             double a = *px;
 #pragma unroll
             for (int l = 0; l < R; ++l)
                 a -= w[l] * sS[l * nrhs + c];
-            *px = a;
+            *px = (PT)a;
         }
     }
 }
@@ -443,9 +449,11 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
 #undef t1
 #undef t2
 
+template <typename PT>
 __global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
+    PT *__restrict__ Xp = (PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     if (r == 0)
@@ -468,17 +476,17 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A0)
             const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
             for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
                 int l = idx / LV_RT, i = idx % LV_RT;
-                sWt[i][l] = (i < nr) ? A.Xt[(A.colW + l) * n + i0 + i] : 0.0;
+                sWt[i][l] = (i < nr) ? (double)Xp[(A.colW + l) * n + i0 + i] : 0.0;
             }
             __syncthreads();
             for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
                 int c = idx / LV_RT, i = idx % LV_RT;
                 if (i < nr) {
-                    double *px = A.Xt + (int64_t)A.cols[c0 + c] * n + i0 + i;
+                    PT *px = Xp + (int64_t)A.cols[c0 + c] * n + i0 + i;
                     double a = *px;
                     for (int l = 0; l < r; ++l)
                         a -= sWt[i][l] * sS[l][c];
-                    *px = a;
+                    *px = (PT)a;
                 }
             }
             __syncthreads();
@@ -505,8 +513,8 @@ static LevelArgs level_args(Pipeline &P, int d)
     const Plan &p = *P.plan;
     LevelArgs A;
     A.n = p.n;
-    A.W = wsp<double>(P, P.lay.W);
-    A.Xt = wsp<double>(P, P.lay.Xt);
+    A.W = P.ws + P.lay.W;
+    A.Xt = P.ws + P.lay.Xt;
     A.cols = wsp<int>(P, P.lay.cols);
     A.colW = p.cofa[d + 1];
     A.rstride = P.rmax[d + 1];
@@ -526,7 +534,8 @@ static LevelArgs level_args(Pipeline &P, int d)
     return A;
 }
 
-static void level_launch(Pipeline &P, int d, LevelArgs A)
+template <typename PT>
+static void level_launch_t(Pipeline &P, int d, LevelArgs A)
 {
     const Plan &p = *P.plan;
     const unsigned nchunks = (unsigned)p.lvl[d].size();
@@ -538,13 +547,13 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
         ProfScope ps(P.stream, PS_LVL_REDUCE);
         const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP, P.nitems);
         if (R == 2)
-            level_reduce_small_kernel<2><<<grid, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<PT, 2><<<grid, 64, 0, P.stream>>>(A);
         else if (R == 4)
-            level_reduce_small_kernel<4><<<grid, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<PT, 4><<<grid, 64, 0, P.stream>>>(A);
         else if (R == 8)
-            level_reduce_small_kernel<8><<<grid, 64, 0, P.stream>>>(A);
+            level_reduce_small_kernel<PT, 8><<<grid, 64, 0, P.stream>>>(A);
         else
-            level_reduce_kernel<<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+            level_reduce_kernel<PT><<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
@@ -553,15 +562,23 @@ static void level_launch(Pipeline &P, int d, LevelArgs A)
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
         if (small_upd && R == 2)
-            level_update_small_kernel<2><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<PT, 2><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else if (small_upd && R == 4)
-            level_update_small_kernel<4><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<PT, 4><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else if (small_upd && R == 8)
-            level_update_small_kernel<8><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
+            level_update_small_kernel<PT, 8><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else
-            level_update_kernel<<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+            level_update_kernel<PT><<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
     }
     HIP_TRY(hipGetLastError());
+}
+
+static void level_launch(Pipeline &P, int d, LevelArgs A)
+{
+    if (P.plan->f32())
+        level_launch_t<float>(P, d, A);
+    else
+        level_launch_t<double>(P, d, A);
 }
 
 void run_levels_factor(Pipeline &P)

@@ -11,7 +11,8 @@ namespace hodlr {
 
 constexpr int FIN_BLOCKS = 512;
 
-__global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const double *b,
+template <typename PT>
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const PT *b,
                                                           int64_t n, double *part, BatchArgs B)
 {
     const int it = blockIdx.z;
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
     part = ioff(part, B, it);
     double s = 0.0;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        s += a[i] * b[i];
+        s += a[i] * (double)b[i];
     s = wave_sum(s);
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0)
@@ -81,8 +82,13 @@ void run_finish(Pipeline &P, const double *y, double *d_out, int ostride)
     int ndp = 0;
     ProfScope ps(P.stream, PS_FINISH);
     if (y) {
-        dot_partial_kernel<<<dim3(FIN_BLOCKS, 1, P.nitems), 256, 0, P.stream>>>(
-            y, wsp<double>(P, P.lay.Xt), p.n, dpart, P.batch);
+        const dim3 g(FIN_BLOCKS, 1, P.nitems);
+        if (p.f32())
+            dot_partial_kernel<float><<<g, 256, 0, P.stream>>>(y, wsp<float>(P, P.lay.Xt), p.n,
+                                                               dpart, P.batch);
+        else
+            dot_partial_kernel<double><<<g, 256, 0, P.stream>>>(y, wsp<double>(P, P.lay.Xt), p.n,
+                                                                dpart, P.batch);
         ndp = FIN_BLOCKS;
     }
     finish_kernel<<<dim3(1, 1, P.nitems), 256, 0, P.stream>>>(
@@ -134,6 +140,104 @@ void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, 
     ProfScope ps(s, PS_MATVEC);
     matvec_kernel<<<blocks, MV_T, 0, s>>>(n, kp, x, v, out);
     HIP_TRY(hipGetLastError());
+}
+
+// ----------------------------------------------------- iterative refinement
+// Helpers of x_{k+1} = x_k + H^{-1} (y - C x_k): the residual is scaled to
+// unit norm before it enters the (possibly FP32) solve vector, and the
+// correction is accumulated into the FP64 iterate.
+template <typename PT>
+__global__ void cast_scaled_kernel(const double *__restrict__ r, double inv, PT *__restrict__ z,
+                                   int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        z[i] = (PT)(r[i] * inv);
+}
+
+template <typename PT>
+__global__ void axpy_kernel(double *__restrict__ x, double s, const PT *__restrict__ z, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        x[i] += s * (double)z[i];
+}
+
+template <typename PT>
+__global__ void widen_kernel(const PT *__restrict__ z, double *__restrict__ out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = (double)z[i];
+}
+
+__global__ void sub_kernel(const double *__restrict__ y, const double *__restrict__ cx,
+                           double *__restrict__ r, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        r[i] = y[i] - cx[i];
+}
+
+__global__ __launch_bounds__(256) void sumsq_kernel(const double *__restrict__ v, int64_t n,
+                                                    double *part)
+{
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += v[i] * v[i];
+    s = wave_sum(s);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 2048); }
+
+void run_cast_scaled(const double *r, double inv, void *z, bool f32, int64_t n, hipStream_t s)
+{
+    if (f32)
+        cast_scaled_kernel<float><<<grid_for(n), 256, 0, s>>>(r, inv, (float *)z, n);
+    else
+        cast_scaled_kernel<double><<<grid_for(n), 256, 0, s>>>(r, inv, (double *)z, n);
+    HIP_TRY(hipGetLastError());
+}
+
+void run_axpy(double *x, double a, const void *z, bool f32, int64_t n, hipStream_t s)
+{
+    if (f32)
+        axpy_kernel<float><<<grid_for(n), 256, 0, s>>>(x, a, (const float *)z, n);
+    else
+        axpy_kernel<double><<<grid_for(n), 256, 0, s>>>(x, a, (const double *)z, n);
+    HIP_TRY(hipGetLastError());
+}
+
+void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s)
+{
+    if (f32)
+        widen_kernel<float><<<grid_for(n), 256, 0, s>>>((const float *)z, out, n);
+    else
+        widen_kernel<double><<<grid_for(n), 256, 0, s>>>((const double *)z, out, n);
+    HIP_TRY(hipGetLastError());
+}
+
+void run_sub(const double *y, const double *cx, double *r, int64_t n, hipStream_t s)
+{
+    sub_kernel<<<grid_for(n), 256, 0, s>>>(y, cx, r, n);
+    HIP_TRY(hipGetLastError());
+}
+
+// sum of squares, partials summed on the host in a fixed order (synchronizes)
+double run_sumsq(const double *v, int64_t n, double *part, hipStream_t s)
+{
+    const unsigned g = 512;
+    sumsq_kernel<<<g, 256, 0, s>>>(v, n, part);
+    HIP_TRY(hipGetLastError());
+    double h[512];
+    HIP_TRY(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (unsigned i = 0; i < g; ++i)
+        t += h[i];
+    return t;
 }
 
 }  // namespace hodlr
