@@ -32,27 +32,28 @@ METRIC = "GP log-likelihoods/s (factor+logdet+solve) at n=2^20; mixed vs FP64 at
 PEAK = {"hbm": 8000.0, "alu_fp64": 78.6, "alu_fp32": 157.3}   # GB/s, TFLOP/s, TFLOP/s
 
 
-def kernel_model(n, leaf_sizes, r, cnt):
+def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     """Algorithmic FLOPs and HBM bytes per call for each kernel kind.
 
     leaf_sizes: sizes of the leaves; r[j]: columns of the depth-j panel
     (j = 1..L); cnt[d] = 1 + sum_{j<=d} r[j] (columns still updated at depth d
-    plus the right-hand side).  Bytes count each FP64 operand moved once.
+    plus the right-hand side).  Bytes count each panel operand moved once
+    (esz bytes per entry: 8 in the FP64 form, 4 in the mixed form).
     """
     L = len(cnt) - 1
     m = np.asarray(leaf_sizes, dtype=np.float64)
     out = {}
     # leaves: Cholesky m^3/3, two triangular solves on cnt[L] columns
     flops = float(np.sum(m ** 3 / 3.0 + 2.0 * m * m * cnt[L]))
-    byts = 8.0 * n * (2 * cnt[L])
+    byts = esz * n * (2 * cnt[L])
     out["leaf_factor"] = (flops, byts)
     fr = br = fu = bu = 0.0
     for d in range(L):
         rr = r[d + 1]
         fr += 2.0 * rr * cnt[d + 1] * n
-        br += 8.0 * n * (cnt[d + 1] + rr)
+        br += esz * n * (cnt[d + 1] + rr)
         fu += 2.0 * rr * cnt[d] * n
-        bu += 8.0 * n * (2 * cnt[d] + rr)
+        bu += esz * n * (2 * cnt[d] + rr)
     out["level_reduce"] = (fr, br)
     out["level_update"] = (fu, bu)
     return out
@@ -100,6 +101,9 @@ def main():
                          "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18")
     ap.add_argument("--mcmc-steps", type=int, default=300)
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: FP32 basis panels, FP64 leaves / coupling LU / log-det sums "
+                         "(matern1d, batched_theta, ragged)")
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -125,7 +129,9 @@ def main():
     t_order = time.perf_counter() - t0
     xs = p.x[perm]
     ys = p.y[perm]
-    opts = H.Opts(max_rank=64)
+    mixed = args.precision == "mixed"
+    prec = H.MIXED if mixed else H.FP64
+    opts = H.Opts(max_rank=64, precision=prec)
     plan = H.Plan(p.n, p.dim, p.leaf, opts)
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
     d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
@@ -154,7 +160,7 @@ def main():
 
     # ranks for the algorithmic model (one untimed build on the same data)
     f = H.hodlr_build(xs, p.kernel, p.theta, p.sigma2, p.leaf, p.tol,
-                      H.Opts(max_rank=64, presorted=1))
+                      H.Opts(max_rank=64, presorted=1, precision=prec))
     info = f.info()
     f.free()
     L = info["levels"]
@@ -164,7 +170,7 @@ def main():
         cnt.append(cnt[-1] + r[j])
     nl = 1 << L
     leaf_sizes = np.diff(np.linspace(0, p.n, nl + 1).round()).astype(int) if L else [p.n]
-    model = kernel_model(p.n, leaf_sizes, r, cnt)
+    model = kernel_model(p.n, leaf_sizes, r, cnt, esz=4 if mixed else 8)
 
     stages = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(stages, key=lambda k: stages[k][0])
@@ -190,11 +196,14 @@ def main():
     res = {
         "metric": METRIC, "value": args.steps / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 arithmetic, f32 panels" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "matern32_1d_n%d_leaf%d_tol%g" % (p.n, p.leaf, p.tol), "n": p.n,
+        "config": {"workload": "matern32_1d_n%d_leaf%d_tol%g%s" % (p.n, p.leaf, p.tol,
+                                                                     "_mixed" if mixed else ""),
+                   "n": p.n,
                    "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
-                   "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": "fp64",
+                   "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": args.precision,
                    "levels": L, "rank_max": r[1:]},
         "roofline": roofline,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
@@ -218,7 +227,8 @@ def bench_batched(args, torch, H, wl, dev):
     one step = one batched call (all items), captured stages replayed as a graph."""
     n, m = 65536, args.batch
     x, y, th = wl.batched_theta(m=m, n=n)
-    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16))
+    mixed = args.precision == "mixed"
+    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=H.MIXED if mixed else H.FP64))
     nb = plan.batch_workspace_bytes(m)
     d_x = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
     d_y = torch.from_numpy(y).to(dev)
@@ -244,11 +254,13 @@ def bench_batched(args, torch, H, wl, dev):
     res = {"metric": "GP log-likelihoods/s, batched hyperparameters (n=65536 shared series)",
            "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64",
            "data": "synthetic",
-           "config": {"workload": "batched_theta_m%d_n%d" % (m, n), "n": n, "items": m,
+           "config": {"workload": "batched_theta_m%d_n%d%s" % (m, n, "_mixed" if mixed else ""),
+                      "n": n, "items": m,
                       "kernel": "matern32", "leaf": 128, "tol": 1e-10, "max_rank": 16,
-                      "graph": True},
+                      "graph": True, "precision": args.precision},
            "finite_items": int(np.isfinite(o[:, 0]).sum())}
     print(json.dumps(res), flush=True)
 
@@ -261,7 +273,8 @@ def bench_ragged(args, torch, H, wl, dev):
     observations are inside the timed region)."""
     m = 512
     xs, ys, th = wl.batched_ragged(m=m)
-    opts = H.Opts(max_rank=16)
+    mixed = args.precision == "mixed"
+    opts = H.Opts(max_rank=16, precision=H.MIXED if mixed else H.FP64)
 
     def step():
         return H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 128, 1e-10, opts, args.workers)
@@ -278,9 +291,11 @@ def bench_ragged(args, torch, H, wl, dev):
     res = {"metric": "GP log-likelihoods/s, independent series of uneven size",
            "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64",
            "data": "synthetic",
-           "config": {"workload": "ragged_m%d_n1024to131072" % m, "items": m,
+           "config": {"workload": "ragged_m%d_n1024to131072%s" % (m, "_mixed" if mixed else ""),
+                      "items": m, "precision": args.precision,
                       "total_points": ntot, "kernel": "matern32", "leaf": 128, "tol": 1e-10,
                       "max_rank": 16, "workers": args.workers, "host_buffers": True},
            "points_per_s": args.steps * ntot / elapsed,

@@ -72,10 +72,10 @@ enum { HODLR_FP64 = 0, HODLR_MIXED = 1 };
 typedef struct {
     int32_t max_rank;    /* per off-diagonal block rank cap (default 64); a hit cap is
                             counted in hodlr_info, not an error                       */
-    int32_t precision;   /* HODLR_FP64 (default) or HODLR_MIXED: the basis panels W, W~
-                            and the solve vector stored in FP32 (the compression and
-                            the panel updates compute in FP64 registers and round on
-                            store; compression tolerance at least 1e-6);
+    int32_t precision;   /* HODLR_FP64 (default) or HODLR_MIXED: the applied bases
+                            W~ = (block inverses) W and the solve vector stored in
+                            FP32 (updates computed in FP64 registers, rounded on
+                            store); compression, bases W,
                             leaf Cholesky factors, coupling-matrix LU and every log-det
                             sum in FP64.  hodlr_solve and gp_loglik then refine against
                             the exact FP64 product (hodlr_matvec_dev); gp_loglik_dev and
@@ -204,7 +204,8 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
  * stream and one device arena sized for the largest item, and take items
  * largest first.  out receives 3 doubles per item {loglik, logdet, quad}; an
  * item that is invalid or whose factorization fails gets NaNs and does not
- * stop the others.  All pointers are host memory owned by the caller; the
+ * stop the others (mixed precision: the quadratic form is unrefined, as in
+ * gp_loglik_dev).  All pointers are host memory owned by the caller; the
  * call returns when every item is done.  Errors: EINVAL (shared arguments),
  * EDEVICE (the device failed; items not reached hold NaN or are untouched). */
 hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const double *const *xs,

@@ -13,10 +13,6 @@
 //   stop when |u| |v| <= tol ||S||_F or at the rank cap; otherwise the next
 //   pivot row is the first argmax |u| over unused rows.
 //
-// The panel is FP64, or FP32 in the mixed form; entries and residuals are
-// always computed in FP64 and rounded when stored, so the noise floor of the
-// FP32 form is its storage rounding.
-//
 // Two paths, no communication between work-groups inside a launch (on this
 // chip the L2 caches of the eight dies are not coherent, so intra-launch
 // hand-offs would need device-wide cache write-backs):
@@ -40,7 +36,7 @@ struct AcaArgs {
     int64_t n;
     KParams kp;
     double tol;
-    void *W;   // panel: double, or float in the mixed form
+    double *W;
     const int64_t *start, *end;
     const int64_t *cofa;
     int cap;
@@ -101,7 +97,6 @@ struct SmallArgs {
     int *status;        // per node AcaDone
 };
 
-template <typename PT>
 __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
 {
     const AcaArgs &A = S.a;
@@ -110,10 +105,10 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
     const int64_t na = m - s, nb = e - m, n = A.n;
     const int64_t col0 = A.cofa[depth_of_node(h) + 1];
-    PT *__restrict__ W = (PT *)A.W;
+    double *__restrict__ W = A.W;
     __shared__ double rv[4], rs[4], red[4];
     __shared__ int64_t ri[4];
-    __shared__ PT sfix[RMAX_ABS];
+    __shared__ double sfix[RMAX_ABS];
     __shared__ double vdot[RMAX_ABS];
     __shared__ unsigned char used[ACA_SMALL];
     const int64_t full = na < nb ? na : nb;
@@ -125,7 +120,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
     int k = 0, zeros = 0, nused = 0, done = (cap <= 0) ? ACA_EXHAUSTED : ACA_ACTIVE;
     int64_t istar = na - 1;
     double s2 = 0.0;
-    PT uv[SM_EPT];
+    double uv[SM_EPT];
     while (done == ACA_ACTIVE) {
         // residual row at i*
         // (written by other threads of this work-group: read past the L1)
@@ -137,12 +132,12 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
 #pragma unroll
         for (int t = 0; t < SM_EPT; ++t) {
             int64_t j = tid + (int64_t)t * ACA_THREADS;
-            uv[t] = PT(0);
+            uv[t] = 0.0;
             if (j < nb) {
                 double a = kentry(A.kp, A.x, n, s + istar, m + j);
                 for (int l = 0; l < k; ++l)
-                    a -= (double)sfix[l] * (double)W[(col0 + l) * n + m + j];
-                W[(col0 + k) * n + m + j] = (PT)a;
+                    a -= sfix[l] * W[(col0 + l) * n + m + j];
+                W[(col0 + k) * n + m + j] = a;
                 uv[t] = a;
                 sq += a * a;
                 if (fabs(a) > bv) {
@@ -196,13 +191,13 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
 #pragma unroll
         for (int t = 0; t < SM_EPT; ++t) {
             int64_t i = tid + (int64_t)t * ACA_THREADS;
-            uv[t] = PT(0);
+            uv[t] = 0.0;
             if (i < na) {
                 double a = kentry(A.kp, A.x, n, s + i, m + jstar);
                 for (int l = 0; l < k; ++l)
-                    a -= (double)sfix[l] * (double)W[(col0 + l) * n + s + i];
+                    a -= sfix[l] * W[(col0 + l) * n + s + i];
                 a = a / delta;
-                W[(col0 + k) * n + s + i] = (PT)a;
+                W[(col0 + k) * n + s + i] = a;
                 uv[t] = a;
                 sq += a * a;
                 if (!used[i] && fabs(a) > bv) {
@@ -248,7 +243,6 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
 // every internal node of every batch item (item = blockIdx.z).  Used rows are
 // kept as a list in LDS; the dots with earlier terms re-read the panel
 // entries the same thread wrote.
-template <typename PT>
 __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, BatchArgs B, int *rank0,
                                                                int *status0)
 {
@@ -256,7 +250,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
     const int64_t h = blockIdx.x;
     const int tid = threadIdx.x;
     const KParams kp = item_kp(A0.kp, B, it);
-    PT *__restrict__ W = ioff((PT *)A0.W, B, it);
+    double *__restrict__ W = ioff(A0.W, B, it);
     int *rank = ioff(rank0, B, it);
     int *status = ioff(status0, B, it);
     const int64_t s = A0.start[h], e = A0.end[h], m = s + (e - s) / 2;
@@ -264,7 +258,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
     const int64_t col0 = A0.cofa[depth_of_node(h) + 1];
     __shared__ double rv[4], rs[4], red[4];
     __shared__ int64_t ri[4];
-    __shared__ PT sfix[RMAX_ABS];
+    __shared__ double sfix[RMAX_ABS];
     __shared__ double vdot[RMAX_ABS];
     __shared__ int usedl[USED_MAX];
     const int64_t full = na < nb ? na : nb;
@@ -282,8 +276,8 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
         for (int64_t j = tid; j < nb; j += ACA_THREADS) {
             double a = kentry(kp, A0.x, n, s + istar, m + j);
             for (int l = 0; l < k; ++l)
-                a -= (double)sfix[l] * (double)W[(col0 + l) * n + m + j];
-            W[(col0 + k) * n + m + j] = (PT)a;
+                a -= sfix[l] * W[(col0 + l) * n + m + j];
+            W[(col0 + k) * n + m + j] = a;
             sq += a * a;
             if (fabs(a) > bv) {
                 bv = fabs(a);
@@ -335,9 +329,9 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
         for (int64_t i = tid; i < na; i += ACA_THREADS) {
             double a = kentry(kp, A0.x, n, s + i, m + jstar);
             for (int l = 0; l < k; ++l)
-                a -= (double)sfix[l] * (double)W[(col0 + l) * n + s + i];
+                a -= sfix[l] * W[(col0 + l) * n + s + i];
             a = a / delta;
-            W[(col0 + k) * n + s + i] = (PT)a;
+            W[(col0 + k) * n + s + i] = a;
             sq += a * a;
             bool elig = true;
             for (int q = 0; q < nused && q < USED_MAX; ++q)
@@ -412,12 +406,11 @@ __global__ __launch_bounds__(256) void aca_batch_stats_kernel(const int *rank0, 
 }
 
 // zero panel columns [rank, rmax_all) of every block of every item
-template <typename PT>
-__global__ void aca_batch_pad_kernel(PT *W0, int64_t n, const Chunk *chunks, const int *rank0,
+__global__ void aca_batch_pad_kernel(double *W0, int64_t n, const Chunk *chunks, const int *rank0,
                                      const int *rmax_all, const int64_t *cofa, BatchArgs B)
 {
     const int it = blockIdx.z;
-    PT *W = ioff(W0, B, it);
+    double *W = ioff(W0, B, it);
     const int *rank = ioff(rank0, B, it);
     const Chunk ch = chunks[blockIdx.x];
     int d = depth_of_node(ch.node);
@@ -425,7 +418,7 @@ __global__ void aca_batch_pad_kernel(PT *W0, int64_t n, const Chunk *chunks, con
     int64_t col0 = cofa[d + 1];
     for (int c = r0; c < r1; ++c)
         for (int64_t g = ch.lo + threadIdx.x; g < ch.hi; g += blockDim.x)
-            W[(col0 + c) * n + g] = PT(0);
+            W[(col0 + c) * n + g] = 0.0;
 }
 
 // Batched compression: one launch for every block of every item, then the
@@ -451,8 +444,8 @@ void run_aca_batched(Pipeline &P)
     A.x = P.x;
     A.n = p.n;
     A.kp = P.kp;
-    A.tol = p.f32() ? std::max(P.tol, ACA_TOL_F32) : P.tol;
-    A.W = P.ws + P.lay.W;
+    A.tol = P.tol;
+    A.W = wsp<double>(P, P.lay.W);
     A.start = p.d_start;
     A.end = p.d_end;
     A.cofa = d_cofa;
@@ -461,12 +454,8 @@ void run_aca_batched(Pipeline &P)
     int *status = wsp<int>(P, P.lay.aca_status);
     {
         ProfScope ps(s, PS_ACA_SMALL);
-        if (p.f32())
-            aca_block_kernel<float><<<dim3((unsigned)p.nint, 1, P.nitems), ACA_THREADS, 0, s>>>(
-                A, P.batch, rank, status);
-        else
-            aca_block_kernel<double><<<dim3((unsigned)p.nint, 1, P.nitems), ACA_THREADS, 0, s>>>(
-                A, P.batch, rank, status);
+        aca_block_kernel<<<dim3((unsigned)p.nint, 1, P.nitems), ACA_THREADS, 0, s>>>(A, P.batch, rank,
+                                                                                 status);
     }
     {
         ProfScope ps(s, PS_ACA_MISC);
@@ -482,15 +471,8 @@ void run_aca_batched(Pipeline &P)
     P.capped = host[64];
     ProfScope ps(s, PS_ACA_MISC);
     if (!p.pad_chunks.empty())
-    {
-        const dim3 g((unsigned)p.pad_chunks.size(), 1, P.nitems);
-        if (p.f32())
-            aca_batch_pad_kernel<float><<<g, 256, 0, s>>>((float *)A.W, p.n, p.d_pad_chunks, rank,
-                                                          d_rmax_all, d_cofa, P.batch);
-        else
-            aca_batch_pad_kernel<double><<<g, 256, 0, s>>>((double *)A.W, p.n, p.d_pad_chunks,
-                                                           rank, d_rmax_all, d_cofa, P.batch);
-    }
+        aca_batch_pad_kernel<<<dim3((unsigned)p.pad_chunks.size(), 1, P.nitems), 256, 0, s>>>(
+            A.W, p.n, p.d_pad_chunks, rank, d_rmax_all, d_cofa, P.batch);
     HIP_TRY(hipGetLastError());
 }
 
@@ -567,7 +549,7 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
     block_argmax(bv, bi, bs, rv, ri, rs);   // ends with a barrier: dots[] visible
 }
 
-template <typename PT, bool ROW>
+template <bool ROW>
 __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 {
     const AcaArgs &A = B.a;
@@ -577,7 +559,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     __shared__ double rv[4], rs[4], red[4];
     __shared__ int64_t ri[4];
-    __shared__ PT sfix[RMAX_ABS];
+    __shared__ double sfix[RMAX_ABS];
     __shared__ double dots[RMAX_ABS + 1];
     __shared__ double sdot[4][RMAX_ABS + 1];
     __shared__ int sused[USED_MAX];
@@ -586,7 +568,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     const int64_t na = m - s, n = A.n;
     const bool lead = ch.lo == (ROW ? m : s);   // the block's first chunk writes its state
     const int64_t col0 = A.cofa[depth_of_node(h) + 1];
-    PT *__restrict__ W = (PT *)A.W;
+    double *__restrict__ W = A.W;
     int *used = B.used + (int64_t)b * USED_MAX;
     const double *prec = B.pin + (int64_t)B.pbase[b] * B.pw;
     const int pn = B.pnch[b];
@@ -630,18 +612,18 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         for (int l = tid; l < k; l += ACA_THREADS)
             sfix[l] = W[(col0 + l) * n + fix];
         __syncthreads();
-        PT val[ACA_EPT];
+        double val[ACA_EPT];
         double bv = -1.0, bs = 0.0, sq = 0.0;
         int64_t bi = INT64_MAX;
 #pragma unroll
         for (int q = 0; q < ACA_EPT; ++q) {
             int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-            val[q] = PT(0);
+            val[q] = 0.0;
             if (g < ch.hi) {
                 double a = kentry(A.kp, A.x, n, fix, g);
                 for (int l = 0; l < k; ++l)
-                    a -= (double)sfix[l] * (double)W[(col0 + l) * n + g];
-                W[(col0 + k) * n + g] = (PT)a;
+                    a -= sfix[l] * W[(col0 + l) * n + g];
+                W[(col0 + k) * n + g] = a;
                 val[q] = a;
                 sq += a * a;
                 if (fabs(a) > bv) {
@@ -724,19 +706,19 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     for (int l = tid; l < k; l += ACA_THREADS)
         sfix[l] = W[(col0 + l) * n + fix];
     __syncthreads();
-    PT val[ACA_EPT];
+    double val[ACA_EPT];
     double cv = -1.0, cs = 0.0, sq = 0.0;
     int64_t ci = INT64_MAX;
 #pragma unroll
     for (int q = 0; q < ACA_EPT; ++q) {
         int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-        val[q] = PT(0);
+        val[q] = 0.0;
         if (g < ch.hi) {
             double a = kentry(A.kp, A.x, n, g, fix);
             for (int l = 0; l < k; ++l)
-                a -= (double)sfix[l] * (double)W[(col0 + l) * n + g];
+                a -= sfix[l] * W[(col0 + l) * n + g];
             a = a / t.delta;
-            W[(col0 + k) * n + g] = (PT)a;
+            W[(col0 + k) * n + g] = a;
             val[q] = a;
             sq += a * a;
             int li = (int)(g - s);
@@ -818,8 +800,7 @@ __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const i
 }
 
 // zero columns [rank, rmax) of the panel on the rows of each chunk's block
-template <typename PT>
-__global__ void aca_pad_kernel(PT *W, int64_t n, const Chunk *chunks, const int *rank,
+__global__ void aca_pad_kernel(double *W, int64_t n, const Chunk *chunks, const int *rank,
                                const int *rmax, const int64_t *cofa)
 {
     const Chunk ch = chunks[blockIdx.x];
@@ -828,7 +809,7 @@ __global__ void aca_pad_kernel(PT *W, int64_t n, const Chunk *chunks, const int 
     int64_t col0 = cofa[d + 1];
     for (int c = r0; c < r1; ++c)
         for (int64_t g = ch.lo + threadIdx.x; g < ch.hi; g += blockDim.x)
-            W[(col0 + c) * n + g] = PT(0);
+            W[(col0 + c) * n + g] = 0.0;
 }
 
 // 64 pinned ints per host thread, allocated on first use and released when
@@ -869,8 +850,8 @@ void run_aca(Pipeline &P)
     A.x = P.x;
     A.n = p.n;
     A.kp = P.kp;
-    A.tol = p.f32() ? std::max(P.tol, ACA_TOL_F32) : P.tol;
-    A.W = P.ws + P.lay.W;
+    A.tol = P.tol;
+    A.W = wsp<double>(P, P.lay.W);
     A.start = p.d_start;
     A.end = p.d_end;
     A.cofa = d_cofa;
@@ -890,10 +871,7 @@ void run_aca(Pipeline &P)
         S.rank = rank;
         S.status = status;
         ProfScope ps(s, PS_ACA_SMALL);
-        if (p.f32())
-            aca_small_kernel<float><<<(unsigned)p.aca_small.size(), ACA_THREADS, 0, s>>>(S);
-        else
-            aca_small_kernel<double><<<(unsigned)p.aca_small.size(), ACA_THREADS, 0, s>>>(S);
+        aca_small_kernel<<<(unsigned)p.aca_small.size(), ACA_THREADS, 0, s>>>(S);
         HIP_TRY(hipGetLastError());
     }
     const int nbig = (int)p.aca_big.size();
@@ -935,17 +913,11 @@ void run_aca(Pipeline &P)
         for (; it < max_iter; ++it) {
             {
                 ProfScope ps(s, PS_ACA_ROW);
-                if (p.f32())
-                    aca_big_pass_kernel<float, true><<<nrow, ACA_THREADS, 0, s>>>(R);
-                else
-                    aca_big_pass_kernel<double, true><<<nrow, ACA_THREADS, 0, s>>>(R);
+                aca_big_pass_kernel<true><<<nrow, ACA_THREADS, 0, s>>>(R);
             }
             {
                 ProfScope ps(s, PS_ACA_COL);
-                if (p.f32())
-                    aca_big_pass_kernel<float, false><<<ncol, ACA_THREADS, 0, s>>>(C);
-                else
-                    aca_big_pass_kernel<double, false><<<ncol, ACA_THREADS, 0, s>>>(C);
+                aca_big_pass_kernel<false><<<ncol, ACA_THREADS, 0, s>>>(C);
             }
             HIP_TRY(hipGetLastError());
             // a converged block is counted by the row pass that absorbs its last
@@ -980,15 +952,8 @@ void run_aca(Pipeline &P)
     // zero the padding columns of every block below its panel's maximum rank
     ProfScope ps(s, PS_ACA_MISC);
     if (!p.pad_chunks.empty())
-    {
-        const unsigned g = (unsigned)p.pad_chunks.size();
-        if (p.f32())
-            aca_pad_kernel<float><<<g, 256, 0, s>>>((float *)A.W, p.n, p.d_pad_chunks, rank, d_rmax,
-                                                    d_cofa);
-        else
-            aca_pad_kernel<double><<<g, 256, 0, s>>>((double *)A.W, p.n, p.d_pad_chunks, rank,
-                                                     d_rmax, d_cofa);
-    }
+        aca_pad_kernel<<<(unsigned)p.pad_chunks.size(), 256, 0, s>>>(A.W, p.n, p.d_pad_chunks,
+                                                                      rank, d_rmax, d_cofa);
     HIP_TRY(hipGetLastError());
 }
 

@@ -17,10 +17,6 @@ namespace hodlr {
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
 constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (large blocks)
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
-// Smallest relative tolerance the FP32 cross approximation can meet: its
-// residual entries carry rounding noise near 1e-7 of the block, and a
-// tighter request would keep adding noise terms up to the rank cap.
-constexpr double ACA_TOL_F32 = 1e-6;
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
 constexpr int LVL_ROWS = 512;     // rows per level work-group
@@ -192,10 +188,6 @@ __device__ __forceinline__ double ld_coherent(const double *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ float ld_coherent(const float *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ int ld_coherent(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -275,7 +267,8 @@ struct Plan {
         return d;
     }
     int64_t first_at(int d) const { return ((int64_t)1 << d) - 1; }
-    // the mixed form keeps the basis panels W, W~ (and the solve vector) in FP32
+    // the mixed form keeps the applied-basis panel W~ (and the solve vector) in
+    // FP32; the compressed bases W stay FP64
     bool f32() const { return precision == HODLR_MIXED; }
     size_t panel_bytes() const { return f32() ? sizeof(float) : sizeof(double); }
 };

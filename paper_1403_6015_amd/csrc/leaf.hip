@@ -20,8 +20,8 @@ struct LeafArgs {
     KParams kp;
     const int64_t *start, *end;
     int64_t leaf0;          // heap index of the first leaf
-    const void *W;          // original bases (source columns; float in the mixed form)
-    void *Xt;               // destination columns (same type)
+    const double *W;        // original bases (source columns)
+    void *Xt;               // destination columns (float in the mixed form)
     const double *y;        // right-hand side for column 0 (nullable)
     const int *cols;
     int ncols, cbeg;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     const int l = tid & 63, r = l & 15, q = l >> 4;
     const int it = blockIdx.z;   // batch item
     const KParams kp = item_kp(A.kp, A.B, it);
-    const PT *__restrict__ Wsrc = ioff((const PT *)A.W, A.B, it);
+    const double *__restrict__ Wsrc = ioff(A.W, A.B, it);
     PT *__restrict__ Xdst = ioff((PT *)A.Xt, A.B, it);
     double *leaf_ld = ioff(A.leaf_ld, A.B, it);
     int *status = ioff(A.status, A.B, it);
@@ -355,14 +355,10 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     for (int c0 = A.cbeg + 16 * wid; c0 < A.ncols; c0 += 16 * LEAF_MW) {
         const int nb = min(16, A.ncols - c0);
         const int cr = c0 + r;
-        const double *srcy = nullptr;   // column 0: the FP64 right-hand side
-        const PT *src = nullptr;
+        const double *src = nullptr;
         if (r < nb) {
             int col = A.cols[cr];
-            if (col == 0)
-                srcy = ysrc + s;
-            else
-                src = Wsrc + (int64_t)col * n + s;
+            src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
         }
         d4 X[NT_MAX];
 #pragma unroll
@@ -370,8 +366,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 int i = 16 * I + q + 4 * t;
-                X[I][t] = (I < nt && i < m) ? (srcy ? srcy[i] : src ? (double)src[i] : 0.0)
-                                            : 0.0;
+                X[I][t] = (src && I < nt && i < m) ? src[i] : 0.0;
             }
 #pragma unroll
         for (int J = 0; J < NT_MAX; ++J) {
@@ -442,7 +437,7 @@ static LeafArgs leaf_args(Pipeline &P)
     A.start = p.d_start;
     A.end = p.d_end;
     A.leaf0 = p.nint;
-    A.W = P.ws + P.lay.W;
+    A.W = wsp<double>(P, P.lay.W);
     A.Xt = P.ws + P.lay.Xt;
     A.y = nullptr;
     A.cols = wsp<int>(P, P.lay.cols);

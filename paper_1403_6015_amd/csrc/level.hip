@@ -33,8 +33,8 @@ constexpr int LV_CB = 32;    // right-hand sides per batch in the node solve
 
 struct LevelArgs {
     int64_t n;
-    const void *W;     // panels: double, or float in the mixed form
-    void *Xt;
+    const double *W;   // compressed bases
+    void *Xt;          // applied bases: double, or float in the mixed form
     const int *cols;
     int ncnt;          // columns entering the reduction (prefix of cols)
     int nrhs;          // columns updated (prefix of cols)
@@ -77,7 +77,7 @@ template <typename PT>
 __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
-    const PT *__restrict__ Wp = (const PT *)A.W;
+    const double *__restrict__ Wp = A.W;
     const PT *__restrict__ Xp = (const PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
             const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
             for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
                 int l = idx / LV_RT, i = idx % LV_RT;
-                sW[i][l] = (i < nr) ? (double)Wp[(A.colW + l) * n + i0 + i] : 0.0;
+                sW[i][l] = (i < nr) ? Wp[(A.colW + l) * n + i0 + i] : 0.0;
             }
             for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
                 int c = idx / LV_RT, i = idx % LV_RT;
@@ -140,7 +140,7 @@ template <typename PT, int R>
 __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
-    const PT *__restrict__ Wp = (const PT *)A.W;
+    const double *__restrict__ Wp = A.W;
     const PT *__restrict__ Xp = (const PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
         ok[t] = i < ch.hi;
 #pragma unroll
         for (int l = 0; l < R; ++l)
-            w[t][l] = (ok[t] && l < r) ? (double)Wp[(A.colW + l) * n + i] : 0.0;
+            w[t][l] = (ok[t] && l < r) ? Wp[(A.colW + l) * n + i] : 0.0;
     }
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
     constexpr int CU = 4;   // columns per iteration: more loads in flight
@@ -513,7 +513,7 @@ static LevelArgs level_args(Pipeline &P, int d)
     const Plan &p = *P.plan;
     LevelArgs A;
     A.n = p.n;
-    A.W = P.ws + P.lay.W;
+    A.W = wsp<double>(P, P.lay.W);
     A.Xt = P.ws + P.lay.Xt;
     A.cols = wsp<int>(P, P.lay.cols);
     A.colW = p.cofa[d + 1];

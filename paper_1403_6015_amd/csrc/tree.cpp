@@ -313,7 +313,7 @@ Layout make_layout(const Plan &p, bool store_leaf)
     for (int j = 1; j <= L; ++j)
         capmax = std::max(capmax, p.capj[j]);
     y.store_leaf = store_leaf;
-    y.W = take(p.panel_bytes() * (size_t)n * (size_t)p.ncol);
+    y.W = take(sizeof(double) * (size_t)n * (size_t)p.ncol);
     y.Xt = take(p.panel_bytes() * (size_t)n * (size_t)p.ncol);
     int64_t lm = p.leafmax;
     y.G = take(store_leaf ? sizeof(double) * (size_t)p.nleaf * (size_t)(lm * (lm + 1) / 2) : 8);
