@@ -148,6 +148,7 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
         return;
     const int lane = threadIdx.x;
     const int64_t n = A.n;
+    __shared__ double red[64 * (4 * R + 1)];
     double w[LV_SROWS][R];
     bool ok[LV_SROWS];
 #pragma unroll
@@ -184,14 +185,39 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
                 }
             }
         }
+        // cross-lane sums of the CU*R accumulators through LDS: each output
+        // gets 64/(CU*R) lanes (or one lane several outputs), then a few
+        // shuffles, instead of one full wave reduction per output
+        constexpr int NO = CU * R;
 #pragma unroll
         for (int u = 0; u < CU; ++u)
 #pragma unroll
-            for (int l = 0; l < R; ++l) {
-                double v = wave_sum(acc[u][l]);
-                if (lane == 0 && l < r && c0 + u < cend)
-                    rec[(int64_t)l * A.ncnt + c0 + u] = v;
+            for (int l = 0; l < R; ++l)
+                red[lane * (NO + 1) + u * R + l] = acc[u][l];
+        __syncthreads();
+        if constexpr (NO <= 64) {
+            constexpr int G = 64 / NO;            // lanes per output (power of two)
+            const int o = lane / G, sub = lane % G;
+            double a = 0.0;
+            for (int q = sub; q < 64; q += G)
+                a += red[q * (NO + 1) + o];
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1)
+                a += __shfl_xor(a, off, 64);
+            const int u = o / R, l = o % R;
+            if (sub == 0 && l < r && c0 + u < cend)
+                rec[(int64_t)l * A.ncnt + c0 + u] = a;
+        } else {
+            for (int o = lane; o < NO; o += 64) {
+                double a = 0.0;
+                for (int q = 0; q < 64; ++q)
+                    a += red[q * (NO + 1) + o];
+                const int u = o / R, l = o % R;
+                if (l < r && c0 + u < cend)
+                    rec[(int64_t)l * A.ncnt + c0 + u] = a;
             }
+        }
+        __syncthreads();
     }
 }
 
