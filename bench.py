@@ -132,7 +132,15 @@ def main():
     mixed = args.precision == "mixed"
     prec = H.MIXED if mixed else H.FP64
     opts = H.Opts(max_rank=64, precision=prec)
-    plan = H.Plan(p.n, p.dim, p.leaf, opts)
+    # tiles from the autotuner at the workload's leaf size (untimed); the tuner
+    # is also run with the leaf size free, for information
+    t0 = time.perf_counter()
+    topts = H.Opts(max_rank=64, precision=prec, presorted=1)
+    tune, tune_ms = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, topts,
+                               leaf_cands=[p.leaf], reps=2)
+    free, free_ms = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, topts, reps=2)
+    t_tune = time.perf_counter() - t0
+    plan = H.Plan(p.n, p.dim, p.leaf, opts, tune=tune)
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
     d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
     work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
@@ -147,6 +155,18 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # per-kernel breakdown in a pass of its own (every launch timed), then the
+    # timed region with events around the dominant kernel only
+    H.profile_select(None)
+    H.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    breakdown = H.profile_read()
+    H.profile_enable(False)
+    stages = {k: v for k, v in breakdown.items() if v[1] > 0}
+    dom = max(stages, key=lambda k: stages[k][0])
+    H.profile_select([dom])
     H.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -156,6 +176,7 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = H.profile_read()
     H.profile_enable(False)
+    H.profile_select(None)
     loglik, logdet, quad = out[:3].cpu().tolist()
 
     # ranks for the algorithmic model (one untimed build on the same data)
@@ -172,19 +193,21 @@ def main():
     leaf_sizes = np.diff(np.linspace(0, p.n, nl + 1).round()).astype(int) if L else [p.n]
     model = kernel_model(p.n, leaf_sizes, r, cnt, esz=4 if mixed else 8)
 
-    stages = {k: v for k, v in prof.items() if v[1] > 0}
-    dom = max(stages, key=lambda k: stages[k][0])
-    dom_ms, dom_launches = stages[dom]
+    dom_ms, dom_launches = prof[dom]
     roofline = None
     if dom in model:
         flops, byts = model[dom]
         per_call_s = dom_ms / 1e3 / args.steps
         ai = flops / byts
         if ai > PEAK["alu_fp64"] * 1e12 / (PEAK["hbm"] * 1e9):
+            # above the ridge: the leaf kernel's products run on FP64 MFMA
+            # (dense FP64 matrix peak 78.6 TFLOP/s, the same figure as the
+            # vector FP64 peak on this chip)
+            bound = "mfma" if dom == "leaf_factor" else "alu"
             ach = flops / per_call_s / 1e12
-            roofline = {"bound": "alu", "achieved": ach, "peak": PEAK["alu_fp64"], "unit": "TFLOP/s",
-                        "frac": ach / PEAK["alu_fp64"], "traffic": None, "kernel": dom,
-                        "dtype": "fp64", "avg_launch_ms": dom_ms / dom_launches,
+            roofline = {"bound": bound, "achieved": ach, "peak": PEAK["alu_fp64"],
+                        "unit": "TFLOP/s", "frac": ach / PEAK["alu_fp64"], "traffic": None,
+                        "kernel": dom, "dtype": "fp64", "avg_launch_ms": dom_ms / dom_launches,
                         "algorithmic_per_call": {"flops": flops, "bytes": byts}}
         else:
             ach = byts / per_call_s / 1e9
@@ -204,11 +227,17 @@ def main():
                    "n": p.n,
                    "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
                    "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": args.precision,
-                   "levels": L, "rank_max": r[1:]},
+                   "levels": L, "rank_max": r[1:], "level_rows": tune.level_rows,
+                   "reduce_cols": tune.reduce_cols},
         "roofline": roofline,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "stage_launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+        "stage_note": "stage times from a separate pass with every launch timed; the timed "
+                      "region records events around %s only" % dom,
         "ordering_s": t_order,
+        "autotune": {"tiles_at_leaf": tune.as_dict(), "candidate_ms": tune_ms,
+                     "free_leaf_best": free.as_dict(), "free_leaf_ms": min(free_ms),
+                     "seconds": t_tune},
         "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
     }
     if not args.no_cpu_baseline and args.n == 1 << 20:

@@ -163,6 +163,39 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
                                hodlr_plan *out);
 void hodlr_plan_destroy(hodlr_plan p);
 
+/* Launch shape chosen by the autotuner: the leaf size (any leaf <= 128) and
+ * the level stage's tiles, rows per chunk (256, 512 or 1024) and columns per
+ * reduction step (4 or 8).  The method's result does not depend on the tiles;
+ * the leaf size changes the tree (and so the approximation) within the
+ * compression tolerance.                                                     */
+typedef struct {
+    int32_t leaf;
+    int32_t level_rows;
+    int32_t reduce_cols;
+} hodlr_tune_t;
+
+/* As hodlr_plan_create, with the leaf size and tiles from `tune`.           */
+hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *opts,
+                                     const hodlr_tune_t *tune, hodlr_plan *out);
+
+/* Times the whole likelihood on the caller's problem (host arrays as for
+ * gp_loglik) for each leaf size in leaf_cands (NULL/0: 32, 64, 96, 128) with
+ * the default tiles, then the six tile shapes at the fastest leaf; keeps the
+ * best of `reps` runs after a warm-up per candidate.  *best receives the
+ * fastest shape; times_ms (nullable, nleaf + 6 doubles, 4 + 6 for the
+ * defaults) the per-candidate times in that order.  The result is also cached
+ * per (ceil log2 n, dim, kernel, precision) for hodlr_tune_lookup.  Allocates
+ * and frees device memory per candidate.  Errors: EINVAL, ENOTSPD, ENOMEM,
+ * EDEVICE.                                                                   */
+hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
+                            const double theta[2], double sigma2, const double *y, double tol,
+                            const hodlr_opts *opts, const int32_t *leaf_cands, int32_t nleaf,
+                            int32_t reps, hodlr_tune_t *best, double *times_ms);
+/* The cached result of an earlier hodlr_autotune for this problem class in
+ * this process; EINVAL if there is none.                                    */
+hodlr_status hodlr_tune_lookup(int64_t n, int32_t dim, hodlr_kernel k, int32_t precision,
+                               hodlr_tune_t *out);
+
 /* Bytes of device workspace one gp_loglik_dev call needs (256-byte aligned).*/
 hodlr_status hodlr_plan_workspace_size(hodlr_plan p, size_t *bytes);
 
@@ -350,6 +383,10 @@ typedef struct {
 
 /* on = 1 starts timing (and clears the counters), 0 stops.  Process-wide.  */
 hodlr_status hodlr_profile_enable(int32_t on);
+/* Bit s of mask (stage s in the order hodlr_profile_read reports them)
+ * selects which kinds are timed; default: all.  Timing only the kernel of
+ * interest keeps the event overhead out of a throughput measurement.        */
+hodlr_status hodlr_profile_select(uint32_t mask);
 /* Copies the counters accumulated by completed calls.                      */
 hodlr_status hodlr_profile_read(hodlr_profile_t *out);
 

@@ -21,7 +21,7 @@ __all__ = [
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
     "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
     "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
-    "gp_sample_dev",
+    "gp_sample_dev", "Tune", "plan_tuned_create", "autotune", "tune_lookup",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
@@ -35,7 +35,8 @@ EXPORTED = [
     "gp_loglik_batch_dev", "gp_loglik_ragged", "hodlr_mlp_workspace_size", "hodlr_mlp_cast_dev",
     "hodlr_mlp_forward_dev", "hodlr_mlp_grad_dev", "hodlr_mlp_train_step_dev",
     "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
-    "hodlr_sampler_workspace_size", "gp_sample_dev",
+    "hodlr_sampler_workspace_size", "gp_sample_dev", "hodlr_plan_tuned_create", "hodlr_autotune",
+    "hodlr_tune_lookup", "hodlr_profile_select",
 ]
 MLP_NPARAM = 17153
 
@@ -99,6 +100,14 @@ class SamplerCfg(ctypes.Structure):
         c = np.asarray(chol, dtype=np.float64).reshape(9)
         super().__init__(int(walkers), int(steps), (ctypes.c_double * 3)(*lo),
                          (ctypes.c_double * 3)(*hi), (ctypes.c_double * 9)(*c), int(init_state))
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("level_rows", ctypes.c_int32),
+                ("reduce_cols", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"leaf": self.leaf, "level_rows": self.level_rows, "reduce_cols": self.reduce_cols}
 
 
 class SamplerStats(ctypes.Structure):
@@ -196,6 +205,17 @@ def lib():
                                 ctypes.POINTER(SamplerCfg), vp, vp, vp, vp, vp, vp, vp,
                                 ctypes.c_size_t, vp, vp, ctypes.POINTER(SamplerStats)]
     del fp
+    L.hodlr_plan_tuned_create.restype = st
+    L.hodlr_plan_tuned_create.argtypes = [i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(Tune),
+                                          ctypes.POINTER(vp)]
+    L.hodlr_autotune.restype = st
+    L.hodlr_autotune.argtypes = [dp, i64, i32, ctypes.c_int, dp, ctypes.c_double, dp,
+                                 ctypes.c_double, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(ctypes.c_int32), i32, i32, ctypes.POINTER(Tune), dp]
+    L.hodlr_tune_lookup.restype = st
+    L.hodlr_tune_lookup.argtypes = [i64, i32, ctypes.c_int, i32, ctypes.POINTER(Tune)]
+    L.hodlr_profile_select.restype = st
+    L.hodlr_profile_select.argtypes = [ctypes.c_uint32]
     L.hodlr_profile_enable.restype = st
     L.hodlr_profile_enable.argtypes = [i32]
     L.hodlr_profile_read.restype = st
@@ -337,13 +357,21 @@ def hodlr_free(f: Factor):
 
 
 class Plan:
-    """hodlr_plan_create / hodlr_plan_workspace_size / hodlr_plan_destroy."""
+    """hodlr_plan_create (or hodlr_plan_tuned_create when ``tune`` is given) /
+    hodlr_plan_workspace_size / hodlr_plan_destroy."""
 
-    def __init__(self, n: int, dim: int, leaf: int, opts: Opts | None = None):
+    def __init__(self, n: int, dim: int, leaf: int, opts: Opts | None = None,
+                 tune: "Tune | None" = None):
         h = ctypes.c_void_p()
-        _check(lib().hodlr_plan_create(int(n), int(dim), int(leaf),
-                                       ctypes.byref(opts) if opts is not None else None,
-                                       ctypes.byref(h)))
+        if tune is not None:
+            leaf = tune.leaf
+            _check(lib().hodlr_plan_tuned_create(int(n), int(dim),
+                                                 ctypes.byref(opts) if opts is not None else None,
+                                                 ctypes.byref(tune), ctypes.byref(h)))
+        else:
+            _check(lib().hodlr_plan_create(int(n), int(dim), int(leaf),
+                                           ctypes.byref(opts) if opts is not None else None,
+                                           ctypes.byref(h)))
         self._h = h.value
         self.n, self.dim, self.leaf = int(n), int(dim), int(leaf)
         sz = ctypes.c_size_t()
@@ -511,6 +539,35 @@ def gp_sample_dev(plan: Plan, d_x, kernel: int, d_y, tol: float, d_wbf16, norm, 
             "accepted": S.accepted}
 
 
+def plan_tuned_create(n: int, dim: int, tune: Tune, opts: Opts | None = None) -> Plan:
+    return Plan(n, dim, tune.leaf, opts, tune)
+
+
+def autotune(x, y, kernel: int, theta, sigma2: float, tol: float, opts: Opts | None = None,
+             leaf_cands=None, reps: int = 3):
+    """Returns (Tune, per-candidate ms list) from hodlr_autotune."""
+    x = _pts(x)
+    n, dim = x.shape
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
+    th = _theta(theta)
+    lc = None if leaf_cands is None else np.ascontiguousarray(leaf_cands, dtype=np.int32)
+    nl = 0 if lc is None else len(lc)
+    times = np.zeros((nl if nl else 4) + 6)
+    best = Tune()
+    _check(lib().hodlr_autotune(_dp(x), n, dim, int(kernel), _dp(th), float(sigma2), _dp(y),
+                                float(tol), ctypes.byref(opts) if opts is not None else None,
+                                None if lc is None else lc.ctypes.data_as(
+                                    ctypes.POINTER(ctypes.c_int32)),
+                                nl, int(reps), ctypes.byref(best), _dp(times)))
+    return best, times.tolist()
+
+
+def tune_lookup(n: int, dim: int, kernel: int, precision: int = FP64) -> Tune:
+    t = Tune()
+    _check(lib().hodlr_tune_lookup(int(n), int(dim), int(kernel), int(precision), ctypes.byref(t)))
+    return t
+
+
 def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d_v, d_out,
                      stream=None):
     th = _theta(theta)
@@ -522,6 +579,16 @@ def hodlr_matvec_dev(n: int, dim: int, d_x, kernel: int, theta, sigma2: float, d
 def profile_enable(on: bool = True):
     """Start (and reset) or stop per-kernel HIP-event timing inside the library."""
     _check(lib().hodlr_profile_enable(1 if on else 0))
+
+
+PROFILE_STAGES = ["aca_row_pass", "aca_col_pass", "aca_small", "aca_misc", "leaf_factor",
+                  "leaf_solve", "level_reduce", "level_solve", "level_update", "finish", "matvec"]
+
+
+def profile_select(stages=None):
+    """Time only the named kernel kinds (None: all)."""
+    mask = 0xFFFFFFFF if stages is None else sum(1 << PROFILE_STAGES.index(s) for s in stages)
+    _check(lib().hodlr_profile_select(mask))
 
 
 def profile_read() -> dict:

@@ -575,6 +575,29 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
     });
 }
 
+hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *opts,
+                                     const hodlr_tune_t *tune, hodlr_plan *out)
+{
+    return guarded([&]() {
+        if (!tune)
+            throw Error{HODLR_EINVAL, "tune is NULL"};
+        hodlr_opts o = opts ? *opts : default_opts();
+        check_sizes(n, dim, tune->leaf);
+        check_opts(o);
+        if (!out)
+            throw Error{HODLR_EINVAL, "out is NULL"};
+        auto p = std::make_unique<hodlr_plan_s>();
+        p->opts = o;
+        plan_build(p->plan, n, dim, tune->leaf, &o, tune->level_rows, tune->reduce_cols);
+        if (p->plan.leafmax > LEAF_LDS_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+        plan_upload(p->plan);
+        p->lay = make_layout(p->plan, false);
+        *out = p.release();
+        return HODLR_OK;
+    });
+}
+
 void hodlr_plan_destroy(hodlr_plan p)
 {
     if (p) {

@@ -19,7 +19,7 @@ constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (larg
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
-constexpr int LVL_ROWS = 512;     // rows per level work-group
+constexpr int LVL_ROWS = 512;     // default rows per level work-group
 constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored in LDS
 constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices live in LDS)
 // rows a block may try as pivots: every accepted term can follow ZERO_RETRY zero rows
@@ -219,6 +219,8 @@ struct Plan {
     int L = 0;
     int cap = 64;
     int precision = HODLR_FP64;
+    int lvl_rows = LVL_ROWS;   // rows per level-stage chunk (256, 512 or 1024)
+    int red_cols = 4;          // columns per iteration of the small-rank reduction (4 or 8)
     double refine_tol = 1e-10;
     int max_refine = 8;
     int64_t nint = 0;    // internal (split) nodes 2^L - 1
@@ -290,7 +292,8 @@ struct Layout {
 Layout make_layout(const Plan &p, bool store_leaf);
 
 // Build the plan (host); upload tables to the current device.
-void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts);
+void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts,
+                int lvl_rows = LVL_ROWS, int red_cols = 4);
 void plan_upload(Plan &p);
 void plan_release(Plan &p);
 size_t plan_image(Plan &p, std::vector<char> &host);   // table image + offsets
@@ -326,7 +329,7 @@ enum ProfStage {
     PS_ACA_ROW = 0, PS_ACA_COL, PS_ACA_SMALL, PS_ACA_MISC, PS_LEAF, PS_LEAF_SOLVE, PS_LVL_REDUCE, PS_LVL_SOLVE,
     PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_COUNT
 };
-bool prof_on();
+bool prof_on(int stage);
 void prof_suspend(bool on);   // no event recording (e.g. while a stream is captured)
 int prof_begin(hipStream_t s);
 void prof_end(int slot, hipStream_t s, int stage);
@@ -337,7 +340,7 @@ struct ProfScope {
     int stage;
     ProfScope(hipStream_t s_, int st) : slot(-1), s(s_), stage(st)
     {
-        if (prof_on())
+        if (prof_on(st))
             slot = prof_begin(s);
     }
     ~ProfScope()

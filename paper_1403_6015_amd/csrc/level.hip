@@ -133,10 +133,10 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 // one wave per chunk for the reduction, the chunk's W rows kept in registers
 // and every column reduced across the wave; one thread per row for the
 // update, with S in LDS.  Both stream each X column once, coalesced.
-constexpr int LV_SROWS = LVL_ROWS / 64;   // rows per lane in the reduction
 constexpr int LV_CGRP = 8;                 // columns per wave in the reduction
 
-template <typename PT, int R>
+// SR rows per lane (chunk = 64 SR rows), CU columns per iteration
+template <typename PT, int R, int SR, int CU>
 __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
@@ -148,11 +148,11 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
         return;
     const int lane = threadIdx.x;
     const int64_t n = A.n;
-    __shared__ double red[64 * (4 * R + 1)];
-    double w[LV_SROWS][R];
-    bool ok[LV_SROWS];
+    __shared__ double red[64 * (CU * R + 1)];
+    double w[SR][R];
+    bool ok[SR];
 #pragma unroll
-    for (int t = 0; t < LV_SROWS; ++t) {
+    for (int t = 0; t < SR; ++t) {
         const int64_t i = ch.lo + lane + 64 * t;
         ok[t] = i < ch.hi;
 #pragma unroll
@@ -160,7 +160,6 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
             w[t][l] = (ok[t] && l < r) ? Wp[(A.colW + l) * n + i] : 0.0;
     }
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
-    constexpr int CU = 4;   // columns per iteration: more loads in flight
     const int cend = min(A.ncnt, (int)(blockIdx.y + 1) * LV_CGRP);
     for (int c0 = blockIdx.y * LV_CGRP; c0 < cend; c0 += CU) {
         const PT *xc[CU];
@@ -174,7 +173,7 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
             for (int l = 0; l < R; ++l)
                 acc[u][l] = 0.0;
 #pragma unroll
-        for (int t = 0; t < LV_SROWS; ++t) {
+        for (int t = 0; t < SR; ++t) {
             if (ok[t]) {
 #pragma unroll
                 for (int u = 0; u < CU; ++u) {
@@ -560,6 +559,34 @@ static LevelArgs level_args(Pipeline &P, int d)
     return A;
 }
 
+template <typename PT, int R>
+static void reduce_small_rows(int sr, int cu, dim3 grid, hipStream_t s, const LevelArgs &A)
+{
+    if (sr == 4 && cu == 4)
+        level_reduce_small_kernel<PT, R, 4, 4><<<grid, 64, 0, s>>>(A);
+    else if (sr == 4)
+        level_reduce_small_kernel<PT, R, 4, 8><<<grid, 64, 0, s>>>(A);
+    else if (sr == 8 && cu == 4)
+        level_reduce_small_kernel<PT, R, 8, 4><<<grid, 64, 0, s>>>(A);
+    else if (sr == 8)
+        level_reduce_small_kernel<PT, R, 8, 8><<<grid, 64, 0, s>>>(A);
+    else if (cu == 4)
+        level_reduce_small_kernel<PT, R, 16, 4><<<grid, 64, 0, s>>>(A);
+    else
+        level_reduce_small_kernel<PT, R, 16, 8><<<grid, 64, 0, s>>>(A);
+}
+
+template <typename PT>
+static void reduce_small_launch(int R, int sr, int cu, dim3 grid, hipStream_t s, const LevelArgs &A)
+{
+    if (R == 2)
+        reduce_small_rows<PT, 2>(sr, cu, grid, s, A);
+    else if (R == 4)
+        reduce_small_rows<PT, 4>(sr, cu, grid, s, A);
+    else
+        reduce_small_rows<PT, 8>(sr, cu, grid, s, A);
+}
+
 template <typename PT>
 static void level_launch_t(Pipeline &P, int d, LevelArgs A)
 {
@@ -572,12 +599,8 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
         const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP, P.nitems);
-        if (R == 2)
-            level_reduce_small_kernel<PT, 2><<<grid, 64, 0, P.stream>>>(A);
-        else if (R == 4)
-            level_reduce_small_kernel<PT, 4><<<grid, 64, 0, P.stream>>>(A);
-        else if (R == 8)
-            level_reduce_small_kernel<PT, 8><<<grid, 64, 0, P.stream>>>(A);
+        if (R > 0)
+            reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else
             level_reduce_kernel<PT><<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
     }

@@ -16,6 +16,7 @@ struct Rec {
 };
 struct Prof {
     std::atomic<bool> on{false};
+    std::atomic<uint32_t> mask{~0u};   // bit s: time stage s
     std::mutex mu;
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
@@ -48,7 +49,12 @@ hipEvent_t take(Prof &p)
 
 thread_local bool t_suspended = false;
 
-bool prof_on() { return !t_suspended && P().on.load(std::memory_order_relaxed); }
+bool prof_on(int stage)
+{
+    Prof &p = P();
+    return !t_suspended && p.on.load(std::memory_order_relaxed) &&
+           ((p.mask.load(std::memory_order_relaxed) >> stage) & 1u);
+}
 
 void prof_suspend(bool on) { t_suspended = on; }
 
@@ -108,6 +114,12 @@ hodlr_status hodlr_profile_enable(int32_t on)
         }
     }
     p.on.store(on != 0);
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_profile_select(uint32_t mask)
+{
+    hodlr::P().mask.store(mask);
     return HODLR_OK;
 }
 

@@ -72,8 +72,15 @@ static void make_chunks(int node, int side, int64_t lo, int64_t hi, int64_t size
     }
 }
 
-void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
+void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, int lvl_rows,
+                int red_cols)
 {
+    if (lvl_rows != 256 && lvl_rows != 512 && lvl_rows != 1024)
+        throw Error{HODLR_EINVAL, "level_rows must be 256, 512 or 1024"};
+    if (red_cols != 4 && red_cols != 8)
+        throw Error{HODLR_EINVAL, "reduce_cols must be 4 or 8"};
+    p.lvl_rows = lvl_rows;
+    p.red_cols = red_cols;
     p.n = n;
     p.dim = dim;
     p.leaf = leaf;
@@ -171,7 +178,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts)
             for (int side = 0; side < 2; ++side) {
                 int64_t lo = side ? m : s, hi = side ? e : m;
                 int64_t len = hi - lo;
-                const int64_t csz = LVL_ROWS;   // the small-rank kernels assume this
+                const int64_t csz = p.lvl_rows;   // the small-rank kernels assume this
                 if (len > 0)
                     make_chunks((int)h, side, lo, hi, csz, p.lvl[d], slot);
             }
