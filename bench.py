@@ -59,6 +59,28 @@ def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     return out
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none or the kernel's source changed since the counters were taken."""
+    import hashlib
+    files = {"leaf_factor": ("profiles/leaf_factor_traffic_matern32_n2p20.md",
+                             "paper_1403_6015_amd/csrc/leaf.hip")}
+    if kernel not in files:
+        return None
+    summary, src = (os.path.join(ROOT, f) for f in files[kernel])
+    try:
+        text = open(summary).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+    if vals.get("source_sha256", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(sample_n: int):
     """The dense FP64 oracle on the first-`sample_n`-points slice of the
     workload (same density), extrapolated to n = 2^20 by the n^3 cost of a
@@ -93,13 +115,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
-                    choices=["matern1d", "batched_theta", "ragged", "learned"],
+                    choices=["matern1d", "batched_theta", "ragged", "learned", "copy"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
                          "with n log-uniform in [1024, 131072] per step; learned: surrogate-"
                          "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18")
     ap.add_argument("--mcmc-steps", type=int, default=300)
+    ap.add_argument("--autotune-free-leaf", action="store_true",
+                    help="also run the autotuner with the leaf size free (reported only)")
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: FP32 basis panels, FP64 leaves / coupling LU / log-det sums "
@@ -123,6 +147,8 @@ def main():
         return bench_ragged(args, torch, H, wl, dev)
     if args.workload == "learned":
         return bench_learned(args, torch, H, wl, dev)
+    if args.workload == "copy":
+        return bench_copy(args, torch, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -138,7 +164,9 @@ def main():
     topts = H.Opts(max_rank=64, precision=prec, presorted=1)
     tune, tune_ms = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, topts,
                                leaf_cands=[p.leaf], reps=2)
-    free, free_ms = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, topts, reps=2)
+    free = None
+    if args.autotune_free_leaf:
+        free, free_ms = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, topts, reps=2)
     t_tune = time.perf_counter() - t0
     plan = H.Plan(p.n, p.dim, p.leaf, opts, tune=tune)
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
@@ -206,7 +234,9 @@ def main():
             bound = "mfma" if dom == "leaf_factor" else "alu"
             ach = flops / per_call_s / 1e12
             roofline = {"bound": bound, "achieved": ach, "peak": PEAK["alu_fp64"],
-                        "unit": "TFLOP/s", "frac": ach / PEAK["alu_fp64"], "traffic": None,
+                        "unit": "TFLOP/s", "frac": ach / PEAK["alu_fp64"],
+                        "traffic": None if mixed else measured_traffic(dom),
+                        "traffic_unit": "HBM bytes per launch",
                         "kernel": dom, "dtype": "fp64", "avg_launch_ms": dom_ms / dom_launches,
                         "algorithmic_per_call": {"flops": flops, "bytes": byts}}
         else:
@@ -236,7 +266,8 @@ def main():
                       "region records events around %s only" % dom,
         "ordering_s": t_order,
         "autotune": {"tiles_at_leaf": tune.as_dict(), "candidate_ms": tune_ms,
-                     "free_leaf_best": free.as_dict(), "free_leaf_ms": min(free_ms),
+                     "free_leaf_best": free.as_dict() if free else None,
+                     "free_leaf_ms": min(free_ms) if free else None,
                      "seconds": t_tune},
         "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
     }
@@ -396,6 +427,30 @@ def bench_learned(args, torch, H, wl, dev):
            "laplace": {"mode_log_theta": mode.tolist(), "sd_log_theta": sd.tolist()},
            "ess_per_s_including_training": da["ess"] / (da["seconds"] + t_train + t_data)}
     print(json.dumps(res), flush=True)
+
+
+def bench_copy(args, torch, dev):
+    """Calibration for the HBM byte counters: a plain elementwise copy of
+    2^28 doubles (2 GiB read, 2 GiB written per launch), one launch per step."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gbs = 2 * 8 * n * args.steps / el / 1e9
+    print(json.dumps({"metric": "copy bandwidth (counter calibration)", "value": gbs,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": "copy_2p28_f64", "bytes_read_per_launch": 8 * n,
+                                 "bytes_written_per_launch": 8 * n}}), flush=True)
 
 
 if __name__ == "__main__":
