@@ -128,7 +128,7 @@ __device__ __forceinline__ double rdlane(double v, int lane)
 //     with the same broadcast reads of L.
 // If g is given, the factor's rows (global rows row0 + i < m) go to the packed
 // lower store.  Returns sum_i log L_ii (uniform) or NaN on a bad pivot.
-__device__ double diag_factor(double *T, double *g, int row0, int m)
+__device__ __forceinline__ double diag_factor(double *T, double *g, int row0, int m)
 {
     const int lane = threadIdx.x & 63;
     const int ii = lane & 15;
@@ -153,8 +153,16 @@ __device__ double diag_factor(double *T, double *g, int row0, int m)
         const double sj = s0 + s1;
         const double d = rdlane(sj, j);
         bad = bad || !(d > 0.0);
-        const double gj = sqrt(d > 0.0 ? d : 1.0);
-        ginv[j] = 1.0 / gj;
+        // 1/sqrt(d): hardware estimate refined by two Newton steps
+        // r <- r (3 - d r^2) / 2 (quadratic convergence: full FP64 from ~23
+        // bits), then L_jj = d r; no correctly rounded divide or square root
+        // on this serial path
+        const double dd = d > 0.0 ? d : 1.0;
+        double rr = __builtin_amdgcn_rsq(dd);
+        rr = rr * (1.5 - 0.5 * dd * rr * rr);
+        rr = rr * (1.5 - 0.5 * dd * rr * rr);
+        const double gj = dd * rr;
+        ginv[j] = rr;
         a[j] = (ii == j) ? gj : sj * ginv[j];
         mydiag = (ii == j) ? gj : mydiag;
         if (lane < 16 && ii >= j)
@@ -350,10 +358,14 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                 gout[idx] = Gt[tix(i >> 4, k >> 4) * TSZ + (k & 15) * TLD + (i & 15)];
         }
     }
-    // C_lambda^{-1} on every column of the list: each wave owns 16 columns in
-    // registers and runs both substitutions on its own
-    for (int c0 = A.cbeg + 16 * wid; c0 < A.ncols; c0 += 16 * LEAF_MW) {
-        const int nb = min(16, A.ncols - c0);
+    // C_lambda^{-1} on every column of the list: each wave owns up to 16
+    // columns in registers and runs both substitutions on its own.  Up to 64
+    // columns are split evenly over the four waves (one pass each, all waves
+    // busy); more go round-robin in groups of 16.
+    const int ncl = A.ncols - A.cbeg;
+    const int gsz = ncl <= 16 * LEAF_MW ? (ncl + LEAF_MW - 1) / LEAF_MW : 16;
+    for (int c0 = A.cbeg + gsz * wid; gsz > 0 && c0 < A.ncols; c0 += gsz * LEAF_MW) {
+        const int nb = min(gsz, A.ncols - c0);
         const int cr = c0 + r;
         const double *src = nullptr;
         if (r < nb) {
