@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
-                    choices=["matern1d", "batched_theta", "ragged", "learned", "copy"],
+                    choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
@@ -149,6 +149,8 @@ def main():
         return bench_learned(args, torch, H, wl, dev)
     if args.workload == "copy":
         return bench_copy(args, torch, dev)
+    if args.workload == "se2d":
+        return bench_se2d(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -426,6 +428,71 @@ def bench_learned(args, torch, H, wl, dev):
                          "laplace_seconds": t_laplace},
            "laplace": {"mode_log_theta": mode.tolist(), "sd_log_theta": sd.tolist()},
            "ess_per_s_including_training": da["ess"] / (da["seconds"] + t_train + t_data)}
+    print(json.dumps(res), flush=True)
+
+
+def bench_se2d(args, torch, H, wl, dev):
+    """The 2-D configuration: SE l = 0.05, sigma^2 = 1e-2, ranks capped at 64,
+    points ~ U([0,s]^2) at the density of n = 2^22 on the unit square (n from
+    --n, default 2^20), k-d ordered, leaf 128.  Timed: the device likelihood
+    (factor + log det + one solve through the factor).  Once, untimed in the
+    rate: the refined solve of the host entry point (mixed form: refinement
+    against the exact FP64 product to 1e-10) with its residual and time."""
+    n = args.n
+    p = wl.se2d(n)
+    leaf = 128
+    mixed = args.precision == "mixed"
+    prec = H.MIXED if mixed else H.FP64
+    perm = H.hodlr_order(p.x, leaf)
+    xs, ys = p.x[perm], p.y[perm]
+    plan = H.Plan(n, 2, leaf, H.Opts(max_rank=64, precision=prec))
+    d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
+    d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
+    work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+
+    def step():
+        H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                        plan.workspace_bytes, None, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    loglik, logdet, quad = out[:3].cpu().tolist()
+    t1 = time.perf_counter()
+    f = H.hodlr_build(xs, p.kernel, p.theta, p.sigma2, leaf, p.tol,
+                      H.Opts(max_rank=64, precision=prec, presorted=1, max_refine=40))
+    t_build = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    refined = {}
+    try:
+        f.solve(ys)
+        refined["status"] = "OK"
+    except H.HodlrError as e:
+        refined["status"] = e.name
+    refined["seconds"] = time.perf_counter() - t2
+    info = f.info()
+    f.free()
+    refined.update({"refine_steps": info["refine_steps"],
+                    "relative_residual": info["refine_residual"],
+                    "build_seconds": t_build})
+    res = {"metric": "GP log-likelihoods/s, 2-D SE (ranks capped at 64)",
+           "value": args.steps / el, "unit": "likelihoods/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64", "data": "synthetic",
+           "config": {"workload": "se2d_n%d_leaf128_cap64%s" % (n, "_mixed" if mixed else ""),
+                      "n": n, "dim": 2, "kernel": "se", "l": 0.05, "sigma2": 1e-2,
+                      "side": p.meta["side"], "leaf": leaf, "max_rank": 64, "tol": p.tol,
+                      "precision": args.precision},
+           "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
+           "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
+           "refined_solve": refined if mixed else None}
     print(json.dumps(res), flush=True)
 
 

@@ -78,11 +78,13 @@ typedef struct {
                             store); compression, bases W,
                             leaf Cholesky factors, coupling-matrix LU and every log-det
                             sum in FP64.  hodlr_solve and gp_loglik then refine against
-                            the exact FP64 product (hodlr_matvec_dev); gp_loglik_dev and
+                            the exact FP64 product (hodlr_matvec_dev) by conjugate
+                            gradients preconditioned with the factor; gp_loglik_dev and
                             the batched form return the unrefined quadratic form      */
-    double refine_tol;   /* mixed form: stop at ||y - C x|| / ||y|| <= refine_tol
-                            (default 1e-10)                                           */
-    int32_t max_refine;  /* mixed form: at most this many refinement steps (default 8) */
+    double refine_tol;   /* mixed form: stop at ||y - C x|| / ||y|| <= refine_tol, the
+                            true residual (default 1e-10)                             */
+    int32_t max_refine;  /* mixed form: at most 1 + max_refine preconditioned steps,
+                            each one exact product and one factor solve (default 8)   */
     int32_t presorted;   /* 1: the points are already in tree order; skip ordering     */
 } hodlr_opts;          /* pass NULL for all defaults */
 

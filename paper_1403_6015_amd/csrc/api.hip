@@ -274,45 +274,86 @@ struct Refined {
 };
 
 // d_x = C^{-1} d_y in tree order (device FP64 vectors).  An FP64 factor
-// applies its inverse once.  A mixed factor refines: x_0 = H^{-1} y and
-// x_{k+1} = x_k + H^{-1} (y - C x_k), the residual from the exact FP64
-// product, until ||y - C x|| <= refine_tol ||y|| or max_refine corrections.
-Refined solve_tree(hodlr_factor_s *f, Pipeline &P, const double *d_y, double *d_x, double *d_r,
-                   double *d_cx, double *part)
+// applies its inverse once.  A mixed factor refines against the exact FP64
+// product by conjugate gradients preconditioned with the factor (flexible
+// form, since the FP32 factor is only nearly symmetric): with an accurate
+// factor this converges like x_{k+1} = x_k + H^{-1}(y - C x_k), and it still
+// converges when rank caps make the factor too rough for that stationary
+// iteration.  Stops at ||y - C x|| <= refine_tol ||y|| (true residual) or
+// after 1 + max_refine products.
+struct Work {
+    double *r, *q, *z, *p, *part;
+};
+
+Refined solve_tree(hodlr_factor_s *f, Pipeline &P, const double *d_y, double *d_x, const Work &w)
 {
     const int64_t n = f->plan.n;
     const bool f32 = f->plan.f32();
-    void *z = P.ws + P.lay.Xt;   // column 0 of the panel carries the vector
+    void *zp = P.ws + P.lay.Xt;   // column 0 of the panel carries the vector
     hipStream_t s = P.stream;
     if (!f32) {
-        HIP_TRY(hipMemcpyAsync(z, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        run_leaf_solve(P, z);
+        HIP_TRY(hipMemcpyAsync(zp, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        run_leaf_solve(P, zp);
         run_levels_apply(P);
-        HIP_TRY(hipMemcpyAsync(d_x, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_x, zp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         return {0, -1.0, true};
     }
-    const double ynorm = std::sqrt(run_sumsq(d_y, n, part, s));
+    // z = H^{-1} v, the vector scaled to unit norm through the FP32 panel
+    auto precond = [&](const double *v, double vnorm, double *out) {
+        run_cast_scaled(v, 1.0 / vnorm, zp, true, n, s);
+        run_leaf_solve(P, zp);
+        run_levels_apply(P);
+        run_widen(zp, true, out, n, s, vnorm);
+    };
+    const double ynorm = std::sqrt(run_sumsq(d_y, n, w.part, s));
     HIP_TRY(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
     if (ynorm == 0.0)
         return {0, 0.0, true};
-    HIP_TRY(hipMemcpyAsync(d_r, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    const double tol = f->plan.refine_tol;
+    const int maxit = 1 + f->plan.max_refine;
+    HIP_TRY(hipMemcpyAsync(w.r, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     double rnorm = ynorm;
-    for (int k = 0;; ++k) {
-        run_cast_scaled(d_r, 1.0 / rnorm, z, true, n, s);
-        run_leaf_solve(P, z);
-        run_levels_apply(P);
-        run_axpy(d_x, rnorm, z, true, n, s);
-        run_matvec(n, f->kp, f->dx, d_x, d_cx, s);
-        run_sub(d_y, d_cx, d_r, n, s);
-        rnorm = std::sqrt(run_sumsq(d_r, n, part, s));
-        const double rel = rnorm / ynorm;
-        if (!std::isfinite(rel))
-            return {k, rel, false};
-        if (rel <= f->plan.refine_tol)
-            return {k, rel, true};
-        if (k >= f->plan.max_refine)
-            return {k, rel, false};
+    precond(w.r, rnorm, w.z);
+    HIP_TRY(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double rz = run_dot(w.r, w.z, n, w.part, s);
+    double rel = 1.0;
+    for (int it = 0; it < maxit; ++it) {
+        run_matvec(n, f->kp, f->dx, w.p, w.q, s);
+        const double pq = run_dot(w.p, w.q, n, w.part, s);
+        if (!(pq > 0.0) || !std::isfinite(rz))
+            return {it, rel, false};
+        const double alpha = rz / pq;
+        run_axpy(d_x, alpha, w.p, false, n, s);
+        run_axpy(w.r, -alpha, w.q, false, n, s);
+        rnorm = std::sqrt(run_sumsq(w.r, n, w.part, s));
+        const bool last = it + 1 == maxit;
+        if (rnorm <= tol * ynorm || last) {
+            // confirm with the true residual y - C x (the recurrence drifts)
+            run_matvec(n, f->kp, f->dx, d_x, w.q, s);
+            run_sub(d_y, w.q, w.r, n, s);
+            rnorm = std::sqrt(run_sumsq(w.r, n, w.part, s));
+            rel = rnorm / ynorm;
+            if (!std::isfinite(rel))
+                return {it, rel, false};
+            if (rel <= tol)
+                return {it, rel, true};
+            if (last)
+                return {it, rel, false};
+            // restart from the true residual
+            precond(w.r, rnorm, w.z);
+            HIP_TRY(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            rz = run_dot(w.r, w.z, n, w.part, s);
+            continue;
+        }
+        rel = rnorm / ynorm;
+        const double rzold = run_dot(w.r, w.z, n, w.part, s);   // r_{k+1} . z_k
+        precond(w.r, rnorm, w.z);
+        const double rznew = run_dot(w.r, w.z, n, w.part, s);
+        const double beta = (rznew - rzold) / rz;
+        rz = rznew;
+        run_xpby(w.z, beta, w.p, n, s);
     }
+    return {maxit - 1, rel, false};
 }
 
 }  // namespace
@@ -409,8 +450,10 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
         Pipeline P = factor_pipeline_of(f);
         const bool f32 = f->plan.f32();
         DevBuf dy(sizeof(double) * n), dx(sizeof(double) * n);
-        DevBuf dr(f32 ? sizeof(double) * n : 8), dcx(f32 ? sizeof(double) * n : 8),
-            part(sizeof(double) * 512);
+        const size_t vb = f32 ? sizeof(double) * n : 8;
+        DevBuf dr(vb), dq(vb), dz(vb), dp(vb), part(sizeof(double) * 512);
+        const Work w{(double *)dr.p, (double *)dq.p, (double *)dz.p, (double *)dp.p,
+                     (double *)part.p};
         std::vector<double> buf(n), res(n);
         int steps = 0;
         double worst = f32 ? 0.0 : -1.0;
@@ -420,8 +463,7 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
             for (int64_t k = 0; k < n; ++k)
                 buf[k] = yc[f->perm[k]];
             HIP_TRY(hipMemcpy(dy.p, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-            Refined r = solve_tree(f, P, (const double *)dy.p, (double *)dx.p, (double *)dr.p,
-                                   (double *)dcx.p, (double *)part.p);
+            Refined r = solve_tree(f, P, (const double *)dy.p, (double *)dx.p, w);
             HIP_TRY(hipMemcpy(buf.data(), dx.p, sizeof(double) * n, hipMemcpyDeviceToHost));
             prof_collect();
             steps = std::max(steps, r.steps);

@@ -360,7 +360,10 @@ void run_finish(Pipeline &P, const double *y, double *d_out, int ostride = 8);  
 // refinement helpers (misc.hip); z is the panel-typed solve vector
 void run_cast_scaled(const double *r, double inv, void *z, bool f32, int64_t n, hipStream_t s);
 void run_axpy(double *x, double a, const void *z, bool f32, int64_t n, hipStream_t s);
-void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s);
+void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s,
+               double scale = 1.0);
+void run_xpby(const double *z, double beta, double *p, int64_t n, hipStream_t s);   // p = z + beta p
+double run_dot(const double *a, const double *b, int64_t n, double *part, hipStream_t s);
 void run_sub(const double *y, const double *cx, double *r, int64_t n, hipStream_t s);
 double run_sumsq(const double *v, int64_t n, double *part, hipStream_t s);
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,

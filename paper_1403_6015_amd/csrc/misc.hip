@@ -162,10 +162,34 @@ __global__ void axpy_kernel(double *__restrict__ x, double s, const PT *__restri
 }
 
 template <typename PT>
-__global__ void widen_kernel(const PT *__restrict__ z, double *__restrict__ out, int64_t n)
+__global__ void widen_kernel(const PT *__restrict__ z, double scale, double *__restrict__ out,
+                             int64_t n)
 {
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        out[i] = (double)z[i];
+        out[i] = scale * (double)z[i];
+}
+
+__global__ void xpby_kernel(const double *__restrict__ z, double beta, double *__restrict__ p,
+                            int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = z[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(const double *__restrict__ a,
+                                                  const double *__restrict__ b, int64_t n,
+                                                  double *part)
+{
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += a[i] * b[i];
+    s = wave_sum(s);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void sub_kernel(const double *__restrict__ y, const double *__restrict__ cx,
@@ -210,13 +234,34 @@ void run_axpy(double *x, double a, const void *z, bool f32, int64_t n, hipStream
     HIP_TRY(hipGetLastError());
 }
 
-void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s)
+void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s, double scale)
 {
     if (f32)
-        widen_kernel<float><<<grid_for(n), 256, 0, s>>>((const float *)z, out, n);
+        widen_kernel<float><<<grid_for(n), 256, 0, s>>>((const float *)z, scale, out, n);
     else
-        widen_kernel<double><<<grid_for(n), 256, 0, s>>>((const double *)z, out, n);
+        widen_kernel<double><<<grid_for(n), 256, 0, s>>>((const double *)z, scale, out, n);
     HIP_TRY(hipGetLastError());
+}
+
+void run_xpby(const double *z, double beta, double *p, int64_t n, hipStream_t s)
+{
+    xpby_kernel<<<grid_for(n), 256, 0, s>>>(z, beta, p, n);
+    HIP_TRY(hipGetLastError());
+}
+
+// a . b, partials summed on the host in a fixed order (synchronizes)
+double run_dot(const double *a, const double *b, int64_t n, double *part, hipStream_t s)
+{
+    const unsigned g = 512;
+    dot_kernel<<<g, 256, 0, s>>>(a, b, n, part);
+    HIP_TRY(hipGetLastError());
+    double h[512];
+    HIP_TRY(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (unsigned i = 0; i < g; ++i)
+        t += h[i];
+    return t;
 }
 
 void run_sub(const double *y, const double *cx, double *r, int64_t n, hipStream_t s)
