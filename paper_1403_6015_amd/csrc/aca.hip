@@ -27,7 +27,12 @@
 
 namespace hodlr {
 
-constexpr int SM_EPT = ACA_SMALL / ACA_THREADS;   // entries per thread, small path
+// work-group size of the small-block path.  Measured at n = 2^20: 256 threads
+// 0.39 ms, 128 threads 0.49 ms, one wave 0.42 ms (no barriers, but 32 entries
+// per lane need 256 VGPRs): the per-step cost is the re-reads of the earlier
+// terms, not the work-group reductions.
+constexpr int ACA_SMALL_TH = 256;
+
 
 enum BigPhase { BP_FRESH = 0, BP_ROWDONE = 1, BP_COLDONE = 2, BP_RETRY = 3 };
 
@@ -89,6 +94,26 @@ __device__ double block_sum(double v, double *red)
     return s;
 }
 
+// reductions over a work-group of TH threads: one wave needs no LDS or barrier
+template <int TH>
+__device__ __forceinline__ void grp_argmax(double &v, int64_t &i, double &sgn, double *rv,
+                                           int64_t *ri, double *rs)
+{
+    if constexpr (TH == 64)
+        wave_argmax_signed(v, i, sgn);
+    else
+        block_argmax(v, i, sgn, rv, ri, rs);
+}
+
+template <int TH>
+__device__ __forceinline__ double grp_sum(double v, double *red)
+{
+    if constexpr (TH == 64)
+        return wave_sum(v);
+    else
+        return block_sum(v, red);
+}
+
 // ------------------------------------------------------------ small blocks
 struct SmallArgs {
     AcaArgs a;
@@ -97,10 +122,12 @@ struct SmallArgs {
     int *status;        // per node AcaDone
 };
 
-__global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
+template <int TH>
+__global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
 {
     const AcaArgs &A = S.a;
     const int64_t h = S.nodes[blockIdx.x];
+    constexpr int EPT = ACA_SMALL / TH;   // entries per thread
     const int tid = threadIdx.x;
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
     const int64_t na = m - s, nb = e - m, n = A.n;
@@ -114,24 +141,24 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
     const int64_t full = na < nb ? na : nb;
     const int cap = (int)(A.cap < full ? A.cap : full);
     const bool usercap = A.cap < full;
-    for (int64_t i = tid; i < na; i += ACA_THREADS)
+    for (int64_t i = tid; i < na; i += TH)
         used[i] = 0;
     __syncthreads();
     int k = 0, zeros = 0, nused = 0, done = (cap <= 0) ? ACA_EXHAUSTED : ACA_ACTIVE;
     int64_t istar = na - 1;
     double s2 = 0.0;
-    double uv[SM_EPT];
+    double uv[EPT];
     while (done == ACA_ACTIVE) {
         // residual row at i*
         // (written by other threads of this work-group: read past the L1)
-        for (int l = tid; l < k; l += ACA_THREADS)
+        for (int l = tid; l < k; l += TH)
             sfix[l] = ld_coherent(&W[(col0 + l) * n + s + istar]);
         __syncthreads();
         double bv = -1.0, bs = 0.0, sq = 0.0;
         int64_t bi = INT64_MAX;
 #pragma unroll
-        for (int t = 0; t < SM_EPT; ++t) {
-            int64_t j = tid + (int64_t)t * ACA_THREADS;
+        for (int t = 0; t < EPT; ++t) {
+            int64_t j = tid + (int64_t)t * TH;
             uv[t] = 0.0;
             if (j < nb) {
                 double a = kentry(A.kp, A.x, n, s + istar, m + j);
@@ -147,7 +174,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
                 }
             }
         }
-        block_argmax(bv, bi, bs, rv, ri, rs);
+        grp_argmax<TH>(bv, bi, bs, rv, ri, rs);
         if (tid == 0)
             used[istar] = 1;
         ++nused;
@@ -165,23 +192,23 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
             continue;
         }
         zeros = 0;
-        const double v2 = block_sum(sq, red);
+        const double v2 = grp_sum<TH>(sq, red);
         for (int l = 0; l < k; ++l) {
             double d = 0.0;
 #pragma unroll
-            for (int t = 0; t < SM_EPT; ++t) {
-                int64_t j = tid + (int64_t)t * ACA_THREADS;
+            for (int t = 0; t < EPT; ++t) {
+                int64_t j = tid + (int64_t)t * TH;
                 if (j < nb)
                     d += uv[t] * W[(col0 + l) * n + m + j];
             }
-            d = block_sum(d, red);
+            d = grp_sum<TH>(d, red);
             if (tid == 0)
                 vdot[l] = d;
         }
         // residual column at j*
         const int64_t jstar = bi;
         const double delta = bs;
-        for (int l = tid; l < k; l += ACA_THREADS)
+        for (int l = tid; l < k; l += TH)
             sfix[l] = ld_coherent(&W[(col0 + l) * n + m + jstar]);
         __syncthreads();
         bv = -1.0;
@@ -189,8 +216,8 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
         bi = INT64_MAX;
         sq = 0.0;
 #pragma unroll
-        for (int t = 0; t < SM_EPT; ++t) {
-            int64_t i = tid + (int64_t)t * ACA_THREADS;
+        for (int t = 0; t < EPT; ++t) {
+            int64_t i = tid + (int64_t)t * TH;
             uv[t] = 0.0;
             if (i < na) {
                 double a = kentry(A.kp, A.x, n, s + i, m + jstar);
@@ -207,18 +234,18 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_small_kernel(SmallArgs S)
                 }
             }
         }
-        block_argmax(bv, bi, bs, rv, ri, rs);
-        const double u2 = block_sum(sq, red);
+        grp_argmax<TH>(bv, bi, bs, rv, ri, rs);
+        const double u2 = grp_sum<TH>(sq, red);
         double cross = 0.0;
         for (int l = 0; l < k; ++l) {
             double d = 0.0;
 #pragma unroll
-            for (int t = 0; t < SM_EPT; ++t) {
-                int64_t i = tid + (int64_t)t * ACA_THREADS;
+            for (int t = 0; t < EPT; ++t) {
+                int64_t i = tid + (int64_t)t * TH;
                 if (i < na)
                     d += uv[t] * W[(col0 + l) * n + s + i];
             }
-            d = block_sum(d, red);
+            d = grp_sum<TH>(d, red);
             cross += d * vdot[l];
         }
         s2 += u2 * v2 + 2.0 * cross;
@@ -871,7 +898,7 @@ void run_aca(Pipeline &P)
         S.rank = rank;
         S.status = status;
         ProfScope ps(s, PS_ACA_SMALL);
-        aca_small_kernel<<<(unsigned)p.aca_small.size(), ACA_THREADS, 0, s>>>(S);
+        aca_small_kernel<ACA_SMALL_TH><<<(unsigned)p.aca_small.size(), ACA_SMALL_TH, 0, s>>>(S);
         HIP_TRY(hipGetLastError());
     }
     const int nbig = (int)p.aca_big.size();

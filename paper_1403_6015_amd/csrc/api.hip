@@ -609,7 +609,7 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
         p->opts = o;
         plan_build(p->plan, n, dim, leaf, &o);
         if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
         *out = p.release();
@@ -632,7 +632,7 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
         p->opts = o;
         plan_build(p->plan, n, dim, tune->leaf, &o, tune->level_rows, tune->reduce_cols);
         if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
         *out = p.release();
@@ -710,7 +710,7 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
             throw Error{HODLR_EINVAL, "workspace too small: need " +
                                           std::to_string(istride * (size_t)nitems) + " bytes"};
         if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         Pipeline P;
         P.plan = &p->plan;
         P.lay = p->lay;

@@ -121,11 +121,11 @@ __device__ __forceinline__ double rdlane(double v, int lane)
 // Cholesky of one 16 x 16 diagonal tile (column-major in LDS); the tile is
 // overwritten with the inverse of its lower factor.  One wave.
 //   factor (Crout, column by column): lane i < 16 keeps row i of the factor in
-//     registers and writes each new entry to the tile, where later columns read
-//     it back with uniform-address (broadcast) LDS loads; the pivot of column j
-//     moves to all lanes with one read-lane;
-//   inverse: lane c < 16 computes column c of L^{-1} by forward substitution
-//     with the same broadcast reads of L.
+//     registers; step j broadcasts row j (held by lane j) with read-lanes, and
+//     the pivot of column j moves to all lanes with one more read-lane;
+//   inverse: in the same step j, lane c extends column c of L^{-1} by its
+//     row j, Linv[j][c] = (delta_jc - sum_k L[j][k] Linv[k][c]) / L[j][j],
+//     reusing the broadcast row L[j][.] (two independent FMA chains per step).
 // If g is given, the factor's rows (global rows row0 + i < m) go to the packed
 // lower store.  Returns sum_i log L_ii (uniform) or NaN on a bad pivot.
 __device__ __forceinline__ double diag_factor(double *T, double *g, int row0, int m)
@@ -136,19 +136,25 @@ __device__ __forceinline__ double diag_factor(double *T, double *g, int row0, in
 #pragma unroll
     for (int c = 0; c < 16; ++c)
         a[c] = T[c * TLD + ii];
-    double ginv[16];
+    double x[16];          // column ii of L^{-1}, built row by row with the factor
     double mydiag = 1.0;   // L[ii][ii]
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
+        // column j of L (lane i: L[i][j]) and row j of L^{-1} (lane c:
+        // Linv[j][c]) from the same broadcast row L[j][0..j-1] of lane j
         double s0 = a[j], s1 = 0.0;
+        double t0 = (ii == j) ? 1.0 : 0.0, t1 = 0.0;
 #pragma unroll
         for (int k = 0; k < j; ++k) {
-            double ljk = T[k * TLD + j];   // L[j][k], written by lane j at column k
-            if (k & 1)
+            const double ljk = rdlane(a[k], j);   // L[j][k], held by lane j
+            if (k & 1) {
                 s1 -= a[k] * ljk;
-            else
+                t1 -= ljk * x[k];
+            } else {
                 s0 -= a[k] * ljk;
+                t0 -= ljk * x[k];
+            }
         }
         const double sj = s0 + s1;
         const double d = rdlane(sj, j);
@@ -162,11 +168,9 @@ __device__ __forceinline__ double diag_factor(double *T, double *g, int row0, in
         rr = rr * (1.5 - 0.5 * dd * rr * rr);
         rr = rr * (1.5 - 0.5 * dd * rr * rr);
         const double gj = dd * rr;
-        ginv[j] = rr;
-        a[j] = (ii == j) ? gj : sj * ginv[j];
+        a[j] = (ii == j) ? gj : sj * rr;
         mydiag = (ii == j) ? gj : mydiag;
-        if (lane < 16 && ii >= j)
-            T[j * TLD + ii] = a[j];
+        x[j] = (t0 + t1) * rr;
     }
     double lg = (lane < 16) ? log(mydiag) : 0.0;
     lg += __shfl_xor(lg, 8, 64);
@@ -182,21 +186,6 @@ __device__ __forceinline__ double diag_factor(double *T, double *g, int row0, in
                 if (c <= ii)
                     g[tri(i) + row0 + c] = a[c];
         }
-    }
-    // column ii of L^{-1}
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        double s0 = (i == ii) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) {
-            double lik = T[k * TLD + i];
-            if (k & 1)
-                s1 -= lik * x[k];
-            else
-                s0 -= lik * x[k];
-        }
-        x[i] = (s0 + s1) * ginv[i];
     }
     if (lane < 16) {
 #pragma unroll
@@ -467,7 +456,7 @@ void run_leaf_factor(Pipeline &P, const double *y)
 {
     const Plan &p = *P.plan;
     if (p.leafmax > LEAF_LDS_MAX)
-        throw Error{HODLR_EINVAL, "leaf size above 128 is not supported by this build"};
+        throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
     LeafArgs A = leaf_args(P);
     A.y = y;
     A.cbeg = y ? 0 : 1;
