@@ -131,8 +131,9 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(each GPU would own a subtree; only the top levels would exchange "
+              "KB-sized coupling sums)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -260,7 +261,7 @@ def main():
                    "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
                    "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": args.precision,
                    "levels": L, "rank_max": r[1:], "level_rows": tune.level_rows,
-                   "reduce_cols": tune.reduce_cols},
+                   "reduce_cols": tune.reduce_cols, "reduce_group": tune.reduce_group},
         "roofline": roofline,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "stage_launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},

@@ -166,14 +166,15 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
 void hodlr_plan_destroy(hodlr_plan p);
 
 /* Launch shape chosen by the autotuner: the leaf size (any leaf <= 128) and
- * the level stage's tiles, rows per chunk (256, 512 or 1024) and columns per
- * reduction step (4 or 8).  The method's result does not depend on the tiles;
+ * the level stage's tiles, rows per chunk (256, 512 or 1024), columns per
+ * reduction step (4 or 8) and columns per reduction work-group (8 or 64).  The method's result does not depend on the tiles;
  * the leaf size changes the tree (and so the approximation) within the
  * compression tolerance.                                                     */
 typedef struct {
     int32_t leaf;
     int32_t level_rows;
     int32_t reduce_cols;
+    int32_t reduce_group;
 } hodlr_tune_t;
 
 /* As hodlr_plan_create, with the leaf size and tiles from `tune`.           */
@@ -182,10 +183,11 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
 
 /* Times the whole likelihood on the caller's problem (host arrays as for
  * gp_loglik) for each leaf size in leaf_cands (NULL/0: 32, 64, 96, 128) with
- * the default tiles, then the six tile shapes at the fastest leaf; keeps the
- * best of `reps` runs after a warm-up per candidate.  *best receives the
- * fastest shape; times_ms (nullable, nleaf + 6 doubles, 4 + 6 for the
- * defaults) the per-candidate times in that order.  The result is also cached
+ * the default tiles (512, 4, 8), then the twelve tile shapes at the fastest
+ * leaf (rows outer, then columns per step, then group); keeps the best of
+ * `reps` runs after a warm-up per candidate.  *best receives the fastest
+ * shape; times_ms (nullable, nleaf + 12 doubles, 4 + 12 for the defaults) the
+ * per-candidate times in that order.  The result is also cached
  * per (ceil log2 n, dim, kernel, precision) for hodlr_tune_lookup.  Allocates
  * and frees device memory per candidate.  Errors: EINVAL, ENOTSPD, ENOMEM,
  * EDEVICE.                                                                   */

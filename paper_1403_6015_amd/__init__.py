@@ -104,10 +104,14 @@ class SamplerCfg(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("level_rows", ctypes.c_int32),
-                ("reduce_cols", ctypes.c_int32)]
+                ("reduce_cols", ctypes.c_int32), ("reduce_group", ctypes.c_int32)]
+
+    def __init__(self, leaf=128, level_rows=512, reduce_cols=4, reduce_group=8):
+        super().__init__(int(leaf), int(level_rows), int(reduce_cols), int(reduce_group))
 
     def as_dict(self):
-        return {"leaf": self.leaf, "level_rows": self.level_rows, "reduce_cols": self.reduce_cols}
+        return {"leaf": self.leaf, "level_rows": self.level_rows, "reduce_cols": self.reduce_cols,
+                "reduce_group": self.reduce_group}
 
 
 class SamplerStats(ctypes.Structure):
@@ -552,7 +556,7 @@ def autotune(x, y, kernel: int, theta, sigma2: float, tol: float, opts: Opts | N
     th = _theta(theta)
     lc = None if leaf_cands is None else np.ascontiguousarray(leaf_cands, dtype=np.int32)
     nl = 0 if lc is None else len(lc)
-    times = np.zeros((nl if nl else 4) + 6)
+    times = np.zeros((nl if nl else 4) + 12)
     best = Tune()
     _check(lib().hodlr_autotune(_dp(x), n, dim, int(kernel), _dp(th), float(sigma2), _dp(y),
                                 float(tol), ctypes.byref(opts) if opts is not None else None,

@@ -630,7 +630,8 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
             throw Error{HODLR_EINVAL, "out is NULL"};
         auto p = std::make_unique<hodlr_plan_s>();
         p->opts = o;
-        plan_build(p->plan, n, dim, tune->leaf, &o, tune->level_rows, tune->reduce_cols);
+        plan_build(p->plan, n, dim, tune->leaf, &o, tune->level_rows, tune->reduce_cols,
+                   tune->reduce_group);
         if (p->plan.leafmax > LEAF_LDS_MAX)
             throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         plan_upload(p->plan);

@@ -221,6 +221,7 @@ struct Plan {
     int precision = HODLR_FP64;
     int lvl_rows = LVL_ROWS;   // rows per level-stage chunk (256, 512 or 1024)
     int red_cols = 4;          // columns per iteration of the small-rank reduction (4 or 8)
+    int red_grp = 8;           // columns per work-group of the small-rank reduction (8 or 64)
     double refine_tol = 1e-10;
     int max_refine = 8;
     int64_t nint = 0;    // internal (split) nodes 2^L - 1
@@ -293,7 +294,7 @@ Layout make_layout(const Plan &p, bool store_leaf);
 
 // Build the plan (host); upload tables to the current device.
 void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts,
-                int lvl_rows = LVL_ROWS, int red_cols = 4);
+                int lvl_rows = LVL_ROWS, int red_cols = 4, int red_grp = 8);
 void plan_upload(Plan &p);
 void plan_release(Plan &p);
 size_t plan_image(Plan &p, std::vector<char> &host);   // table image + offsets

@@ -52,6 +52,7 @@ struct LevelArgs {
     double *node_ld;
     int *status;
     int factor;        // 1: build the coupling factors; 0: apply stored ones
+    int cgrp;          // columns per work-group of the small-rank reduction
     BatchArgs B;
 };
 
@@ -133,7 +134,9 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 // one wave per chunk for the reduction, the chunk's W rows kept in registers
 // and every column reduced across the wave; one thread per row for the
 // update, with S in LDS.  Both stream each X column once, coalesced.
-constexpr int LV_CGRP = 8;                 // columns per wave in the reduction
+// columns per work-group of the small-rank reduction: the plan's red_grp (8 or
+// 64).  Every work-group of a chunk re-reads the chunk's W rows, so wide groups
+// read W once; narrow groups give more work-groups.
 
 // SR rows per lane (chunk = 64 SR rows), CU columns per iteration
 template <typename PT, int R, int SR, int CU>
@@ -160,8 +163,8 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
             w[t][l] = (ok[t] && l < r) ? Wp[(A.colW + l) * n + i] : 0.0;
     }
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
-    const int cend = min(A.ncnt, (int)(blockIdx.y + 1) * LV_CGRP);
-    for (int c0 = blockIdx.y * LV_CGRP; c0 < cend; c0 += CU) {
+    const int cend = min(A.ncnt, (int)(blockIdx.y + 1) * A.cgrp);
+    for (int c0 = blockIdx.y * A.cgrp; c0 < cend; c0 += CU) {
         const PT *xc[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -556,6 +559,7 @@ static LevelArgs level_args(Pipeline &P, int d)
     A.node_ld = wsp<double>(P, P.lay.node_ld);
     A.status = wsp<int>(P, P.lay.status);
     A.B = P.batch;
+    A.cgrp = p.red_grp;
     return A;
 }
 
@@ -598,7 +602,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     const bool small_upd = R > 0 && sbytes <= 48 * 1024;
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
-        const dim3 grid(nchunks, (A.ncnt + LV_CGRP - 1) / LV_CGRP, P.nitems);
+        const dim3 grid(nchunks, (A.ncnt + p.red_grp - 1) / p.red_grp, P.nitems);
         if (R > 0)
             reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else

@@ -73,8 +73,11 @@ static void make_chunks(int node, int side, int64_t lo, int64_t hi, int64_t size
 }
 
 void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, int lvl_rows,
-                int red_cols)
+                int red_cols, int red_grp)
 {
+    if (red_grp != 8 && red_grp != 64)
+        throw Error{HODLR_EINVAL, "reduce_group must be 8 or 64"};
+    p.red_grp = red_grp;
     if (lvl_rows != 256 && lvl_rows != 512 && lvl_rows != 1024)
         throw Error{HODLR_EINVAL, "level_rows must be 256, 512 or 1024"};
     if (red_cols != 4 && red_cols != 8)

@@ -1,10 +1,11 @@
 // Autotuner of the launch shape: leaf size (the block size of the finest
 // level, which trades leaf work against tree depth) and the level stage's
-// tiles (rows per chunk, columns per reduction step).  Candidates are timed on
+// tiles (rows per chunk, columns per reduction step, columns per reduction
+// work-group).  Candidates are timed on
 // the caller's own problem (points, observations, hyperparameters), wall clock
 // around the whole likelihood pipeline including its one synchronization, the
 // best of `reps` runs after a warm-up.  Search: leaf sizes first with the
-// default tiles, then the six tile shapes at the best leaf.  Results are
+// default tiles, then the twelve tile shapes at the best leaf.  Results are
 // cached per (ceil log2 n, dim, kernel, precision) for hodlr_tune_lookup.
 #include <chrono>
 #include <map>
@@ -52,7 +53,7 @@ struct Dev {
 // best wall time (ms) of one likelihood for this configuration
 double time_config(const double *x, int64_t n, int dim, int k, const double theta[2],
                    double sigma2, const double *y, double tol, const hodlr_opts &o, int leaf,
-                   int rows, int cols, int reps, hipStream_t s)
+                   int rows, int cols, int grp, int reps, hipStream_t s)
 {
     std::vector<int64_t> perm(n);
     if (o.presorted)
@@ -60,7 +61,7 @@ double time_config(const double *x, int64_t n, int dim, int k, const double thet
     else
         order_points(x, n, dim, leaf, perm.data());
     Plan plan;
-    plan_build(plan, n, dim, leaf, &o, rows, cols);
+    plan_build(plan, n, dim, leaf, &o, rows, cols, grp);
     if (plan.leafmax > LEAF_LDS_MAX)
         throw Error{HODLR_EINVAL, "leaf candidate above 128"};
     plan_upload(plan);
@@ -149,32 +150,33 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
         } sg{s};
         int slot = 0;
         double bt = 1e300;
-        hodlr_tune_t b{leaves[0], LVL_ROWS, 4};
+        hodlr_tune_t b{leaves[0], LVL_ROWS, 4, 8};
         for (int l : leaves) {
-            const double t = time_config(x, n, dim, k, theta, sigma2, y, tol, o, l, LVL_ROWS, 4,
+            const double t = time_config(x, n, dim, k, theta, sigma2, y, tol, o, l, LVL_ROWS, 4, 8,
                                          reps, s);
             if (times_ms)
                 times_ms[slot] = t;
             ++slot;
             if (t < bt) {
                 bt = t;
-                b = {l, LVL_ROWS, 4};
+                b = {l, LVL_ROWS, 4, 8};
             }
         }
-        const int rows_c[3] = {256, 512, 1024}, cols_c[2] = {4, 8};
+        const int rows_c[3] = {256, 512, 1024}, cols_c[2] = {4, 8}, grp_c[2] = {8, 64};
         const int leaf = b.leaf;
         for (int rr : rows_c)
-            for (int cc : cols_c) {
-                const double t = time_config(x, n, dim, k, theta, sigma2, y, tol, o, leaf, rr, cc,
-                                             reps, s);
-                if (times_ms)
-                    times_ms[slot] = t;
-                ++slot;
-                if (t < bt) {
-                    bt = t;
-                    b = {leaf, rr, cc};
+            for (int cc : cols_c)
+                for (int gg : grp_c) {
+                    const double t = time_config(x, n, dim, k, theta, sigma2, y, tol, o, leaf, rr,
+                                                 cc, gg, reps, s);
+                    if (times_ms)
+                        times_ms[slot] = t;
+                    ++slot;
+                    if (t < bt) {
+                        bt = t;
+                        b = {leaf, rr, cc, gg};
+                    }
                 }
-            }
         *best = b;
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[Key{ceil_log2(n), dim, (int)k, o.precision}] = b;

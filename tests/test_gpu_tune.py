@@ -37,9 +37,10 @@ def test_tile_shapes_give_the_same_likelihood(precision):
     res = []
     for rows in (256, 512, 1024):
         for cols in (4, 8):
-            t = H.Tune(128, rows, cols)
-            plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=precision), tune=t)
-            res.append(_dev_loglik(p, plan))
+            for grp in (8, 64):
+                t = H.Tune(128, rows, cols, grp)
+                plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=precision), tune=t)
+                res.append(_dev_loglik(p, plan))
     res = np.array(res)
     # FP64: reordered sums only; mixed: a reordered FP64 sum can move an FP32
     # store of W~ by one unit in the last place, which the coupling solves carry
@@ -56,6 +57,9 @@ def test_bad_tiles_are_rejected():
     with pytest.raises(H.HodlrError) as e:
         H.Plan(4096, 1, 64, None, tune=H.Tune(64, 300, 4))
     assert e.value.name == "EINVAL"
+    with pytest.raises(H.HodlrError) as e:
+        H.Plan(4096, 1, 64, None, tune=H.Tune(64, 512, 4, 16))
+    assert e.value.name == "EINVAL"
 
 
 def test_autotune_picks_its_fastest_candidate_and_caches_it():
@@ -64,14 +68,15 @@ def test_autotune_picks_its_fastest_candidate_and_caches_it():
     announce("autotune n=%d" % n)
     best, times = H.autotune(p.x, p.y, p.kernel, p.theta, p.sigma2, p.tol, H.Opts(max_rank=16),
                              leaf_cands=[64, 128], reps=2)
-    assert len(times) == 2 + 6 and all(t > 0 for t in times)
+    assert len(times) == 2 + 12 and all(t > 0 for t in times)
     assert best.leaf in (64, 128)
     assert best.level_rows in (256, 512, 1024) and best.reduce_cols in (4, 8)
     assert min(times) == pytest.approx(min(times[:2] + times[2:]))
     # the winner is the fastest timed candidate
-    shapes = [(64, 512, 4), (128, 512, 4)] + [(best.leaf, r, c) for r in (256, 512, 1024)
-                                              for c in (4, 8)]
-    assert shapes[int(np.argmin(times))] == (best.leaf, best.level_rows, best.reduce_cols)
+    shapes = [(64, 512, 4, 8), (128, 512, 4, 8)] + [(best.leaf, r, c, g) for r in (256, 512, 1024)
+                                                    for c in (4, 8) for g in (8, 64)]
+    assert shapes[int(np.argmin(times))] == (best.leaf, best.level_rows, best.reduce_cols,
+                                             best.reduce_group)
     again = H.tune_lookup(n, 1, p.kernel, H.FP64)
     assert again.as_dict() == best.as_dict()
     plan = H.Plan(n, 1, best.leaf, H.Opts(max_rank=16), tune=best)
