@@ -291,14 +291,39 @@ def bench_batched(args, torch, H, wl, dev):
     n, m = 65536, args.batch
     x, y, th = wl.batched_theta(m=m, n=n)
     mixed = args.precision == "mixed"
-    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=H.MIXED if mixed else H.FP64))
-    nb = plan.batch_workspace_bytes(m)
+    prec = H.MIXED if mixed else H.FP64
     d_x = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
     d_y = torch.from_numpy(y).to(dev)
     d_p = torch.from_numpy(np.ascontiguousarray(th)).to(dev)
-    work = torch.empty(nb, dtype=torch.uint8, device=dev)
     out = torch.zeros((m, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream()
+    # tiles: the autotuner's twelve shapes at leaf 128, each timed on this
+    # batched call (untimed in the rate); a shape tuned on one item is not
+    # always the best for a whole batch in one launch per stage
+    sweep = {}
+    best_t, tune = None, None
+    for rows in (256, 512, 1024):
+        for cols in (4, 8):
+            for grp in (8, 64):
+                t = H.Tune(128, rows, cols, grp)
+                pl = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=prec), tune=t)
+                nbt = pl.batch_workspace_bytes(m)
+                wk = torch.empty(nbt, dtype=torch.uint8, device=dev)
+                with torch.cuda.stream(stream):
+                    for rep_ in range(2):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        H.gp_loglik_batch_dev(pl, d_x, H.K_MATERN32, d_p, m, d_y, 0, 1e-10, wk,
+                                              nbt, stream, out, True)
+                        torch.cuda.synchronize()
+                        el = time.perf_counter() - t0
+                sweep["%d/%d/%d" % (rows, cols, grp)] = el * 1e3
+                if best_t is None or el < best_t:
+                    best_t, tune = el, t
+                del wk, pl
+    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=prec), tune=tune)
+    nb = plan.batch_workspace_bytes(m)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
 
     def step():
         H.gp_loglik_batch_dev(plan, d_x, H.K_MATERN32, d_p, m, d_y, 0, 1e-10, work, nb, stream,
@@ -323,7 +348,8 @@ def bench_batched(args, torch, H, wl, dev):
            "config": {"workload": "batched_theta_m%d_n%d%s" % (m, n, "_mixed" if mixed else ""),
                       "n": n, "items": m,
                       "kernel": "matern32", "leaf": 128, "tol": 1e-10, "max_rank": 16,
-                      "graph": True, "precision": args.precision},
+                      "graph": True, "precision": args.precision, "tiles": tune.as_dict()},
+           "tile_sweep_ms": sweep,
            "finite_items": int(np.isfinite(o[:, 0]).sum())}
     print(json.dumps(res), flush=True)
 
@@ -337,7 +363,18 @@ def bench_ragged(args, torch, H, wl, dev):
     m = 512
     xs, ys, th = wl.batched_ragged(m=m)
     mixed = args.precision == "mixed"
-    opts = H.Opts(max_rank=16, precision=H.MIXED if mixed else H.FP64)
+    prec = H.MIXED if mixed else H.FP64
+    opts = H.Opts(max_rank=16, precision=prec)
+    # autotune the tiles once per size class (first item of each class,
+    # untimed); the workers take them from the tuner's cache
+    tuned = {}
+    for i in range(m):
+        cls = int(np.ceil(np.log2(len(xs[i]))))
+        if cls not in tuned:
+            t, _ = H.autotune(xs[i], ys[i], H.K_MATERN32, th[i, :2], th[i, 2], 1e-10,
+                              H.Opts(max_rank=16, precision=prec, presorted=1),
+                              leaf_cands=[128], reps=1)
+            tuned[cls] = t.as_dict()
 
     def step():
         return H.gp_loglik_ragged(xs, ys, H.K_MATERN32, th, 128, 1e-10, opts, args.workers)
@@ -360,7 +397,8 @@ def bench_ragged(args, torch, H, wl, dev):
            "config": {"workload": "ragged_m%d_n1024to131072%s" % (m, "_mixed" if mixed else ""),
                       "items": m, "precision": args.precision,
                       "total_points": ntot, "kernel": "matern32", "leaf": 128, "tol": 1e-10,
-                      "max_rank": 16, "workers": args.workers, "host_buffers": True},
+                      "max_rank": 16, "workers": args.workers, "host_buffers": True,
+                      "tiles_per_size_class": {str(k): v for k, v in sorted(tuned.items())}},
            "points_per_s": args.steps * ntot / elapsed,
            "finite_items": int(np.isfinite(o[:, 0]).sum())}
     print(json.dumps(res), flush=True)

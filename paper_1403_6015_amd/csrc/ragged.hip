@@ -16,6 +16,9 @@
 
 using namespace hodlr;
 
+extern "C" hodlr_status hodlr_tune_lookup(int64_t n, int32_t dim, hodlr_kernel k,
+                                          int32_t precision, hodlr_tune_t *out);
+
 namespace hodlr {
 void prime_level_attributes();
 hodlr_status report(hodlr_status st, const std::string &msg);   // sets hodlr_last_error
@@ -118,13 +121,23 @@ void worker(RaggedJob *J)
                     xsoa[(size_t)d * n + k] = J->xs[i][perm[k] * dim + d];
             for (int64_t k = 0; k < n; ++k)
                 yord[k] = J->ys[i][perm[k]];
+            // tiles from the autotuner's cache for this size class, if tuned
+            // (the leaf size stays the caller's: it changes the approximation)
+            hodlr_tune_t tt{J->leaf, LVL_ROWS, 4, 8};
+            if (hodlr_tune_lookup(n, dim, (hodlr_kernel)J->kernel, J->opts.precision, &tt) !=
+                HODLR_OK)
+                tt = {J->leaf, LVL_ROWS, 4, 8};
             Plan plan;
-            plan_build(plan, n, dim, J->leaf, &J->opts);
+            plan_build(plan, n, dim, J->leaf, &J->opts, tt.level_rows, tt.reduce_cols,
+                       tt.reduce_group);
             if (plan.leafmax > LEAF_LDS_MAX)
                 throw Error{HODLR_EINVAL, "leaf above 128"};
             Layout lay = make_layout(plan, false);
             size_t tb = plan_image(plan, image);
             // arena: [workspace | tables | x | y]
+            if (a256(lay.total) + a256(tb) + a256(sizeof(double) * n * dim) +
+                    sizeof(double) * n > J->arena)
+                throw Error{HODLR_ENOMEM, "item layout exceeds the worker arena"};
             char *ws = arena;
             char *tables = arena + a256(lay.total);
             double *dx = (double *)(tables + a256(tb));
@@ -206,8 +219,10 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
         int64_t nmax = 1;
         for (int i = 0; i < m; ++i)
             nmax = std::max(nmax, ns[i]);
+        // the largest item with the smallest level chunks (256 rows: the most
+        // partial-sum records) bounds every item's layout
         Plan big;
-        plan_build(big, nmax, dim, leaf, &J.opts);
+        plan_build(big, nmax, dim, leaf, &J.opts, 256, 4, 8);
         std::vector<char> img;
         size_t tb = plan_image(big, img);
         Layout lay = make_layout(big, false);

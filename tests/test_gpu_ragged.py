@@ -37,10 +37,11 @@ def test_ragged_items_equal_single_calls_and_kalman(nworkers):
     for i in range(m):
         a, ell, s2 = th[i]
         ll, ld, q = H.gp_loglik(xs[i], ys[i], H.K_MATERN32, (a, ell), s2, 64, 1e-10, opts)
-        # same plan, same kernels, deterministic reductions
-        assert out[i, 0] == pytest.approx(ll, rel=1e-13, abs=1e-12), i
-        assert out[i, 1] == pytest.approx(ld, rel=1e-13, abs=1e-12), i
-        assert out[i, 2] == pytest.approx(q, rel=1e-13, abs=1e-12), i
+        # same tree and kernels; the workers may take autotuned tiles, which
+        # only reorder sums
+        assert out[i, 0] == pytest.approx(ll, rel=1e-12, abs=1e-12), i
+        assert out[i, 1] == pytest.approx(ld, rel=1e-12, abs=1e-12), i
+        assert out[i, 2] == pytest.approx(q, rel=1e-12, abs=1e-12), i
         kf = oracle.kalman_matern32(xs[i][:, 0], ys[i], (a, ell), s2, want_alpha=False)
         assert abs(out[i, 1] - kf["logdet"]) <= 1e-10 * max(abs(kf["logdet"]), 1.0), i
         assert abs(out[i, 0] - kf["loglik"]) <= 1e-9 * max(abs(kf["loglik"]), 1.0), i
