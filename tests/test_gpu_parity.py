@@ -204,15 +204,17 @@ def test_exact_matvec_matches_oracle_rows():
     assert np.allclose(out.cpu().numpy()[rows], ref, rtol=1e-12, atol=1e-12)
 
 
-def test_full_size_matern_against_kalman():
+@pytest.mark.parametrize("tiles", [None, (1024, 8, 64), (256, 4, 8)])
+def test_full_size_matern_against_kalman(tiles):
     """n = 2^20 Matern-3/2 workload (leaf 128, tol 1e-10) at the launch
-    configuration the benchmark times: log det, quad and C^{-1} y against the
-    exact Kalman oracle, and residual rows against the exact operator."""
+    configurations the benchmark times (default and autotuned tile shapes):
+    log det, quad and C^{-1} y against the exact Kalman oracle, and residual
+    rows against the exact operator."""
     import torch
     p = wl.matern1d()
-    announce("full size n=2^20 Matern-3/2 via gp_loglik_dev")
+    announce("full size n=2^20 Matern-3/2 via gp_loglik_dev tiles=%s" % (tiles,))
     dev = torch.device("cuda:0")
-    plan = H.Plan(p.n, 1, p.leaf)
+    plan = H.Plan(p.n, 1, p.leaf, tune=H.Tune(p.leaf, *tiles) if tiles else None)
     xs = torch.from_numpy(np.ascontiguousarray(p.x.T)).to(dev)
     ys = torch.from_numpy(p.y).to(dev)
     work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
@@ -232,3 +234,27 @@ def test_full_size_matern_against_kalman():
     # sampled residual rows, scaled like the full relative residual
     res = np.linalg.norm(p.y[rows] - cz) / np.linalg.norm(p.y[rows])
     assert res <= RES_TOL
+
+
+def test_full_size_matern_mixed_against_kalman():
+    """The mixed form at n = 2^20 on the device path (unrefined quadratic
+    form): log det within 1e-8 of the Kalman oracle, quad and C^{-1} y to the
+    FP32 storage level."""
+    import torch
+    p = wl.matern1d()
+    announce("full size n=2^20 Matern-3/2 mixed via gp_loglik_dev")
+    dev = torch.device("cuda:0")
+    plan = H.Plan(p.n, 1, p.leaf, H.Opts(precision=H.MIXED))
+    xs = torch.from_numpy(np.ascontiguousarray(p.x.T)).to(dev)
+    ys = torch.from_numpy(p.y).to(dev)
+    work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+    z = torch.empty(p.n, dtype=torch.float64, device=dev)
+    H.gp_loglik_dev(plan, xs, p.kernel, p.theta, p.sigma2, ys, p.tol, work, plan.workspace_bytes,
+                    None, out, z)
+    torch.cuda.synchronize()
+    ll, ld, q = out[:3].cpu().tolist()
+    kf = oracle.kalman_matern32(p.x[:, 0], p.y, p.theta, p.sigma2)
+    assert abs(ld - kf["logdet"]) <= 1e-8 * abs(kf["logdet"])
+    assert abs(q - kf["quad"]) <= 1e-6 * abs(kf["quad"])
+    assert np.linalg.norm(z.cpu().numpy() - kf["alpha"]) <= 1e-5 * np.linalg.norm(kf["alpha"])
