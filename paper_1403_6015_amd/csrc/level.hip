@@ -30,6 +30,9 @@ constexpr int LV_THREADS = 256;
 constexpr int LV_RT = 64;    // rows per LDS tile
 constexpr int LV_CT = 32;    // columns per LDS tile
 constexpr int LV_CB = 32;    // right-hand sides per batch in the node solve
+// threads per node in the node solve (n = 2^20: 256 threads 0.37 ms per
+// likelihood, one wave 0.81 ms)
+constexpr int LV_SOLVE_TH = 256;
 
 struct LevelArgs {
     int64_t n;
@@ -259,7 +262,8 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArg
     }
 }
 
-__global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
+template <int TH>
+__global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
     const int64_t loc = blockIdx.x;
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
 #define t1(i, c) t1b[(i) * (LV_CB + 1) + (c)]
 #define t2(i, c) t2b[(i) * (LV_CB + 1) + (c)]
     __shared__ int piv[RMAX_ABS];
-    __shared__ double red[4];
+    __shared__ double red[TH / 64];
     __shared__ int sbad;
     const int nch = A.nch[loc], base = A.base[loc];
     const int ncnt = A.ncnt, rs = A.rstride;
@@ -293,9 +297,9 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
         // node's records; groups stay inside one wave for the final sum
         const int nout = 2 * r * ncnt;
         int G = 1;
-        while (G < 64 && G * 2 * nout <= LV_THREADS && G < nch)
+        while (G < 64 && G * 2 * nout <= TH && G < nch)
             G *= 2;
-        const int per = LV_THREADS / G;   // outputs per pass
+        const int per = TH / G;   // outputs per pass
         const int sub = tid % G;
         for (int o0 = 0; o0 < nout; o0 += per) {
             const int o = o0 + tid / G;
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
     double *sm = A.small + h * A.sstride;   // [N_LU r*r | P r*r | Q r*r | piv r]
     if (A.factor) {
         const int cp = A.nrhs;   // the child panel's columns follow the updated ones
-        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * r; idx += TH) {
             int i = idx / r, j = idx % r;
             sP(i, j) = T[(int64_t)i * ncnt + cp + j];
             sQ(i, j) = T[(int64_t)(rs + i) * ncnt + cp + j];
@@ -329,7 +333,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
         if (tid == 0)
             sbad = 0;
         __syncthreads();
-        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * r; idx += TH) {
             int i = idx / r, j = idx % r;
             double a = (i == j) ? 1.0 : 0.0;
             for (int k = 0; k < r; ++k)
@@ -354,19 +358,19 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
             __syncthreads();
             int p = piv[k];
             if (p != k)
-                for (int j = tid; j < r; j += LV_THREADS) {
+                for (int j = tid; j < r; j += TH) {
                     double a = sN(k, j);
                     sN(k, j) = sN(p, j);
                     sN(p, j) = a;
                 }
             __syncthreads();
             double pv = sN(k, k);
-            for (int i = k + 1 + tid; i < r; i += LV_THREADS)
+            for (int i = k + 1 + tid; i < r; i += TH)
                 if (pv != 0.0)
                     sN(i, k) /= pv;
             __syncthreads();
             int tr = r - k - 1;
-            for (int idx = tid; idx < tr * tr; idx += LV_THREADS) {
+            for (int idx = tid; idx < tr * tr; idx += TH) {
                 int i = k + 1 + idx / tr, j = k + 1 + idx % tr;
                 sN(i, j) -= sN(i, k) * sN(k, j);
             }
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
         // log det M = log det(I - QP); it must be positive for an SPD C
         double lg = 0.0;
         int neg = 0;
-        for (int i = tid; i < r; i += LV_THREADS) {
+        for (int i = tid; i < r; i += TH) {
             double u = sN(i, i);
             lg += log(fabs(u));
             neg += (u < 0.0) ? 1 : 0;
@@ -391,29 +395,31 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
         }
         __syncthreads();
         if (tid == 0) {
-            double v = (red[0] + red[1]) + (red[2] + red[3]);
+            double v = red[0];
+            for (int w = 1; w < TH / 64; ++w)
+                v += red[w];
             if (sbad) {
                 atomicOr(A.status, DS_NOTSPD_NODE);
                 v = __builtin_nan("");
             }
             A.node_ld[h] = v;
         }
-        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * r; idx += TH) {
             int i = idx / r, j = idx % r;
             sm[idx] = sN(i, j);
             sm[r * r + idx] = sP(i, j);
             sm[2 * r * r + idx] = sQ(i, j);
         }
-        for (int i = tid; i < r; i += LV_THREADS)
+        for (int i = tid; i < r; i += TH)
             sm[3 * r * r + i] = (double)piv[i];
     } else {
-        for (int idx = tid; idx < r * r; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * r; idx += TH) {
             int i = idx / r, j = idx % r;
             sN(i, j) = sm[idx];
             sP(i, j) = sm[r * r + idx];
             sQ(i, j) = sm[2 * r * r + idx];
         }
-        for (int i = tid; i < r; i += LV_THREADS)
+        for (int i = tid; i < r; i += TH)
             piv[i] = (int)sm[3 * r * r + i];
     }
     __syncthreads();
@@ -422,13 +428,13 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
     const int nrhs = A.nrhs;
     for (int c0 = 0; c0 < nrhs; c0 += LV_CB) {
         const int nb = min(LV_CB, nrhs - c0);
-        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * nb; idx += TH) {
             int i = idx / nb, c = idx % nb;
             t1(i, c) = T[(int64_t)i * ncnt + c0 + c];
         }
         __syncthreads();
         // t2 := t2 - Q t1, with the row permutation of the LU applied after
-        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * nb; idx += TH) {
             int i = idx / nb, c = idx % nb;
             double a = T[(int64_t)(rs + i) * ncnt + c0 + c];
             for (int k = 0; k < r; ++k)
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_solve_kernel(LevelArgs A0)
             }
         }
         __syncthreads();
-        for (int idx = tid; idx < r * nb; idx += LV_THREADS) {
+        for (int idx = tid; idx < r * nb; idx += TH) {
             int i = idx / nb, c = idx % nb;
             double a = t1(i, c);
             for (int k = 0; k < r; ++k)
@@ -526,7 +532,7 @@ static size_t solve_lds(int rs)
 {
     static bool attr = false;   // allow the rank-64 size (about 134 KB) once per process
     if (!attr) {
-        HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel,
+        HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel<LV_SOLVE_TH>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         attr = true;
     }
@@ -610,7 +616,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
-        level_solve_kernel<<<dim3(nodes, 1, P.nitems), LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
+        level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
@@ -647,7 +653,7 @@ void run_levels_factor(Pipeline &P)
             // every block of this level has rank 0: coupling determinants are 1
             const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
             ProfScope ps(P.stream, PS_LVL_SOLVE);
-            level_solve_kernel<<<dim3(nodes, 1, P.nitems), LV_THREADS, solve_lds(A.rstride), P.stream>>>(A);
+            level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
             HIP_TRY(hipGetLastError());
             continue;
         }
