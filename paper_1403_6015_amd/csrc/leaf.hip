@@ -1,12 +1,15 @@
 // Leaf stage: the dense diagonal blocks C_lambda = K(lambda, lambda) +
 // sigma^2 I of the finest level (the factor K_kappa of §3.2), their Cholesky
-// factors and log-dets, and the application of C_lambda^{-1} to the rows of
-// every off-diagonal basis that covers the leaf ("a p x p inverse ... applied
-// to all left low-rank factors", §3.3) together with the right-hand side.
+// factors and log-dets, and C_lambda^{-1} applied to the leaf's rows of every
+// off-diagonal basis above it and of the right-hand side (§3.3 notes that this
+// application, not the small inverse itself, is what costs most at the leaves).
 //
 // One work-group per leaf.  The block is evaluated on the fly from the
-// ordered coordinates straight into LDS (packed lower triangle), factored
-// there, and the basis columns stream through LDS in batches.
+// ordered coordinates straight into LDS as 16 x 16 tiles of its lower
+// triangle, factored there on FP64 MFMA, and the basis columns are solved in
+// registers, 16 columns per wave at a time.
+#include <utility>
+
 #include "common.h"
 
 namespace hodlr {
@@ -111,73 +114,98 @@ __device__ __forceinline__ d4 tile_mma(const double *A, const double *B, d4 acc)
     return acc;
 }
 
-__device__ __forceinline__ double rdlane(double v, int lane)
+// Lane K of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
+// In the diagonal-tile wave the four rows hold identical copies, so every lane
+// receives lane K's value, and it arrives in a VGPR: read-lanes would route
+// each broadcast through SGPRs, which run out when many broadcasts are live.
+template <int K>
+__device__ __forceinline__ double row_bcast(double v)
 {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, true);
 }
 
-// Cholesky of one 16 x 16 diagonal tile (column-major in LDS); the tile is
-// overwritten with the inverse of its lower factor.  One wave.
-//   factor (Crout, column by column): lane i < 16 keeps row i of the factor in
-//     registers; step j broadcasts row j (held by lane j) with read-lanes, and
-//     the pivot of column j moves to all lanes with one more read-lane;
-//   inverse: in the same step j, lane c extends column c of L^{-1} by its
-//     row j, Linv[j][c] = (delta_jc - sum_k L[j][k] Linv[k][c]) / L[j][j],
-//     reusing the broadcast row L[j][.] (two independent FMA chains per step).
-// If g is given, the factor's rows (global rows row0 + i < m) go to the packed
-// lower store.  Returns sum_i log L_ii (uniform) or NaN on a bad pivot.
-__device__ __forceinline__ double diag_factor(double *T, double *g, int row0, int m)
+// Pivot step J of the right-looking Cholesky of a 16 x 16 diagonal tile.
+// Lane i (i = lane % 16) holds row i of the partly reduced tile in a[] and
+// column i of L^{-1} in x[] (the forward substitution L y = e_i, kept as its
+// running right-hand side).  With d = A[J][J] and rr = 1/sqrt(d):
+//   L[i][J] = A[i][J] rr on every lane, so lane k's value is L[k][J];
+//   A[i][k] -= L[i][J] L[k][J]   for k > J   (trailing update of row i);
+//   y[J] = w[J] rr, w[k] -= L[k][J] y[J]   for k > J   (substitution step).
+// Only the pivot's reciprocal square root is serial; the 2 (15 - J) updates
+// are independent of each other.
+template <int J, int K>
+__device__ __forceinline__ void pivot_update(double (&a)[16], double (&x)[16], double lij, double yj)
+{
+    if constexpr (K > J) {
+        const double lkj = row_bcast<K>(lij);
+        a[K] -= lij * lkj;
+        x[K] -= lkj * yj;
+    }
+}
+
+template <int J, int... K>
+__device__ __forceinline__ void pivot_updates(double (&a)[16], double (&x)[16], double lij, double yj,
+                                              std::integer_sequence<int, K...>)
+{
+    (pivot_update<J, K>(a, x, lij, yj), ...);
+}
+
+template <int J>
+__device__ __forceinline__ void pivot_step(double (&a)[16], double (&x)[16], double &mydiag, bool &bad,
+                                           int ii)
+{
+    const double d = row_bcast<J>(a[J]);
+    bad = bad || !(d > 0.0);
+    // 1/sqrt(d): hardware estimate refined by two Newton steps
+    // r <- r (3 - d r^2) / 2 (quadratic convergence: full FP64 from ~23
+    // bits), then L_JJ = d r; no correctly rounded divide or square root on
+    // this serial path.  A non-positive pivot continues as 1 (flagged).
+    const double dd = d > 0.0 ? d : 1.0;
+    double rr = __builtin_amdgcn_rsq(dd);
+    rr = rr * (1.5 - 0.5 * dd * rr * rr);
+    rr = rr * (1.5 - 0.5 * dd * rr * rr);
+    const double gj = dd * rr;
+    const double lij = a[J] * rr;
+    const double yj = x[J] * rr;
+    x[J] = yj;
+    pivot_updates<J>(a, x, lij, yj, std::make_integer_sequence<int, 16>{});
+    a[J] = (ii == J) ? gj : lij;
+    mydiag = (ii == J) ? gj : mydiag;
+}
+
+template <int... J>
+__device__ __forceinline__ void pivot_steps(double (&a)[16], double (&x)[16], double &mydiag, bool &bad,
+                                            int ii, std::integer_sequence<int, J...>)
+{
+    (pivot_step<J>(a, x, mydiag, bad, ii), ...);
+}
+
+// Cholesky of one 16 x 16 diagonal tile (column-major in LDS) by one wave.
+// The tile is overwritten with the inverse of its lower factor, the factor's
+// diagonal goes to diag[0..15], and if g is given the factor's rows (global
+// rows row0 + i < m) go to the packed lower store.  Returns true if a pivot
+// was not positive (the factorization then continues with pivot 1, so every
+// value stays finite).
+__device__ __forceinline__ bool diag_factor(double *T, double *diag, double *g, int row0, int m)
 {
     const int lane = threadIdx.x & 63;
     const int ii = lane & 15;
-    double a[16];
+    double a[16], x[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
+    for (int c = 0; c < 16; ++c) {
         a[c] = T[c * TLD + ii];
-    double x[16];          // column ii of L^{-1}, built row by row with the factor
-    double mydiag = 1.0;   // L[ii][ii]
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        // column j of L (lane i: L[i][j]) and row j of L^{-1} (lane c:
-        // Linv[j][c]) from the same broadcast row L[j][0..j-1] of lane j
-        double s0 = a[j], s1 = 0.0;
-        double t0 = (ii == j) ? 1.0 : 0.0, t1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            const double ljk = rdlane(a[k], j);   // L[j][k], held by lane j
-            if (k & 1) {
-                s1 -= a[k] * ljk;
-                t1 -= ljk * x[k];
-            } else {
-                s0 -= a[k] * ljk;
-                t0 -= ljk * x[k];
-            }
-        }
-        const double sj = s0 + s1;
-        const double d = rdlane(sj, j);
-        bad = bad || !(d > 0.0);
-        // 1/sqrt(d): hardware estimate refined by two Newton steps
-        // r <- r (3 - d r^2) / 2 (quadratic convergence: full FP64 from ~23
-        // bits), then L_jj = d r; no correctly rounded divide or square root
-        // on this serial path
-        const double dd = d > 0.0 ? d : 1.0;
-        double rr = __builtin_amdgcn_rsq(dd);
-        rr = rr * (1.5 - 0.5 * dd * rr * rr);
-        rr = rr * (1.5 - 0.5 * dd * rr * rr);
-        const double gj = dd * rr;
-        a[j] = (ii == j) ? gj : sj * rr;
-        mydiag = (ii == j) ? gj : mydiag;
-        x[j] = (t0 + t1) * rr;
+        x[c] = (c == ii) ? 1.0 : 0.0;
     }
-    double lg = (lane < 16) ? log(mydiag) : 0.0;
-    lg += __shfl_xor(lg, 8, 64);
-    lg += __shfl_xor(lg, 4, 64);
-    lg += __shfl_xor(lg, 2, 64);
-    lg += __shfl_xor(lg, 1, 64);
-    lg = rdlane(lg, 0);
+    double mydiag = 1.0;
+    bool bad = false;
+    pivot_steps(a, x, mydiag, bad, ii, std::make_integer_sequence<int, 16>{});
+    // Only lanes 0-15 store the inverse.  This empty asm gives its values a
+    // use on every lane, so the compiler cannot sink the substitution out of
+    // the pivot steps into that conditional store, which would keep all 120
+    // broadcasts live until then.
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        asm volatile("" : "+v"(x[k]));
     if (g && lane < 16) {
         const int i = row0 + ii;
         if (i < m) {
@@ -188,11 +216,12 @@ __device__ __forceinline__ double diag_factor(double *T, double *g, int row0, in
         }
     }
     if (lane < 16) {
+        diag[ii] = mydiag;
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             T[ii * TLD + i] = (i >= ii) ? x[i] : 0.0;
     }
-    return bad ? __builtin_nan("") : lg;
+    return bad;
 }
 
 // acc += op(A) * B with A in LDS (op = identity or transpose) and B a tile
@@ -217,7 +246,9 @@ template <typename PT>
 __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 {
     __shared__ double Gt[NTRI * TSZ];   // lower factor tiles; diagonal slots hold L_JJ^{-1}
-    __shared__ double s_lg;
+    __shared__ double s_diag[LEAF_LDS_MAX];   // diagonal of the factor
+    __shared__ double s_red[LEAF_MW];
+    __shared__ int s_bad;
     const int tid = threadIdx.x, wid = tid >> 6;
     const int l = tid & 63, r = l & 15, q = l >> 4;
     const int it = blockIdx.z;   // batch item
@@ -279,9 +310,9 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         }
     }
     __syncthreads();
-    double lgsum = 0.0;   // wave 0 only
+    bool bad = false;   // wave 0 only
     if (wid == 0)
-        lgsum += diag_factor(Gt, gout, 0, m);
+        bad = diag_factor(Gt, s_diag, gout, 0, m);
     __syncthreads();
     for (int J = 0; J < nt; ++J) {
         // panel: L_IJ = C_IJ L_JJ^{-T}
@@ -304,12 +335,14 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     T[r * TLD + q + 4 * t] -= acc[t];
-                lgsum += diag_factor(T, gout, 16 * (J + 1), m);
+                bad = diag_factor(T, s_diag + 16 * (J + 1), gout, 16 * (J + 1), m) || bad;
             }
-            // remaining trailing tiles C_IK -= L_IJ L_KJ^T (J < K <= I), other waves first
+            // remaining trailing tiles C_IK -= L_IJ L_KJ^T (J < K <= I) on the
+            // other three waves, so that nothing waits behind the serial
+            // diagonal factorization on wave 0
             const int Tn = nt - 1 - J;
             const int ntask = Tn * (Tn + 1) / 2 - 1;
-            for (int task = (wid + LEAF_MW - 1) % LEAF_MW; task < ntask; task += LEAF_MW) {
+            for (int task = wid - 1; wid > 0 && task < ntask; task += LEAF_MW - 1) {
                 int tt = task + 1;   // skip the look-ahead tile (I = K = J+1)
                 int I = 0;
                 while ((I + 1) * (I + 2) / 2 <= tt)
@@ -327,11 +360,24 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         }
         __syncthreads();
     }
+    // log det of the leaf, 2 sum_i log L_ii over its real rows: one log per
+    // thread, off the serial path of the factorization
+    double lgp = 0.0;
+    if (tid < m)
+        lgp = log(s_diag[tid]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        lgp += __shfl_xor(lgp, o, 64);
+    if (l == 0)
+        s_red[wid] = lgp;
     if (tid == 0)
-        s_lg = lgsum;
+        s_bad = bad ? 1 : 0;
     __syncthreads();
-    const double lg = s_lg;
-    if (!(lg == lg)) {
+    double lg = 0.0;
+#pragma unroll
+    for (int w = 0; w < LEAF_MW; ++w)
+        lg += s_red[w];
+    if (s_bad || !(lg == lg)) {
         if (tid == 0) {
             atomicOr(status, DS_NOTSPD_LEAF);
             leaf_ld[b] = __builtin_nan("");
