@@ -285,27 +285,74 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
             xk[d][I] = (d < kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
         }
     }
+    // Separable form for 1-D exponential-family kernels on an ascending leaf:
+    // for x_i >= x_k, exp(-c (x_i - x_k)) = E_i F_k with E_i = exp(-c (x_i -
+    // x_0)) and F_k = exp(c (x_k - x_0)), x_0 the leaf's first point, so a
+    // thread takes 16 exponentials instead of one exponential and one square
+    // root per entry.  Used when the leaf is checked to be in ascending order
+    // and c times its span is below 500 (every factor far inside the FP64
+    // range); the entries then differ from direct evaluation by a few units
+    // in the last place, and the diagonal is exactly a^2 + sigma^2.
+    const bool sep_kind = kp.dim == 1 && (kp.kind == HODLR_K_MATERN32 || kp.kind == HODLR_K_EXP);
+    const int unsorted = (sep_kind && tid + 1 < m && A.x[s + tid + 1] < A.x[s + tid]) ? 1 : 0;
+    const int any_unsorted = __syncthreads_or(unsorted);
+    const double x0 = A.x[s];
+    const bool sep = sep_kind && !any_unsorted && kp.c * (A.x[s + m - 1] - x0) < 500.0;
+    // Entries above the diagonal of a diagonal tile are never read by the
+    // factorization (it works on the lower triangle) and are left zero.
+    if (sep) {
+        double E[NT_MAX], F[NT_MAX];
 #pragma unroll
-    for (int I = 0; I < NT_MAX; ++I) {
+        for (int I = 0; I < NT_MAX; ++I) {
+            E[I] = (16 * I + rr < m) ? exp(-kp.c * (xr[0][I] - x0)) : 0.0;
+            F[I] = (16 * I + cc < m) ? exp(kp.c * (xk[0][I] - x0)) : 0.0;
+        }
 #pragma unroll
-        for (int K = 0; K <= I; ++K) {
-            if (I < nt) {
-                int i = 16 * I + rr, k = 16 * K + cc;
-                double v;
-                if (i < m && k < m) {
-                    double r2 = 0.0;
+        for (int I = 0; I < NT_MAX; ++I) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        double t = xr[d][I] - xk[d][K];
-                        r2 += t * t;
+            for (int K = 0; K <= I; ++K) {
+                if (I < nt) {
+                    const int i = 16 * I + rr, k = 16 * K + cc;
+                    double v;
+                    if (i < m && k < m) {
+                        if (i > k) {
+                            const double e = E[I] * F[K];
+                            v = kp.kind == HODLR_K_MATERN32
+                                    ? kp.a2 * (1.0 + kp.c * (xr[0][I] - xk[0][K])) * e
+                                    : kp.a2 * e;
+                        } else {
+                            v = (i == k) ? kp.a2 + kp.sigma2 : 0.0;
+                        }
+                    } else {
+                        v = (i == k) ? 1.0 : 0.0;
                     }
-                    v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
-                    if (i == k)
-                        v += kp.sigma2;
-                } else {
-                    v = (i == k) ? 1.0 : 0.0;
+                    Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
                 }
-                Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int I = 0; I < NT_MAX; ++I) {
+#pragma unroll
+            for (int K = 0; K <= I; ++K) {
+                if (I < nt) {
+                    const int i = 16 * I + rr, k = 16 * K + cc;
+                    double v;
+                    if (i < m && k < m && i >= k) {
+                        double r2 = 0.0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            double t = xr[d][I] - xk[d][K];
+                            r2 += t * t;
+                        }
+                        v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
+                        if (i == k)
+                            v += kp.sigma2;
+                    } else {
+                        v = (i == k) ? 1.0 : 0.0;
+                    }
+                    Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
+                }
             }
         }
     }
