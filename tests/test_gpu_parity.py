@@ -110,6 +110,33 @@ def test_exponential_exact_rank_one():
     assert max(info["rank_max"]) <= 2
 
 
+@pytest.mark.parametrize("kind", [wl.K_MATERN32, wl.K_EXP])
+def test_leaves_of_every_span(kind):
+    """Leaves whose span keeps the separable exponentials in range and leaves
+    where it does not (evaluated entry by entry) in one 1-D problem."""
+    p = wl.clustered1d(4096, kind)
+    check_against_dense(p, ld_tol=1e-12)
+
+
+def test_presorted_input_out_of_order_inside_leaves():
+    """presorted = 1 with adjacent pairs swapped inside leaves: those leaves
+    fail the in-kernel order check and are evaluated entry by entry; the
+    factorization is still of the matrix in the caller's order."""
+    p = wl.matern1d(4096)
+    x = p.x.copy()
+    for i in range(5, p.n - 1, 97):
+        x[[i, i + 1]] = x[[i + 1, i]]
+    q = wl.GPProblem(p.name + "_swapped", x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol)
+    announce("presorted out of order n=%d" % q.n)
+    ref = oracle.gp_dense(q.x, q.y, q.kernel, q.theta, q.sigma2)
+    f = H.hodlr_build(q.x, q.kernel, q.theta, q.sigma2, q.leaf, q.tol, H.Opts(presorted=1))
+    ld = f.logdet()
+    alpha = f.solve(q.y)
+    f.free()
+    assert abs(ld - ref["logdet"]) <= LD_TOL * abs(ref["logdet"])
+    assert dense_residual(q, alpha) <= RES_TOL
+
+
 def test_constant_kernel_closed_form():
     p = wl.rank1_points(1000)
     announce("constant kernel n=1000 leaf=16")

@@ -87,6 +87,21 @@ def matern1d(n: int = 1 << 20, span: float | None = None) -> GPProblem:
                      meta={"span": span})
 
 
+def clustered1d(n: int = 4096, kernel: int = K_MATERN32, seed: int = 103) -> GPProblem:
+    """Half the points ~ U(0, 1), half ~ U(100, 1000), sorted; y ~ N(0,1).
+
+    With l = 0.1 the leaves of the dense half span about c * 0.06 in units of
+    the kernel's decay, those of the sparse half thousands, so one problem has
+    leaves of both kinds for kernels whose leaf evaluation depends on the span.
+    """
+    rng = np.random.default_rng(seed)
+    h = n // 2
+    x = np.sort(np.concatenate([rng.uniform(0.0, 1.0, h), rng.uniform(100.0, 1000.0, n - h)]))
+    y = np.random.default_rng(seed + 100).standard_normal(n)
+    return GPProblem("clustered1d_n%d_k%d" % (n, kernel), x.astype(np.float64).reshape(n, 1), y,
+                     kernel, (1.0, 0.1), 0.05, 128, 1e-12)
+
+
 def se2d(n: int = 1 << 22, side: float | None = None, max_rank: int = 64) -> GPProblem:
     """2-D points ~ U([0,side]^2) (seed 103), y ~ N(0,1) (seed 203), SE l=0.05.
 
