@@ -813,10 +813,23 @@ __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const i
     if (threadIdx.x == 0)
         scap = 0;
     __syncthreads();
+    // nodes of depth d are the heap range [2^d - 1, 2^(d+1) - 1): a register
+    // maximum per depth, then one LDS atomic per wave
     int mycap = 0;
-    for (int64_t h = threadIdx.x; h < nint; h += 256) {
-        atomicMax(&smax[depth_of_node(h) + 1], rank[h]);
-        mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
+    for (int d = 0; d < 62; ++d) {
+        const int64_t h0 = ((int64_t)1 << d) - 1;
+        if (h0 >= nint)
+            break;
+        const int64_t h1 = std::min<int64_t>(nint, ((int64_t)2 << d) - 1);
+        int m = 0;
+        for (int64_t h = h0 + threadIdx.x; h < h1; h += 256) {
+            m = std::max(m, rank[h]);
+            mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            m = std::max(m, __shfl_xor(m, off, 64));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax(&smax[d + 1], m);
     }
     atomicAdd(&scap, mycap);
     __syncthreads();

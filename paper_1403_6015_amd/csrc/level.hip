@@ -56,6 +56,7 @@ struct LevelArgs {
     int *status;
     int factor;        // 1: build the coupling factors; 0: apply stored ones
     int cgrp;          // columns per work-group of the small-rank reduction
+    int rows;          // rows per chunk (a node's chunks: its alpha rows, then its beta rows)
     BatchArgs B;
 };
 
@@ -294,7 +295,12 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
     {
         // each output gets a power-of-two group of threads that splits the
-        // node's records; groups stay inside one wave for the final sum
+        // node's records; groups stay inside one wave for the final sum.
+        // The node's records are its alpha chunks, then its beta chunks, so
+        // each side is one contiguous range (na = alpha chunks).
+        const int64_t ns = A.chunks[base].lo, ne = A.chunks[base + nch - 1].hi;
+        const int64_t alen = (ne - ns) / 2;
+        const int na = (int)((alen + A.rows - 1) / A.rows);
         const int nout = 2 * r * ncnt;
         int G = 1;
         while (G < 64 && G * 2 * nout <= TH && G < nch)
@@ -310,9 +316,19 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
                 c = o % ncnt;
                 side = row2 < r ? 1 : 0;
                 l = row2 < r ? row2 : row2 - r;
-                for (int q = base + sub; q < base + nch; q += G)
-                    if (A.chunks[q].side == side)
-                        acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+                const int q1 = side ? base + nch : base + na;
+                int q = (side ? base + na : base) + sub;
+                // four independent partial sums keep several loads in flight
+                double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                for (; q + 3 * G < q1; q += 4 * G) {
+                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+                    a1 += A.part[((int64_t)(q + G) * rs + l) * ncnt + c];
+                    a2 += A.part[((int64_t)(q + 2 * G) * rs + l) * ncnt + c];
+                    a3 += A.part[((int64_t)(q + 3 * G) * rs + l) * ncnt + c];
+                }
+                for (; q < q1; q += G)
+                    acc += A.part[((int64_t)q * rs + l) * ncnt + c];
+                acc = (acc + a1) + (a2 + a3);
             }
             for (int off = G / 2; off > 0; off >>= 1)
                 acc += __shfl_xor(acc, off, 64);
@@ -566,6 +582,7 @@ static LevelArgs level_args(Pipeline &P, int d)
     A.status = wsp<int>(P, P.lay.status);
     A.B = P.batch;
     A.cgrp = p.red_grp;
+    A.rows = p.lvl_rows;
     return A;
 }
 

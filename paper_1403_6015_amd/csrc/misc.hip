@@ -32,6 +32,23 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
 }
 
 // one work-group: fixed-order sums, so repeated calls agree bit for bit
+// this thread's share (stride 256) of v[0, cnt), as four independent sums
+// so that several loads are in flight
+__device__ __forceinline__ double strided_sum(const double *v, int64_t cnt)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t i = threadIdx.x;
+    for (; i + 768 < cnt; i += 1024) {
+        s0 += v[i];
+        s1 += v[i + 256];
+        s2 += v[i + 512];
+        s3 += v[i + 768];
+    }
+    for (; i < cnt; i += 256)
+        s0 += v[i];
+    return (s0 + s1) + (s2 + s3);
+}
+
 __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int64_t nleaf,
                                                      const double *node_ld, int64_t nint,
                                                      const double *dpart, int ndp, int64_t n,
@@ -43,13 +60,9 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int6
     dpart = ioff(dpart, B, it);
     out += (int64_t)it * ostride;
     __shared__ double red[3][4];
-    double a = 0.0, b = 0.0, q = 0.0;
-    for (int64_t i = threadIdx.x; i < nleaf; i += 256)
-        a += leaf_ld[i];
-    for (int64_t i = threadIdx.x; i < nint; i += 256)
-        b += node_ld[i];
-    for (int i = threadIdx.x; i < ndp; i += 256)
-        q += dpart[i];
+    double a = strided_sum(leaf_ld, nleaf);
+    double b = strided_sum(node_ld, nint);
+    double q = strided_sum(dpart, ndp);
     a = wave_sum(a);
     b = wave_sum(b);
     q = wave_sum(q);
