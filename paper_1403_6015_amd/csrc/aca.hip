@@ -27,10 +27,12 @@
 
 namespace hodlr {
 
-// work-group size of the small-block path.  Measured at n = 2^20: 256 threads
-// 0.39 ms, 128 threads 0.49 ms, one wave 0.42 ms (no barriers, but 32 entries
-// per lane need 256 VGPRs): the per-step cost is the re-reads of the earlier
-// terms, not the work-group reductions.
+// work-group size of the small-block path for blocks with a side above
+// ACA_TINY; blocks with both sides <= ACA_TINY run on one wave (four entries
+// per lane, wave reductions only).  Measured at n = 2^20: all blocks on 256
+// threads 0.39 ms, on 128 threads 0.49 ms, on one wave 0.42 ms (32 entries
+// per lane need 256 VGPRs); 256 threads plus one wave for the 128- and
+// 256-point sides (6144 of the 7936 blocks) 0.22 ms.
 constexpr int ACA_SMALL_TH = 256;
 
 
@@ -122,12 +124,12 @@ struct SmallArgs {
     int *status;        // per node AcaDone
 };
 
-template <int TH>
+template <int TH, int MAXS>
 __global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
 {
     const AcaArgs &A = S.a;
     const int64_t h = S.nodes[blockIdx.x];
-    constexpr int EPT = ACA_SMALL / TH;   // entries per thread
+    constexpr int EPT = MAXS / TH;   // entries per thread (block sides <= MAXS)
     const int tid = threadIdx.x;
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
     const int64_t na = m - s, nb = e - m, n = A.n;
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
     __shared__ int64_t ri[4];
     __shared__ double sfix[RMAX_ABS];
     __shared__ double vdot[RMAX_ABS];
-    __shared__ unsigned char used[ACA_SMALL];
+    __shared__ unsigned char used[MAXS];
     const int64_t full = na < nb ? na : nb;
     const int cap = (int)(A.cap < full ? A.cap : full);
     const bool usercap = A.cap < full;
@@ -911,8 +913,19 @@ void run_aca(Pipeline &P)
         S.rank = rank;
         S.status = status;
         ProfScope ps(s, PS_ACA_SMALL);
-        aca_small_kernel<ACA_SMALL_TH><<<(unsigned)p.aca_small.size(), ACA_SMALL_TH, 0, s>>>(S);
-        HIP_TRY(hipGetLastError());
+        // blocks with both sides <= ACA_TINY (listed last) run on one wave,
+        // with wave-level reductions only
+        const int nwide = p.aca_small_wide;
+        if (nwide > 0) {
+            aca_small_kernel<ACA_SMALL_TH, ACA_SMALL><<<(unsigned)nwide, ACA_SMALL_TH, 0, s>>>(S);
+            HIP_TRY(hipGetLastError());
+        }
+        const int ntiny = (int)p.aca_small.size() - nwide;
+        if (ntiny > 0) {
+            S.nodes = p.d_aca_small + nwide;
+            aca_small_kernel<64, ACA_TINY><<<(unsigned)ntiny, 64, 0, s>>>(S);
+            HIP_TRY(hipGetLastError());
+        }
     }
     const int nbig = (int)p.aca_big.size();
     if (nbig > 0) {

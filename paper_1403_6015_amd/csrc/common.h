@@ -17,6 +17,7 @@ namespace hodlr {
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
 constexpr int ACA_CHUNK = 1024;   // block entries per work-group and pass (large blocks)
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
+constexpr int ACA_TINY = 256;     // ... and on a single wave when both sides are <= this
 constexpr int ACA_THREADS = 256;
 constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
 constexpr int LVL_ROWS = 512;     // default rows per level work-group
@@ -233,6 +234,7 @@ struct Plan {
     int64_t ncol = 1;                  // columns of W / Xt (column 0 is the solve vector)
     // cross-approximation tables
     std::vector<int> aca_small;            // heap indices of blocks done by one work-group
+    int aca_small_wide = 0;                // the first ones, with a side above ACA_TINY
     std::vector<int> aca_big;              // heap indices of multi-work-group blocks
     int aca_big_active = 0;                // big blocks with a positive rank cap
     std::vector<Chunk> aca_row, aca_col;   // big blocks: chunks over beta / alpha

@@ -143,6 +143,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
     p.pad_chunks.clear();
     p.aca_big_active = 0;
     int rslot = 0, cslot = 0, pslot = 0;
+    std::vector<int> tiny;   // small blocks with both sides <= ACA_TINY, listed last
     for (int64_t h = 0; h < p.nint; ++h) {
         int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
         if (m - s == 0 || e - m == 0 || p.cap == 0)
@@ -150,7 +151,10 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
         make_chunks((int)h, 0, s, m, 4096, p.pad_chunks, pslot);
         make_chunks((int)h, 1, m, e, 4096, p.pad_chunks, pslot);
         if (m - s <= ACA_SMALL && e - m <= ACA_SMALL) {
-            p.aca_small.push_back((int)h);
+            if (m - s <= ACA_TINY && e - m <= ACA_TINY)
+                tiny.push_back((int)h);
+            else
+                p.aca_small.push_back((int)h);
             continue;
         }
         int b = (int)p.aca_big.size();
@@ -167,6 +171,8 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
         while ((int)p.aca_colidx.size() < cslot)
             p.aca_colidx.push_back(b);
     }
+    p.aca_small_wide = (int)p.aca_small.size();
+    p.aca_small.insert(p.aca_small.end(), tiny.begin(), tiny.end());
     p.aca_pw = std::max(p.cap, 1) + 4;
 
     // level tables: for depth d, chunks over the rows of each child of each node
