@@ -32,7 +32,8 @@ namespace hodlr {
 // per lane, wave reductions only).  Measured at n = 2^20: all blocks on 256
 // threads 0.39 ms, on 128 threads 0.49 ms, on one wave 0.42 ms (32 entries
 // per lane need 256 VGPRs); 256 threads plus one wave for the 128- and
-// 256-point sides (6144 of the 7936 blocks) 0.22 ms.
+// 256-point sides (6144 of the 7936 blocks) 0.22 ms; a third class (sides up
+// to 512 on one wave, or up to 1024 on 128 threads) measured no faster.
 constexpr int ACA_SMALL_TH = 256;
 
 
@@ -59,8 +60,9 @@ __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t b
     return v > bv || (v == bv && i < bi);
 }
 
-// block argmax (ties to the smaller index) carrying the signed value; every
-// thread returns the result
+// block argmax over NW waves (ties to the smaller index) carrying the signed
+// value; every thread returns the result
+template <int NW>
 __device__ void block_argmax(double &v, int64_t &i, double &sgn, double *rv, int64_t *ri,
                              double *rs)
 {
@@ -75,7 +77,7 @@ __device__ void block_argmax(double &v, int64_t &i, double &sgn, double *rv, int
     v = rv[0];
     i = ri[0];
     sgn = rs[0];
-    for (int w = 1; w < ACA_THREADS / 64; ++w)
+    for (int w = 1; w < NW; ++w)
         if (better(rv[w], ri[w], v, i)) {
             v = rv[w];
             i = ri[w];
@@ -84,14 +86,16 @@ __device__ void block_argmax(double &v, int64_t &i, double &sgn, double *rv, int
     __syncthreads();
 }
 
+template <int NW>
 __device__ double block_sum(double v, double *red)
 {
+    static_assert(NW == 2 || NW == 4, "two or four waves");
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     v = wave_sum(v);
     if (lane == 0)
         red[wid] = v;
     __syncthreads();
-    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    double s = (NW == 4) ? (red[0] + red[1]) + (red[2] + red[3]) : red[0] + red[1];
     __syncthreads();
     return s;
 }
@@ -104,7 +108,7 @@ __device__ __forceinline__ void grp_argmax(double &v, int64_t &i, double &sgn, d
     if constexpr (TH == 64)
         wave_argmax_signed(v, i, sgn);
     else
-        block_argmax(v, i, sgn, rv, ri, rs);
+        block_argmax<TH / 64>(v, i, sgn, rv, ri, rs);
 }
 
 template <int TH>
@@ -113,7 +117,7 @@ __device__ __forceinline__ double grp_sum(double v, double *red)
     if constexpr (TH == 64)
         return wave_sum(v);
     else
-        return block_sum(v, red);
+        return block_sum<TH / 64>(v, red);
 }
 
 // ------------------------------------------------------------ small blocks
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
                 bi = j;
             }
         }
-        block_argmax(bv, bi, bs, rv, ri, rs);
+        block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);
         if (tid == 0 && nused < USED_MAX)
             usedl[nused] = (int)istar;
         ++nused;
@@ -337,12 +341,12 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
             continue;
         }
         zeros = 0;
-        const double v2 = block_sum(sq, red);
+        const double v2 = block_sum<ACA_THREADS / 64>(sq, red);
         for (int l = 0; l < k; ++l) {
             double d = 0.0;
             for (int64_t j = tid; j < nb; j += ACA_THREADS)
                 d += W[(col0 + k) * n + m + j] * W[(col0 + l) * n + m + j];
-            d = block_sum(d, red);
+            d = block_sum<ACA_THREADS / 64>(d, red);
             if (tid == 0)
                 vdot[l] = d;
         }
@@ -371,14 +375,14 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
                 bi = i;
             }
         }
-        block_argmax(bv, bi, bs, rv, ri, rs);
-        const double u2 = block_sum(sq, red);
+        block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);
+        const double u2 = block_sum<ACA_THREADS / 64>(sq, red);
         double cross = 0.0;
         for (int l = 0; l < k; ++l) {
             double d = 0.0;
             for (int64_t i = tid; i < na; i += ACA_THREADS)
                 d += W[(col0 + k) * n + s + i] * W[(col0 + l) * n + s + i];
-            d = block_sum(d, red);
+            d = block_sum<ACA_THREADS / 64>(d, red);
             cross += d * vdot[l];
         }
         s2 += u2 * v2 + 2.0 * cross;
@@ -558,7 +562,7 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
         double acc = 0.0;
         for (int c = tid; c < nrec; c += ACA_THREADS)
             acc += rec[(int64_t)c * pw + slot];
-        acc = block_sum(acc, red);
+        acc = block_sum<ACA_THREADS / 64>(acc, red);
         if (tid == 0)
             dots[l] = acc;
     }
@@ -575,7 +579,7 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
             bs = rec[(int64_t)c * pw + 3];
         }
     }
-    block_argmax(bv, bi, bs, rv, ri, rs);   // ends with a barrier: dots[] visible
+    block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);   // ends with a barrier: dots[] visible
 }
 
 template <bool ROW>
@@ -677,7 +681,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         sq = wave_sum(sq);
         if (lane == 0)
             sdot[wid][k] = sq;
-        block_argmax(bv, bi, bs, rv, ri, rs);
+        block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);
         double *rec = B.pout + (int64_t)ch.part * B.pw;
         if (tid == 0) {
             rec[0] = bv;
@@ -776,7 +780,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     sq = wave_sum(sq);
     if (lane == 0)
         sdot[wid][k] = sq;
-    block_argmax(cv, ci, cs, rv, ri, rs);
+    block_argmax<ACA_THREADS / 64>(cv, ci, cs, rv, ri, rs);
     double *rec = B.pout + (int64_t)ch.part * B.pw;
     if (tid == 0) {
         rec[0] = cv;
