@@ -552,34 +552,68 @@ __global__ void aca_big_init_kernel(BigState *st, const int *bnode, int nbig, Ac
 // Reduce the previous pass's records of one big block: slot 0 = max |value|
 // (over eligible indices), 1 = its index, 2 = squared norm, 3 = signed value,
 // 4 + l = dot with term l.  Every thread ends with the same results.
+// Combine the previous pass's per-work-group records of one block: the sums
+// of slots 4 + l (l < k) and of slot 2 into dots[0..k], and the argmax of
+// slot 0 (index in slot 1, signed value in slot 3).  One sweep over the
+// records: the first RR_REG sums and the argmax stay in registers and are
+// reduced together behind one barrier; sums beyond RR_REG (ranks above it)
+// take a work-group sum each.
+constexpr int RR_REG = 8;
+
 __device__ void reduce_records(const double *rec, int nrec, int pw, int k, double *dots,
                                double &bv, int64_t &bi, double &bs, double *rv, int64_t *ri,
-                               double *rs, double *red)
+                               double *rs, double *red, double (*sred)[RR_REG + 1])
 {
-    const int tid = threadIdx.x;
-    for (int l = 0; l <= k; ++l) {
-        int slot = (l < k) ? 4 + l : 2;
-        double acc = 0.0;
-        for (int c = tid; c < nrec; c += ACA_THREADS)
-            acc += rec[(int64_t)c * pw + slot];
-        acc = block_sum<ACA_THREADS / 64>(acc, red);
-        if (tid == 0)
-            dots[l] = acc;
-    }
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int kr = k < RR_REG ? k : RR_REG;
+    double acc[RR_REG + 1];
+#pragma unroll
+    for (int l = 0; l <= RR_REG; ++l)
+        acc[l] = 0.0;
     bv = -1.0;
     bs = 0.0;
     bi = INT64_MAX;
     for (int c = tid; c < nrec; c += ACA_THREADS) {
-        double v = rec[(int64_t)c * pw + 0];
-        double di = rec[(int64_t)c * pw + 1];
-        int64_t i = di < 0.0 ? INT64_MAX : (int64_t)di;
+        const double *r = rec + (int64_t)c * pw;
+        const double v = r[0], di = r[1], sv = r[3];
+        acc[RR_REG] += r[2];
+#pragma unroll
+        for (int l = 0; l < RR_REG; ++l)
+            if (l < kr)
+                acc[l] += r[4 + l];
+        const int64_t i = di < 0.0 ? INT64_MAX : (int64_t)di;
         if (better(v, i, bv, bi)) {
             bv = v;
             bi = i;
-            bs = rec[(int64_t)c * pw + 3];
+            bs = sv;
         }
     }
-    block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);   // ends with a barrier: dots[] visible
+#pragma unroll
+    for (int l = 0; l <= RR_REG; ++l)
+        if (l < kr || l == RR_REG) {
+            const double w = wave_sum(acc[l]);
+            if (lane == 0)
+                sred[wid][l] = w;
+        }
+    // the argmax ends with a barrier, after which sred is complete
+    block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);
+    if (tid <= kr) {
+        const int l = (tid == kr) ? RR_REG : tid;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < ACA_THREADS / 64; ++w)
+            t += sred[w][l];
+        dots[tid == kr ? k : tid] = t;
+    }
+    for (int l = RR_REG; l < k; ++l) {
+        double a = 0.0;
+        for (int c = tid; c < nrec; c += ACA_THREADS)
+            a += rec[(int64_t)c * pw + 4 + l];
+        a = block_sum<ACA_THREADS / 64>(a, red);
+        if (tid == 0)
+            dots[l] = a;
+    }
+    __syncthreads();   // dots[] visible
 }
 
 template <bool ROW>
@@ -595,6 +629,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     __shared__ double sfix[RMAX_ABS];
     __shared__ double dots[RMAX_ABS + 1];
     __shared__ double sdot[4][RMAX_ABS + 1];
+    __shared__ double sred[ACA_THREADS / 64][RR_REG + 1];
     __shared__ int sused[USED_MAX];
     BigState t = B.sin[b];
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
@@ -615,7 +650,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
             // finish the previous step from the column records
             double bv, bs;
             int64_t bi;
-            reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red);
+            reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red, sred);
             double u2 = dots[t.k];
             double cross = 0.0;
             for (int l = 0; l < t.k; ++l)
@@ -703,7 +738,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     // ---- column pass: pick the pivot column from the row records
     double bv, bs;
     int64_t bi;
-    reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red);
+    reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red, sred);
     const int nu = t.nused < USED_MAX ? t.nused : USED_MAX;
     for (int q = tid; q < nu; q += ACA_THREADS)
         sused[q] = used[q];

@@ -440,12 +440,12 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                 gout[idx] = Gt[tix(i >> 4, k >> 4) * TSZ + (k & 15) * TLD + (i & 15)];
         }
     }
-    // C_lambda^{-1} on every column of the list: each wave owns up to 16
-    // columns in registers and runs both substitutions on its own.  Up to 64
-    // columns are split evenly over the four waves (one pass each, all waves
-    // busy); more go round-robin in groups of 16.
-    const int ncl = A.ncols - A.cbeg;
-    const int gsz = ncl <= 16 * LEAF_MW ? (ncl + LEAF_MW - 1) / LEAF_MW : 16;
+    // C_lambda^{-1} on every column of the list: each wave owns 16 columns in
+    // registers and runs both substitutions on its own; groups of 16 go to
+    // the waves round-robin.  Full groups issue the fewest MFMAs (42 columns:
+    // 16 + 16 + 10 on three waves measured faster than 11 + 11 + 11 + 9 on
+    // four, the other work-group on the CU taking the free matrix cycles).
+    const int gsz = 16;
     for (int c0 = A.cbeg + gsz * wid; gsz > 0 && c0 < A.ncols; c0 += gsz * LEAF_MW) {
         const int nb = min(gsz, A.ncols - c0);
         const int cr = c0 + r;
