@@ -911,6 +911,27 @@ int *pinned_scratch()
     return buf.p;
 }
 
+// rank statistics of all blocks and their copies to the host (one
+// synchronization): rmax in pinned[0..L+1], the capped count in pinned[48],
+// the finished large-block count (if d_ndone is given) in pinned[49]
+static void read_rank_stats(Pipeline &P, const int *rank, const int *status, int *d_rmax,
+                            int *d_capped, const int *d_ndone, int *pinned)
+{
+    const Plan &p = *P.plan;
+    hipStream_t s = P.stream;
+    {
+        ProfScope ps(s, PS_ACA_MISC);
+        aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
+    }
+    HIP_TRY(hipGetLastError());
+    if (d_ndone)
+        HIP_TRY(hipMemcpyAsync(pinned + 49, d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * (p.L + 2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(pinned + 48, d_capped, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(P.ranks.data(), rank, sizeof(int) * p.nint, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+}
+
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -1001,6 +1022,7 @@ void run_aca(Pipeline &P)
         C.pout = crec;
         const int nrow = (int)p.aca_row.size(), ncol = (int)p.aca_col.size();
         const int max_iter = (p.cap + 1) * (ZERO_RETRY + 2) + 4;
+        const int hint = __atomic_load_n(&p.aca_iters, __ATOMIC_RELAXED);
         int it = 0;
         for (; it < max_iter; ++it) {
             {
@@ -1012,32 +1034,30 @@ void run_aca(Pipeline &P)
                 aca_big_pass_kernel<false><<<ncol, ACA_THREADS, 0, s>>>(C);
             }
             HIP_TRY(hipGetLastError());
-            // a converged block is counted by the row pass that absorbs its last
-            // column; poll every other step from the third on
-            if (it >= 2 && (it & 1) == 0) {
-                HIP_TRY(hipMemcpyAsync(pinned, d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                if (pinned[0] >= p.aca_big_active)
+            // A converged block is counted by the row pass that absorbs its last
+            // column.  Poll from the step where the previous call on this plan
+            // finished (else every other step from the third on); a poll that
+            // may be the last also takes the ranks and their statistics, so
+            // that one synchronization serves both.  If blocks remain, the
+            // loop goes on and the final poll rewrites them.
+            const bool poll = hint > 0 ? it + 1 >= hint : (it >= 2 && (it & 1) == 0);
+            if (poll) {
+                {
+                    ProfScope ps(s, PS_ACA_MISC);
+                    aca_big_finish_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big,
+                                                                             nbig, rank, status);
+                }
+                read_rank_stats(P, rank, status, d_rmax, d_capped, d_ndone, pinned);
+                if (pinned[49] >= p.aca_big_active)
                     break;
             }
         }
         if (it >= max_iter)
             throw Error{HODLR_EDEVICE, "cross approximation did not terminate"};
-        {
-            ProfScope ps(s, PS_ACA_MISC);
-            aca_big_finish_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big, nbig,
-                                                                     rank, status);
-        }
+        __atomic_store_n(&p.aca_iters, it + 1, __ATOMIC_RELAXED);
+    } else {
+        read_rank_stats(P, rank, status, d_rmax, d_capped, nullptr, pinned);
     }
-    {
-        ProfScope ps(s, PS_ACA_MISC);
-        aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
-    }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * (p.L + 2), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(pinned + 48, d_capped, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(P.ranks.data(), rank, sizeof(int) * p.nint, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     for (int j = 0; j <= p.L + 1 && j < 48; ++j)
         P.rmax[j] = pinned[j];
     P.capped = pinned[48];

@@ -235,6 +235,8 @@ struct Plan {
     // cross-approximation tables
     std::vector<int> aca_small;            // heap indices of blocks done by one work-group
     int aca_small_wide = 0;                // the first ones, with a side above ACA_TINY
+    mutable int aca_iters = 0;             // large-block steps the last call took (poll hint;
+                                           // relaxed atomic accesses, plans may be shared)
     std::vector<int> aca_big;              // heap indices of multi-work-group blocks
     int aca_big_active = 0;                // big blocks with a positive rank cap
     std::vector<Chunk> aca_row, aca_col;   // big blocks: chunks over beta / alpha
