@@ -932,6 +932,38 @@ static void read_rank_stats(Pipeline &P, const int *rank, const int *status, int
     HIP_TRY(hipStreamSynchronize(s));
 }
 
+// Per-call initialization in one launch instead of a memset or copy each:
+// zero the status words, the counters and every block's rank and state, and
+// write the panel column offsets (passed by value).
+struct InitArgs {
+    int *status;   // 4 status words
+    int *ndone, *capped;
+    int *rank, *astatus;
+    int64_t nint;
+    int64_t *cofa;
+    int ncofa;
+    int64_t cofa_v[64];
+};
+
+__global__ __launch_bounds__(256) void pipeline_init_kernel(InitArgs a)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = g; i < a.nint; i += (int64_t)gridDim.x * blockDim.x) {
+        a.rank[i] = 0;   // blocks with an empty side keep rank 0 and count as done
+        a.astatus[i] = 0;
+    }
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 4)
+            a.status[threadIdx.x] = 0;
+        if (threadIdx.x == 0 && a.ndone) {
+            *a.ndone = 0;
+            *a.capped = 0;
+        }
+        if ((int)threadIdx.x < a.ncofa)
+            a.cofa[threadIdx.x] = a.cofa_v[threadIdx.x];
+    }
+}
+
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -939,15 +971,20 @@ void run_aca(Pipeline &P)
     P.rmax.assign(p.L + 2, 0);
     P.ranks.assign(p.nint, 0);
     P.capped = 0;
-    if (p.L == 0)
+    InitArgs ia{};
+    ia.status = wsp<int>(P, P.lay.status);
+    if (p.L == 0) {
+        pipeline_init_kernel<<<1, 256, 0, s>>>(ia);
+        HIP_TRY(hipGetLastError());
         return;
+    }
     int *pinned = pinned_scratch();
     int64_t *d_cofa = wsp<int64_t>(P, P.lay.misc);          // [0, 512): column offsets
     int *d_rmax = wsp<int>(P, P.lay.misc + 512);             // [512, 784): rmax per depth
     int *d_capped = wsp<int>(P, P.lay.misc + 784);
     int *d_ndone = wsp<int>(P, P.lay.misc + 1024);
-    HIP_TRY(hipMemcpyAsync(d_cofa, p.cofa.data(), sizeof(int64_t) * p.cofa.size(),
-                           hipMemcpyHostToDevice, s));
+    if (p.cofa.size() > 64)
+        throw Error{HODLR_EINVAL, "more than 62 tree levels"};
     AcaArgs A;
     A.x = P.x;
     A.n = p.n;
@@ -960,11 +997,21 @@ void run_aca(Pipeline &P)
     A.cap = p.cap;
     int *rank = wsp<int>(P, P.lay.rank);
     int *status = wsp<int>(P, P.lay.aca_status);
-    HIP_TRY(hipMemsetAsync(d_ndone, 0, sizeof(int), s));
-    HIP_TRY(hipMemsetAsync(d_capped, 0, sizeof(int), s));
-    // blocks with an empty side keep rank 0 and count as done
-    HIP_TRY(hipMemsetAsync(rank, 0, sizeof(int) * p.nint, s));
-    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int) * p.nint, s));
+    ia.ndone = d_ndone;
+    ia.capped = d_capped;
+    ia.rank = rank;
+    ia.astatus = status;
+    ia.nint = p.nint;
+    ia.cofa = d_cofa;
+    ia.ncofa = (int)p.cofa.size();
+    for (size_t j = 0; j < p.cofa.size(); ++j)
+        ia.cofa_v[j] = p.cofa[j];
+    {
+        ProfScope ps(s, PS_ACA_MISC);
+        const int64_t nb = std::min<int64_t>((p.nint + 255) / 256, 1024);
+        pipeline_init_kernel<<<(unsigned)std::max<int64_t>(nb, 1), 256, 0, s>>>(ia);
+    }
+    HIP_TRY(hipGetLastError());
     // small blocks: the whole loop per work-group, one launch
     if (!p.aca_small.empty()) {
         SmallArgs S;

@@ -169,8 +169,7 @@ void raise_status(int st)
 // compression, leaves, levels, finish: everything for one likelihood
 void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
 {
-    HIP_TRY(hipMemsetAsync(wsp<int>(P, P.lay.status), 0, 4 * sizeof(int), P.stream));
-    run_aca(P);
+    run_aca(P);   // its first launch also zeroes the status words
     make_columns(P);
     if (!d_y)
         HIP_TRY(hipMemsetAsync(P.ws + P.lay.Xt, 0, P.plan->panel_bytes() * P.plan->n, P.stream));
