@@ -242,6 +242,94 @@ __device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
     return acc;
 }
 
+// Step J of the forward substitution L y = x on 16 columns held in registers
+// (row tile I of the group in X[I], MFMA result layout): y_J = L_JJ^{-1} x_J,
+// then x_I -= L_IJ y_J for I > J.  Gt holds L_JJ^{-1} in the diagonal slots.
+template <int J>
+__device__ __forceinline__ void fwd_step(d4 (&X)[NT_MAX], const double *Gt, int nt)
+{
+    const d4 z = {0.0, 0.0, 0.0, 0.0};
+    X[J] = tile_mma_rb<false, false>(Gt + tix(J, J) * TSZ, X[J], z);
+#pragma unroll
+    for (int I = J + 1; I < NT_MAX; ++I)
+        if (I < nt)
+            X[I] = tile_mma_rb<false, true>(Gt + tix(I, J) * TSZ, X[J], X[I]);
+}
+
+// the same for a run-time J (uniform): a switch, so that X stays in registers
+__device__ __forceinline__ void fwd_step_rt(int J, d4 (&X)[NT_MAX], const double *Gt, int nt)
+{
+    static_assert(NT_MAX == 8, "one case per row tile");
+    switch (J) {
+    case 0: fwd_step<0>(X, Gt, nt); break;
+    case 1: fwd_step<1>(X, Gt, nt); break;
+    case 2: fwd_step<2>(X, Gt, nt); break;
+    case 3: fwd_step<3>(X, Gt, nt); break;
+    case 4: fwd_step<4>(X, Gt, nt); break;
+    case 5: fwd_step<5>(X, Gt, nt); break;
+    case 6: fwd_step<6>(X, Gt, nt); break;
+    case 7: fwd_step<7>(X, Gt, nt); break;
+    default: break;
+    }
+}
+
+// backward substitution L^T z = y on the same register tiles
+__device__ __forceinline__ void bwd_all(d4 (&X)[NT_MAX], const double *Gt, int nt)
+{
+#pragma unroll
+    for (int J = NT_MAX - 1; J >= 0; --J) {
+        if (J < nt) {
+            const d4 z = {0.0, 0.0, 0.0, 0.0};
+            X[J] = tile_mma_rb<true, false>(Gt + tix(J, J) * TSZ, X[J], z);
+#pragma unroll
+            for (int I = 0; I < J; ++I)
+                X[I] = tile_mma_rb<true, true>(Gt + tix(J, I) * TSZ, X[J], X[I]);
+        }
+    }
+}
+
+// columns [c0, c0 + 16) of the list (column 0 = the right-hand side y,
+// others basis columns of W) on the leaf's rows into register tiles, lane
+// (r, q) holding column c0 + r, rows 16 I + q + 4 t; missing entries are 0
+__device__ __forceinline__ void rhs_load(d4 (&X)[NT_MAX], const LeafArgs &A, int c0,
+                                         const double *ysrc, const double *Wsrc, int64_t s,
+                                         int64_t n, int nt, int m)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    const int nb = min(16, A.ncols - c0);
+    const double *src = nullptr;
+    if (r < nb) {
+        const int col = A.cols[c0 + r];
+        src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
+    }
+#pragma unroll
+    for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = 16 * I + q + 4 * t;
+            X[I][t] = (src && I < nt && i < m) ? src[i] : 0.0;
+        }
+}
+
+template <typename PT>
+__device__ __forceinline__ void rhs_store(const d4 (&X)[NT_MAX], const LeafArgs &A, int c0,
+                                          PT *Xdst, int64_t s, int64_t n, int nt, int m)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    const int nb = min(16, A.ncols - c0);
+    if (r < nb) {
+        PT *dst = Xdst + (int64_t)A.cols[c0 + r] * n + s;
+#pragma unroll
+        for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = 16 * I + q + 4 * t;
+                if (I < nt && i < m)
+                    dst[i] = (PT)X[I][t];
+            }
+    }
+}
+
 template <typename PT>
 __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
 {
@@ -357,6 +445,18 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         }
     }
     __syncthreads();
+    // C_lambda^{-1} is applied to the column list in groups of 16 columns, one
+    // group per wave, held in registers.  Groups 0..2 belong to waves 1..3
+    // from the start: their forward substitution runs inside the
+    // factorization (step J once L_JJ^{-1} and column J of L exist), in the
+    // time those waves would otherwise wait for wave 0's serial diagonal
+    // factorizations; only the backward substitution is left after it.
+    const int ngrp = (A.ncols - A.cbeg + 15) / 16;
+    const int pg = wid - 1;
+    const bool piped = wid > 0 && pg < ngrp;
+    d4 X[NT_MAX];
+    if (piped)
+        rhs_load(X, A, A.cbeg + 16 * pg, ysrc, Wsrc, s, n, nt, m);
     bool bad = false;   // wave 0 only
     if (wid == 0)
         bad = diag_factor(Gt, s_diag, gout, 0, m);
@@ -405,6 +505,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                     T[r * TLD + q + 4 * t] -= acc[t];
             }
         }
+        if (piped)
+            fwd_step_rt(J, X, Gt, nt);
         __syncthreads();
     }
     // log det of the leaf, 2 sum_i log L_ii over its real rows: one log per
@@ -440,60 +542,22 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                 gout[idx] = Gt[tix(i >> 4, k >> 4) * TSZ + (k & 15) * TLD + (i & 15)];
         }
     }
-    // C_lambda^{-1} on every column of the list: each wave owns 16 columns in
-    // registers and runs both substitutions on its own; groups of 16 go to
-    // the waves round-robin.  Full groups issue the fewest MFMAs (42 columns:
-    // 16 + 16 + 10 on three waves measured faster than 11 + 11 + 11 + 9 on
-    // four, the other work-group on the CU taking the free matrix cycles).
-    const int gsz = 16;
-    for (int c0 = A.cbeg + gsz * wid; gsz > 0 && c0 < A.ncols; c0 += gsz * LEAF_MW) {
-        const int nb = min(gsz, A.ncols - c0);
-        const int cr = c0 + r;
-        const double *src = nullptr;
-        if (r < nb) {
-            int col = A.cols[cr];
-            src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
-        }
-        d4 X[NT_MAX];
+    if (piped) {
+        bwd_all(X, Gt, nt);
+        rhs_store(X, A, A.cbeg + 16 * pg, Xdst, s, n, nt, m);
+    }
+    // further groups: both substitutions here, round-robin over the waves.
+    // Full groups of 16 issue the fewest MFMAs (42 columns: 16 + 16 + 10 on
+    // three waves measured faster than 11 + 11 + 11 + 9 on four).
+    for (int g = (LEAF_MW - 1) + wid; g < ngrp; g += LEAF_MW) {
+        const int c0 = A.cbeg + 16 * g;
+        rhs_load(X, A, c0, ysrc, Wsrc, s, n, nt, m);
 #pragma unroll
-        for (int I = 0; I < NT_MAX; ++I)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int i = 16 * I + q + 4 * t;
-                X[I][t] = (src && I < nt && i < m) ? src[i] : 0.0;
-            }
-#pragma unroll
-        for (int J = 0; J < NT_MAX; ++J) {
-            if (J < nt) {
-                d4 z = {0.0, 0.0, 0.0, 0.0};
-                X[J] = tile_mma_rb<false, false>(Gt + tix(J, J) * TSZ, X[J], z);
-#pragma unroll
-                for (int I = J + 1; I < NT_MAX; ++I)
-                    if (I < nt)
-                        X[I] = tile_mma_rb<false, true>(Gt + tix(I, J) * TSZ, X[J], X[I]);
-            }
-        }
-#pragma unroll
-        for (int J = NT_MAX - 1; J >= 0; --J) {
-            if (J < nt) {
-                d4 z = {0.0, 0.0, 0.0, 0.0};
-                X[J] = tile_mma_rb<true, false>(Gt + tix(J, J) * TSZ, X[J], z);
-#pragma unroll
-                for (int I = 0; I < J; ++I)
-                    X[I] = tile_mma_rb<true, true>(Gt + tix(J, I) * TSZ, X[J], X[I]);
-            }
-        }
-        if (r < nb) {
-            PT *dst = Xdst + (int64_t)A.cols[cr] * n + s;
-#pragma unroll
-            for (int I = 0; I < NT_MAX; ++I)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    int i = 16 * I + q + 4 * t;
-                    if (I < nt && i < m)
-                        dst[i] = (PT)X[I][t];
-                }
-        }
+        for (int J = 0; J < NT_MAX; ++J)
+            if (J < nt)
+                fwd_step_rt(J, X, Gt, nt);
+        bwd_all(X, Gt, nt);
+        rhs_store(X, A, c0, Xdst, s, n, nt, m);
     }
 }
 
