@@ -484,12 +484,18 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                     T[r * TLD + q + 4 * t] -= acc[t];
                 bad = diag_factor(T, s_diag + 16 * (J + 1), gout, 16 * (J + 1), m) || bad;
             }
-            // remaining trailing tiles C_IK -= L_IJ L_KJ^T (J < K <= I) on the
-            // other three waves, so that nothing waits behind the serial
-            // diagonal factorization on wave 0
+            // remaining trailing tiles C_IK -= L_IJ L_KJ^T (J < K <= I): the
+            // first ones on the other three waves (which also run their
+            // forward substitution step), and while there are many, the last
+            // (ntask - 8) / 3 on wave 0 after its diagonal factorization
+            // (the balance point measured per step)
             const int Tn = nt - 1 - J;
             const int ntask = Tn * (Tn + 1) / 2 - 1;
-            for (int task = wid - 1; wid > 0 && task < ntask; task += LEAF_MW - 1) {
+            const int n0 = ntask > 8 ? (ntask - 8) / 3 : 0;
+            const int t0 = wid == 0 ? ntask - n0 : wid - 1;
+            const int t1 = wid == 0 ? ntask : ntask - n0;
+            const int ts = wid == 0 ? 1 : LEAF_MW - 1;
+            for (int task = t0; task < t1; task += ts) {
                 int tt = task + 1;   // skip the look-ahead tile (I = K = J+1)
                 int I = 0;
                 while ((I + 1) * (I + 2) / 2 <= tt)
