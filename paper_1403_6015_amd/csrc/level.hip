@@ -142,25 +142,26 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
 // 64).  Every work-group of a chunk re-reads the chunk's W rows, so wide groups
 // read W once; narrow groups give more work-groups.
 
-// SR rows per lane (chunk = 64 SR rows), CU columns per iteration
-template <typename PT, int R, int SR, int CU>
-__global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
+// Body of the small-rank reduction for one chunk (SR rows per lane, chunk =
+// 64 SR rows; CU columns per iteration).  Row of slot t of a lane: lo + lane
+// + 64 t, or with PAIR lo + 128 (t / 2) + 2 lane + t % 2, so that an FP32
+// panel is read as float2 (two adjacent rows per lane: as many bytes per load
+// instruction as the FP64 panel, which keeps twice the bytes in flight).
+template <typename PT, int R, int SR, int CU, bool PAIR>
+__device__ __forceinline__ void reduce_chunk(const LevelArgs &A, const Chunk &ch, int r, double *red)
 {
-    const LevelArgs A = item_args(A0);
     const double *__restrict__ Wp = A.W;
     const PT *__restrict__ Xp = (const PT *)A.Xt;
-    const Chunk ch = A.chunks[blockIdx.x];
-    const int r = A.rank[ch.node];
-    if (r == 0)
-        return;
     const int lane = threadIdx.x;
     const int64_t n = A.n;
-    __shared__ double red[64 * (CU * R + 1)];
+    auto row = [&](int t) -> int64_t {
+        return PAIR ? ch.lo + 128 * (t >> 1) + 2 * lane + (t & 1) : ch.lo + lane + 64 * t;
+    };
     double w[SR][R];
     bool ok[SR];
 #pragma unroll
     for (int t = 0; t < SR; ++t) {
-        const int64_t i = ch.lo + lane + 64 * t;
+        const int64_t i = row(t);
         ok[t] = i < ch.hi;
 #pragma unroll
         for (int l = 0; l < R; ++l)
@@ -179,15 +180,41 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
 #pragma unroll
             for (int l = 0; l < R; ++l)
                 acc[u][l] = 0.0;
+        if constexpr (PAIR) {
+            static_assert(SR % 2 == 0, "pairs of slots");
 #pragma unroll
-        for (int t = 0; t < SR; ++t) {
-            if (ok[t]) {
+            for (int p = 0; p < SR / 2; ++p) {
+                if (ok[2 * p]) {
 #pragma unroll
-                for (int u = 0; u < CU; ++u) {
-                    const double x = xc[u] ? (double)xc[u][ch.lo + lane + 64 * t] : 0.0;
+                    for (int u = 0; u < CU; ++u) {
+                        double x0 = 0.0, x1 = 0.0;
+                        if (xc[u]) {
+                            const int64_t i0 = row(2 * p);
+                            if (ok[2 * p + 1]) {
+                                const float2 v = *(const float2 *)(xc[u] + i0);
+                                x0 = v.x;
+                                x1 = v.y;
+                            } else {
+                                x0 = xc[u][i0];
+                            }
+                        }
 #pragma unroll
-                    for (int l = 0; l < R; ++l)
-                        acc[u][l] += w[t][l] * x;
+                        for (int l = 0; l < R; ++l)
+                            acc[u][l] += w[2 * p][l] * x0 + w[2 * p + 1][l] * x1;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < SR; ++t) {
+                if (ok[t]) {
+#pragma unroll
+                    for (int u = 0; u < CU; ++u) {
+                        const double x = xc[u] ? (double)xc[u][row(t)] : 0.0;
+#pragma unroll
+                        for (int l = 0; l < R; ++l)
+                            acc[u][l] += w[t][l] * x;
+                    }
                 }
             }
         }
@@ -225,6 +252,28 @@ __global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
         }
         __syncthreads();
     }
+}
+
+
+// SR rows per lane (chunk = 64 SR rows), CU columns per iteration
+template <typename PT, int R, int SR, int CU>
+__global__ __launch_bounds__(64) void level_reduce_small_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    constexpr int NO = CU * R;
+    __shared__ double red[64 * (NO + 1)];
+    // an FP32 panel with an even chunk start (and even n) is read in pairs
+    if constexpr (sizeof(PT) == 4 && SR % 2 == 0) {
+        if (((ch.lo | A.n) & 1) == 0) {
+            reduce_chunk<PT, R, SR, CU, true>(A, ch, r, red);
+            return;
+        }
+    }
+    reduce_chunk<PT, R, SR, CU, false>(A, ch, r, red);
 }
 
 template <typename PT, int R>
