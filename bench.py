@@ -249,6 +249,21 @@ def main():
                         "avg_launch_ms": dom_ms / dom_launches,
                         "algorithmic_per_call": {"flops": flops, "bytes": byts}}
 
+    # whole-pipeline model: each modelled stage at the larger of its HBM time
+    # (algorithmic bytes at 8 TB/s) and its FP64 compute time, plus the cross
+    # approximation's basis writes (8 B x n x sum of ranks); against the
+    # measured time per likelihood
+    ms_step = elapsed / args.steps * 1e3
+    bound_ms = {k: max(b / (PEAK["hbm"] * 1e9), f / (PEAK["alu_fp64"] * 1e12)) * 1e3
+                for k, (f, b) in model.items()}
+    bound_ms["aca_bases"] = 8.0 * p.n * sum(r[1:]) / (PEAK["hbm"] * 1e9) * 1e3
+    pipeline = {"model_ms": sum(bound_ms.values()), "measured_ms": ms_step,
+                "frac": sum(bound_ms.values()) / ms_step,
+                "stage_bound_ms": bound_ms,
+                "note": "sum over stages of max(bytes / 8 TB/s, flops / 78.6 TFLOP/s); "
+                        "stages without a model (node solves, cross-approximation passes, "
+                        "log-det sums) count as zero"}
+
     res = {
         "metric": METRIC, "value": args.steps / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -263,6 +278,7 @@ def main():
                    "levels": L, "rank_max": r[1:], "level_rows": tune.level_rows,
                    "reduce_cols": tune.reduce_cols, "reduce_group": tune.reduce_group},
         "roofline": roofline,
+        "pipeline_roofline": pipeline,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "stage_launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
         "stage_note": "stage times from a separate pass with every launch timed; the timed "
