@@ -599,9 +599,22 @@ static size_t solve_lds(int rs)
     if (!attr) {
         HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel<LV_SOLVE_TH>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel<64>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         attr = true;
     }
     return sizeof(double) * ((size_t)3 * rs * (rs + 1) + (size_t)2 * rs * (LV_CB + 1) + 1);
+}
+
+// node solves of one level: levels with many small-rank nodes (few records
+// each) on one wave per node, the others on LV_SOLVE_TH threads (whose record
+// sums need the loads in flight)
+static void launch_solve(Pipeline &P, const LevelArgs &A, unsigned nodes)
+{
+    if (nodes >= 512 && A.rstride <= 8)
+        level_solve_kernel<64><<<dim3(nodes, 1, P.nitems), 64, solve_lds(A.rstride), P.stream>>>(A);
+    else
+        level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
 }
 
 // set once, outside any stream capture
@@ -682,7 +695,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
-        level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
+        launch_solve(P, A, nodes);
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
@@ -719,7 +732,7 @@ void run_levels_factor(Pipeline &P)
             // every block of this level has rank 0: coupling determinants are 1
             const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
             ProfScope ps(P.stream, PS_LVL_SOLVE);
-            level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
+            launch_solve(P, A, nodes);
             HIP_TRY(hipGetLastError());
             continue;
         }
