@@ -12,6 +12,8 @@ Contents
   (paper §1 Eq. (1), §2.1).
 * ``kalman.c`` / ``kalman_matern32``: exact O(n) reference for 1-D Matern-3/2
   through the state-space form mentioned in §2.4.
+* ``cross_matrix`` / ``gp_predict_dense``: the prediction of §2.1 (predictive
+  mean and variance at new inputs) written out with dense matrices.
 * ``matvec_rows``: exact rows of C v evaluated entry by entry, for residuals
   ||y - C x|| / ||y|| at sizes where C cannot be formed.
 * ``hodlr_ref``: the method's own steps (tree, cross approximation, leaf
@@ -71,6 +73,9 @@ def lib():
         L.oracle_gp.restype = ctypes.c_int
         L.oracle_gp.argtypes = [dp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
+        L.oracle_cross_matrix.restype = None
+        L.oracle_cross_matrix.argtypes = [dp, i64, dp, i64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, dp]
         L.oracle_matvec_rows.restype = None
         L.oracle_matvec_rows.argtypes = [dp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, dp,
@@ -152,6 +157,38 @@ def gp_dense(x, y, kind: int, theta, sigma2: float):
     if st != 0:
         raise OracleError("covariance not positive definite (pivot %d)" % (st - 1))
     return {"logdet": ld.value, "quad": q.value, "loglik": ll.value, "alpha": alpha}
+
+
+def cross_matrix(xa, xb, kind: int, theta) -> np.ndarray:
+    """K(xa, xb) entry by entry (no noise term), shape (len(xa), len(xb))."""
+    xa = _pts(xa)
+    xb = _pts(xb)
+    if xa.shape[1] != xb.shape[1]:
+        raise ValueError("point sets of different dimension")
+    out = np.empty((xa.shape[0], xb.shape[0]), dtype=np.float64)
+    lib().oracle_cross_matrix(_p(xa), xa.shape[0], _p(xb), xb.shape[0], xa.shape[1], int(kind),
+                              float(theta[0]), float(theta[1]), _p(out))
+    return out
+
+
+def gp_predict_dense(x, y, xt, kind: int, theta, sigma2: float, want_var: bool = True):
+    """§2.1 prediction written out with dense FP64 matrices (mean function 0):
+    mean = k(xt, x) C^{-1} y and var = k(xt, xt) - k(xt, x) C^{-1} k(x, xt), the
+    variance of the latent f, with C = sigma^2 I + K factored by the oracle's
+    Cholesky.  Returns (mean, var or None)."""
+    C = dense_matrix(x, kind, theta, sigma2)
+    G = cholesky(C)
+    alpha = chol_solve(G, y)
+    Ks = cross_matrix(xt, x, kind, theta)
+    mean = Ks @ alpha
+    if not want_var:
+        return mean, None
+    xt = _pts(xt)
+    var = np.empty(xt.shape[0])
+    for j in range(xt.shape[0]):
+        v = chol_solve(G, Ks[j])
+        var[j] = kernel_value(kind, xt[j], xt[j], theta[0], theta[1]) - Ks[j] @ v
+    return mean, var
 
 
 def matvec_rows(x, kind: int, theta, sigma2: float, v, rows) -> np.ndarray:

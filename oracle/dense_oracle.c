@@ -52,6 +52,18 @@ double oracle_kernel(int kind, const double *xi, const double *xj, int dim,
     }
 }
 
+/* Cross matrix K(xa, xb) (no noise term), row-major na x nb:
+ * out[i * nb + j] = k(xa_i, xb_j), point-major inputs.  The prediction of
+ * §2.1 needs it with xa the new inputs and xb the data. */
+void oracle_cross_matrix(const double *xa, int64_t na, const double *xb, int64_t nb, int dim,
+                         int kind, double a, double ell, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < na; ++i)
+        for (int64_t j = 0; j < nb; ++j)
+            out[i * nb + j] = oracle_kernel(kind, xa + i * dim, xb + j * dim, dim, a, ell);
+}
+
 /* Full symmetric matrix C = sigma2*I + K, row-major n x n. */
 void oracle_dense_matrix(const double *x, int64_t n, int dim, int kind, double a,
                          double ell, double sigma2, double *C)
