@@ -144,6 +144,23 @@ hodlr_status hodlr_logdet(hodlr_factor f, double *logdet);
  * not reached; x still holds the best iterate).                             */
 hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrhs);
 
+/* Prediction at m new inputs through the factor (§2.1, predictive mean and
+ * variance of f, mean function 0):
+ *   mean_j = k(xt_j, x) C^{-1} y,
+ *   var_j  = k(xt_j, xt_j) - k(xt_j, x) C^{-1} k(x, xt_j)
+ * (the variance of the latent f; add sigma2 for a new noisy observation).
+ * y: n doubles in the caller's order (the observations the factor's x
+ * belongs to); xt: point-major m*dim doubles, any order; mean, var: m
+ * doubles (var may be NULL: the mean needs one solve, each variance one
+ * solve more).  Every kernel entry is evaluated exactly; the solves are the
+ * factor's (mixed factors refine them as hodlr_solve does: ENOCONV if a solve
+ * misses refine_tol, with all outputs written; hodlr_info reports the largest
+ * step count and residual).  m = 0 is a no-op.
+ * Errors: EINVAL (NULL with m > 0, m < 0, non-finite y or xt), ENOMEM,
+ * EDEVICE, ENOCONV.                                                         */
+hodlr_status hodlr_predict(hodlr_factor f, const double *y, const double *xt, int64_t m,
+                           double *mean, double *var);
+
 /* Gaussian log-likelihood of y (Eq. (1) with the normal constant, mean 0):
  *   loglik = -y^T C^{-1} y / 2 - log det C / 2 - (n/2) log(2 pi).
  * logdet and quad (= y^T C^{-1} y) are optional outputs (NULL to skip).     */

@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "HodlrError", "Opts", "Factor", "Plan", "lib", "hodlr_order", "hodlr_num_levels",
-    "hodlr_build", "hodlr_logdet", "hodlr_solve", "gp_loglik", "hodlr_info", "hodlr_free",
+    "hodlr_build", "hodlr_logdet", "hodlr_solve", "hodlr_predict", "gp_loglik", "hodlr_info",
+    "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
     "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
@@ -36,7 +37,7 @@ EXPORTED = [
     "hodlr_mlp_forward_dev", "hodlr_mlp_grad_dev", "hodlr_mlp_train_step_dev",
     "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
     "hodlr_sampler_workspace_size", "gp_sample_dev", "hodlr_plan_tuned_create", "hodlr_autotune",
-    "hodlr_tune_lookup", "hodlr_profile_select",
+    "hodlr_tune_lookup", "hodlr_profile_select", "hodlr_predict",
 ]
 MLP_NPARAM = 17153
 
@@ -151,6 +152,8 @@ def lib():
     L.hodlr_logdet.argtypes = [vp, dp]
     L.hodlr_solve.restype = st
     L.hodlr_solve.argtypes = [vp, dp, dp, i64]
+    L.hodlr_predict.restype = st
+    L.hodlr_predict.argtypes = [vp, dp, dp, i64, dp, dp]
     L.gp_loglik.restype = st
     L.gp_loglik.argtypes = [dp, i64, i32, ctypes.c_int, dp, ctypes.c_double, dp, i32,
                             ctypes.c_double, ctypes.POINTER(Opts), dp, dp, dp]
@@ -288,6 +291,9 @@ class Factor:
     def solve(self, y) -> np.ndarray:
         return hodlr_solve(self, y)
 
+    def predict(self, y, xt, var: bool = True):
+        return hodlr_predict(self, y, xt, var)
+
     def info(self) -> dict:
         return hodlr_info(self)
 
@@ -319,6 +325,27 @@ def hodlr_logdet(f: Factor) -> float:
     out = ctypes.c_double()
     _check(lib().hodlr_logdet(f.handle, ctypes.byref(out)))
     return out.value
+
+
+def hodlr_predict(f: Factor, y, xt, var: bool = True):
+    """Predictive mean (and variance of f, if var) at the rows of xt (§2.1):
+    returns (mean, var or None) as float64 arrays of len(xt)."""
+    info = hodlr_info(f)
+    Y = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    if Y.size != info["n"]:
+        raise HodlrError(1, "y must hold the factor's n observations")
+    XT = np.asarray(xt, dtype=np.float64)
+    if XT.ndim == 1:
+        XT = XT.reshape(-1, 1)
+    XT = np.ascontiguousarray(XT)
+    if XT.ndim != 2 or XT.shape[1] != info["dim"]:
+        raise HodlrError(1, "xt must be m x dim with the factor's dim")
+    m = XT.shape[0]
+    mean = np.empty(m)
+    v = np.empty(m) if var else None
+    _check(lib().hodlr_predict(f.handle, _dp(Y), _dp(XT), m, _dp(mean),
+                               _dp(v) if v is not None else None))
+    return mean, v
 
 
 def hodlr_solve(f: Factor, y) -> np.ndarray:
@@ -586,7 +613,8 @@ def profile_enable(on: bool = True):
 
 
 PROFILE_STAGES = ["aca_row_pass", "aca_col_pass", "aca_small", "aca_misc", "leaf_factor",
-                  "leaf_solve", "level_reduce", "level_solve", "level_update", "finish", "matvec"]
+                  "leaf_solve", "level_reduce", "level_solve", "level_update", "finish", "matvec",
+                  "predict"]
 
 
 def profile_select(stages=None):

@@ -482,6 +482,77 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
     });
 }
 
+hodlr_status hodlr_predict(hodlr_factor f, const double *y, const double *xt, int64_t m,
+                           double *mean, double *var)
+{
+    return guarded([&]() {
+        if (!f || !y || m < 0 || (m > 0 && (!xt || !mean)))
+            throw Error{HODLR_EINVAL, "bad argument"};
+        const int64_t n = f->plan.n;
+        const int dim = f->plan.dim;
+        check_finite(y, n, "y");
+        check_finite(xt, m * dim, "xt");
+        if (m == 0)
+            return HODLR_OK;
+        HIP_TRY(hipSetDevice(f->device));
+        Pipeline P = factor_pipeline_of(f);
+        hipStream_t s = P.stream;
+        const bool f32 = f->plan.f32();
+        DevBuf dy(sizeof(double) * n), da(sizeof(double) * n);
+        const size_t vb = f32 ? sizeof(double) * n : 8;
+        DevBuf dr(vb), dq(vb), dz(vb), dp(vb), part(sizeof(double) * 512);
+        const Work w{(double *)dr.p, (double *)dq.p, (double *)dz.p, (double *)dp.p,
+                     (double *)part.p};
+        // alpha = C^{-1} y in tree order
+        std::vector<double> buf(n);
+        for (int64_t k = 0; k < n; ++k)
+            buf[k] = y[f->perm[k]];
+        HIP_TRY(hipMemcpy(dy.p, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        Refined ra = solve_tree(f, P, (const double *)dy.p, (double *)da.p, w);
+        int steps = ra.steps;
+        double worst = f32 ? ra.residual : -1.0;
+        bool all_ok = ra.converged;
+        // test points, coordinate-major
+        std::vector<double> xs((size_t)m * dim);
+        for (int d = 0; d < dim; ++d)
+            for (int64_t j = 0; j < m; ++j)
+                xs[(size_t)d * m + j] = xt[j * dim + d];
+        DevBuf dxt(sizeof(double) * xs.size()), dmean(sizeof(double) * m);
+        DevBuf dpart(sizeof(double) * (size_t)predict_slices(n, m) * m);
+        HIP_TRY(hipMemcpy(dxt.p, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
+        run_predict_mean(n, f->kp, f->dx, (const double *)da.p, m, (const double *)dxt.p,
+                         (double *)dpart.p, (double *)dmean.p, s);
+        HIP_TRY(hipMemcpyAsync(mean, dmean.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (var) {
+            // var_j = k(xt_j, xt_j) - k_j . C^{-1} k_j with k_j = k(x, xt_j) in tree
+            // order; k(r = 0) = a^2 for every kernel here
+            const int nb = (int)std::min<int64_t>(m, 16);
+            DevBuf dk(sizeof(double) * n * nb), dv(sizeof(double) * n);
+            for (int64_t j0 = 0; j0 < m; j0 += nb) {
+                const int cnt = (int)std::min<int64_t>(nb, m - j0);
+                run_kcross(n, f->kp, f->dx, m, (const double *)dxt.p, j0, cnt, (double *)dk.p, s);
+                for (int c = 0; c < cnt; ++c) {
+                    const double *kc = (const double *)dk.p + (int64_t)c * n;
+                    Refined rv = solve_tree(f, P, kc, (double *)dv.p, w);
+                    steps = std::max(steps, rv.steps);
+                    if (f32)
+                        worst = std::max(worst, rv.residual);
+                    all_ok = all_ok && rv.converged;
+                    var[j0 + c] = f->kp.a2 - run_dot(kc, (const double *)dv.p, n, w.part, s);
+                }
+            }
+        }
+        prof_collect();
+        f->refine_steps = steps;
+        f->refine_residual = worst;
+        if (!all_ok)
+            throw Error{HODLR_ENOCONV, "refinement did not reach refine_tol within max_refine "
+                                       "steps (the outputs were written)"};
+        return HODLR_OK;
+    });
+}
+
 hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
                        const double theta[2], double sigma2, const double *y, int32_t leaf,
                        double tol, const hodlr_opts *opts, double *loglik, double *logdet,

@@ -333,7 +333,7 @@ struct Pipeline {
 // Optional HIP-event timing of every launch, per kernel kind (tracing aid).
 enum ProfStage {
     PS_ACA_ROW = 0, PS_ACA_COL, PS_ACA_SMALL, PS_ACA_MISC, PS_LEAF, PS_LEAF_SOLVE, PS_LVL_REDUCE, PS_LVL_SOLVE,
-    PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_COUNT
+    PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_PREDICT, PS_COUNT
 };
 bool prof_on(int stage);
 void prof_suspend(bool on);   // no event recording (e.g. while a stream is captured)
@@ -370,6 +370,13 @@ void run_widen(const void *z, bool f32, double *out, int64_t n, hipStream_t s,
                double scale = 1.0);
 void run_xpby(const double *z, double beta, double *p, int64_t n, hipStream_t s);   // p = z + beta p
 double run_dot(const double *a, const double *b, int64_t n, double *part, hipStream_t s);
+// prediction (predict.hip): the mean k(xt, x) alpha (part holds
+// predict_slices(n, m) x m doubles) and columns of k(x, xt)
+int predict_slices(int64_t n, int64_t m);
+void run_predict_mean(int64_t n, const KParams &kp, const double *x, const double *alpha,
+                      int64_t m, const double *xt, double *part, double *mean, hipStream_t s);
+void run_kcross(int64_t n, const KParams &kp, const double *x, int64_t m, const double *xt,
+                int64_t j0, int nb, double *out, hipStream_t s);
 void run_sub(const double *y, const double *cx, double *r, int64_t n, hipStream_t s);
 double run_sumsq(const double *v, int64_t n, double *part, hipStream_t s);
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,

@@ -31,7 +31,7 @@ Prof &P()
 const char *kNames[PS_COUNT] = {"aca_row_pass", "aca_col_pass", "aca_small", "aca_misc",
                                 "leaf_factor",
                                 "leaf_solve",   "level_reduce", "level_solve", "level_update",
-                                "finish",       "matvec"};
+                                "finish",       "matvec",      "predict"};
 
 hipEvent_t take(Prof &p)
 {
