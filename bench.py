@@ -115,12 +115,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
-                    choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d"],
+                    choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d",
+                             "predict"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
                          "with n log-uniform in [1024, 131072] per step; learned: surrogate-"
-                         "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18")
+                         "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18; "
+                         "predict: posterior means at --m new inputs through an n=2^20 factor")
+    ap.add_argument("--m", type=int, default=8192, help="new inputs per step (predict)")
     ap.add_argument("--mcmc-steps", type=int, default=300)
     ap.add_argument("--autotune-free-leaf", action="store_true",
                     help="also run the autotuner with the leaf size free (reported only)")
@@ -152,6 +155,8 @@ def main():
         return bench_copy(args, torch, dev)
     if args.workload == "se2d":
         return bench_se2d(args, torch, H, wl, dev)
+    if args.workload == "predict":
+        return bench_predict(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -548,6 +553,87 @@ def bench_se2d(args, torch, H, wl, dev):
            "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
            "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
            "refined_solve": refined if mixed else None}
+    print(json.dumps(res), flush=True)
+
+
+# VALU instructions per kernel evaluation in the inner loop of the 1-D
+# Matern-3/2 product kernel (gfx950 assembly, -O3: 109 instructions per
+# unrolled iteration of 4 evaluations: subtract, |d| c, the exponential's
+# reduction, polynomial and scaling, its range selects, (1 + s), the product
+# with alpha and the accumulation)
+PREDICT_VALU_PER_EVAL = 109 / 4
+
+
+def bench_predict(args, torch, H, wl, dev):
+    """Prediction through the factor (§2.1) at the benchmark configuration:
+    the n = 2^20 Matern-3/2 series, factor built once (untimed); one step =
+    posterior means at --m new inputs ~ U(0, 1000) (hodlr_predict without
+    variances: C^{-1} y through the factor, then the exact products
+    k(xt, x) alpha over all n training points).  The product kernel is bound
+    by FP64 vector arithmetic; its roofline peak is the VALU issue rate (256
+    CUs x 4 SIMDs x 16 lanes x 2.4 GHz) over the instructions one evaluation
+    takes.  Once, untimed in the rate: variances at 8 inputs (one solve
+    each)."""
+    import oracle
+    p = wl.matern1d(args.n)
+    m = args.m
+    f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(max_rank=64))
+    xt = np.random.default_rng(2024).uniform(0.0, 1000.0, (m, 1))
+    for _ in range(args.warmup):
+        f.predict(p.y, xt, var=False)
+    H.profile_select(["predict"])
+    H.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mean, _ = f.predict(p.y, xt, var=False)
+    el = time.perf_counter() - t0
+    prof = H.profile_read()
+    H.profile_enable(False)
+    H.profile_select(None)
+    k_ms, k_launches = prof["predict"]
+    per_launch_s = k_ms / 1e3 / k_launches
+    evals = float(p.n) * m
+    peak = 256 * 4 * 16 * 2.4e9 / PREDICT_VALU_PER_EVAL / 1e9
+    ach = evals / per_launch_s / 1e9
+    roofline = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "Geval/s",
+                "frac": ach / peak, "traffic": None, "kernel": "predict_part_kernel<matern32,1>",
+                "avg_launch_ms": per_launch_s * 1e3,
+                "algorithmic_per_launch": {"kernel_evaluations": evals,
+                                           "valu_per_evaluation": PREDICT_VALU_PER_EVAL},
+                "note": "peak = 256 CUs x 64 FP64 lanes x 2.4 GHz / VALU instructions per "
+                        "evaluation; the inputs (16 MB) are read once per slice from L2/LDS"}
+    t1 = time.perf_counter()
+    _, var8 = f.predict(p.y, xt[:8])
+    t_var = time.perf_counter() - t1
+    f.free()
+    res = {"metric": "posterior means/s through the n=2^20 factor (exact k(xt, x) alpha)",
+           "value": m * args.steps / el, "unit": "means/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "predict_matern32_n%d_m%d" % (p.n, m), "n": p.n, "m": m,
+                      "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
+                      "leaf": p.leaf, "tol": p.tol},
+           "roofline": roofline,
+           "variance": {"inputs": 8, "seconds": t_var, "values": var8.tolist()}}
+    if not args.no_cpu_baseline:
+        # the oracle: exact alpha from the O(n) Kalman solves, then entry-by-entry
+        # kernel rows (OpenMP over rows) times alpha, for every new input
+        oracle.build(force=False)
+        t2 = time.perf_counter()
+        alpha = oracle.kalman_matern32(p.x[:, 0], p.y, p.theta, p.sigma2)["alpha"]
+        ref = np.empty(m)
+        for j0 in range(0, m, 64):
+            ref[j0:j0 + 64] = oracle.cross_matrix(xt[j0:j0 + 64], p.x, p.kernel, p.theta) @ alpha
+        dt = time.perf_counter() - t2
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": m / dt, "unit": "means/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "all %d means of one step: Kalman alpha at n=%d plus "
+                                         "%d x %d kernel entries times alpha, %.1f s on %d "
+                                         "threads" % (m, p.n, m, p.n, dt, threads)}
+        res["oracle_check"] = {"mean_max_rel_err": float(np.max(np.abs(mean - ref))
+                                                         / max(1.0, np.max(np.abs(ref))))}
     print(json.dumps(res), flush=True)
 
 

@@ -14,8 +14,7 @@
 
 namespace hodlr {
 
-constexpr int LEAF_THREADS = 256;
-constexpr int LEAF_XB = 32;   // columns per batch of the triangular solves
+constexpr int LEAF_SOLVE_T = 64;   // one wave per leaf in the solve with stored factors
 
 struct LeafArgs {
     const double *x;
@@ -45,37 +44,6 @@ __device__ __forceinline__ int tri_row(int idx)
     while (tri(i) > idx)
         --i;
     return i;
-}
-
-// Forward and backward substitution with the packed factor in LDS on nb
-// columns of Xs (row stride LEAF_XB + 1): Xs <- C^{-1} Xs.
-__device__ void leaf_trsm(const double *Ap, double *Xs, int m, int nb)
-{
-    const int tid = threadIdx.x;
-    const int ld = LEAF_XB + 1;
-    for (int j = 0; j < m; ++j) {
-        double g = Ap[tri(j) + j];
-        for (int c = tid; c < nb; c += LEAF_THREADS)
-            Xs[j * ld + c] /= g;
-        __syncthreads();
-        int rows = m - j - 1;
-        for (int idx = tid; idx < rows * nb; idx += LEAF_THREADS) {
-            int i = j + 1 + idx / nb, c = idx % nb;
-            Xs[i * ld + c] -= Ap[tri(i) + j] * Xs[j * ld + c];
-        }
-        __syncthreads();
-    }
-    for (int j = m - 1; j >= 0; --j) {
-        double g = Ap[tri(j) + j];
-        for (int c = tid; c < nb; c += LEAF_THREADS)
-            Xs[j * ld + c] /= g;
-        __syncthreads();
-        for (int idx = tid; idx < j * nb; idx += LEAF_THREADS) {
-            int i = idx / nb, c = idx % nb;
-            Xs[i * ld + c] -= Ap[tri(j) + i] * Xs[j * ld + c];
-        }
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -567,13 +535,26 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     }
 }
 
-// z <- C_lambda^{-1} z on each leaf with the stored packed factors
-template <typename PT>
-__global__ __launch_bounds__(LEAF_THREADS) void leaf_solve_kernel(LeafArgs A, PT *z)
+// the value lane l (uniform) holds, in every lane
+__device__ __forceinline__ double lane_value(double v, int l)
 {
-    __shared__ double Ap[LEAF_LDS_MAX * (LEAF_LDS_MAX + 1) / 2];
-    __shared__ double Xs[LEAF_LDS_MAX * (LEAF_XB + 1)];
-    const int tid = threadIdx.x;
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// z <- C_lambda^{-1} z on each leaf with the stored packed factors (row i of
+// L at G[i (i + 1) / 2 ...]): one wave per leaf, the factor copied to LDS with
+// coalesced loads, lane l holding rows l and l + 64 of the vector.  Forward
+// substitution by columns (step j reads L_ij down column j, whose packed
+// addresses fall in distinct LDS banks for 32 consecutive rows), then the
+// backward one by rows of L (contiguous); each step broadcasts the finished
+// entry from its lane and scales it by the reciprocal of L_jj.
+template <typename PT>
+__global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT *z)
+{
+    extern __shared__ double Lp[];
+    const int lane = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int64_t h = A.leaf0 + b;
     const int64_t s = A.start[h];
@@ -581,14 +562,119 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_solve_kernel(LeafArgs A, PT
     if (m == 0)
         return;
     const double *g = A.G + b * A.gstride;
-    for (int idx = tid; idx < tri(m); idx += LEAF_THREADS)
-        Ap[idx] = g[idx];
-    for (int i = tid; i < m; i += LEAF_THREADS)
-        Xs[i * (LEAF_XB + 1)] = z[s + i];
+    const int ntri = tri(m);
+    // the copy in rounds of 16 pairs per lane (16 KB in flight per wave) when
+    // the leaf's factor starts on 16 bytes, else of 8 entries per lane
+    constexpr int CU = 16;
+    const bool pairs = ((uintptr_t)g & 15) == 0;
+    int base = 0;
+    for (; pairs && base + 2 * CU * LEAF_SOLVE_T <= ntri; base += 2 * CU * LEAF_SOLVE_T) {
+        double2 v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            v[u] = *(const double2 *)(g + base + 2 * (u * LEAF_SOLVE_T + lane));
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            *(double2 *)(Lp + base + 2 * (u * LEAF_SOLVE_T + lane)) = v[u];
+    }
+    for (; base + 8 * LEAF_SOLVE_T <= ntri; base += 8 * LEAF_SOLVE_T) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = g[base + u * LEAF_SOLVE_T + lane];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            Lp[base + u * LEAF_SOLVE_T + lane] = v[u];
+    }
+    for (int idx = base + lane; idx < ntri; idx += LEAF_SOLVE_T)
+        Lp[idx] = g[idx];
+    const int ra = lane, rb = lane + 64;
+    const bool ina = ra < m, inb = rb < m;
+    double xa = ina ? (double)z[s + ra] : 0.0;
+    double xb = inb ? (double)z[s + rb] : 0.0;
     __syncthreads();
-    leaf_trsm(Ap, Xs, m, 1);
-    for (int i = tid; i < m; i += LEAF_THREADS)
-        z[s + i] = (PT)Xs[i * (LEAF_XB + 1)];
+    const int ta = tri(ra), tb = tri(rb);
+    const double ia = ina ? 1.0 / Lp[ta + ra] : 0.0;
+    const double ib = inb ? 1.0 / Lp[tb + rb] : 0.0;
+    const int ma = min(m, 64);
+    // Steps go in blocks of SB: the block's LDS entries are read first (they
+    // do not depend on the broadcasts), then its steps run.  A lane whose
+    // entry is not used reads index 0 and drops it, so every index read is
+    // below tri(m).
+    constexpr int SB = 8;
+    auto fa = [&](int j) { return ra > j && ina ? Lp[ta + j] : 0.0; };
+    auto fb = [&](int j) { return rb > j && inb ? Lp[tb + j] : 0.0; };
+    auto ga = [&](int j) { return ra < j ? Lp[tri(j) + ra] : 0.0; };
+    auto gb = [&](int j) { return rb < j ? Lp[tri(j) + rb] : 0.0; };
+    // L u = z, by columns
+    for (int j0 = 0; j0 < ma; j0 += SB) {
+        double ca[SB], cb[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            ca[u] = fa(j0 + u);
+            cb[u] = fb(j0 + u);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = j0 + u;
+            if (j < ma) {
+                const double uj = lane_value(xa, j) * lane_value(ia, j);
+                xa = ra == j ? uj : fma(-ca[u], uj, xa);
+                xb = fma(-cb[u], uj, xb);
+            }
+        }
+    }
+    for (int j0 = 64; j0 < m; j0 += SB) {
+        double cb[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u)
+            cb[u] = fb(j0 + u);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = j0 + u;
+            if (j < m) {
+                const double uj = lane_value(xb, j - 64) * lane_value(ib, j - 64);
+                xb = rb == j ? uj : fma(-cb[u], uj, xb);
+            }
+        }
+    }
+    // L^T w = u, by rows of L (contiguous over the lanes)
+    for (int j0 = m - 1; j0 >= 64; j0 -= SB) {
+        double ca[SB], cb[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = max(j0 - u, 0);
+            ca[u] = ga(j);
+            cb[u] = gb(j);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = j0 - u;
+            if (j >= 64) {
+                const double wj = lane_value(xb, j - 64) * lane_value(ib, j - 64);
+                xb = rb == j ? wj : fma(-cb[u], wj, xb);
+                xa = fma(-ca[u], wj, xa);
+            }
+        }
+    }
+    for (int j0 = ma - 1; j0 >= 0; j0 -= SB) {
+        double ca[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u)
+            ca[u] = ga(max(j0 - u, 0));
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = j0 - u;
+            if (j >= 0) {
+                const double wj = lane_value(xa, j) * lane_value(ia, j);
+                xa = ra == j ? wj : fma(-ca[u], wj, xa);
+            }
+        }
+    }
+    if (ina)
+        z[s + ra] = (PT)xa;
+    if (inb)
+        z[s + rb] = (PT)xb;
 }
 
 static LeafArgs leaf_args(Pipeline &P)
@@ -637,11 +723,21 @@ void run_leaf_solve(Pipeline &P, void *z)
 {
     const Plan &p = *P.plan;
     LeafArgs A = leaf_args(P);
+    static bool attr = false;   // room for the packed factor of a 128-point leaf (66 KB)
+    if (!attr) {
+        const int most = sizeof(double) * LEAF_LDS_MAX * (LEAF_LDS_MAX + 1) / 2;
+        HIP_TRY(hipFuncSetAttribute((const void *)leaf_solve_kernel<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, most));
+        HIP_TRY(hipFuncSetAttribute((const void *)leaf_solve_kernel<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, most));
+        attr = true;
+    }
+    const size_t lds = sizeof(double) * (size_t)p.leafmax * (p.leafmax + 1) / 2;
     ProfScope ps(P.stream, PS_LEAF_SOLVE);
     if (p.f32())
-        leaf_solve_kernel<float><<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, (float *)z);
+        leaf_solve_kernel<float><<<(unsigned)p.nleaf, LEAF_SOLVE_T, lds, P.stream>>>(A, (float *)z);
     else
-        leaf_solve_kernel<double><<<(unsigned)p.nleaf, LEAF_THREADS, 0, P.stream>>>(A, (double *)z);
+        leaf_solve_kernel<double><<<(unsigned)p.nleaf, LEAF_SOLVE_T, lds, P.stream>>>(A, (double *)z);
     HIP_TRY(hipGetLastError());
 }
 
