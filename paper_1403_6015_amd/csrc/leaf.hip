@@ -544,12 +544,15 @@ __device__ __forceinline__ double lane_value(double v, int l)
 }
 
 // z <- C_lambda^{-1} z on each leaf with the stored packed factors (row i of
-// L at G[i (i + 1) / 2 ...]): one wave per leaf, the factor copied to LDS with
-// coalesced loads, lane l holding rows l and l + 64 of the vector.  Forward
-// substitution by columns (step j reads L_ij down column j, whose packed
-// addresses fall in distinct LDS banks for 32 consecutive rows), then the
-// backward one by rows of L (contiguous); each step broadcasts the finished
-// entry from its lane and scales it by the reciprocal of L_jj.
+// L at G[i (i + 1) / 2 ...]): one wave per leaf, the factor copied to LDS by
+// direct global-to-LDS loads, lane l holding rows l and l + 64 of the vector.
+// With D = diag(L) and the unit-diagonal L' = L D^{-1}:  L' v = z, then
+// L'^T w = D^{-2} v gives w = C^{-1} z.  The forward sweep goes by columns of
+// L' (step j reads L_ij down column j, whose packed addresses fall in distinct
+// LDS banks for 32 consecutive rows), the backward one by rows of L
+// (contiguous); each step broadcasts the finished entry from its lane, and the
+// scaling by 1 / L_jj is applied to the read entries, off the dependency
+// chain of the sweep.
 template <typename PT>
 __global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT *z)
 {
@@ -563,20 +566,14 @@ __global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT
         return;
     const double *g = A.G + b * A.gstride;
     const int ntri = tri(m);
-    // the copy in rounds of 16 pairs per lane (16 KB in flight per wave) when
-    // the leaf's factor starts on 16 bytes, else of 8 entries per lane
-    constexpr int CU = 16;
-    const bool pairs = ((uintptr_t)g & 15) == 0;
+    // 1 KB per instruction (16 bytes a lane) when the leaf's factor starts on
+    // 16 bytes, all issued before one wait; the rest by ordinary loads
     int base = 0;
-    for (; pairs && base + 2 * CU * LEAF_SOLVE_T <= ntri; base += 2 * CU * LEAF_SOLVE_T) {
-        double2 v[CU];
-#pragma unroll
-        for (int u = 0; u < CU; ++u)
-            v[u] = *(const double2 *)(g + base + 2 * (u * LEAF_SOLVE_T + lane));
-#pragma unroll
-        for (int u = 0; u < CU; ++u)
-            *(double2 *)(Lp + base + 2 * (u * LEAF_SOLVE_T + lane)) = v[u];
-    }
+    if (((uintptr_t)g & 15) == 0)
+        for (; base + 2 * LEAF_SOLVE_T <= ntri; base += 2 * LEAF_SOLVE_T)
+            __builtin_amdgcn_global_load_lds((const void *)(g + base + 2 * lane),
+                                             (__attribute__((address_space(3))) void *)(Lp + base),
+                                             16, 0, 0);
     for (; base + 8 * LEAF_SOLVE_T <= ntri; base += 8 * LEAF_SOLVE_T) {
         double v[8];
 #pragma unroll
@@ -592,35 +589,41 @@ __global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT
     const bool ina = ra < m, inb = rb < m;
     double xa = ina ? (double)z[s + ra] : 0.0;
     double xb = inb ? (double)z[s + rb] : 0.0;
+    __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed in LDS
     __syncthreads();
     const int ta = tri(ra), tb = tri(rb);
     const double ia = ina ? 1.0 / Lp[ta + ra] : 0.0;
     const double ib = inb ? 1.0 / Lp[tb + rb] : 0.0;
     const int ma = min(m, 64);
-    // Steps go in blocks of SB: the block's LDS entries are read first (they
-    // do not depend on the broadcasts), then its steps run.  A lane whose
-    // entry is not used reads index 0 and drops it, so every index read is
-    // below tri(m).
+    // Steps go in blocks of SB: the block's LDS entries are read and scaled
+    // first (they do not depend on the broadcasts), then its steps run.  A
+    // lane whose entry is not used takes 0 (its value is left as it is), so
+    // every index read is below tri(m).
     constexpr int SB = 8;
-    auto fa = [&](int j) { return ra > j && ina ? Lp[ta + j] : 0.0; };
-    auto fb = [&](int j) { return rb > j && inb ? Lp[tb + j] : 0.0; };
-    auto ga = [&](int j) { return ra < j ? Lp[tri(j) + ra] : 0.0; };
-    auto gb = [&](int j) { return rb < j ? Lp[tri(j) + rb] : 0.0; };
-    // L u = z, by columns
+    auto pick = [&](bool use, int idx) {   // an unconditional read, then a select
+        const double v = Lp[use ? idx : 0];
+        return use ? v : 0.0;
+    };
+    auto fa = [&](int j) { return pick(ra > j && ina, ta + j); };
+    auto fb = [&](int j) { return pick(rb > j && inb, tb + j); };
+    auto ga = [&](int j) { return pick(ra < j, tri(j) + ra); };
+    auto gb = [&](int j) { return pick(rb < j, tri(j) + rb); };
+    // L' v = z, by columns
     for (int j0 = 0; j0 < ma; j0 += SB) {
         double ca[SB], cb[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            ca[u] = fa(j0 + u);
-            cb[u] = fb(j0 + u);
+            const double d = lane_value(ia, min(j0 + u, 63));
+            ca[u] = fa(j0 + u) * d;
+            cb[u] = fb(j0 + u) * d;
         }
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = j0 + u;
             if (j < ma) {
-                const double uj = lane_value(xa, j) * lane_value(ia, j);
-                xa = ra == j ? uj : fma(-ca[u], uj, xa);
-                xb = fma(-cb[u], uj, xb);
+                const double vj = lane_value(xa, j);
+                xa = fma(-ca[u], vj, xa);
+                xb = fma(-cb[u], vj, xb);
             }
         }
     }
@@ -628,31 +631,33 @@ __global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT
         double cb[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u)
-            cb[u] = fb(j0 + u);
+            cb[u] = fb(j0 + u) * lane_value(ib, min(j0 + u - 64, 63));
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = j0 + u;
             if (j < m) {
-                const double uj = lane_value(xb, j - 64) * lane_value(ib, j - 64);
-                xb = rb == j ? uj : fma(-cb[u], uj, xb);
+                const double vj = lane_value(xb, j - 64);
+                xb = fma(-cb[u], vj, xb);
             }
         }
     }
-    // L^T w = u, by rows of L (contiguous over the lanes)
+    // L'^T w = D^{-2} v, by rows of L (row j of L scaled by 1 / L_ii in lane i)
+    xa *= ia * ia;
+    xb *= ib * ib;
     for (int j0 = m - 1; j0 >= 64; j0 -= SB) {
         double ca[SB], cb[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = max(j0 - u, 0);
-            ca[u] = ga(j);
-            cb[u] = gb(j);
+            ca[u] = ga(j) * ia;
+            cb[u] = gb(j) * ib;
         }
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = j0 - u;
             if (j >= 64) {
-                const double wj = lane_value(xb, j - 64) * lane_value(ib, j - 64);
-                xb = rb == j ? wj : fma(-cb[u], wj, xb);
+                const double wj = lane_value(xb, j - 64);
+                xb = fma(-cb[u], wj, xb);
                 xa = fma(-ca[u], wj, xa);
             }
         }
@@ -661,13 +666,13 @@ __global__ __launch_bounds__(LEAF_SOLVE_T) void leaf_solve_kernel(LeafArgs A, PT
         double ca[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u)
-            ca[u] = ga(max(j0 - u, 0));
+            ca[u] = ga(max(j0 - u, 0)) * ia;
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = j0 - u;
             if (j >= 0) {
-                const double wj = lane_value(xa, j) * lane_value(ia, j);
-                xa = ra == j ? wj : fma(-ca[u], wj, xa);
+                const double wj = lane_value(xa, j);
+                xa = fma(-ca[u], wj, xa);
             }
         }
     }
