@@ -964,6 +964,63 @@ __global__ __launch_bounds__(256) void pipeline_init_kernel(InitArgs a)
     }
 }
 
+// A second stream of the calling host thread on each device (default
+// priority), with the events that fork work onto it and join it back.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static SideStream &side_stream()
+{
+    struct Table {
+        SideStream e[16];
+        ~Table()
+        {
+            for (SideStream &x : e) {
+                if (x.s)
+                    (void)hipStreamDestroy(x.s);
+                if (x.fork)
+                    (void)hipEventDestroy(x.fork);
+                if (x.join)
+                    (void)hipEventDestroy(x.join);
+            }
+        }
+    };
+    thread_local Table t;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16)
+        throw Error{HODLR_EDEVICE, "device index above 15"};
+    SideStream &x = t.e[dev];
+    if (!x.s) {
+        HIP_TRY(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+    }
+    return x;
+}
+
+// Makes the pipeline's stream wait for what was forked onto the side stream,
+// at the latest when it goes out of scope (also when an error unwinds).
+struct SideJoin {
+    hipStream_t main;
+    SideStream *side = nullptr;
+    void wait()
+    {
+        if (side) {
+            SideStream *x = side;
+            side = nullptr;
+            HIP_TRY(hipStreamWaitEvent(main, x->join, 0));
+        }
+    }
+    ~SideJoin()
+    {
+        if (side)
+            (void)hipStreamWaitEvent(main, side->join, 0);
+    }
+};
+
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -1012,29 +1069,47 @@ void run_aca(Pipeline &P)
         pipeline_init_kernel<<<(unsigned)std::max<int64_t>(nb, 1), 256, 0, s>>>(ia);
     }
     HIP_TRY(hipGetLastError());
-    // small blocks: the whole loop per work-group, one launch
+    const int nbig = (int)p.aca_big.size();
+    // small blocks: the whole loop per work-group.  When there are large
+    // blocks too, they run on the side stream, alongside the large blocks'
+    // passes (which occupy few work-groups per launch), and are joined before
+    // the first rank statistics.
+    SideJoin join{s};
     if (!p.aca_small.empty()) {
+        hipStream_t ss = s;
+        if (nbig > 0) {
+            SideStream &x = side_stream();
+            HIP_TRY(hipEventRecord(x.fork, s));
+            HIP_TRY(hipStreamWaitEvent(x.s, x.fork, 0));
+            ss = x.s;
+        }
         SmallArgs S;
         S.a = A;
         S.nodes = p.d_aca_small;
         S.rank = rank;
         S.status = status;
-        ProfScope ps(s, PS_ACA_SMALL);
-        // blocks with both sides <= ACA_TINY (listed last) run on one wave,
-        // with wave-level reductions only
-        const int nwide = p.aca_small_wide;
-        if (nwide > 0) {
-            aca_small_kernel<ACA_SMALL_TH, ACA_SMALL><<<(unsigned)nwide, ACA_SMALL_TH, 0, s>>>(S);
-            HIP_TRY(hipGetLastError());
+        {
+            ProfScope ps(ss, PS_ACA_SMALL);
+            // blocks with both sides <= ACA_TINY (listed last) run on one wave,
+            // with wave-level reductions only
+            const int nwide = p.aca_small_wide;
+            if (nwide > 0) {
+                aca_small_kernel<ACA_SMALL_TH, ACA_SMALL><<<(unsigned)nwide, ACA_SMALL_TH, 0, ss>>>(S);
+                HIP_TRY(hipGetLastError());
+            }
+            const int ntiny = (int)p.aca_small.size() - nwide;
+            if (ntiny > 0) {
+                S.nodes = p.d_aca_small + nwide;
+                aca_small_kernel<64, ACA_TINY><<<(unsigned)ntiny, 64, 0, ss>>>(S);
+                HIP_TRY(hipGetLastError());
+            }
         }
-        const int ntiny = (int)p.aca_small.size() - nwide;
-        if (ntiny > 0) {
-            S.nodes = p.d_aca_small + nwide;
-            aca_small_kernel<64, ACA_TINY><<<(unsigned)ntiny, 64, 0, s>>>(S);
-            HIP_TRY(hipGetLastError());
+        if (ss != s) {
+            SideStream &x = side_stream();
+            HIP_TRY(hipEventRecord(x.join, ss));
+            join.side = &x;
         }
     }
-    const int nbig = (int)p.aca_big.size();
     if (nbig > 0) {
         BigState *st0 = wsp<BigState>(P, P.lay.aca_state);
         BigState *st1 = st0 + nbig;
@@ -1089,6 +1164,7 @@ void run_aca(Pipeline &P)
             // loop goes on and the final poll rewrites them.
             const bool poll = hint > 0 ? it + 1 >= hint : (it >= 2 && (it & 1) == 0);
             if (poll) {
+                join.wait();   // the small blocks' ranks are part of the statistics
                 {
                     ProfScope ps(s, PS_ACA_MISC);
                     aca_big_finish_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big,

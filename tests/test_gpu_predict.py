@@ -117,3 +117,29 @@ def test_edges_and_errors():
         f.predict(p.y, np.array([[np.nan]]))
     assert e.value.name == "EINVAL"
     f.free()
+
+
+def test_regression_rmse_follows_the_tolerance():
+    """§5.6 experiment: the regression estimate K C^{-1} y at the 1024 data
+    points of the synthetic model through the GPU factor; its RMSE differs
+    from the dense oracle's by an amount proportional to the factorization
+    precision, for smallest blocks of 20 and 64 points."""
+    p = wl.regression_model()
+    n = p.n
+    exact, _ = oracle.gp_predict_dense(p.x, p.y, p.x, p.kernel, p.theta, p.sigma2, want_var=False)
+    rm_exact = np.linalg.norm(p.y - exact) / np.sqrt(n)
+    errs = {}
+    for tol in (1e-4, 1e-7, 1e-10):
+        for leaf in (20, 64):
+            announce("regression tol=%g leaf=%d" % (tol, leaf))
+            f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, leaf, tol)
+            yh, _ = f.predict(p.y, p.x, var=False)
+            f.free()
+            d = abs(np.linalg.norm(p.y - yh) / np.sqrt(n) - rm_exact)
+            e = np.max(np.abs(yh - exact))
+            print("tol %g leaf %d: |dRMSE| %.2e, max |dy| %.2e" % (tol, leaf, d, e))
+            assert d <= 1e-2 * tol + 1e-13
+            assert e <= 10 * tol + 1e-11
+            errs[tol, leaf] = e
+    for leaf in (20, 64):
+        assert errs[1e-4, leaf] > errs[1e-7, leaf] > errs[1e-10, leaf]

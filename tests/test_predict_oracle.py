@@ -84,3 +84,39 @@ def test_interpolation_limit():
     mean, var = oracle.gp_predict_dense(x, y, x, wl.K_MATERN32, (1.0, 1.0), 1e-12)
     assert np.max(np.abs(mean - y)) <= 1e-8
     assert np.max(np.abs(var)) <= 1e-8
+
+
+def test_regression_estimate_at_the_data():
+    # at the training points K C^{-1} = I - sigma^2 C^{-1}, so the regression
+    # estimate of §5.6 equals y - sigma^2 C^{-1} y (C^{-1} y by LAPACK here,
+    # independent of the oracle's Cholesky)
+    p = wl.regression_model(256)
+    yhat, _ = oracle.gp_predict_dense(p.x, p.y, p.x, p.kernel, p.theta, p.sigma2, want_var=False)
+    C = oracle.dense_matrix(p.x, p.kernel, p.theta, p.sigma2)
+    alpha = np.linalg.solve(C, p.y)
+    assert np.max(np.abs(yhat - (p.y - p.sigma2 * alpha))) <= 1e-12 * np.max(np.abs(p.y))
+
+
+def test_walkthrough_rmse_difference_follows_tolerance():
+    # §5.6: the RMSE of the regression through the HODLR factor differs from the
+    # exact one by an amount proportional to the factorization precision, for
+    # any size of the smallest blocks (walk-through of the method against the
+    # dense oracle)
+    from oracle import hodlr_ref as hr
+    p = wl.regression_model()
+    n = p.n
+    exact, _ = oracle.gp_predict_dense(p.x, p.y, p.x, p.kernel, p.theta, p.sigma2, want_var=False)
+    rm_exact = np.linalg.norm(p.y - exact) / np.sqrt(n)
+    Ks = oracle.cross_matrix(p.x, p.x, p.kernel, p.theta)
+    errs = {}
+    for tol in (1e-4, 1e-7, 1e-10):
+        for leaf in (20, 64):
+            ref = hr.HodlrRef(p.x, p.kernel, p.theta, p.sigma2, leaf, tol)
+            yh = Ks @ ref.solve(p.y)
+            d = abs(np.linalg.norm(p.y - yh) / np.sqrt(n) - rm_exact)
+            e = np.max(np.abs(yh - exact))
+            assert d <= 1e-2 * tol + 1e-14, (tol, leaf, d)
+            assert e <= 10 * tol, (tol, leaf, e)
+            errs[tol, leaf] = e
+    for leaf in (20, 64):
+        assert errs[1e-4, leaf] > errs[1e-7, leaf] > errs[1e-10, leaf]
