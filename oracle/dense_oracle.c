@@ -19,6 +19,8 @@
  *   1  Matern nu=3/2        a^2 (1 + sqrt(3) r / l) exp(-sqrt(3) r / l)
  *   2  exponential (O-U)    a^2 exp(-r / l)
  *   3  constant             a^2                       (rank one)
+ *   4  inverse multiquadric a^2 / sqrt(1 + r^2 / l^2) (§5's inverse
+ *                                                   multiquadric with a length scale)
  * with r the Euclidean distance between points.  Points are stored
  * point-major: x[i*dim + d].
  */
@@ -47,6 +49,8 @@ double oracle_kernel(int kind, const double *xi, const double *xj, int dim,
         return a2 * exp(-sqrt(r2) / ell);
     case 3:
         return a2;
+    case 4: /* inverse multiquadric (§5), with a length scale */
+        return a2 / sqrt(1.0 + r2 / (ell * ell));
     default:
         return NAN;
     }

@@ -63,6 +63,8 @@ def kernel_block(kind: int, xa: np.ndarray, xb: np.ndarray, a: float, ell: float
         return a2 * np.exp(-np.sqrt(r2) / ell)
     if kind == 3:
         return np.full(r2.shape, a2)
+    if kind == 4:
+        return a2 / np.sqrt(1.0 + r2 / (ell * ell))
     raise ValueError("unknown kernel %r" % kind)
 
 

@@ -17,7 +17,7 @@ import oracle
 from oracle import hodlr_ref
 import workloads as wl
 
-KINDS = [wl.K_SE, wl.K_MATERN32, wl.K_EXP, wl.K_CONST]
+KINDS = [wl.K_SE, wl.K_MATERN32, wl.K_EXP, wl.K_CONST, wl.K_IMQ]
 
 
 def test_kernel_closed_forms(oracle_lib):
@@ -30,11 +30,30 @@ def test_kernel_closed_forms(oracle_lib):
         pytest.approx(2 * a * a / e, rel=1e-14)
     assert oracle.kernel_value(wl.K_EXP, [1.0], [1.0 - ell], a, ell) == pytest.approx(a * a / e, rel=1e-14)
     assert oracle.kernel_value(wl.K_CONST, [3.0], [-9.0], a, ell) == a * a
+    # inverse multiquadric: 1 / sqrt(1 + 3) = 1/2 at r = sqrt(3) l, 1/3 at
+    # r = sqrt(8) l (in 2-D: the offset (2 l, 2 l))
+    assert oracle.kernel_value(wl.K_IMQ, [0.5], [0.5 + math.sqrt(3) * ell], a, ell) == \
+        pytest.approx(a * a / 2, rel=1e-15)
+    assert oracle.kernel_value(wl.K_IMQ, [0.0, 0.0], [2 * ell, 2 * ell], a, ell) == \
+        pytest.approx(a * a / 3, rel=1e-15)
     # Euclidean distance in 2-D and 3-D: |(3,4)| = 5, |(1,2,2)| = 3
     assert oracle.kernel_value(wl.K_EXP, [0.0, 0.0], [3.0, 4.0], 1.0, 5.0) == pytest.approx(1 / e, rel=1e-15)
     assert oracle.kernel_value(wl.K_EXP, [0, 0, 0], [1, 2, 2], 1.0, 3.0) == pytest.approx(1 / e, rel=1e-15)
     for k in KINDS:
         assert oracle.kernel_value(k, [0.3, 0.1], [0.3, 0.1], a, ell) == pytest.approx(a * a, rel=1e-15)
+
+
+def test_inverse_multiquadric_is_a_gaussian_scale_mixture(oracle_lib):
+    # (1 + u)^(-1/2) = pi^(-1/2) int_0^inf t^(-1/2) exp(-t (1 + u)) dt, evaluated
+    # by quadrature (substitution t = s^2 removes the endpoint singularity)
+    from scipy.integrate import quad
+    a, ell = 0.8, 0.3
+    for r in (0.0, 0.1, 0.45, 2.0, 17.0):
+        u = (r / ell) ** 2
+        val, _ = quad(lambda s_: 2.0 * math.exp(-s_ * s_ * (1.0 + u)), 0.0, math.inf,
+                      epsabs=0.0, epsrel=1e-13)
+        assert oracle.kernel_value(wl.K_IMQ, [1.0], [1.0 + r], a, ell) == \
+            pytest.approx(a * a * val / math.sqrt(math.pi), rel=1e-12)
 
 
 def test_numpy_kernel_agrees_with_c_kernel(oracle_lib):

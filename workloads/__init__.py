@@ -37,7 +37,9 @@ K_SE = 0
 K_MATERN32 = 1
 K_EXP = 2
 K_CONST = 3
-KERNEL_NAMES = {K_SE: "se", K_MATERN32: "matern32", K_EXP: "exp", K_CONST: "const"}
+K_IMQ = 4
+KERNEL_NAMES = {K_SE: "se", K_MATERN32: "matern32", K_EXP: "exp", K_CONST: "const",
+                K_IMQ: "imq"}
 
 
 @dataclass
