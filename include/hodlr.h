@@ -64,7 +64,9 @@ typedef enum {
     HODLR_K_SE = 0,        /* a^2 exp(-r^2 / (2 l^2))                      */
     HODLR_K_MATERN32 = 1,  /* a^2 (1 + sqrt(3) r / l) exp(-sqrt(3) r / l)  */
     HODLR_K_EXP = 2,       /* a^2 exp(-r / l)  (Ornstein-Uhlenbeck)         */
-    HODLR_K_CONST = 3      /* a^2  (rank one; for tests)                    */
+    HODLR_K_CONST = 3,     /* a^2  (rank one; for tests)                    */
+    HODLR_K_IMQ = 4        /* a^2 / sqrt(1 + r^2 / l^2)  (inverse
+                              multiquadric, §5)                             */
 } hodlr_kernel;
 
 enum { HODLR_FP64 = 0, HODLR_MIXED = 1 };

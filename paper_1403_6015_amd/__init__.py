@@ -17,7 +17,7 @@ __all__ = [
     "HodlrError", "Opts", "Factor", "Plan", "lib", "hodlr_order", "hodlr_num_levels",
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "hodlr_predict", "gp_loglik", "hodlr_info",
     "hodlr_free",
-    "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST",
+    "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST", "K_IMQ",
     "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
     "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
@@ -25,7 +25,7 @@ __all__ = [
     "gp_sample_dev", "Tune", "plan_tuned_create", "autotune", "tune_lookup",
 ]
 
-K_SE, K_MATERN32, K_EXP, K_CONST = 0, 1, 2, 3
+K_SE, K_MATERN32, K_EXP, K_CONST, K_IMQ = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOCONV"}
 EXPORTED = [

@@ -73,7 +73,7 @@ void check_opts(const hodlr_opts &o)
 
 void check_params(int k, const double theta[2], double sigma2, double tol)
 {
-    if (k < HODLR_K_SE || k > HODLR_K_CONST)
+    if (k < HODLR_K_SE || k > HODLR_K_IMQ)
         throw Error{HODLR_EINVAL, "unknown kernel"};
     if (!theta)
         throw Error{HODLR_EINVAL, "theta is NULL"};
@@ -770,7 +770,7 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
     return guarded([&]() {
         if (!p || !d_x || !d_params || !d_y || !d_work || !d_out || nitems < 1)
             throw Error{HODLR_EINVAL, "bad argument"};
-        if (k < HODLR_K_SE || k > HODLR_K_CONST)
+        if (k < HODLR_K_SE || k > HODLR_K_IMQ)
             throw Error{HODLR_EINVAL, "unknown kernel"};
         if (!(tol > 0.0) || !std::isfinite(tol))
             throw Error{HODLR_EINVAL, "tol must be positive and finite"};

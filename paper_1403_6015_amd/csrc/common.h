@@ -78,6 +78,7 @@ inline KParams make_kparams(int kind, int dim, const double theta[2], double sig
     case HODLR_K_SE: k.c = 1.0 / (2.0 * l * l); break;
     case HODLR_K_MATERN32: k.c = std::sqrt(3.0) / l; break;
     case HODLR_K_EXP: k.c = 1.0 / l; break;
+    case HODLR_K_IMQ: k.c = 1.0 / (l * l); break;
     default: k.c = 0.0; break;
     }
     k.sigma2 = sigma2;
@@ -96,6 +97,8 @@ __device__ __forceinline__ T kfun_r2(int kind, T a2, T c, T r2)
     }
     case HODLR_K_EXP:
         return a2 * exp(-c * sqrt(r2));
+    case HODLR_K_IMQ:
+        return a2 / sqrt(T(1) + c * r2);
     default:
         return a2;
     }
@@ -138,7 +141,8 @@ __device__ __forceinline__ KParams item_kp(KParams kp, const BatchArgs &B, int i
         kp.a2 = a * a;
         kp.c = (kp.kind == HODLR_K_SE) ? 1.0 / (2.0 * l * l)
              : (kp.kind == HODLR_K_MATERN32) ? 1.7320508075688772 / l
-             : (kp.kind == HODLR_K_EXP) ? 1.0 / l : 0.0;
+             : (kp.kind == HODLR_K_EXP) ? 1.0 / l
+             : (kp.kind == HODLR_K_IMQ) ? 1.0 / (l * l) : 0.0;
         kp.sigma2 = B.params[3 * item + 2];
     }
     return kp;

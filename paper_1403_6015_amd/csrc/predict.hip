@@ -35,6 +35,8 @@ __device__ __forceinline__ double kshape(const KParams &kp, const double (&a)[3]
         const double r = DIM == 1 ? fabs(a[0] - b[0]) : sqrt(r2);
         const double s = kp.c * r;
         return KIND == HODLR_K_MATERN32 ? (1.0 + s) * exp(-s) : exp(-s);
+    } else if constexpr (KIND == HODLR_K_IMQ) {
+        return 1.0 / sqrt(1.0 + kp.c * r2);
     } else {
         return 1.0;
     }
@@ -125,6 +127,7 @@ static void by_kind_dim(int kind, int dim, Args &&...args)
     case HODLR_K_SE: go(std::integral_constant<int, HODLR_K_SE>{}); break;
     case HODLR_K_MATERN32: go(std::integral_constant<int, HODLR_K_MATERN32>{}); break;
     case HODLR_K_EXP: go(std::integral_constant<int, HODLR_K_EXP>{}); break;
+    case HODLR_K_IMQ: go(std::integral_constant<int, HODLR_K_IMQ>{}); break;
     default: go(std::integral_constant<int, HODLR_K_CONST>{}); break;
     }
 }

@@ -186,7 +186,7 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
 {
     try {
         if (m < 1 || !ns || !xs || !ys || !params || !out || dim < 1 || dim > 3 || leaf < 1 ||
-            k < HODLR_K_SE || k > HODLR_K_CONST || !(tol > 0.0) || !std::isfinite(tol))
+            k < HODLR_K_SE || k > HODLR_K_IMQ || !(tol > 0.0) || !std::isfinite(tol))
             return report(HODLR_EINVAL, "bad shared argument");
         RaggedJob J;
         J.m = m;

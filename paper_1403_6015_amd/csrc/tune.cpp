@@ -117,7 +117,7 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
 {
     try {
         if (!x || !y || !theta || !best || n < 1 || dim < 1 || dim > 3 ||
-            k < HODLR_K_SE || k > HODLR_K_CONST || !(tol > 0.0) || reps < 1 ||
+            k < HODLR_K_SE || k > HODLR_K_IMQ || !(tol > 0.0) || reps < 1 ||
             (nleaf > 0 && !leaf_cands) || nleaf < 0)
             return report(HODLR_EINVAL, "bad autotune argument");
         hodlr_opts o;

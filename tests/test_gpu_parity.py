@@ -110,6 +110,18 @@ def test_exponential_exact_rank_one():
     assert max(info["rank_max"]) <= 2
 
 
+@pytest.mark.parametrize("dim,ell,sigma2", [(1, 0.1, 0.05), (2, 2.0, 0.1)])
+def test_inverse_multiquadric(dim, ell, sigma2):
+    """The inverse multiquadric kernel of §5 (with a length scale) in 1-D and
+    2-D against the dense oracle (its slow 1/r decay keeps 2-D ranks within
+    the cap of 64 only for smooth length scales)."""
+    n = 3000 if dim == 1 else 2000
+    p = wl.random_problem(n, dim, wl.K_IMQ, seed=60 + dim, ell=ell, sigma2=sigma2, leaf=64,
+                          tol=1e-12 if dim == 1 else 1e-13)
+    info = check_against_dense(p, H.Opts(max_rank=64))
+    assert info["capped_blocks"] == 0
+
+
 @pytest.mark.parametrize("kind", [wl.K_MATERN32, wl.K_EXP])
 def test_leaves_of_every_span(kind):
     """Leaves whose span keeps the separable exponentials in range and leaves

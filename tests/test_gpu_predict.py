@@ -62,6 +62,11 @@ def test_two_dimensional():
                              tol=1e-13), H.Opts(max_rank=64))
 
 
+def test_inverse_multiquadric():
+    _check(wl.random_problem(3000, 1, wl.K_IMQ, seed=61, ell=0.1, sigma2=0.05, leaf=64,
+                             tol=1e-12))
+
+
 def test_mixed_factor_refined_solves():
     _check(wl.matern1d(4096), H.Opts(precision=H.MIXED), m=32, tol=1e-8)
 
