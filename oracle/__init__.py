@@ -83,6 +83,9 @@ def lib():
         L.oracle_kalman_matern32.restype = ctypes.c_int
         L.oracle_kalman_matern32.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, dp, dp, dp, dp]
+        L.oracle_kalman_matern32_noise.restype = ctypes.c_int
+        L.oracle_kalman_matern32_noise.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -159,6 +162,28 @@ def gp_dense(x, y, kind: int, theta, sigma2: float):
     return {"logdet": ld.value, "quad": q.value, "loglik": ll.value, "alpha": alpha}
 
 
+def gp_dense_noise(x, y, kind: int, theta, sigma2: float, noise):
+    """§5's covariance C_ij = (sigma^2 + sigma_i^2) delta_ij + k(x_i, x_j) with
+    per-point variances sigma_i^2 = noise[i] (caller's order), by the plain
+    definitions: the oracle's dense K, the diagonal added, its Cholesky, log
+    det = 2 sum log G_ii, alpha by the two triangular solves.  Returns the same
+    dict as gp_dense."""
+    x = _pts(x)
+    n = x.shape[0]
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
+    noise = np.asarray(noise, dtype=np.float64).ravel()
+    if noise.size != n:
+        raise ValueError("noise must hold one variance per point")
+    C = dense_matrix(x, kind, theta, sigma2)
+    C[np.diag_indices(n)] += noise
+    G = cholesky(C)
+    ld = 2.0 * float(np.sum(np.log(np.diag(G))))
+    alpha = chol_solve(G, y)
+    q = float(y @ alpha)
+    return {"logdet": ld, "quad": q, "loglik": -0.5 * q - 0.5 * ld - 0.5 * n * np.log(2.0 * np.pi),
+            "alpha": alpha}
+
+
 def cross_matrix(xa, xb, kind: int, theta) -> np.ndarray:
     """K(xa, xb) entry by entry (no noise term), shape (len(xa), len(xb))."""
     xa = _pts(xa)
@@ -205,17 +230,27 @@ def matvec_rows(x, kind: int, theta, sigma2: float, v, rows) -> np.ndarray:
     return out
 
 
-def kalman_matern32(t, y, theta, sigma2: float, want_alpha: bool = True):
-    """Exact 1-D Matern-3/2 log det, quad and C^{-1}y in O(n) (t sorted)."""
+def kalman_matern32(t, y, theta, sigma2: float, want_alpha: bool = True, noise=None):
+    """Exact 1-D Matern-3/2 log det, quad and C^{-1}y in O(n) (t sorted);
+    noise: optional per-point variances added to sigma2 (§5's sigma_i^2)."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).ravel())
     y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
     n = t.size
     ld = ctypes.c_double()
     q = ctypes.c_double()
     alpha = np.empty(n, dtype=np.float64) if want_alpha else None
-    st = lib().oracle_kalman_matern32(_p(t), n, float(theta[0]), float(theta[1]), float(sigma2),
-                                      _p(y), ctypes.byref(ld), ctypes.byref(q),
-                                      _p(alpha) if want_alpha else None)
+    if noise is None:
+        st = lib().oracle_kalman_matern32(_p(t), n, float(theta[0]), float(theta[1]),
+                                          float(sigma2), _p(y), ctypes.byref(ld),
+                                          ctypes.byref(q), _p(alpha) if want_alpha else None)
+    else:
+        nz = np.ascontiguousarray(np.asarray(noise, dtype=np.float64).ravel())
+        if nz.size != n:
+            raise ValueError("noise must hold one variance per point")
+        st = lib().oracle_kalman_matern32_noise(_p(t), n, float(theta[0]), float(theta[1]),
+                                                float(sigma2), _p(nz), _p(y), ctypes.byref(ld),
+                                                ctypes.byref(q),
+                                                _p(alpha) if want_alpha else None)
     if st != 0:
         raise OracleError("kalman oracle failed (status %d)" % st)
     loglik = -0.5 * q.value - 0.5 * ld.value - 0.5 * n * np.log(2.0 * np.pi)

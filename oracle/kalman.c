@@ -10,11 +10,13 @@
  *     s(t+dt) = A(dt) s(t) + q,   q ~ N(0, Q(dt)),
  *     A(dt) = exp(-lam dt) [[1 + lam dt, dt], [-lam^2 dt, 1 - lam dt]],
  *     P_inf = diag(a^2, lam^2 a^2),   Q = P_inf - A P_inf A^T,
- * and y_i = f(t_i) + e_i with e_i ~ N(0, sigma^2).  The filter's innovations
- * v_i and their variances S_i give the exact Gaussian quantities
+ * and y_i = f(t_i) + e_i with e_i ~ N(0, s_i), s_i = sigma^2 (+ a per-point
+ * variance sigma_i^2 when one is given: §5 writes the diagonal of C as
+ * sigma_i^2).  The filter's innovations v_i and their variances S_i give the
+ * exact Gaussian quantities
  *     log det C = sum_i log S_i,     y^T C^{-1} y = sum_i v_i^2 / S_i,
  * and the Rauch-Tung-Striebel smoothed mean m_s gives
- *     C^{-1} y = (y - m_s) / sigma^2   (since Cov(e, y) = sigma^2 I).
+ *     C^{-1} y = D^{-1} (y - m_s)   (since Cov(e, y) = D = diag(s_i)).
  * Times must be sorted ascending.
  */
 #include <math.h>
@@ -45,21 +47,25 @@ static void sandwich(const m22 *A, const double *P, double *out)
 }
 
 /*
- * Returns 0 on success, 1 on bad arguments (unsorted times, sigma2 <= 0 when
- * alpha is requested, non-positive innovation variance), -1 on allocation
- * failure.  alpha (C^{-1} y) may be NULL.
+ * Returns 0 on success, 1 on bad arguments (unsorted times, a noise variance
+ * <= 0 when alpha is requested, non-positive innovation variance), -1 on
+ * allocation failure.  alpha (C^{-1} y) may be NULL; noise (per-point
+ * variances added to sigma2) may be NULL.
  */
-int oracle_kalman_matern32(const double *t, int64_t n, double a, double ell,
-                           double sigma2, const double *y, double *logdet,
-                           double *quad, double *alpha)
+int oracle_kalman_matern32_noise(const double *t, int64_t n, double a, double ell,
+                                 double sigma2, const double *noise, const double *y,
+                                 double *logdet, double *quad, double *alpha)
 {
     if (n < 1)
         return 1;
     for (int64_t i = 1; i < n; ++i)
         if (!(t[i] >= t[i - 1]))
             return 1;
-    if (alpha && !(sigma2 > 0.0))
-        return 1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double si = sigma2 + (noise ? noise[i] : 0.0);
+        if (alpha && !(si > 0.0))
+            return 1;
+    }
     double lam = sqrt(3.0) / ell;
     double pinf[3] = {a * a, 0.0, lam * lam * a * a};
     /* filtered and predicted moments, kept for the smoother */
@@ -93,7 +99,7 @@ int oracle_kalman_matern32(const double *t, int64_t n, double a, double ell,
             Ppr[1] = APA[1] + (pinf[1] - Api[1]);
             Ppr[2] = APA[2] + (pinf[2] - Api[2]);
         }
-        double S = Ppr[0] + sigma2;
+        double S = Ppr[0] + sigma2 + (noise ? noise[i] : 0.0);
         if (!(S > 0.0)) {
             if (alpha) { free(mf); free(mp); free(Pf); free(Pp); }
             return 1;
@@ -121,7 +127,7 @@ int oracle_kalman_matern32(const double *t, int64_t n, double a, double ell,
     if (alpha) {
         /* RTS backward pass for the smoothed mean of f */
         double ms0 = mf[2 * (n - 1)], ms1 = mf[2 * (n - 1) + 1];
-        alpha[n - 1] = (y[n - 1] - ms0) / sigma2;
+        alpha[n - 1] = (y[n - 1] - ms0) / (sigma2 + (noise ? noise[n - 1] : 0.0));
         for (int64_t i = n - 2; i >= 0; --i) {
             m22 A = trans(lam, t[i + 1] - t[i]);
             const double *Pi = Pf + 3 * i;
@@ -140,9 +146,16 @@ int oracle_kalman_matern32(const double *t, int64_t n, double a, double ell,
             double n1 = mf[2 * i + 1] + g10 * d0 + g11 * d1;
             ms0 = n0;
             ms1 = n1;
-            alpha[i] = (y[i] - ms0) / sigma2;
+            alpha[i] = (y[i] - ms0) / (sigma2 + (noise ? noise[i] : 0.0));
         }
         free(mf); free(mp); free(Pf); free(Pp);
     }
     return 0;
+}
+
+int oracle_kalman_matern32(const double *t, int64_t n, double a, double ell,
+                           double sigma2, const double *y, double *logdet,
+                           double *quad, double *alpha)
+{
+    return oracle_kalman_matern32_noise(t, n, a, ell, sigma2, NULL, y, logdet, quad, alpha);
 }
