@@ -88,6 +88,14 @@ typedef struct {
     int32_t max_refine;  /* mixed form: at most 1 + max_refine preconditioned steps,
                             each one exact product and one factor solve (default 8)   */
     int32_t presorted;   /* 1: the points are already in tree order; skip ordering     */
+    const double *noise; /* optional per-point noise variances sigma_i^2 (host memory,
+                            n entries in the caller's point order, each >= 0 and
+                            finite; §5 writes the diagonal of C as sigma_i^2): the
+                            diagonal of C becomes sigma2 + noise[i].  Read during the
+                            call only (the factor keeps its own copy).  Taken by
+                            hodlr_build and gp_loglik; the plan-based, batched,
+                            uneven-size and autotuning entry points reject a non-NULL
+                            value with HODLR_EINVAL.  Default NULL                    */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one

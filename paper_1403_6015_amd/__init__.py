@@ -57,11 +57,20 @@ class HodlrError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("presorted", ctypes.c_int32)]
+                ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p)]
 
-    def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0):
+    def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0,
+                 noise=None):
+        """noise: optional per-point variances (one per point, caller's order),
+        added to sigma2 on the diagonal; the array is kept alive with the
+        options."""
+        self._noise = None
+        ptr = None
+        if noise is not None:
+            self._noise = np.ascontiguousarray(np.asarray(noise, dtype=np.float64).ravel())
+            ptr = self._noise.ctypes.data
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
-                         int(presorted))
+                         int(presorted), ptr)
 
 
 class Profile(ctypes.Structure):
@@ -309,10 +318,17 @@ class Factor:
             pass
 
 
+def _noise_len(opts, n):
+    if opts is not None and opts._noise is not None and opts._noise.size != n:
+        raise ValueError("opts.noise must hold one variance per point (%d, got %d)"
+                         % (n, opts._noise.size))
+
+
 def hodlr_build(x, kernel: int, theta, sigma2: float, leaf: int, tol: float,
                 opts: Opts | None = None) -> Factor:
     x = _pts(x)
     n, dim = x.shape
+    _noise_len(opts, n)
     th = _theta(theta)
     h = ctypes.c_void_p()
     _check(lib().hodlr_build(_dp(x), n, dim, int(kernel), _dp(th), float(sigma2), int(leaf),
@@ -362,6 +378,7 @@ def gp_loglik(x, y, kernel: int, theta, sigma2: float, leaf: int, tol: float,
     """Returns (loglik, logdet, quad)."""
     x = _pts(x)
     n, dim = x.shape
+    _noise_len(opts, n)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
     th = _theta(theta)
     ll, ld, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

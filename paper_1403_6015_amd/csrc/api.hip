@@ -46,7 +46,23 @@ hodlr_opts default_opts()
     o.refine_tol = 1e-10;
     o.max_refine = 8;
     o.presorted = 0;
+    o.noise = nullptr;
     return o;
+}
+
+// per-point variances: finite and >= 0
+void check_noise(const double *noise, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!(noise[i] >= 0.0) || !std::isfinite(noise[i]))
+            throw Error{HODLR_EINVAL, "noise variances must be >= 0 and finite"};
+}
+
+// entry points that take no per-point noise
+void no_noise(const hodlr_opts &o)
+{
+    if (o.noise)
+        throw Error{HODLR_EINVAL, "per-point noise is taken by hodlr_build and gp_loglik only"};
 }
 
 void check_sizes(int64_t n, int32_t dim, int32_t leaf)
@@ -120,6 +136,18 @@ struct DevBuf {
         return q;
     }
 };
+
+// the per-point variances in tree order into d (n doubles; nothing without)
+void upload_noise(DevBuf &d, const double *noise, const std::vector<int64_t> &perm)
+{
+    if (!noise)
+        return;
+    const int64_t n = (int64_t)perm.size();
+    std::vector<double> ns(n);
+    for (int64_t i = 0; i < n; ++i)
+        ns[i] = noise[perm[i]];
+    HIP_TRY(hipMemcpy(d.p, ns.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+}
 
 // ordered, coordinate-major copy of caller points
 std::vector<double> ordered_soa(const double *x, int64_t n, int dim, const std::vector<int64_t> &perm)
@@ -223,6 +251,7 @@ struct hodlr_factor_s {
     hodlr_opts opts;
     void *ws = nullptr;
     double *dx = nullptr;
+    double *dnoise = nullptr;   // per-point variances in tree order (or none)
     std::vector<int64_t> perm;
     KParams kp;
     double tol = 0;
@@ -241,6 +270,8 @@ struct hodlr_factor_s {
             (void)hipFree(ws);
         if (dx)
             (void)hipFree(dx);
+        if (dnoise)
+            (void)hipFree(dnoise);
         plan_release(plan);
         (void)hipSetDevice(cur);
     }
@@ -385,11 +416,14 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         check_opts(o);
         check_params(k, theta, sigma2, tol);
         check_finite(x, n * dim, "x");
+        if (o.noise)
+            check_noise(o.noise, n);
         if (!out)
             throw Error{HODLR_EINVAL, "out is NULL"};
         auto f = std::make_unique<hodlr_factor_s>();
         HIP_TRY(hipGetDevice(&f->device));
         f->opts = o;
+        f->opts.noise = nullptr;   // the caller's array is not kept
         f->perm.resize(n);
         if (o.presorted)
             for (int64_t i = 0; i < n; ++i)
@@ -400,6 +434,8 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         plan_upload(f->plan);
         f->lay = make_layout(f->plan, true);
         DevBuf ws(f->lay.total), dxb(sizeof(double) * n * dim);
+        DevBuf dnz(o.noise ? sizeof(double) * n : 8);
+        upload_noise(dnz, o.noise, f->perm);
         std::vector<double> xs = ordered_soa(x, n, dim, f->perm);
         HIP_TRY(hipMemcpy(dxb.p, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
         Pipeline P;
@@ -409,6 +445,7 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         P.stream = nullptr;
         P.x = (const double *)dxb.p;
         P.kp = make_kparams(k, dim, theta, sigma2);
+        P.kp.noise = o.noise ? (const double *)dnz.p : nullptr;
         P.tol = tol;
         double *d_out = wsp<double>(P, P.lay.out);
         factor_pipeline(P, nullptr, d_out);
@@ -425,6 +462,8 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         f->capped = P.capped;
         f->ws = ws.release();
         f->dx = (double *)dxb.release();
+        if (o.noise)
+            f->dnoise = (double *)dnz.release();
         *out = f.release();
         return HODLR_OK;
     });
@@ -565,6 +604,8 @@ hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
         check_params(k, theta, sigma2, tol);
         check_finite(x, n * dim, "x");
         check_finite(y, n, "y");
+        if (o.noise)
+            check_noise(o.noise, n);
         if (!loglik)
             throw Error{HODLR_EINVAL, "loglik is NULL"};
         if (o.precision == HODLR_MIXED) {
@@ -604,6 +645,8 @@ hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
         } pg{plan};
         Layout lay = make_layout(plan, false);
         DevBuf ws(lay.total), dxb(sizeof(double) * n * dim), dyb(sizeof(double) * n);
+        DevBuf dnz(o.noise ? sizeof(double) * n : 8);
+        upload_noise(dnz, o.noise, perm);
         std::vector<double> xs = ordered_soa(x, n, dim, perm);
         std::vector<double> ys(n);
         for (int64_t i = 0; i < n; ++i)
@@ -617,6 +660,7 @@ hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
         P.stream = nullptr;
         P.x = (const double *)dxb.p;
         P.kp = make_kparams(k, dim, theta, sigma2);
+        P.kp.noise = o.noise ? (const double *)dnz.p : nullptr;
         P.tol = tol;
         double *d_out = wsp<double>(P, lay.out);
         factor_pipeline(P, (const double *)dyb.p, d_out);
@@ -659,7 +703,7 @@ hodlr_status hodlr_info(hodlr_factor f, hodlr_info_t *out)
         I.max_rank_used = std::max(I.max_rank_used, mx);
     }
     I.device_bytes = (int64_t)f->lay.total + (int64_t)f->plan.dev_tables_bytes +
-                     (int64_t)sizeof(double) * f->plan.n * f->plan.dim;
+                     (int64_t)sizeof(double) * f->plan.n * (f->plan.dim + (f->dnoise ? 1 : 0));
     *out = I;
     return HODLR_OK;
 }
@@ -673,6 +717,7 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
         hodlr_opts o = opts ? *opts : default_opts();
         check_sizes(n, dim, leaf);
         check_opts(o);
+        no_noise(o);
         if (!out)
             throw Error{HODLR_EINVAL, "out is NULL"};
         auto p = std::make_unique<hodlr_plan_s>();
@@ -696,6 +741,7 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
         hodlr_opts o = opts ? *opts : default_opts();
         check_sizes(n, dim, tune->leaf);
         check_opts(o);
+        no_noise(o);
         if (!out)
             throw Error{HODLR_EINVAL, "out is NULL"};
         auto p = std::make_unique<hodlr_plan_s>();

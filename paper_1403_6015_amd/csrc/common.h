@@ -65,6 +65,7 @@ struct KParams {
     double a2;
     double c;
     double sigma2;
+    const double *noise = nullptr;   // per-point variances added to sigma2, tree order
 };
 
 inline KParams make_kparams(int kind, int dim, const double theta[2], double sigma2)
@@ -82,6 +83,7 @@ inline KParams make_kparams(int kind, int dim, const double theta[2], double sig
     default: k.c = 0.0; break;
     }
     k.sigma2 = sigma2;
+    k.noise = nullptr;
     return k;
 }
 

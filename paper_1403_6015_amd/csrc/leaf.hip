@@ -348,7 +348,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     // root per entry.  Used when the leaf is checked to be in ascending order
     // and c times its span is below 500 (every factor far inside the FP64
     // range); the entries then differ from direct evaluation by a few units
-    // in the last place, and the diagonal is exactly a^2 + sigma^2.
+    // in the last place, and the diagonal is exactly a^2 + sigma^2 (plus the
+    // point's own variance when per-point noise is given).
     const bool sep_kind = kp.dim == 1 && (kp.kind == HODLR_K_MATERN32 || kp.kind == HODLR_K_EXP);
     const int unsorted = (sep_kind && tid + 1 < m && A.x[s + tid + 1] < A.x[s + tid]) ? 1 : 0;
     const int any_unsorted = __syncthreads_or(unsorted);
@@ -377,7 +378,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                                     ? kp.a2 * (1.0 + kp.c * (xr[0][I] - xk[0][K])) * e
                                     : kp.a2 * e;
                         } else {
-                            v = (i == k) ? kp.a2 + kp.sigma2 : 0.0;
+                            v = (i == k) ? kp.a2 + kp.sigma2 + (kp.noise ? kp.noise[s + i] : 0.0)
+                                         : 0.0;
                         }
                     } else {
                         v = (i == k) ? 1.0 : 0.0;
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                         }
                         v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
                         if (i == k)
-                            v += kp.sigma2;
+                            v += kp.sigma2 + (kp.noise ? kp.noise[s + i] : 0.0);
                     } else {
                         v = (i == k) ? 1.0 : 0.0;
                     }

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(MV_T) void matvec_kernel(int64_t n, KParams kp, con
         __syncthreads();
     }
     if (i < n)
-        out[i] = acc + kp.sigma2 * v[i];
+        out[i] = acc + (kp.sigma2 + (kp.noise ? kp.noise[i] : 0.0)) * v[i];
 }
 
 void run_matvec(int64_t n, const KParams &kp, const double *x, const double *v, double *out,

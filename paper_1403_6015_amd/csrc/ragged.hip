@@ -188,6 +188,8 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
         if (m < 1 || !ns || !xs || !ys || !params || !out || dim < 1 || dim > 3 || leaf < 1 ||
             k < HODLR_K_SE || k > HODLR_K_IMQ || !(tol > 0.0) || !std::isfinite(tol))
             return report(HODLR_EINVAL, "bad shared argument");
+        if (opts && opts->noise)
+            return report(HODLR_EINVAL, "per-point noise is taken by hodlr_build and gp_loglik only");
         RaggedJob J;
         J.m = m;
         J.ns = ns;
@@ -206,6 +208,7 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
             J.opts.refine_tol = 1e-10;
             J.opts.max_refine = 8;
             J.opts.presorted = 0;
+            J.opts.noise = nullptr;
         }
         if (J.opts.max_rank < 0 || J.opts.max_rank > RMAX_ABS ||
             (J.opts.precision != HODLR_FP64 && J.opts.precision != HODLR_MIXED))

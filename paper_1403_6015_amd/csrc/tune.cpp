@@ -129,10 +129,13 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
             o.refine_tol = 1e-10;
             o.max_refine = 8;
             o.presorted = 0;
+            o.noise = nullptr;
         }
         if (o.max_rank < 0 || o.max_rank > RMAX_ABS ||
             (o.precision != HODLR_FP64 && o.precision != HODLR_MIXED))
             return report(HODLR_EINVAL, "unsupported options");
+        if (o.noise)
+            return report(HODLR_EINVAL, "per-point noise is taken by hodlr_build and gp_loglik only");
         std::vector<int> leaves;
         if (nleaf > 0)
             leaves.assign(leaf_cands, leaf_cands + nleaf);

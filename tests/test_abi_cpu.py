@@ -79,3 +79,24 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(H.HodlrError) as ei:
         H.gp_loglik(p.x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(max_rank=100000))
     assert ei.value.name == "EINVAL"
+
+
+def test_per_point_noise_is_validated():
+    """Per-point variances (§5's sigma_i^2): negative or non-finite values, a
+    wrong length and the entry points that take none are rejected before any
+    device work."""
+    p = wl.se1d_small(64)
+    for nz in (np.full(64, -0.1), np.r_[np.zeros(63), np.nan], np.r_[np.inf, np.zeros(63)]):
+        with pytest.raises(H.HodlrError) as ei:
+            H.gp_loglik(p.x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(noise=nz))
+        assert ei.value.name == "EINVAL"
+        with pytest.raises(H.HodlrError) as ei:
+            H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(noise=nz))
+        assert ei.value.name == "EINVAL"
+    with pytest.raises(ValueError):
+        H.gp_loglik(p.x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol,
+                    H.Opts(noise=np.zeros(10)))
+    with pytest.raises(H.HodlrError) as ei:
+        H.Plan(64, 1, 16, H.Opts(noise=np.zeros(64)))
+    assert ei.value.name == "EINVAL"
+
