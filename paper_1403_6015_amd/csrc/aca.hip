@@ -19,7 +19,7 @@
 //   * small blocks (both sides <= ACA_SMALL): one work-group runs the whole
 //     loop for one block, all blocks in a single launch;
 //   * large blocks: each step is a row pass and a column pass over all large
-//     blocks, every work-group covering ACA_CHUNK indices of one block.  Each
+//     blocks, every work-group covering the plan's chunk of indices of one block.  Each
 //     pass first re-derives the pivot and the norms from the previous pass's
 //     per-work-group records (identically in every work-group of the block),
 //     so state only moves across launch boundaries (double-buffered).
@@ -616,7 +616,7 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
     __syncthreads();   // dots[] visible
 }
 
-template <bool ROW>
+template <bool ROW, int EPT>
 __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 {
     const AcaArgs &A = B.a;
@@ -680,11 +680,11 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         for (int l = tid; l < k; l += ACA_THREADS)
             sfix[l] = W[(col0 + l) * n + fix];
         __syncthreads();
-        double val[ACA_EPT];
+        double val[EPT];
         double bv = -1.0, bs = 0.0, sq = 0.0;
         int64_t bi = INT64_MAX;
 #pragma unroll
-        for (int q = 0; q < ACA_EPT; ++q) {
+        for (int q = 0; q < EPT; ++q) {
             int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
             val[q] = 0.0;
             if (g < ch.hi) {
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         for (int l = 0; l < k; ++l) {
             double d = 0.0;
 #pragma unroll
-            for (int q = 0; q < ACA_EPT; ++q) {
+            for (int q = 0; q < EPT; ++q) {
                 int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
                 if (g < ch.hi)
                     d += val[q] * W[(col0 + l) * n + g];
@@ -774,11 +774,11 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     for (int l = tid; l < k; l += ACA_THREADS)
         sfix[l] = W[(col0 + l) * n + fix];
     __syncthreads();
-    double val[ACA_EPT];
+    double val[EPT];
     double cv = -1.0, cs = 0.0, sq = 0.0;
     int64_t ci = INT64_MAX;
 #pragma unroll
-    for (int q = 0; q < ACA_EPT; ++q) {
+    for (int q = 0; q < EPT; ++q) {
         int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
         val[q] = 0.0;
         if (g < ch.hi) {
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     for (int l = 0; l < k; ++l) {
         double d = 0.0;
 #pragma unroll
-        for (int q = 0; q < ACA_EPT; ++q) {
+        for (int q = 0; q < EPT; ++q) {
             int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
             if (g < ch.hi)
                 d += val[q] * W[(col0 + l) * n + g];
@@ -1077,7 +1077,7 @@ void run_aca(Pipeline &P)
     SideJoin join{s};
     if (!p.aca_small.empty()) {
         hipStream_t ss = s;
-        if (nbig > 0) {
+        if (nbig > 0 && P.side_stream) {
             SideStream &x = side_stream();
             HIP_TRY(hipEventRecord(x.fork, s));
             HIP_TRY(hipStreamWaitEvent(x.s, x.fork, 0));
@@ -1149,11 +1149,17 @@ void run_aca(Pipeline &P)
         for (; it < max_iter; ++it) {
             {
                 ProfScope ps(s, PS_ACA_ROW);
-                aca_big_pass_kernel<true><<<nrow, ACA_THREADS, 0, s>>>(R);
+                if (p.aca_chunk == ACA_CHUNK_1D)
+                    aca_big_pass_kernel<true, ACA_CHUNK_1D / ACA_THREADS><<<nrow, ACA_THREADS, 0, s>>>(R);
+                else
+                    aca_big_pass_kernel<true, ACA_CHUNK_ND / ACA_THREADS><<<nrow, ACA_THREADS, 0, s>>>(R);
             }
             {
                 ProfScope ps(s, PS_ACA_COL);
-                aca_big_pass_kernel<false><<<ncol, ACA_THREADS, 0, s>>>(C);
+                if (p.aca_chunk == ACA_CHUNK_1D)
+                    aca_big_pass_kernel<false, ACA_CHUNK_1D / ACA_THREADS><<<ncol, ACA_THREADS, 0, s>>>(C);
+                else
+                    aca_big_pass_kernel<false, ACA_CHUNK_ND / ACA_THREADS><<<ncol, ACA_THREADS, 0, s>>>(C);
             }
             HIP_TRY(hipGetLastError());
             // A converged block is counted by the row pass that absorbs its last

@@ -15,12 +15,17 @@ namespace hodlr {
 
 // ------------------------------------------------------------- constants
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
-constexpr int ACA_CHUNK = 2048;   // block entries per work-group and pass (large blocks;
-                                  // measured at n = 2^20: 512 0.52 ms, 1024 0.39, 2048 0.37, 4096 0.39)
+// block entries per work-group and pass of the large blocks' cross
+// approximation.  1-D (ranks ~3) measured at n = 2^20: 512 0.52 ms, 1024 0.39,
+// 2048 0.37, 4096 0.39 per likelihood; 2-D SE at n = 2^18 (ranks up to 64,
+// about 130 passes): 1024 gives 23.3 likelihoods/s, 2048 19.8, since each
+// entry subtracts up to 64 earlier terms and fewer, longer work-groups per
+// pass lengthen every pass.
+constexpr int ACA_CHUNK_1D = 2048;
+constexpr int ACA_CHUNK_ND = 1024;
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_TINY = 256;     // ... and on a single wave when both sides are <= this
 constexpr int ACA_THREADS = 256;
-constexpr int ACA_EPT = ACA_CHUNK / ACA_THREADS;
 constexpr int LVL_ROWS = 512;     // default rows per level work-group
 constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored in LDS
 constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices live in LDS)
@@ -252,6 +257,7 @@ struct Plan {
     std::vector<int> aca_rowbase, aca_colbase;
     std::vector<Chunk> pad_chunks;         // all blocks, both sides
     int aca_pw = 0;                        // doubles per ACA partial record
+    int aca_chunk = ACA_CHUNK_1D;          // block entries per large-block pass work-group
     // level tables: per depth d, chunks over rows of the children of depth-d nodes
     std::vector<std::vector<Chunk>> lvl;
     std::vector<std::vector<int>> lvl_nch;   // per depth, per node: chunks (both sides)
@@ -327,6 +333,7 @@ struct Pipeline {
     int nitems = 1;       // batch size (all items share the plan)
     BatchArgs batch;      // istride = lay.total rounded, params per item
     bool capturing = false;
+    bool side_stream = true;  // small-block compression on a second stream of this thread
     // host-side results of the compression
     std::vector<int> rmax;    // per depth j (1..L), used columns of the panel
     std::vector<int> cols;    // used column indices, depth-ascending, cols[0] = 0

@@ -152,6 +152,9 @@ void worker(RaggedJob *J)
             P.lay = lay;
             P.ws = ws;
             P.stream = s;
+            // the workers' own streams already overlap items; a second stream
+            // per worker measured slower (4.7k vs 5.3k likelihoods/s)
+            P.side_stream = false;
             P.x = dx;
             const double th[2] = {J->params[3 * i], J->params[3 * i + 1]};
             P.kp = make_kparams(J->kernel, dim, th, J->params[3 * i + 2]);

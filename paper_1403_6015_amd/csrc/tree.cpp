@@ -129,7 +129,8 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
 
     // cross-approximation tables: blocks whose sides fit ACA_SMALL run whole in
     // one work-group; larger ones get per-pass chunks (row passes sweep beta,
-    // column passes sweep alpha)
+    // column passes sweep alpha), longer ones for 1-D points (low ranks)
+    p.aca_chunk = dim == 1 ? ACA_CHUNK_1D : ACA_CHUNK_ND;
     p.aca_small.clear();
     p.aca_big.clear();
     p.aca_row.clear();
@@ -162,8 +163,8 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
         p.aca_big_active += 1;
         p.aca_rowbase.push_back(rslot);
         p.aca_colbase.push_back(cslot);
-        make_chunks((int)h, 1, m, e, ACA_CHUNK, p.aca_row, rslot);
-        make_chunks((int)h, 0, s, m, ACA_CHUNK, p.aca_col, cslot);
+        make_chunks((int)h, 1, m, e, p.aca_chunk, p.aca_row, rslot);
+        make_chunks((int)h, 0, s, m, p.aca_chunk, p.aca_col, cslot);
         p.aca_nrow.push_back(rslot - p.aca_rowbase.back());
         p.aca_ncol.push_back(cslot - p.aca_colbase.back());
         while ((int)p.aca_rowidx.size() < rslot)
