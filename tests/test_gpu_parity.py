@@ -297,3 +297,34 @@ def test_full_size_matern_mixed_against_kalman():
     assert abs(ld - kf["logdet"]) <= 1e-8 * abs(kf["logdet"])
     assert abs(q - kf["quad"]) <= 1e-6 * abs(kf["quad"])
     assert np.linalg.norm(z.cpu().numpy() - kf["alpha"]) <= 1e-5 * np.linalg.norm(kf["alpha"])
+
+
+def _golden_rows(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            n, err = line.split()
+            rows.append((int(n), float(err)))
+    return rows
+
+
+@pytest.mark.parametrize("n,err", [r for r in _golden_rows("gaussian_1d_solution_error.txt")
+                                   if r[0] <= 50000])
+def test_papers_gaussian_table_accuracy(n, err):
+    """§5's Gaussian table, one-dimensional columns: relative error of the
+    solution of C x = b (b from a known x by the oracle's exact product)
+    within a factor 10 of the printed order of magnitude."""
+    p = wl.gaussian_table(n)
+    announce("gaussian table n=%d printed error %g" % (n, err))
+    b = oracle.matvec_rows(p.x, p.kernel, p.theta, p.sigma2, p.y, np.arange(n))
+    f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(max_rank=64))
+    xs = f.solve(b)
+    info = f.info()
+    f.free()
+    rel = np.linalg.norm(xs - p.y) / np.linalg.norm(p.y)
+    print("n %d: solution error %.2e (printed %g), ranks %s" % (n, rel, err, info["rank_max"][:4]))
+    assert info["capped_blocks"] == 0
+    assert rel <= 10 * err

@@ -210,3 +210,30 @@ def test_kalman_matches_dense(oracle_lib, n):
 def test_kalman_rejects_unsorted(oracle_lib):
     with pytest.raises(oracle.OracleError):
         oracle.kalman_matern32([0.0, 1.0, 0.5], [1.0, 2.0, 3.0], (1.0, 1.0), 0.1)
+
+
+def _golden_rows(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            n, err = line.split()
+            rows.append((int(n), float(err)))
+    return rows
+
+
+@pytest.mark.parametrize("n,err", [r for r in _golden_rows("gaussian_1d_solution_error.txt")
+                                   if r[0] <= 20000])
+def test_walkthrough_meets_the_papers_gaussian_table(oracle_lib, n, err):
+    # §5's Gaussian table (one-dimensional columns): the solution error of the
+    # method's own steps (walk-through) on the table's test problem, with b
+    # formed from the known x by the oracle's exact product, is within a
+    # factor 10 of the printed value (the table gives orders of magnitude)
+    p = wl.gaussian_table(n)
+    b = oracle.matvec_rows(p.x, p.kernel, p.theta, p.sigma2, p.y, np.arange(n))
+    ref = hodlr_ref.HodlrRef(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol)
+    xs = ref.solve(b)
+    rel = np.linalg.norm(xs - p.y) / np.linalg.norm(p.y)
+    assert rel <= 10 * err, rel

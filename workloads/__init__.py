@@ -227,3 +227,19 @@ def regression_model(n: int = 1024, tol: float = 1e-8, leaf: int = 20,
     y = np.sin(2.0 * x) + np.exp(x) / 8.0 + rng.standard_normal(n)
     return GPProblem("regression_n%d_tol%g_leaf%d" % (n, tol, leaf), x.reshape(n, 1), y, K_SE,
                      (1.0, 1.0 / math.sqrt(2.0)), 1.0, leaf, tol)
+
+
+def gaussian_table(n: int, dim: int = 1, seed: int = 101) -> GPProblem:
+    """The Gaussian-covariance table of §5: r ~ U([-3, 3]^dim), C_ij =
+    2 delta_ij + exp(-|r_i - r_j|^2) (SE with a = 1, l = 1/sqrt(2), sigma^2 = 2).
+    ``y`` holds the known solution x of the test problem C x = b (N(0, 1)
+    entries); b is formed from it by the caller.  Smallest blocks of 64
+    points, tolerance 1e-14 (the table's accuracy at these sizes)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-3.0, 3.0, size=(n, dim))
+    if dim == 1:
+        x = np.sort(x, axis=0)
+    xt = rng.standard_normal(n)
+    return GPProblem("gauss_table_d%d_n%d" % (dim, n), x.astype(np.float64), xt, K_SE,
+                     (1.0, 1.0 / math.sqrt(2.0)), 2.0, 64, 1e-14)
+
