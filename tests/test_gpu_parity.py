@@ -311,14 +311,20 @@ def _golden_rows(name):
     return rows
 
 
-@pytest.mark.parametrize("n,err", [r for r in _golden_rows("gaussian_1d_solution_error.txt")
-                                   if r[0] <= 50000])
-def test_papers_gaussian_table_accuracy(n, err):
-    """§5's Gaussian table, one-dimensional columns: relative error of the
-    solution of C x = b (b from a known x by the oracle's exact product)
-    within a factor 10 of the printed order of magnitude."""
-    p = wl.gaussian_table(n)
-    announce("gaussian table n=%d printed error %g" % (n, err))
+TABLES = [("gaussian_1d_solution_error.txt", wl.K_SE),
+          ("exponential_1d_solution_error.txt", wl.K_EXP),
+          ("imq_1d_solution_error.txt", wl.K_IMQ)]
+
+
+@pytest.mark.parametrize("kind,n,err", [(k, n, e) for f, k in TABLES for n, e in _golden_rows(f)
+                                        if n <= 50000])
+def test_papers_table_accuracy(kind, n, err):
+    """§5's one-dimensional timing tables (Gaussian, exponential, inverse
+    multiquadric): relative error of the solution of C x = b (b from a known
+    x by the oracle's exact product) within a factor 10 of the printed order
+    of magnitude."""
+    p = wl.paper_table(kind, n)
+    announce("paper table kernel=%d n=%d printed error %g" % (kind, n, err))
     b = oracle.matvec_rows(p.x, p.kernel, p.theta, p.sigma2, p.y, np.arange(n))
     f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(max_rank=64))
     xs = f.solve(b)

@@ -224,14 +224,20 @@ def _golden_rows(name):
     return rows
 
 
-@pytest.mark.parametrize("n,err", [r for r in _golden_rows("gaussian_1d_solution_error.txt")
-                                   if r[0] <= 20000])
-def test_walkthrough_meets_the_papers_gaussian_table(oracle_lib, n, err):
-    # §5's Gaussian table (one-dimensional columns): the solution error of the
-    # method's own steps (walk-through) on the table's test problem, with b
-    # formed from the known x by the oracle's exact product, is within a
-    # factor 10 of the printed value (the table gives orders of magnitude)
-    p = wl.gaussian_table(n)
+TABLES = [("gaussian_1d_solution_error.txt", wl.K_SE),
+          ("exponential_1d_solution_error.txt", wl.K_EXP),
+          ("imq_1d_solution_error.txt", wl.K_IMQ)]
+
+
+@pytest.mark.parametrize("kind,n,err", [(k, n, e) for f, k in TABLES for n, e in _golden_rows(f)
+                                        if n <= 20000])
+def test_walkthrough_meets_the_papers_tables(oracle_lib, kind, n, err):
+    # §5's timing tables (one-dimensional Gaussian, exponential and inverse
+    # multiquadric): the solution error of the method's own steps
+    # (walk-through) on the table's test problem, with b formed from the known
+    # x by the oracle's exact product, is within a factor 10 of the printed
+    # value (the tables give orders of magnitude)
+    p = wl.paper_table(kind, n)
     b = oracle.matvec_rows(p.x, p.kernel, p.theta, p.sigma2, p.y, np.arange(n))
     ref = hodlr_ref.HodlrRef(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol)
     xs = ref.solve(b)

@@ -229,17 +229,21 @@ def regression_model(n: int = 1024, tol: float = 1e-8, leaf: int = 20,
                      (1.0, 1.0 / math.sqrt(2.0)), 1.0, leaf, tol)
 
 
-def gaussian_table(n: int, dim: int = 1, seed: int = 101) -> GPProblem:
-    """The Gaussian-covariance table of §5: r ~ U([-3, 3]^dim), C_ij =
-    2 delta_ij + exp(-|r_i - r_j|^2) (SE with a = 1, l = 1/sqrt(2), sigma^2 = 2).
-    ``y`` holds the known solution x of the test problem C x = b (N(0, 1)
-    entries); b is formed from it by the caller.  Smallest blocks of 64
-    points, tolerance 1e-14 (the table's accuracy at these sizes)."""
+def paper_table(kind: int, n: int, dim: int = 1, seed: int = 101) -> GPProblem:
+    """The test problems of §5's timing tables: r ~ U([-3, 3]^dim) and
+    C_ij = s delta_ij + k(r_i, r_j) with the table's kernel:
+    Gaussian exp(-|r|^2) (SE, a = 1, l = 1/sqrt(2)) with s = 2; exponential
+    exp(-|r|) (a = 1, l = 1) with s = 1; inverse multiquadric
+    1/sqrt(1 + |r|^2) (a = 1, l = 1) with s = 1.  ``y`` holds the known
+    solution x of the test problem C x = b (N(0, 1) entries); b is formed from
+    it by the caller.  Smallest blocks of 64 points, tolerance 1e-14."""
+    params = {K_SE: ((1.0, 1.0 / math.sqrt(2.0)), 2.0), K_EXP: ((1.0, 1.0), 1.0),
+              K_IMQ: ((1.0, 1.0), 1.0)}
+    theta, s = params[kind]
     rng = np.random.default_rng(seed)
     x = rng.uniform(-3.0, 3.0, size=(n, dim))
     if dim == 1:
         x = np.sort(x, axis=0)
     xt = rng.standard_normal(n)
-    return GPProblem("gauss_table_d%d_n%d" % (dim, n), x.astype(np.float64), xt, K_SE,
-                     (1.0, 1.0 / math.sqrt(2.0)), 2.0, 64, 1e-14)
-
+    return GPProblem("table_k%d_d%d_n%d" % (kind, dim, n), x.astype(np.float64), xt, kind,
+                     theta, s, 64, 1e-14)
