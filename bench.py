@@ -527,6 +527,14 @@ def bench_se2d(args, torch, H, wl, dev):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     loglik, logdet, quad = out[:3].cpu().tolist()
+    # per-stage breakdown in a pass of its own (every launch timed)
+    H.profile_select(None)
+    H.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    breakdown = H.profile_read()
+    H.profile_enable(False)
     t1 = time.perf_counter()
     f = H.hodlr_build(xs, p.kernel, p.theta, p.sigma2, leaf, p.tol,
                       H.Opts(max_rank=64, precision=prec, presorted=1, max_refine=40))
@@ -554,6 +562,7 @@ def bench_se2d(args, torch, H, wl, dev):
                       "side": p.meta["side"], "leaf": leaf, "max_rank": 64, "tol": p.tol,
                       "precision": args.precision},
            "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
+           "stage_ms_per_step": {k: v[0] / args.steps for k, v in breakdown.items() if v[1] > 0},
            "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
            "refined_solve": refined if mixed else None}
     print(json.dumps(res), flush=True)
@@ -682,6 +691,14 @@ def bench_paper_table(args, torch, H, wl, dev):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     loglik, logdet, quad = out[:3].cpu().tolist()
+    # per-stage breakdown in a pass of its own (every launch timed)
+    H.profile_select(None)
+    H.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    breakdown = H.profile_read()
+    H.profile_enable(False)
     f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, opts)
     info = f.info()
     f.free()
@@ -700,6 +717,7 @@ def bench_paper_table(args, torch, H, wl, dev):
                       "kernel": wl.KERNEL_NAMES[kind], "theta": list(p.theta),
                       "sigma2": p.sigma2, "leaf": p.leaf, "tol": p.tol, "max_rank": 64},
            "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
+           "stage_ms_per_step": {k: v[0] / args.steps for k, v in breakdown.items() if v[1] > 0},
            "result": {"loglik": loglik, "logdet": logdet, "quad": quad}}
     print(json.dumps(res), flush=True)
 

@@ -10,16 +10,20 @@
 // P = W_beta^T W~_beta and Q = W_alpha^T W~_alpha, and Sylvester's theorem
 // (§4) gives det of the block as det M = det(I - Q P).
 //
-// Per level three launches:
+// Per level three launches (four when the top levels' partial sums are
+// large):
 //   reduce  -- T = [W_beta^T X_beta; W_alpha^T X_alpha] over every column X
 //              still to be updated plus the child panel itself (which yields
-//              P and Q), as per-work-group partial sums (tall-skinny products
-//              through LDS tiles);
-//   solve   -- one work-group per node sums the partials, forms I - Q P,
+//              P and Q), as per-chunk partial sums: for ranks up to 8 one wave
+//              per chunk with W's rows in registers (bandwidth-bound), above
+//              that on FP64 MFMA;
+//   solve   -- one work-group per node sums the partials (or a sum kernel
+//              with one thread per output does it first), forms I - Q P,
 //              LU-factors it with partial pivoting in LDS, records its
 //              log-det, and solves M S = T for the remaining columns
 //              (s2 = (I - QP)^{-1} (t2 - Q t1), s1 = t1 - P s2);
-//   update  -- X_alpha -= W~_alpha S_top, X_beta -= W~_beta S_bottom.
+//   update  -- X_alpha -= W~_alpha S_top, X_beta -= W~_beta S_bottom (one
+//              thread per row for small ranks, FP64 MFMA above 8).
 // The solve path reuses the three kernels on the single vector z with the
 // stored small factors.
 #include "common.h"
@@ -27,12 +31,17 @@
 namespace hodlr {
 
 constexpr int LV_THREADS = 256;
-constexpr int LV_RT = 64;    // rows per LDS tile
-constexpr int LV_CT = 32;    // columns per LDS tile
 constexpr int LV_CB = 32;    // right-hand sides per batch in the node solve
 // threads per node in the node solve (n = 2^20: 256 threads 0.37 ms per
 // likelihood, one wave 0.81 ms)
 constexpr int LV_SOLVE_TH = 256;
+// levels whose nodes each hold more than LV_SUM_MIN record entries (chunks
+// per node x 2 r x columns) sum them in a kernel of their own, one thread per
+// output, before the node solves.  2-D SE at n = 2^18 (ranks up to 64): node
+// solves 8.25 -> 5.0 ms per likelihood; doing so on every level with at most
+// 64 nodes cost the 1-D Matern workload 0.08 ms (small records, one more
+// launch per level).
+constexpr double LV_SUM_MIN = 262144.0;
 
 struct LevelArgs {
     int64_t n;
@@ -57,6 +66,7 @@ struct LevelArgs {
     int factor;        // 1: build the coupling factors; 0: apply stored ones
     int cgrp;          // columns per work-group of the small-rank reduction
     int rows;          // rows per chunk (a node's chunks: its alpha rows, then its beta rows)
+    int tsum;          // 1: T was summed from the records by level_sum_kernel
     BatchArgs B;
 };
 
@@ -76,62 +86,6 @@ __device__ __forceinline__ LevelArgs item_args(LevelArgs A)
         A.status = ioff(A.status, A.B, it);
     }
     return A;
-}
-
-template <typename PT>
-__global__ __launch_bounds__(LV_THREADS) void level_reduce_kernel(LevelArgs A0)
-{
-    const LevelArgs A = item_args(A0);
-    const double *__restrict__ Wp = A.W;
-    const PT *__restrict__ Xp = (const PT *)A.Xt;
-    const Chunk ch = A.chunks[blockIdx.x];
-    const int r = A.rank[ch.node];
-    if (r == 0)
-        return;
-    __shared__ double sW[LV_RT][RMAX_ABS + 1];
-    __shared__ double sX[LV_RT][LV_CT + 1];
-    const int tid = threadIdx.x;
-    const int64_t n = A.n;
-    for (int c0 = 0; c0 < A.ncnt; c0 += LV_CT) {
-        const int nc = min(LV_CT, A.ncnt - c0);
-        const int nout = r * nc;
-        double acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            acc[q] = 0.0;
-        for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += LV_RT) {
-            const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
-            for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
-                int l = idx / LV_RT, i = idx % LV_RT;
-                sW[i][l] = (i < nr) ? Wp[(A.colW + l) * n + i0 + i] : 0.0;
-            }
-            for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
-                int c = idx / LV_RT, i = idx % LV_RT;
-                sX[i][c] = (i < nr) ? (double)Xp[(int64_t)A.cols[c0 + c] * n + i0 + i] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                int o = tid + q * LV_THREADS;
-                if (o < nout) {
-                    int l = o / nc, c = o % nc;
-                    double a = acc[q];
-                    for (int i = 0; i < LV_RT; ++i)
-                        a += sW[i][l] * sX[i][c];
-                    acc[q] = a;
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int o = tid + q * LV_THREADS;
-            if (o < nout) {
-                int l = o / nc, c = o % nc;
-                A.part[((int64_t)ch.part * A.rstride + l) * A.ncnt + c0 + c] = acc[q];
-            }
-        }
-    }
 }
 
 // Small-rank variants (panel rank <= R, the usual case for 1-D kernels):
@@ -312,6 +266,42 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArg
     }
 }
 
+// T of every node of a level with few nodes: one thread per output, summing
+// the node's chunk records of that side in chunk order (four partial sums).
+// The node solve would otherwise sum a top-level node's many records in one
+// work-group.
+__global__ __launch_bounds__(LV_THREADS) void level_sum_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
+    const int64_t loc = blockIdx.x;
+    const int64_t h = A.node0 + loc;
+    const int r = A.rank[h];
+    const int ncnt = A.ncnt, rs = A.rstride;
+    const int o = blockIdx.y * LV_THREADS + threadIdx.x;
+    if (r == 0 || o >= 2 * r * ncnt)
+        return;
+    const int nch = A.nch[loc], base = A.base[loc];
+    const int64_t ns = A.chunks[base].lo, ne = A.chunks[base + nch - 1].hi;
+    const int64_t alen = (ne - ns) / 2;
+    const int na = (int)((alen + A.rows - 1) / A.rows);
+    const int row2 = o / ncnt, c = o % ncnt;
+    const int side = row2 < r ? 1 : 0;
+    const int l = row2 < r ? row2 : row2 - r;
+    const int q1 = side ? base + nch : base + na;
+    int q = side ? base + na : base;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; q + 3 < q1; q += 4) {
+        a0 += A.part[((int64_t)q * rs + l) * ncnt + c];
+        a1 += A.part[((int64_t)(q + 1) * rs + l) * ncnt + c];
+        a2 += A.part[((int64_t)(q + 2) * rs + l) * ncnt + c];
+        a3 += A.part[((int64_t)(q + 3) * rs + l) * ncnt + c];
+    }
+    for (; q < q1; ++q)
+        a0 += A.part[((int64_t)q * rs + l) * ncnt + c];
+    double *T = A.Tbuf + loc * A.tstride;
+    T[(int64_t)(side ? l : rs + l) * ncnt + c] = (a0 + a1) + (a2 + a3);
+}
+
 template <int TH>
 __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 {
@@ -342,7 +332,7 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     const int ncnt = A.ncnt, rs = A.rstride;
     double *T = A.Tbuf + loc * A.tstride;
     // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
-    {
+    if (!A.tsum) {
         // each output gets a power-of-two group of threads that splits the
         // node's records; groups stay inside one wave for the final sum.
         // The node's records are its alpha chunks, then its beta chunks, so
@@ -548,47 +538,151 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 #undef t1
 #undef t2
 
-template <typename PT>
-__global__ __launch_bounds__(LV_THREADS) void level_update_kernel(LevelArgs A0)
+// Wide ranks (panel rank above 8, e.g. 2-D kernels or tight tolerances) on
+// FP64 MFMA (v_mfma_f64_16x16x4; lane l = 16 q + r supplies A[r][q] and
+// B[q][r] of a 16 x 4 by 4 x 16 step and holds D[q + 4 t][r], t < 4).
+typedef double lv_d4 __attribute__((ext_vector_type(4)));
+constexpr int LVM_NT = 4;   // 16-column tiles per work-group (one per wave in the reduction)
+constexpr int LVM_U = 4;    // 4-row steps whose loads are issued together
+
+// T_part[chunk] = W_chunk^T X_chunk: M = ranks (16 per tile, MT tiles: the
+// level's reserved rank rounded up), N = 16 columns per wave, K = the chunk's
+// rows.  Every wave takes all rank tiles of its column tile, so each X column
+// of the chunk is read once and the chunk's W rows by the 4 waves of a
+// work-group (from L1).
+template <typename PT, int MT>
+__global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    if (r == 0)
+        return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int c0 = (blockIdx.y * LVM_NT + wid) * 16;
+    if (c0 >= A.ncnt)
+        return;   // the whole wave; no work-group barrier follows
+    const int64_t n = A.n;
+    const int c = c0 + lr;
+    // lanes past the last column or rank read a valid column (the first one)
+    // and drop the value, so the loads need no branches
+    const bool cok = c < A.ncnt;
+    const PT *xcol = (const PT *)A.Xt + (int64_t)A.cols[cok ? c : 0] * n;
+    const double *wcol[MT];
+    bool wok[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int l = 16 * m + lr;
+        wok[m] = l < r;
+        wcol[m] = A.W + (A.colW + (wok[m] ? l : 0)) * n;
+    }
+    lv_d4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        acc[m] = lv_d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += 4 * LVM_U) {
+        double bv[LVM_U], av[MT][LVM_U];
+#pragma unroll
+        for (int u = 0; u < LVM_U; ++u) {
+            const int64_t i = i0 + 4 * u + lq;
+            const bool ok = i < ch.hi;
+            const int64_t is = ok ? i : ch.lo;
+            const double xv = (double)xcol[is];
+            bv[u] = (cok && ok) ? xv : 0.0;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const double wv = wcol[m][is];
+                av[m][u] = (wok[m] && ok) ? wv : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LVM_U; ++u)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m][u], bv[u], acc[m], 0, 0, 0);
+    }
+    // lane (lr, lq) holds T[16 m + lq + 4 t][c0 + lr]
+    double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
+    if (cok) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int l = 16 * m + lq + 4 * t;
+                if (l < r)
+                    rec[(int64_t)l * A.ncnt + c] = acc[m][t];
+            }
+    }
+}
+
+// X_chunk[:, cols] -= W~_chunk S: M = 16 rows per tile, N = 16 columns, K =
+// ranks (4 per step, 4 MT steps: the level's reserved rank rounded up).  A
+// work-group takes one chunk and 64 columns: S's slice for them in LDS, each
+// wave every fourth row tile, whose W~ operands serve the 4 column tiles.
+template <typename PT, int MT>
+__global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs A0)
 {
     const LevelArgs A = item_args(A0);
     PT *__restrict__ Xp = (PT *)A.Xt;
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
-    if (r == 0)
-        return;
-    __shared__ double sWt[LV_RT][RMAX_ABS + 1];
-    __shared__ double sS[RMAX_ABS][LV_CT + 1];
-    const int tid = threadIdx.x;
+    const int nrhs = A.nrhs;
+    const int cbase = blockIdx.y * LVM_NT * 16;
+    if (r == 0 || cbase >= nrhs)
+        return;   // the whole work-group
+    __shared__ double sS[RMAX_ABS][LVM_NT * 16 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
     const int64_t n = A.n;
     const int64_t loc = ch.node - A.node0;
     const double *S = A.Sbuf + loc * A.tstride;
     const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
-    const int nrhs = A.nrhs;
-    for (int c0 = 0; c0 < nrhs; c0 += LV_CT) {
-        const int nc = min(LV_CT, nrhs - c0);
-        for (int idx = tid; idx < r * nc; idx += LV_THREADS) {
-            int l = idx / nc, c = idx % nc;
-            sS[l][c] = S[(int64_t)(rowoff + l) * nrhs + c0 + c];
+    constexpr int KS = 4 * MT;   // 4-rank steps
+    for (int idx = tid; idx < 4 * KS * LVM_NT * 16; idx += LV_THREADS) {
+        const int l = idx / (LVM_NT * 16), cc = idx % (LVM_NT * 16);
+        const int col = cbase + cc;
+        sS[l][cc] = (l < r && col < nrhs) ? S[(int64_t)(rowoff + l) * nrhs + col] : 0.0;
+    }
+    __syncthreads();
+    PT *xcol[LVM_NT];
+#pragma unroll
+    for (int j = 0; j < LVM_NT; ++j) {
+        const int col = cbase + 16 * j + lr;
+        xcol[j] = col < nrhs ? Xp + (int64_t)A.cols[col] * n : nullptr;
+    }
+    const int64_t nrt = (ch.hi - ch.lo + 15) >> 4;
+    for (int64_t rt = wid; rt < nrt; rt += LV_THREADS / 64) {
+        const int64_t i0 = ch.lo + 16 * rt;
+        double a[KS];
+        const int64_t ia = i0 + lr;
+        const bool rok = ia < ch.hi;
+        const int64_t is = rok ? ia : ch.lo;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int l = 4 * st + lq;
+            const double wv = (double)Xp[(A.colW + (l < r ? l : 0)) * n + is];
+            a[st] = (l < r && rok) ? wv : 0.0;
         }
-        for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += LV_RT) {
-            const int nr = (int)min<int64_t>(LV_RT, ch.hi - i0);
-            for (int idx = tid; idx < r * LV_RT; idx += LV_THREADS) {
-                int l = idx / LV_RT, i = idx % LV_RT;
-                sWt[i][l] = (i < nr) ? (double)Xp[(A.colW + l) * n + i0 + i] : 0.0;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < nc * LV_RT; idx += LV_THREADS) {
-                int c = idx / LV_RT, i = idx % LV_RT;
-                if (i < nr) {
-                    PT *px = Xp + (int64_t)A.cols[c0 + c] * n + i0 + i;
-                    double a = *px;
-                    for (int l = 0; l < r; ++l)
-                        a -= sWt[i][l] * sS[l][c];
-                    *px = (PT)a;
+#pragma unroll
+        for (int j = 0; j < LVM_NT; ++j) {
+            if (cbase + 16 * j >= nrhs)
+                break;
+            lv_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], sS[4 * st + lq][16 * j + lr], acc,
+                                                           0, 0, 0);
+            // lane (lr, lq): rows i0 + lq + 4 t of column cbase + 16 j + lr
+            PT *xc = xcol[j];
+            if (xc) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t i = i0 + lq + 4 * t;
+                    if (i < ch.hi)
+                        xc[i] = (PT)((double)xc[i] - acc[t]);
                 }
             }
-            __syncthreads();
         }
     }
 }
@@ -645,6 +739,7 @@ static LevelArgs level_args(Pipeline &P, int d)
     A.B = P.batch;
     A.cgrp = p.red_grp;
     A.rows = p.lvl_rows;
+    A.tsum = 0;
     return A;
 }
 
@@ -677,6 +772,32 @@ static void reduce_small_launch(int R, int sr, int cu, dim3 grid, hipStream_t s,
 }
 
 template <typename PT>
+static void reduce_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs &A)
+{
+    if (mt == 1)
+        level_reduce_mfma_kernel<PT, 1><<<grid, LV_THREADS, 0, s>>>(A);
+    else if (mt == 2)
+        level_reduce_mfma_kernel<PT, 2><<<grid, LV_THREADS, 0, s>>>(A);
+    else if (mt == 3)
+        level_reduce_mfma_kernel<PT, 3><<<grid, LV_THREADS, 0, s>>>(A);
+    else
+        level_reduce_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
+}
+
+template <typename PT>
+static void update_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs &A)
+{
+    if (mt == 1)
+        level_update_mfma_kernel<PT, 1><<<grid, LV_THREADS, 0, s>>>(A);
+    else if (mt == 2)
+        level_update_mfma_kernel<PT, 2><<<grid, LV_THREADS, 0, s>>>(A);
+    else if (mt == 3)
+        level_update_mfma_kernel<PT, 3><<<grid, LV_THREADS, 0, s>>>(A);
+    else
+        level_update_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
+}
+
+template <typename PT>
 static void level_launch_t(Pipeline &P, int d, LevelArgs A)
 {
     const Plan &p = *P.plan;
@@ -691,10 +812,19 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
         if (R > 0)
             reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else
-            level_reduce_kernel<PT><<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+            reduce_mfma_launch<PT>((A.rstride + 15) / 16,
+                                   dim3(nchunks, (A.ncnt + 16 * LVM_NT - 1) / (16 * LVM_NT), P.nitems),
+                                   P.stream, A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
+        const double per_node = (double)nchunks / nodes * 2.0 * A.rstride * A.ncnt;
+        if (nchunks && per_node > LV_SUM_MIN) {
+            A.tsum = 1;
+            const int most = 2 * A.rstride * A.ncnt;
+            level_sum_kernel<<<dim3(nodes, (most + LV_THREADS - 1) / LV_THREADS, P.nitems), LV_THREADS,
+                               0, P.stream>>>(A);
+        }
         launch_solve(P, A, nodes);
     }
     if (nchunks && A.nrhs > 0) {
@@ -706,7 +836,9 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
         else if (small_upd && R == 8)
             level_update_small_kernel<PT, 8><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else
-            level_update_kernel<PT><<<dim3(nchunks, 1, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+            update_mfma_launch<PT>((A.rstride + 15) / 16,
+                                   dim3(nchunks, (A.nrhs + 16 * LVM_NT - 1) / (16 * LVM_NT), P.nitems),
+                                   P.stream, A);
     }
     HIP_TRY(hipGetLastError());
 }
