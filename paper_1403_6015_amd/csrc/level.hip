@@ -544,12 +544,14 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 typedef double lv_d4 __attribute__((ext_vector_type(4)));
 constexpr int LVM_NT = 4;   // 16-column tiles per work-group (one per wave in the reduction)
 constexpr int LVM_U = 4;    // 4-row steps whose loads are issued together
+constexpr int LVM_CPW = 2;  // column tiles per wave in the reduction
+constexpr int LVM_UNT = 8;  // 16-column tiles per work-group in the update
 
 // T_part[chunk] = W_chunk^T X_chunk: M = ranks (16 per tile, MT tiles: the
-// level's reserved rank rounded up), N = 16 columns per wave, K = the chunk's
-// rows.  Every wave takes all rank tiles of its column tile, so each X column
-// of the chunk is read once and the chunk's W rows by the 4 waves of a
-// work-group (from L1).
+// level's reserved rank rounded up), N = 16 columns per tile, LVM_CPW tiles
+// per wave, K = the chunk's rows.  Every wave takes all rank tiles of its
+// column tiles, so each X column of the chunk is read once and the chunk's W
+// rows by the 4 waves of a work-group (from L1), once per 128 columns.
 template <typename PT, int MT>
 __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs A0)
 {
@@ -560,15 +562,20 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
         return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int lr = lane & 15, lq = lane >> 4;
-    const int c0 = (blockIdx.y * LVM_NT + wid) * 16;
-    if (c0 >= A.ncnt)
+    const int ct0 = (blockIdx.y * LVM_NT + wid) * LVM_CPW;   // this wave's first column tile
+    if (ct0 * 16 >= A.ncnt)
         return;   // the whole wave; no work-group barrier follows
     const int64_t n = A.n;
-    const int c = c0 + lr;
     // lanes past the last column or rank read a valid column (the first one)
     // and drop the value, so the loads need no branches
-    const bool cok = c < A.ncnt;
-    const PT *xcol = (const PT *)A.Xt + (int64_t)A.cols[cok ? c : 0] * n;
+    const PT *xcol[LVM_CPW];
+    bool cok[LVM_CPW];
+#pragma unroll
+    for (int j = 0; j < LVM_CPW; ++j) {
+        const int c = (ct0 + j) * 16 + lr;
+        cok[j] = c < A.ncnt;
+        xcol[j] = (const PT *)A.Xt + (int64_t)A.cols[cok[j] ? c : 0] * n;
+    }
     const double *wcol[MT];
     bool wok[MT];
 #pragma unroll
@@ -577,19 +584,24 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
         wok[m] = l < r;
         wcol[m] = A.W + (A.colW + (wok[m] ? l : 0)) * n;
     }
-    lv_d4 acc[MT];
+    lv_d4 acc[MT][LVM_CPW];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
-        acc[m] = lv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < LVM_CPW; ++j)
+            acc[m][j] = lv_d4{0.0, 0.0, 0.0, 0.0};
     for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += 4 * LVM_U) {
-        double bv[LVM_U], av[MT][LVM_U];
+        double bv[LVM_CPW][LVM_U], av[MT][LVM_U];
 #pragma unroll
         for (int u = 0; u < LVM_U; ++u) {
             const int64_t i = i0 + 4 * u + lq;
             const bool ok = i < ch.hi;
             const int64_t is = ok ? i : ch.lo;
-            const double xv = (double)xcol[is];
-            bv[u] = (cok && ok) ? xv : 0.0;
+#pragma unroll
+            for (int j = 0; j < LVM_CPW; ++j) {
+                const double xv = (double)xcol[j][is];
+                bv[j][u] = (cok[j] && ok) ? xv : 0.0;
+            }
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 const double wv = wcol[m][is];
@@ -600,26 +612,33 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
         for (int u = 0; u < LVM_U; ++u)
 #pragma unroll
             for (int m = 0; m < MT; ++m)
-                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m][u], bv[u], acc[m], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < LVM_CPW; ++j)
+                    acc[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m][u], bv[j][u], acc[m][j],
+                                                                     0, 0, 0);
     }
-    // lane (lr, lq) holds T[16 m + lq + 4 t][c0 + lr]
+    // lane (lr, lq) holds T[16 m + lq + 4 t][16 (ct0 + j) + lr]
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
-    if (cok) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+    for (int j = 0; j < LVM_CPW; ++j) {
+        const int c = (ct0 + j) * 16 + lr;
+        if (cok[j]) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int l = 16 * m + lq + 4 * t;
-                if (l < r)
-                    rec[(int64_t)l * A.ncnt + c] = acc[m][t];
-            }
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int l = 16 * m + lq + 4 * t;
+                    if (l < r)
+                        rec[(int64_t)l * A.ncnt + c] = acc[m][j][t];
+                }
+        }
     }
 }
 
 // X_chunk[:, cols] -= W~_chunk S: M = 16 rows per tile, N = 16 columns, K =
 // ranks (4 per step, 4 MT steps: the level's reserved rank rounded up).  A
-// work-group takes one chunk and 64 columns: S's slice for them in LDS, each
-// wave every fourth row tile, whose W~ operands serve the 4 column tiles.
+// work-group takes one chunk and 128 columns: S's slice for them in LDS, each
+// wave every fourth row tile, whose W~ operands serve the 8 column tiles.
 template <typename PT, int MT>
 __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs A0)
 {
@@ -628,10 +647,10 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
     const int nrhs = A.nrhs;
-    const int cbase = blockIdx.y * LVM_NT * 16;
+    const int cbase = blockIdx.y * LVM_UNT * 16;
     if (r == 0 || cbase >= nrhs)
         return;   // the whole work-group
-    __shared__ double sS[RMAX_ABS][LVM_NT * 16 + 1];
+    __shared__ double sS[RMAX_ABS][LVM_UNT * 16 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     const int64_t n = A.n;
@@ -639,15 +658,15 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     const double *S = A.Sbuf + loc * A.tstride;
     const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
     constexpr int KS = 4 * MT;   // 4-rank steps
-    for (int idx = tid; idx < 4 * KS * LVM_NT * 16; idx += LV_THREADS) {
-        const int l = idx / (LVM_NT * 16), cc = idx % (LVM_NT * 16);
+    for (int idx = tid; idx < 4 * KS * LVM_UNT * 16; idx += LV_THREADS) {
+        const int l = idx / (LVM_UNT * 16), cc = idx % (LVM_UNT * 16);
         const int col = cbase + cc;
         sS[l][cc] = (l < r && col < nrhs) ? S[(int64_t)(rowoff + l) * nrhs + col] : 0.0;
     }
     __syncthreads();
-    PT *xcol[LVM_NT];
+    PT *xcol[LVM_UNT];
 #pragma unroll
-    for (int j = 0; j < LVM_NT; ++j) {
+    for (int j = 0; j < LVM_UNT; ++j) {
         const int col = cbase + 16 * j + lr;
         xcol[j] = col < nrhs ? Xp + (int64_t)A.cols[col] * n : nullptr;
     }
@@ -665,7 +684,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
             a[st] = (l < r && rok) ? wv : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < LVM_NT; ++j) {
+        for (int j = 0; j < LVM_UNT; ++j) {
             if (cbase + 16 * j >= nrhs)
                 break;
             lv_d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -813,7 +832,8 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
             reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else
             reduce_mfma_launch<PT>((A.rstride + 15) / 16,
-                                   dim3(nchunks, (A.ncnt + 16 * LVM_NT - 1) / (16 * LVM_NT), P.nitems),
+                                   dim3(nchunks, (A.ncnt + 16 * LVM_NT * LVM_CPW - 1) /
+                                                     (16 * LVM_NT * LVM_CPW), P.nitems),
                                    P.stream, A);
     }
     {
@@ -837,7 +857,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
             level_update_small_kernel<PT, 8><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else
             update_mfma_launch<PT>((A.rstride + 15) / 16,
-                                   dim3(nchunks, (A.nrhs + 16 * LVM_NT - 1) / (16 * LVM_NT), P.nitems),
+                                   dim3(nchunks, (A.nrhs + 16 * LVM_UNT - 1) / (16 * LVM_UNT), P.nitems),
                                    P.stream, A);
     }
     HIP_TRY(hipGetLastError());
