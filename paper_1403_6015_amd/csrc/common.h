@@ -17,12 +17,12 @@ namespace hodlr {
 constexpr int ZERO_RETRY = 8;     // consecutive zero-pivot rows before a block stops
 // block entries per work-group and pass of the large blocks' cross
 // approximation.  1-D (ranks ~3) measured at n = 2^20: 512 0.52 ms, 1024 0.39,
-// 2048 0.37, 4096 0.39 per likelihood; 2-D SE at n = 2^18 (ranks up to 64,
-// about 130 passes): 1024 gives 23.3 likelihoods/s, 2048 19.8, since each
-// entry subtracts up to 64 earlier terms and fewer, longer work-groups per
-// pass lengthen every pass.
+// 2048 0.37, 4096 0.39 per likelihood.  2-D SE at n = 2^18 (ranks up to 64,
+// about 130 passes, each entry subtracting up to 64 earlier terms):
+// 256 -> 30.0, 512 -> 35.6, 1024 -> 33.2, 2048 -> 19.8 likelihoods/s (short
+// work-groups shorten every pass until the per-pass record sums dominate).
 constexpr int ACA_CHUNK_1D = 2048;
-constexpr int ACA_CHUNK_ND = 1024;
+constexpr int ACA_CHUNK_ND = 512;
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_TINY = 256;     // ... and on a single wave when both sides are <= this
 constexpr int ACA_THREADS = 256;
