@@ -310,8 +310,12 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     const int64_t h = A.node0 + loc;
     const int r = A.rank[h];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // with gridDim.y > 1 (levels whose T is summed beforehand) every
+    // work-group of a node factors M and solves every gridDim.y-th batch of
+    // columns; the first one records the factors
+    const bool first = blockIdx.y == 0;
     if (r == 0) {
-        if (A.factor && tid == 0)
+        if (A.factor && tid == 0 && first)
             A.node_ld[h] = 0.0;
         return;
     }
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
                 atomicOr(&sbad, 2);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && first) {
             double v = red[0];
             for (int w = 1; w < TH / 64; ++w)
                 v += red[w];
@@ -459,14 +463,16 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
             }
             A.node_ld[h] = v;
         }
-        for (int idx = tid; idx < r * r; idx += TH) {
-            int i = idx / r, j = idx % r;
-            sm[idx] = sN(i, j);
-            sm[r * r + idx] = sP(i, j);
-            sm[2 * r * r + idx] = sQ(i, j);
+        if (first) {
+            for (int idx = tid; idx < r * r; idx += TH) {
+                int i = idx / r, j = idx % r;
+                sm[idx] = sN(i, j);
+                sm[r * r + idx] = sP(i, j);
+                sm[2 * r * r + idx] = sQ(i, j);
+            }
+            for (int i = tid; i < r; i += TH)
+                sm[3 * r * r + i] = (double)piv[i];
         }
-        for (int i = tid; i < r; i += TH)
-            sm[3 * r * r + i] = (double)piv[i];
     } else {
         for (int idx = tid; idx < r * r; idx += TH) {
             int i = idx / r, j = idx % r;
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     // S = M^{-1} T on the columns to update, in batches
     double *S = A.Sbuf + loc * A.tstride;
     const int nrhs = A.nrhs;
-    for (int c0 = 0; c0 < nrhs; c0 += LV_CB) {
+    for (int c0 = blockIdx.y * LV_CB; c0 < nrhs; c0 += gridDim.y * LV_CB) {
         const int nb = min(LV_CB, nrhs - c0);
         for (int idx = tid; idx < r * nb; idx += TH) {
             int i = idx / nb, c = idx % nb;
@@ -722,12 +728,13 @@ static size_t solve_lds(int rs)
 // node solves of one level: levels with many small-rank nodes (few records
 // each) on one wave per node, the others on LV_SOLVE_TH threads (whose record
 // sums need the loads in flight)
-static void launch_solve(Pipeline &P, const LevelArgs &A, unsigned nodes)
+static void launch_solve(Pipeline &P, const LevelArgs &A, unsigned nodes, unsigned ysplit = 1)
 {
     if (nodes >= 512 && A.rstride <= 8)
         level_solve_kernel<64><<<dim3(nodes, 1, P.nitems), 64, solve_lds(A.rstride), P.stream>>>(A);
     else
-        level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, 1, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride), P.stream>>>(A);
+        level_solve_kernel<LV_SOLVE_TH><<<dim3(nodes, ysplit, P.nitems), LV_SOLVE_TH, solve_lds(A.rstride),
+                                          P.stream>>>(A);
 }
 
 // set once, outside any stream capture
@@ -839,13 +846,18 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
         const double per_node = (double)nchunks / nodes * 2.0 * A.rstride * A.ncnt;
+        unsigned ysplit = 1;
         if (nchunks && per_node > LV_SUM_MIN) {
             A.tsum = 1;
             const int most = 2 * A.rstride * A.ncnt;
             level_sum_kernel<<<dim3(nodes, (most + LV_THREADS - 1) / LV_THREADS, P.nitems), LV_THREADS,
                                0, P.stream>>>(A);
+            // few nodes with many columns: the column batches go to several
+            // work-groups per node, each factoring the node's small matrix
+            if (nodes <= 64 && A.nrhs > LV_CB)
+                ysplit = (unsigned)std::min((A.nrhs + LV_CB - 1) / LV_CB, 16);
         }
-        launch_solve(P, A, nodes);
+        launch_solve(P, A, nodes, ysplit);
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
