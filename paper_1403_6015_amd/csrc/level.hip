@@ -641,10 +641,11 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
     }
 }
 
-// X_chunk[:, cols] -= W~_chunk S: M = 16 rows per tile, N = 16 columns, K =
-// ranks (4 per step, 4 MT steps: the level's reserved rank rounded up).  A
-// work-group takes one chunk and 128 columns: S's slice for them in LDS, each
-// wave every fourth row tile, whose W~ operands serve the 8 column tiles.
+// X_chunk[:, cols] -= W~_chunk S, as (W~ S)^T = S^T W~^T: M = 16 columns, N =
+// 16 rows per tile, K = ranks (4 per step, 4 MT steps: the level's reserved
+// rank rounded up).  A work-group takes one chunk and 128 columns: S's slice
+// for them in LDS, each wave every fourth row tile, whose W~ operands serve
+// the 8 column tiles.
 template <typename PT, int MT>
 __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs A0)
 {
@@ -657,6 +658,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     if (r == 0 || cbase >= nrhs)
         return;   // the whole work-group
     __shared__ double sS[RMAX_ABS][LVM_UNT * 16 + 1];
+    __shared__ int scol[LVM_UNT * 16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     const int64_t n = A.n;
@@ -669,13 +671,9 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
         const int col = cbase + cc;
         sS[l][cc] = (l < r && col < nrhs) ? S[(int64_t)(rowoff + l) * nrhs + col] : 0.0;
     }
+    for (int cc = tid; cc < LVM_UNT * 16; cc += LV_THREADS)
+        scol[cc] = cbase + cc < nrhs ? A.cols[cbase + cc] : -1;
     __syncthreads();
-    PT *xcol[LVM_UNT];
-#pragma unroll
-    for (int j = 0; j < LVM_UNT; ++j) {
-        const int col = cbase + 16 * j + lr;
-        xcol[j] = col < nrhs ? Xp + (int64_t)A.cols[col] * n : nullptr;
-    }
     const int64_t nrt = (ch.hi - ch.lo + 15) >> 4;
     for (int64_t rt = wid; rt < nrt; rt += LV_THREADS / 64) {
         const int64_t i0 = ch.lo + 16 * rt;
@@ -693,19 +691,23 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
         for (int j = 0; j < LVM_UNT; ++j) {
             if (cbase + 16 * j >= nrhs)
                 break;
+            // the transposed product (W~ S)^T = S^T W~^T, so that a lane's
+            // results lie along rows: lane (lr, lq) holds row i0 + lr of
+            // columns cbase + 16 j + lq + 4 t, and each load or store of X
+            // covers 16 consecutive rows of 4 columns
             lv_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int st = 0; st < KS; ++st)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], sS[4 * st + lq][16 * j + lr], acc,
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sS[4 * st + lq][16 * j + lr], a[st], acc,
                                                            0, 0, 0);
-            // lane (lr, lq): rows i0 + lq + 4 t of column cbase + 16 j + lr
-            PT *xc = xcol[j];
-            if (xc) {
+            if (rok) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int64_t i = i0 + lq + 4 * t;
-                    if (i < ch.hi)
-                        xc[i] = (PT)((double)xc[i] - acc[t]);
+                    const int col = scol[16 * j + lq + 4 * t];
+                    if (col >= 0) {
+                        PT *px = Xp + (int64_t)col * n + ia;
+                        *px = (PT)((double)*px - acc[t]);
+                    }
                 }
             }
         }
