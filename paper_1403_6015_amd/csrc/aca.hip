@@ -616,6 +616,72 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
     __syncthreads();   // dots[] visible
 }
 
+// Terms read per round in residual_terms and term_dots: RT * EPT loads in
+// flight per thread. With few entries per thread one term at a time leaves a
+// pass with k = 64 waiting on 64 dependent round trips per entry; with 8
+// entries per thread eight terms per round raise the kernel from 54 to 171
+// VGPRs and its occupancy from 8 to 2 waves per SIMD.
+template <int EPT>
+constexpr int terms_per_round() { return EPT >= 8 ? 1 : 16 / EPT; }
+
+// val[q] -= sum over the k earlier terms of sfix[l] W[l][g_q] (g_q the
+// thread's entries of the chunk), in order of l
+template <int EPT>
+__device__ __forceinline__ void residual_terms(const double *__restrict__ W, int64_t n, int64_t col0,
+                                               int k, const double *sfix, const Chunk &ch, int tid,
+                                               double (&val)[EPT])
+{
+    constexpr int RT = terms_per_round<EPT>();
+    for (int l0 = 0; l0 < k; l0 += RT) {
+        double w[RT][EPT];
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+                w[u][q] = (l0 + u < k && g < ch.hi) ? W[(col0 + l0 + u) * n + g] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+            if (l0 + u < k)
+#pragma unroll
+                for (int q = 0; q < EPT; ++q)
+                    val[q] -= sfix[l0 + u] * w[u][q];
+    }
+}
+
+// sdot[wave][l] = this wave's part of sum_g val_g W[l][g] for l < k, RT terms
+// at a time (their loads and wave sums independent of each other)
+template <int EPT>
+__device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t n, int64_t col0, int k,
+                                          const Chunk &ch, int tid, const double (&val)[EPT],
+                                          double (*sdot)[RMAX_ABS + 1])
+{
+    constexpr int RT = terms_per_round<EPT>();
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int l0 = 0; l0 < k; l0 += RT) {
+        double d[RT];
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            d[u] = 0.0;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+                if (l0 + u < k && g < ch.hi)
+                    d[u] += val[q] * W[(col0 + l0 + u) * n + g];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+            d[u] = wave_sum(d[u]);
+        if (lane == 0)
+#pragma unroll
+            for (int u = 0; u < RT; ++u)
+                if (l0 + u < k)
+                    sdot[wid][l0 + u] = d[u];
+    }
+}
+
 template <bool ROW, int EPT>
 __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 {
@@ -686,13 +752,15 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-            val[q] = 0.0;
+            val[q] = (g < ch.hi) ? kentry(A.kp, A.x, n, fix, g) : 0.0;
+        }
+        residual_terms<EPT>(W, n, col0, k, sfix, ch, tid, val);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
             if (g < ch.hi) {
-                double a = kentry(A.kp, A.x, n, fix, g);
-                for (int l = 0; l < k; ++l)
-                    a -= sfix[l] * W[(col0 + l) * n + g];
+                const double a = val[q];
                 W[(col0 + k) * n + g] = a;
-                val[q] = a;
                 sq += a * a;
                 if (fabs(a) > bv) {
                     bv = fabs(a);
@@ -701,18 +769,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
                 }
             }
         }
-        for (int l = 0; l < k; ++l) {
-            double d = 0.0;
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-                if (g < ch.hi)
-                    d += val[q] * W[(col0 + l) * n + g];
-            }
-            d = wave_sum(d);
-            if (lane == 0)
-                sdot[wid][l] = d;
-        }
+        term_dots<EPT>(W, n, col0, k, ch, tid, val, sdot);
         sq = wave_sum(sq);
         if (lane == 0)
             sdot[wid][k] = sq;
@@ -780,12 +837,14 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-        val[q] = 0.0;
+        val[q] = (g < ch.hi) ? kentry(A.kp, A.x, n, g, fix) : 0.0;
+    }
+    residual_terms<EPT>(W, n, col0, k, sfix, ch, tid, val);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
         if (g < ch.hi) {
-            double a = kentry(A.kp, A.x, n, g, fix);
-            for (int l = 0; l < k; ++l)
-                a -= sfix[l] * W[(col0 + l) * n + g];
-            a = a / t.delta;
+            const double a = val[q] / t.delta;
             W[(col0 + k) * n + g] = a;
             val[q] = a;
             sq += a * a;
@@ -800,18 +859,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
             }
         }
     }
-    for (int l = 0; l < k; ++l) {
-        double d = 0.0;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-            if (g < ch.hi)
-                d += val[q] * W[(col0 + l) * n + g];
-        }
-        d = wave_sum(d);
-        if (lane == 0)
-            sdot[wid][l] = d;
-    }
+    term_dots<EPT>(W, n, col0, k, ch, tid, val, sdot);
     sq = wave_sum(sq);
     if (lane == 0)
         sdot[wid][k] = sq;
