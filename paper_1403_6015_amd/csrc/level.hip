@@ -42,6 +42,14 @@ constexpr int LV_SOLVE_TH = 256;
 // 64 nodes cost the 1-D Matern workload 0.08 ms (small records, one more
 // launch per level).
 constexpr double LV_SUM_MIN = 262144.0;
+// levels with at most LV_SPLIT_NODES nodes and more than LV_SPLIT_COLS
+// columns to update also sum first, so that their node solves can split the
+// column batches over several work-groups per node (at most LV_SPLIT_GROUPS
+// work-groups per node, LV_SPLIT_TOTAL in all)
+constexpr unsigned LV_SPLIT_NODES = 256;
+constexpr int LV_SPLIT_COLS = 4 * LV_CB;
+constexpr unsigned LV_SPLIT_GROUPS = 16;
+constexpr unsigned LV_SPLIT_TOTAL = 1024;
 
 struct LevelArgs {
     int64_t n;
@@ -849,15 +857,18 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
         ProfScope ps(P.stream, PS_LVL_SOLVE);
         const double per_node = (double)nchunks / nodes * 2.0 * A.rstride * A.ncnt;
         unsigned ysplit = 1;
-        if (nchunks && per_node > LV_SUM_MIN) {
+        const bool wide = nodes <= LV_SPLIT_NODES && A.nrhs > LV_SPLIT_COLS;
+        if (nchunks && (per_node > LV_SUM_MIN || wide)) {
             A.tsum = 1;
             const int most = 2 * A.rstride * A.ncnt;
             level_sum_kernel<<<dim3(nodes, (most + LV_THREADS - 1) / LV_THREADS, P.nitems), LV_THREADS,
                                0, P.stream>>>(A);
             // few nodes with many columns: the column batches go to several
             // work-groups per node, each factoring the node's small matrix
-            if (nodes <= 64 && A.nrhs > LV_CB)
-                ysplit = (unsigned)std::min((A.nrhs + LV_CB - 1) / LV_CB, 16);
+            if (nodes <= LV_SPLIT_NODES && A.nrhs > LV_CB) {
+                const unsigned batches = (unsigned)((A.nrhs + LV_CB - 1) / LV_CB);
+                ysplit = std::min({batches, LV_SPLIT_GROUPS, std::max(1u, LV_SPLIT_TOTAL / nodes)});
+            }
         }
         launch_solve(P, A, nodes, ysplit);
     }
