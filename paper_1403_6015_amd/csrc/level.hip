@@ -46,10 +46,10 @@ constexpr double LV_SUM_MIN = 262144.0;
 // columns to update also sum first, so that their node solves can split the
 // column batches over several work-groups per node (at most LV_SPLIT_GROUPS
 // work-groups per node, LV_SPLIT_TOTAL in all)
-constexpr unsigned LV_SPLIT_NODES = 256;
+constexpr unsigned LV_SPLIT_NODES = 1024;
 constexpr int LV_SPLIT_COLS = 4 * LV_CB;
 constexpr unsigned LV_SPLIT_GROUPS = 16;
-constexpr unsigned LV_SPLIT_TOTAL = 1024;
+constexpr unsigned LV_SPLIT_TOTAL = 4096;
 
 struct LevelArgs {
     int64_t n;
