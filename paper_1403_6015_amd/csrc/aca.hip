@@ -557,12 +557,12 @@ __global__ void aca_big_init_kernel(BigState *st, const int *bnode, int nbig, Ac
 // slot 0 (index in slot 1, signed value in slot 3).  One sweep over the
 // records: the first RR_REG sums and the argmax stay in registers and are
 // reduced together behind one barrier; sums beyond RR_REG (ranks above it)
-// take a work-group sum each.
+// follow RR_REG at a time, each group behind one barrier pair.
 constexpr int RR_REG = 8;
 
 __device__ void reduce_records(const double *rec, int nrec, int pw, int k, double *dots,
                                double &bv, int64_t &bi, double &bs, double *rv, int64_t *ri,
-                               double *rs, double *red, double (*sred)[RR_REG + 1])
+                               double *rs, double (*sred)[RR_REG + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int kr = k < RR_REG ? k : RR_REG;
@@ -605,13 +605,37 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
             t += sred[w][l];
         dots[tid == kr ? k : tid] = t;
     }
-    for (int l = RR_REG; l < k; ++l) {
-        double a = 0.0;
-        for (int c = tid; c < nrec; c += ACA_THREADS)
-            a += rec[(int64_t)c * pw + 4 + l];
-        a = block_sum<ACA_THREADS / 64>(a, red);
-        if (tid == 0)
-            dots[l] = a;
+    // the remaining terms RR_REG at a time: their loads in flight together
+    // and one barrier pair per group instead of per term (same summation
+    // order as a block_sum per term)
+    if (k > RR_REG)
+        __syncthreads();   // sred read above before it is refilled
+    for (int l0 = RR_REG; l0 < k; l0 += RR_REG) {
+        const int kl = k - l0 < RR_REG ? k - l0 : RR_REG;
+        double a[RR_REG];
+#pragma unroll
+        for (int j = 0; j < RR_REG; ++j)
+            a[j] = 0.0;
+        for (int c = tid; c < nrec; c += ACA_THREADS) {
+            const double *r = rec + (int64_t)c * pw + 4 + l0;
+#pragma unroll
+            for (int j = 0; j < RR_REG; ++j)
+                if (j < kl)
+                    a[j] += r[j];
+        }
+#pragma unroll
+        for (int j = 0; j < RR_REG; ++j)
+            if (j < kl) {
+                const double w = wave_sum(a[j]);
+                if (lane == 0)
+                    sred[wid][j] = w;
+            }
+        __syncthreads();
+        if (tid < kl) {
+            static_assert(ACA_THREADS == 256, "four waves");
+            dots[l0 + tid] = (sred[0][tid] + sred[1][tid]) + (sred[2][tid] + sred[3][tid]);
+        }
+        __syncthreads();   // sred free for the next group
     }
     __syncthreads();   // dots[] visible
 }
@@ -690,7 +714,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     const int b = B.cidx[blockIdx.x];
     const int64_t h = B.bnode[b];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    __shared__ double rv[4], rs[4], red[4];
+    __shared__ double rv[4], rs[4];
     __shared__ int64_t ri[4];
     __shared__ double sfix[RMAX_ABS];
     __shared__ double dots[RMAX_ABS + 1];
@@ -716,7 +740,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
             // finish the previous step from the column records
             double bv, bs;
             int64_t bi;
-            reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red, sred);
+            reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, sred);
             double u2 = dots[t.k];
             double cross = 0.0;
             for (int l = 0; l < t.k; ++l)
@@ -795,7 +819,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     // ---- column pass: pick the pivot column from the row records
     double bv, bs;
     int64_t bi;
-    reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, red, sred);
+    reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, sred);
     const int nu = t.nused < USED_MAX ? t.nused : USED_MAX;
     for (int q = tid; q < nu; q += ACA_THREADS)
         sused[q] = used[q];
