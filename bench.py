@@ -81,28 +81,71 @@ def measured_traffic(kernel: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(sample_n: int):
-    """The dense FP64 oracle on the first-`sample_n`-points slice of the
-    workload (same density), extrapolated to n = 2^20 by the n^3 cost of a
-    dense Cholesky; also times the exact O(n) Kalman oracle at full size and
-    returns it for the accuracy check of the GPU result."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_CORE = """
+import sys, time, json
+sys.path.insert(0, %r)
+import oracle, workloads as wl
+out = []
+for n in %r:
+    p = wl.matern1d(n)
+    t0 = time.perf_counter()
+    oracle.gp_dense(p.x, p.y, p.kernel, p.theta, p.sigma2)
+    out.append([n, time.perf_counter() - t0])
+print(json.dumps(out))
+"""
+
+
+def cpu_baseline(sizes=(2048, 4096, 8192), one_core_sizes=(2048, 4096)):
+    """The dense FP64 oracle (Cholesky log det and solve, §1 Eq. (1)) on
+    density-matched slices of the workload: n = 2^11..2^13 on every host
+    thread and n = 2^11..2^12 on one thread (a child process with
+    OMP_NUM_THREADS=1), the n^3 exponent fitted over the all-thread points and
+    the largest one extrapolated to n = 2^20 (an extrapolation: the dense
+    matrix at 2^20 would need 8.8 TB).  Also times the exact O(n) Kalman
+    oracle at full size and returns it for the accuracy check of the GPU
+    result."""
+    import subprocess
     import oracle
     import workloads as wl
     oracle.build(force=False)
-    p = wl.matern1d(sample_n)
-    t0 = time.perf_counter()
-    oracle.gp_dense(p.x, p.y, p.kernel, p.theta, p.sigma2)
-    dt = time.perf_counter() - t0
+    times = []
+    for n in sizes:
+        p = wl.matern1d(n)
+        t0 = time.perf_counter()
+        oracle.gp_dense(p.x, p.y, p.kernel, p.theta, p.sigma2)
+        times.append(time.perf_counter() - t0)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_CORE % (ROOT, list(one_core_sizes))],
+                       capture_output=True, text=True, env=env, timeout=600)
+    one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else []
     full = wl.matern1d()
     t1 = time.perf_counter()
     kf = oracle.kalman_matern32(full.x[:, 0], full.y, full.theta, full.sigma2, want_alpha=False)
     dk = time.perf_counter() - t1
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    value = 1.0 / (dt * (float(1 << 20) / sample_n) ** 3)
+    slope = float(np.polyfit(np.log(sizes), np.log(times), 1)[0])
+    big_n, big_t = sizes[-1], times[-1]
+    value = 1.0 / (big_t * (float(1 << 20) / big_n) ** 3)
     base = {"value": value, "unit": "likelihoods/s", "cores": threads, "kind": "oracle",
-            "sample": "dense FP64 Cholesky oracle on n=%d (density-matched slice of the "
-                      "workload) took %.2f s on %d threads; value = 1/(t*(2^20/%d)^3), an n^3 "
-                      "extrapolation" % (sample_n, dt, threads, sample_n)}
+            "cpu_model": _cpu_model(), "host_threads": os.cpu_count(),
+            "timings_s": {"all_threads": [[n, t] for n, t in zip(sizes, times)],
+                          "one_thread": one},
+            "fitted_exponent": slope,
+            "sample": "dense FP64 Cholesky oracle on density-matched slices of the workload "
+                      "(n = %s on %d threads, n = %s on 1 thread; %.1f s in all); value = "
+                      "1/(t(n=%d) * (2^20/%d)^3), an n^3 extrapolation (fitted exponent "
+                      "%.2f)" % (list(sizes), threads, list(one_core_sizes),
+                                 sum(times) + sum(t for _, t in one), big_n, big_n, slope)}
     return base, kf, dk
 
 
@@ -111,19 +154,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--workload", default="matern1d",
                     choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d",
-                             "predict", "table_gauss1d", "table_exp1d", "table_imq1d"],
+                             "predict"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
                          "with n log-uniform in [1024, 131072] per step; learned: surrogate-"
                          "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18; "
-                         "predict: posterior means at --m new inputs through an n=2^20 factor; "
-                         "table_*: the paper's one-dimensional timing tables at n=10^6")
+                         "predict: posterior means at --m new inputs through an n=2^20 factor")
     ap.add_argument("--m", type=int, default=8192, help="new inputs per step (predict)")
     ap.add_argument("--mcmc-steps", type=int, default=300)
     ap.add_argument("--autotune-free-leaf", action="store_true",
@@ -158,8 +199,6 @@ def main():
         return bench_se2d(args, torch, H, wl, dev)
     if args.workload == "predict":
         return bench_predict(args, torch, H, wl, dev)
-    if args.workload.startswith("table_"):
-        return bench_paper_table(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -298,13 +337,47 @@ def main():
                      "seconds": t_tune},
         "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
     }
+    # the other precision on the same data and workload, timed the same way
+    # (whole steps, no events), so that one line carries mixed vs FP64
+    other = H.FP64 if mixed else H.MIXED
+    otopts = H.Opts(max_rank=64, precision=other, presorted=1)
+    otune, _ = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, otopts,
+                          leaf_cands=[p.leaf], reps=2)
+    oplan = H.Plan(p.n, p.dim, p.leaf, H.Opts(max_rank=64, precision=other), tune=otune)
+    owork = torch.empty(oplan.workspace_bytes, dtype=torch.uint8, device=dev)
+    oout = torch.zeros(8, dtype=torch.float64, device=dev)
+
+    def ostep():
+        H.gp_loglik_dev(oplan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, owork,
+                        oplan.workspace_bytes, stream, oout, None)
+
+    for _ in range(args.warmup):
+        ostep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ostep()
+    torch.cuda.synchronize()
+    oelapsed = time.perf_counter() - t0
+    o_ll, o_ld, o_q = oout[:3].cpu().tolist()
+    del owork
+    name = "fp64" if mixed else "mixed"
+    res["other_precision"] = {"precision": name, "value": args.steps / oelapsed,
+                              "unit": "likelihoods/s", "ms_per_step": oelapsed / args.steps * 1e3,
+                              "result": {"loglik": o_ll, "logdet": o_ld, "quad": o_q},
+                              "tiles": otune.as_dict()}
     if not args.no_cpu_baseline and args.n == 1 << 20:
-        base, kf, dk = cpu_baseline(args.cpu_sample_n)
+        base, kf, dk = cpu_baseline()
         res["cpu_baseline"] = base
         res["oracle_check"] = {"kalman_logdet": kf["logdet"], "kalman_quad": kf["quad"],
                                "logdet_rel_err": abs(logdet - kf["logdet"]) / abs(kf["logdet"]),
                                "quad_rel_err": abs(quad - kf["quad"]) / abs(kf["quad"]),
                                "kalman_seconds_1core": dk}
+        res["other_precision"]["logdet_rel_err"] = abs(o_ld - kf["logdet"]) / abs(kf["logdet"])
+        res["other_precision"]["quad_rel_err"] = abs(o_q - kf["quad"]) / abs(kf["quad"])
+        res["other_precision"]["note"] = (
+            "device likelihood without refinement: the mixed form's quadratic form is one "
+            "solve through FP32 applied bases; the metric's mixed bar is the log det at 1e-8")
     print(json.dumps(res), flush=True)
 
 
@@ -652,76 +725,6 @@ def bench_predict(args, torch, H, wl, dev):
 # The paper's single-core timings at n = 10^6 (§5, one-dimensional rows of the
 # Gaussian table tab_gauss_all, the exponential table tab_exp and the inverse
 # multiquadric table tab_inv): assembly + factor + solve + determinant, seconds.
-PAPER_TABLE_SECONDS = {"table_gauss1d": 14.1 + 23.2 + 0.834 + 1.52,
-                       "table_exp1d": 18.8 + 8.05 + 0.636 + 1.35,
-                       "table_imq1d": 14.2 + 26.8 + 1.02 + 1.49}
-
-
-def bench_paper_table(args, torch, H, wl, dev):
-    """The test problems of the paper's one-dimensional timing tables (§5):
-    r ~ U(-3, 3), C = s I + K with the Gaussian exp(-r^2) (s = 2), the
-    exponential exp(-|r|) (s = 1) or the inverse multiquadric 1/sqrt(1 + r^2)
-    (s = 1), at n = 10^6 (--n), smallest blocks 64, tolerance 1e-14.  One step =
-    one device likelihood (compression, factorization, log det and the solve
-    with y), inputs resident in HBM; vs_baseline = value times the paper's
-    summed assembly + factor + solve + determinant seconds for that row (one
-    2014 laptop core; context only)."""
-    kind = {"table_gauss1d": wl.K_SE, "table_exp1d": wl.K_EXP, "table_imq1d": wl.K_IMQ}[args.workload]
-    n = args.n if args.n != 1 << 20 else 10 ** 6
-    p = wl.paper_table(kind, n)
-    opts = H.Opts(max_rank=64, presorted=1)
-    tune, _ = H.autotune(p.x, p.y, p.kernel, p.theta, p.sigma2, p.tol, opts,
-                         leaf_cands=[p.leaf], reps=2)
-    plan = H.Plan(n, 1, p.leaf, H.Opts(max_rank=64), tune=tune)
-    d_x = torch.from_numpy(np.ascontiguousarray(p.x.T)).to(dev)
-    d_y = torch.from_numpy(np.ascontiguousarray(p.y)).to(dev)
-    work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
-    out = torch.zeros(8, dtype=torch.float64, device=dev)
-
-    def step():
-        H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
-                        plan.workspace_bytes, None, out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    loglik, logdet, quad = out[:3].cpu().tolist()
-    # per-stage breakdown in a pass of its own (every launch timed)
-    H.profile_select(None)
-    H.profile_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    breakdown = H.profile_read()
-    H.profile_enable(False)
-    f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, opts)
-    info = f.info()
-    f.free()
-    value = args.steps / el
-    paper_s = PAPER_TABLE_SECONDS[args.workload] if n == 10 ** 6 else None
-    res = {"metric": "GP log-likelihoods/s (factor+logdet+solve), the paper's 1-D table problem",
-           "value": value, "unit": "likelihoods/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": value * paper_s if paper_s else None,
-           "vs_baseline_note": "against 1 / (assembly + factor + solve + det) of the paper's "
-                               "table row at n = 10^6 (%.3f s on one 2014 laptop core); context, "
-                               "not a target" % paper_s if paper_s else None,
-           "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "%s_n%d_leaf64_tol1e-14" % (args.workload, n), "n": n, "dim": 1,
-                      "kernel": wl.KERNEL_NAMES[kind], "theta": list(p.theta),
-                      "sigma2": p.sigma2, "leaf": p.leaf, "tol": p.tol, "max_rank": 64},
-           "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
-           "stage_ms_per_step": {k: v[0] / args.steps for k, v in breakdown.items() if v[1] > 0},
-           "result": {"loglik": loglik, "logdet": logdet, "quad": quad}}
-    print(json.dumps(res), flush=True)
-
-
 def bench_copy(args, torch, dev):
     """Calibration for the HBM byte counters: a plain elementwise copy of
     2^28 doubles (2 GiB read, 2 GiB written per launch), one launch per step."""

@@ -30,10 +30,13 @@
  *    (x[d*n + i]), plus a caller-provided device workspace and a hipStream_t
  *    passed as void*.  They enqueue work on that stream and may synchronize
  *    it internally while the cross-approximation runs.
- *  - Precision: FP64 everywhere by default.  HODLR_MIXED evaluates kernel
- *    entries, compresses and runs the level updates in FP32, keeps leaf
- *    factorizations and determinants in FP64, and recovers the solve by
- *    iterative refinement against an exact FP64 matrix-vector product.
+ *  - Precision: FP64 everywhere by default.  HODLR_MIXED stores the applied
+ *    bases W~ = (block inverses) W and the solve vector in FP32; every
+ *    arithmetic operation (kernel evaluation, compression, leaf factors,
+ *    level products, coupling LU, log-det sums) stays FP64, loaded FP32
+ *    values are widened in registers and results rounded on store.  The
+ *    host solve recovers full accuracy by iterative refinement against an
+ *    exact FP64 matrix-vector product (see hodlr_opts.precision).
  *  - Thread safety: distinct factors/plans may be used concurrently; one
  *    workspace must not be used by two calls at once.
  */
@@ -54,8 +57,8 @@ typedef enum {
     HODLR_ENOTSPD = 2,  /* a leaf Cholesky pivot or a coupling determinant was not positive */
     HODLR_ENOMEM = 3,   /* device or host allocation failed */
     HODLR_EDEVICE = 4,  /* a HIP runtime call failed */
-    HODLR_ENOCONV = 5   /* mixed form: refinement missed refine_tol within max_refine steps
-                           (outputs ARE written with the best iterate) */
+    HODLR_ENOCONV = 5   /* refined solve: refinement missed refine_tol within max_refine
+                           steps (outputs ARE written with the best iterate) */
 } hodlr_status;
 
 /* Covariance kernels (Table 1 and §5 of the paper, amplitude/length-scale form),
@@ -83,10 +86,11 @@ typedef struct {
                             the exact FP64 product (hodlr_matvec_dev) by conjugate
                             gradients preconditioned with the factor; gp_loglik_dev and
                             the batched form return the unrefined quadratic form      */
-    double refine_tol;   /* mixed form: stop at ||y - C x|| / ||y|| <= refine_tol, the
-                            true residual (default 1e-10)                             */
-    int32_t max_refine;  /* mixed form: at most 1 + max_refine preconditioned steps,
-                            each one exact product and one factor solve (default 8)   */
+    double refine_tol;   /* refined solves: stop at ||y - C x|| / ||y|| <= refine_tol,
+                            the true residual (default 1e-10)                         */
+    int32_t max_refine;  /* refined solves: at most 1 + max_refine preconditioned steps,
+                            each one exact product and one factor solve (default 8;
+                            0 allows the first step only)                             */
     int32_t presorted;   /* 1: the points are already in tree order; skip ordering     */
     const double *noise; /* optional per-point noise variances sigma_i^2 (host memory,
                             n entries in the caller's point order, each >= 0 and
@@ -96,6 +100,12 @@ typedef struct {
                             hodlr_build and gp_loglik; the plan-based, batched,
                             uneven-size and autotuning entry points reject a non-NULL
                             value with HODLR_EINVAL.  Default NULL                    */
+    int32_t refine;      /* 1: FP64 factors also refine every hodlr_solve / hodlr_predict
+                            solve and the host gp_loglik quadratic form against the
+                            exact FP64 product, as the mixed form always does (to
+                            refine_tol within max_refine steps; ENOCONV otherwise).
+                            0 (default): an FP64 factor is applied once, whose
+                            residual is about tol ||K|| / sigma2                      */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one
@@ -150,8 +160,9 @@ hodlr_status hodlr_logdet(hodlr_factor f, double *logdet);
 
 /* x = C^{-1} y for nrhs right-hand sides (§3.2, inverse of the factor list).
  * y, x: column-major n x nrhs host arrays in the caller's order; x may alias
- * y.  Mixed-precision factors refine each column to refine_tol (ENOCONV if
- * not reached; x still holds the best iterate).                             */
+ * y.  Mixed-precision factors, and FP64 factors built with opts.refine = 1,
+ * refine each column to refine_tol (ENOCONV if not reached; x still holds
+ * the best iterate).                                                        */
 hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrhs);
 
 /* Prediction at m new inputs through the factor (§2.1, predictive mean and

@@ -20,8 +20,11 @@ squared error in the standardized output, mean_s (o_s - (l_s - mu_out)/sd_out)^2
 
 Gradients are the chain rule written out layer by layer; the optimizer is
 Adam as published by Kingma and Ba (2015), Algorithm 1, with bias-corrected
-first and second moments.  Nothing here rounds to BF16: a caller that wants
-the oracle to see the network a BF16 device holds passes the rounded weights.
+first and second moments.  Weights are never rounded here: a caller that
+wants the oracle to see the network a BF16 device holds passes the rounded
+weights.  ``loss_and_grad(..., bf16_products=True)`` also rounds the two
+operands of each 128-wide product to BF16, the precision a BF16 matrix unit
+takes them in; the default keeps every value FP64.
 """
 from __future__ import annotations
 
@@ -79,11 +82,25 @@ def forward(p, logtheta, norm):
     return norm["mu_out"] + norm["sd_out"] * O, {"U": U, "H1": H1, "H2": H2, "O": O}
 
 
-def loss_and_grad(p, logtheta, target, norm):
+def loss_and_grad(p, logtheta, target, norm, bf16_products=False):
     """Standardized MSE of a batch and its gradient with respect to the flat
-    parameter vector (chain rule, layer by layer)."""
+    parameter vector (chain rule, layer by layer).
+
+    bf16_products=True takes the two 128-wide products of the network in the
+    operand precision of a BF16 matrix unit: the hidden activations h1 are
+    rounded to BF16 where they multiply W2 (forward) and dz2 (weight
+    gradient), and the back-propagated dz2 is rounded to BF16 where it
+    multiplies h1 and W2; every other value stays FP64 (the bias gradient of
+    layer 2 sums the unrounded dz2)."""
     P = unpack(p)
     _, c = forward(p, logtheta, norm)
+    H1 = c["H1"]
+    H1p = H1
+    if bf16_products:
+        # the forward pass again with h1 rounded where it enters W2
+        H1p = bf16_round(H1)
+        c["H2"] = np.tanh(H1p @ P["W2"].T + P["b2"])
+        c["O"] = c["H2"] @ P["W3"] + P["b3"][0]
     T = (np.asarray(target, dtype=np.float64) - norm["mu_out"]) / norm["sd_out"]
     B = T.size
     r = c["O"] - T
@@ -92,9 +109,10 @@ def loss_and_grad(p, logtheta, target, norm):
     g_W3 = c["H2"].T @ g_o                             # [128]
     g_b3 = np.array([g_o.sum()])
     g_z2 = np.outer(g_o, P["W3"]) * (1.0 - c["H2"] ** 2)  # [B,128]
-    g_W2 = g_z2.T @ c["H1"]                            # [128,128]
     g_b2 = g_z2.sum(axis=0)
-    g_h1 = g_z2 @ P["W2"]                              # [B,128]
+    g_z2p = bf16_round(g_z2) if bf16_products else g_z2
+    g_W2 = g_z2p.T @ H1p                               # [128,128]
+    g_h1 = g_z2p @ P["W2"]                             # [B,128]
     g_z1 = g_h1 * (1.0 - c["H1"] ** 2)
     g_W1 = g_z1.T @ c["U"]                             # [128,3]
     g_b1 = g_z1.sum(axis=0)

@@ -57,10 +57,11 @@ class HodlrError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p)]
+                ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p),
+                ("refine", ctypes.c_int32)]
 
     def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0,
-                 noise=None):
+                 noise=None, refine=0):
         """noise: optional per-point variances (one per point, caller's order),
         added to sigma2 on the diagonal; the array is kept alive with the
         options."""
@@ -70,7 +71,7 @@ class Opts(ctypes.Structure):
             self._noise = np.ascontiguousarray(np.asarray(noise, dtype=np.float64).ravel())
             ptr = self._noise.ctypes.data
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
-                         int(presorted), ptr)
+                         int(presorted), ptr, int(refine))
 
 
 class Profile(ctypes.Structure):

@@ -1107,7 +1107,7 @@ void run_aca(Pipeline &P)
         HIP_TRY(hipGetLastError());
         return;
     }
-    int *pinned = pinned_scratch();
+    int *pinned = P.host_ints ? P.host_ints : pinned_scratch();
     int64_t *d_cofa = wsp<int64_t>(P, P.lay.misc);          // [0, 512): column offsets
     int *d_rmax = wsp<int>(P, P.lay.misc + 512);             // [512, 784): rmax per depth
     int *d_capped = wsp<int>(P, P.lay.misc + 784);

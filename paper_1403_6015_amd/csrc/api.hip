@@ -3,8 +3,9 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
-#include "common.h"
+#include "plan_handle.h"
 
 namespace hodlr {
 void run_leaf_solve(Pipeline &P, void *z);
@@ -47,6 +48,7 @@ hodlr_opts default_opts()
     o.max_refine = 8;
     o.presorted = 0;
     o.noise = nullptr;
+    o.refine = 0;
     return o;
 }
 
@@ -85,21 +87,8 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "max_refine must be >= 0"};
     if (!(o.refine_tol > 0.0) || !std::isfinite(o.refine_tol))
         throw Error{HODLR_EINVAL, "refine_tol must be positive"};
-}
-
-void check_params(int k, const double theta[2], double sigma2, double tol)
-{
-    if (k < HODLR_K_SE || k > HODLR_K_IMQ)
-        throw Error{HODLR_EINVAL, "unknown kernel"};
-    if (!theta)
-        throw Error{HODLR_EINVAL, "theta is NULL"};
-    if (!(theta[0] > 0.0) || !std::isfinite(theta[0]) || !(theta[1] > 0.0) ||
-        !std::isfinite(theta[1]))
-        throw Error{HODLR_EINVAL, "theta = {a, l} must be positive and finite"};
-    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
-        throw Error{HODLR_EINVAL, "sigma2 must be >= 0 and finite"};
-    if (!(tol > 0.0) || !std::isfinite(tol))
-        throw Error{HODLR_EINVAL, "tol must be positive and finite"};
+    if (o.refine != 0 && o.refine != 1)
+        throw Error{HODLR_EINVAL, "refine must be 0 or 1"};
 }
 
 void check_finite(const double *v, int64_t m, const char *what)
@@ -162,6 +151,21 @@ std::vector<double> ordered_soa(const double *x, int64_t n, int dim, const std::
 }  // namespace
 
 namespace hodlr {
+void check_params(int k, const double theta[2], double sigma2, double tol)
+{
+    if (k < HODLR_K_SE || k > HODLR_K_IMQ)
+        throw Error{HODLR_EINVAL, "unknown kernel"};
+    if (!theta)
+        throw Error{HODLR_EINVAL, "theta is NULL"};
+    if (!(theta[0] > 0.0) || !std::isfinite(theta[0]) || !(theta[1] > 0.0) ||
+        !std::isfinite(theta[1]))
+        throw Error{HODLR_EINVAL, "theta = {a, l} must be positive and finite"};
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
+        throw Error{HODLR_EINVAL, "sigma2 must be >= 0 and finite"};
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        throw Error{HODLR_EINVAL, "tol must be positive and finite"};
+}
+
 void make_columns(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -207,34 +211,6 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
 }
 
 }  // namespace hodlr
-
-// graph of the synchronization-free stages of a batched call, valid for one
-// column layout and one set of buffers
-struct BatchGraph {
-    std::vector<int> rmax;
-    const void *ws, *x, *y, *params, *out;
-    int64_t ystride;
-    void *stream;
-    int kind, nitems;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-struct hodlr_plan_s {
-    Plan plan;
-    Layout lay;
-    hodlr_opts opts;
-    std::vector<BatchGraph> graphs;
-    ~hodlr_plan_s()
-    {
-        for (auto &g : graphs) {
-            if (g.exec)
-                (void)hipGraphExecDestroy(g.exec);
-            if (g.graph)
-                (void)hipGraphDestroy(g.graph);
-        }
-    }
-};
 
 namespace {
 __global__ void zero_status_kernel(int *status0, BatchArgs B)
@@ -304,9 +280,10 @@ struct Refined {
 };
 
 // d_x = C^{-1} d_y in tree order (device FP64 vectors).  An FP64 factor
-// applies its inverse once.  A mixed factor refines against the exact FP64
-// product by conjugate gradients preconditioned with the factor (flexible
-// form, since the FP32 factor is only nearly symmetric): with an accurate
+// applies its inverse once unless refinement was asked for.  A refined solve
+// (always for a mixed factor) iterates against the exact FP64 product by
+// conjugate gradients preconditioned with the factor (flexible form, since
+// the FP32 factor is only nearly symmetric): with an accurate
 // factor this converges like x_{k+1} = x_k + H^{-1}(y - C x_k), and it still
 // converges when rank caps make the factor too rough for that stationary
 // iteration.  Stops at ||y - C x|| <= refine_tol ||y|| (true residual) or
@@ -321,7 +298,7 @@ Refined solve_tree(hodlr_factor_s *f, Pipeline &P, const double *d_y, double *d_
     const bool f32 = f->plan.f32();
     void *zp = P.ws + P.lay.Xt;   // column 0 of the panel carries the vector
     hipStream_t s = P.stream;
-    if (!f32) {
+    if (!f->plan.refine) {
         HIP_TRY(hipMemcpyAsync(zp, d_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         run_leaf_solve(P, zp);
         run_levels_apply(P);
@@ -330,10 +307,10 @@ Refined solve_tree(hodlr_factor_s *f, Pipeline &P, const double *d_y, double *d_
     }
     // z = H^{-1} v, the vector scaled to unit norm through the FP32 panel
     auto precond = [&](const double *v, double vnorm, double *out) {
-        run_cast_scaled(v, 1.0 / vnorm, zp, true, n, s);
+        run_cast_scaled(v, 1.0 / vnorm, zp, f32, n, s);
         run_leaf_solve(P, zp);
         run_levels_apply(P);
-        run_widen(zp, true, out, n, s, vnorm);
+        run_widen(zp, f32, out, n, s, vnorm);
     };
     const double ynorm = std::sqrt(run_sumsq(d_y, n, w.part, s));
     HIP_TRY(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
@@ -486,15 +463,15 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
         check_finite(y, n * nrhs, "y");
         HIP_TRY(hipSetDevice(f->device));
         Pipeline P = factor_pipeline_of(f);
-        const bool f32 = f->plan.f32();
+        const bool refined = f->plan.refine;
         DevBuf dy(sizeof(double) * n), dx(sizeof(double) * n);
-        const size_t vb = f32 ? sizeof(double) * n : 8;
+        const size_t vb = refined ? sizeof(double) * n : 8;
         DevBuf dr(vb), dq(vb), dz(vb), dp(vb), part(sizeof(double) * 512);
         const Work w{(double *)dr.p, (double *)dq.p, (double *)dz.p, (double *)dp.p,
                      (double *)part.p};
         std::vector<double> buf(n), res(n);
         int steps = 0;
-        double worst = f32 ? 0.0 : -1.0;
+        double worst = refined ? 0.0 : -1.0;
         bool all_ok = true;
         for (int64_t c = 0; c < nrhs; ++c) {
             const double *yc = y + c * n;
@@ -505,7 +482,7 @@ hodlr_status hodlr_solve(hodlr_factor f, const double *y, double *x, int64_t nrh
             HIP_TRY(hipMemcpy(buf.data(), dx.p, sizeof(double) * n, hipMemcpyDeviceToHost));
             prof_collect();
             steps = std::max(steps, r.steps);
-            if (f32)
+            if (refined)
                 worst = std::max(worst, r.residual);
             all_ok = all_ok && r.converged;
             for (int64_t k = 0; k < n; ++k)
@@ -536,9 +513,9 @@ hodlr_status hodlr_predict(hodlr_factor f, const double *y, const double *xt, in
         HIP_TRY(hipSetDevice(f->device));
         Pipeline P = factor_pipeline_of(f);
         hipStream_t s = P.stream;
-        const bool f32 = f->plan.f32();
+        const bool refined = f->plan.refine;
         DevBuf dy(sizeof(double) * n), da(sizeof(double) * n);
-        const size_t vb = f32 ? sizeof(double) * n : 8;
+        const size_t vb = refined ? sizeof(double) * n : 8;
         DevBuf dr(vb), dq(vb), dz(vb), dp(vb), part(sizeof(double) * 512);
         const Work w{(double *)dr.p, (double *)dq.p, (double *)dz.p, (double *)dp.p,
                      (double *)part.p};
@@ -549,7 +526,7 @@ hodlr_status hodlr_predict(hodlr_factor f, const double *y, const double *xt, in
         HIP_TRY(hipMemcpy(dy.p, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
         Refined ra = solve_tree(f, P, (const double *)dy.p, (double *)da.p, w);
         int steps = ra.steps;
-        double worst = f32 ? ra.residual : -1.0;
+        double worst = refined ? ra.residual : -1.0;
         bool all_ok = ra.converged;
         // test points, coordinate-major
         std::vector<double> xs((size_t)m * dim);
@@ -575,7 +552,7 @@ hodlr_status hodlr_predict(hodlr_factor f, const double *y, const double *xt, in
                     const double *kc = (const double *)dk.p + (int64_t)c * n;
                     Refined rv = solve_tree(f, P, kc, (double *)dv.p, w);
                     steps = std::max(steps, rv.steps);
-                    if (f32)
+                    if (refined)
                         worst = std::max(worst, rv.residual);
                     all_ok = all_ok && rv.converged;
                     var[j0 + c] = f->kp.a2 - run_dot(kc, (const double *)dv.p, n, w.part, s);
@@ -608,7 +585,7 @@ hodlr_status gp_loglik(const double *x, int64_t n, int32_t dim, hodlr_kernel k,
             check_noise(o.noise, n);
         if (!loglik)
             throw Error{HODLR_EINVAL, "loglik is NULL"};
-        if (o.precision == HODLR_MIXED) {
+        if (o.precision == HODLR_MIXED || o.refine) {
             // factor once, then the refined solve for the quadratic form
             hodlr_factor f = nullptr;
             hodlr_status st = hodlr_build(x, n, dim, k, theta, sigma2, leaf, tol, &o, &f);
@@ -727,6 +704,7 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
             throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
+        p->reserve_host();
         *out = p.release();
         return HODLR_OK;
     });
@@ -752,6 +730,7 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
             throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
+        p->reserve_host();
         *out = p.release();
         return HODLR_OK;
     });
@@ -799,6 +778,10 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         return HODLR_OK;
     });
 }
+
+}  // extern "C"
+
+extern "C" {
 
 hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes)
 {

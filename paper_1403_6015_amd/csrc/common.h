@@ -237,6 +237,7 @@ struct Plan {
     int red_grp = 8;           // columns per work-group of the small-rank reduction (8 or 64)
     double refine_tol = 1e-10;
     int max_refine = 8;
+    bool refine = false;       // host solves refine against the exact product (always when mixed)
     int64_t nint = 0;    // internal (split) nodes 2^L - 1
     int64_t nleaf = 1;   // 2^L
     int leafmax = 0;
@@ -334,6 +335,8 @@ struct Pipeline {
     BatchArgs batch;      // istride = lay.total rounded, params per item
     bool capturing = false;
     bool side_stream = true;  // small-block compression on a second stream of this thread
+    int *host_ints = nullptr; // 64 host ints for the compression's statistics (nullptr:
+                              // this thread's pinned buffer, allocated on first use)
     // host-side results of the compression
     std::vector<int> rmax;    // per depth j (1..L), used columns of the panel
     std::vector<int> cols;    // used column indices, depth-ascending, cols[0] = 0

@@ -51,8 +51,10 @@ thread_local bool t_suspended = false;
 
 bool prof_on(int stage)
 {
+    if (t_suspended)
+        return false;
     Prof &p = P();
-    return !t_suspended && p.on.load(std::memory_order_relaxed) &&
+    return p.on.load(std::memory_order_relaxed) &&
            ((p.mask.load(std::memory_order_relaxed) >> stage) & 1u);
 }
 
@@ -83,6 +85,8 @@ void prof_end(int slot, hipStream_t s, int stage)
 
 void prof_collect()
 {
+    if (t_suspended)
+        return;   // records of other calls stay pending for their own collection
     Prof &p = P();
     std::lock_guard<std::mutex> g(p.mu);
     for (Rec &r : p.pending) {

@@ -1,7 +1,7 @@
 """GPU parity of the surrogate network and the sampler kernels against the
 FP64 oracles: the BF16 weight copy bit for bit, the forward pass within a
-bound derived from BF16 rounding of the hidden activations, the gradient per
-parameter block, Adam's first step, and the sampler's stage kernels decision
+bound derived from BF16 rounding of the hidden activations, the gradient element
+by element, Adam's first step, and the sampler's stage kernels decision
 for decision on oracle-supplied likelihood values; then the sampler driver's
 invariants on a small GP."""
 import numpy as np
@@ -79,7 +79,31 @@ def test_forward_matches_oracle(batch):
     assert np.all(err <= bound), (err.max(), bound.min())
 
 
-def test_gradient_matches_oracle_per_block():
+def _grad_terms(p, X, T):
+    """Per gradient entry: the sum of |terms| of the sums that form it, and the
+    largest single |term| (the oracle's chain rule with absolute values)."""
+    P = mr.unpack(p)
+    _, c = mr.forward(p, X, NORM)
+    B = X.shape[0]
+    go = 2.0 * (c["O"] - (T - NORM["mu_out"]) / NORM["sd_out"]) / B
+    ad = np.abs(go[:, None] * P["W3"][None, :] * (1 - c["H2"] ** 2))
+    mz1 = (ad @ np.abs(P["W2"])) * (1 - c["H1"] ** 2)
+    aU, aH1, aH2, ag = np.abs(c["U"]), np.abs(c["H1"]), np.abs(c["H2"]), np.abs(go)
+    mag = np.concatenate([(mz1.T @ aU).ravel(), mz1.sum(0), (ad.T @ aH1).ravel(), ad.sum(0),
+                          aH2.T @ ag, [ag.sum()]])
+    big = np.concatenate([np.max(mz1[:, :, None] * aU[:, None, :], axis=0).ravel(), mz1.max(0),
+                          np.max(ad[:, :, None] * aH1[:, None, :], axis=0).ravel(), ad.max(0),
+                          (aH2 * ag[:, None]).max(0), [ag.max()]])
+    return mag, big
+
+
+def test_gradient_matches_oracle_element_by_element():
+    """Every one of the 17153 gradient entries against the oracle's gradient
+    with the same BF16 operands (h1 and dz2 rounded where they enter the two
+    128-wide products).  What remains is FP32 arithmetic (accumulation order,
+    tanhf) and the rare BF16 rounding decision that FP32 and FP64 values take
+    differently: per entry 1e-5 of its summed term magnitudes plus 4 unit
+    roundoffs of its largest single term."""
     import torch
     B = 200
     announce("mlp gradient batch=%d" % B)
@@ -89,7 +113,8 @@ def test_gradient_matches_oracle_per_block():
     rng = np.random.default_rng(30)
     X = rng.normal(size=(B, 3))
     T = rng.normal(3.0, 4.0, size=B)
-    loss_ref, g_ref = mr.loss_and_grad(pb, X, T, NORM)
+    loss_ref, g_ref = mr.loss_and_grad(pb, X, T, NORM, bf16_products=True)
+    mag, big = _grad_terms(pb, X, T)
     nb = H.mlp_workspace_size(B)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
     grad = torch.empty(mr.NPARAM, dtype=torch.float32, device="cuda")
@@ -98,14 +123,13 @@ def test_gradient_matches_oracle_per_block():
                    nb, grad, loss)
     torch.cuda.synchronize()
     g = grad.cpu().numpy().astype(np.float64)
-    assert abs(loss.item() - loss_ref) <= 4 * U8 * loss_ref
-    k = 0
-    for name, shape in mr.SIZES:
-        m = int(np.prod(shape))
-        a, b = g[k:k + m], g_ref[k:k + m]
-        # BF16 rounding of h1 and of dz2 in the products: a few unit roundoffs
-        assert np.linalg.norm(a - b) <= 4 * U8 * np.linalg.norm(b) + 1e-7, name
-        k += m
+    assert abs(loss.item() - loss_ref) <= 1e-4 * loss_ref
+    bound = 1e-5 * mag + 4 * U8 * big + 1e-9
+    err = np.abs(g - g_ref)
+    worst = int(np.argmax(err / bound))
+    print("mlp gradient: worst entry %d err %.3e bound %.3e; median bound / |g| %.2e" % (
+        worst, err[worst], bound[worst], np.median(bound / (np.abs(g_ref) + 1e-12))))
+    assert np.all(err <= bound), (worst, err[worst], bound[worst])
 
 
 def test_adam_first_step_matches_oracle():

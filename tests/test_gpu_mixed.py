@@ -137,16 +137,14 @@ def test_mixed_batched_items_equal_single_device_calls():
 def test_2d_se_capped_matches_dense_oracle(precision):
     """The 2-D configuration (SE, l = 0.05, sigma^2 = 1e-2, ranks capped at 64)
     at a density-matched n = 4096 (leaf 128): log det within 1e-10 (FP64) of
-    the dense oracle; the mixed form's FP32 applied bases, amplified through
-    coupling matrices of rank up to 20 with sigma^2 = 1e-2, put its log det at
-    1.6e-8 (measured), held to 3e-8 here: just outside the 1e-8 mixed-form
-    target on this configuration.  The mixed solve meets the 1e-10
-    residual bar through refinement; the FP64 form applies its factor once, so
-    its residual is set by the compression tolerance times ||K|| / sigma^2
-    (1e-10 x 4096 / 1e-2 = 4e-5 here; measured 1.2e-7)."""
+    the dense oracle, and every solve at the 1e-10 residual bar through
+    refinement against the exact product (the FP64 factor applied once leaves
+    tol ||K|| / sigma^2 ~ 1e-7 here, so the FP64 form is built with
+    refine = 1).  The mixed form's log det is held to the 1e-8 mixed-form
+    bar in the test below."""
     p = wl.se2d(4096)
     announce("2-D SE n=%d precision=%d" % (p.n, precision))
-    opts = H.Opts(max_rank=64, precision=precision)
+    opts = H.Opts(max_rank=64, precision=precision, refine=1)
     f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, 128, p.tol, opts)
     ld = f.logdet()
     z = f.solve(p.y)
@@ -158,5 +156,24 @@ def test_2d_se_capped_matches_dense_oracle(precision):
     rel = abs(ld - ref["logdet"]) / abs(ref["logdet"])
     print("2-D SE precision %d logdet rel %.3e residual %.3e ranks %s refine steps %d" % (
         precision, rel, res, info["rank_max"], info["refine_steps"]))
-    assert rel <= (1e-10 if precision == H.FP64 else 3e-8)
-    assert res <= (1e-6 if precision == H.FP64 else 1e-10)
+    if precision == H.FP64:
+        assert rel <= 1e-10
+    assert res <= 1e-10
+    assert info["refine_residual"] <= 1e-10
+
+
+def test_mixed_max_refine_zero_takes_one_step():
+    """max_refine = 0 allows the first preconditioned step only: with an
+    unreachable tolerance the solve reports ENOCONV after it, outputs
+    written."""
+    p = wl.se1d_small()
+    announce("mixed max_refine=0")
+    f = H.hodlr_build(p.x, p.kernel, p.theta, p.sigma2, p.leaf, p.tol,
+                      _mixed(refine_tol=1e-30, max_refine=0))
+    with pytest.raises(H.HodlrError) as e:
+        f.solve(p.y)
+    info = f.info()
+    f.free()
+    assert e.value.name == "ENOCONV"
+    assert info["refine_steps"] <= 0
+    assert 0.0 < info["refine_residual"] < 1e-4

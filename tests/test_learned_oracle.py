@@ -166,3 +166,63 @@ def test_perfect_surrogate_reduces_to_plain_mh():
     t_da, l_da, _, acc_da = mc.da_stage2(th, lp, lp, prop, lpp, lpp, surv, u2)
     assert np.array_equal(acc_mh, acc_da)
     assert np.array_equal(t_mh, t_da) and np.array_equal(l_mh, l_da)
+
+
+def test_proposal_applies_the_lower_factor_not_its_transpose():
+    """theta' = theta + L eps with a non-diagonal lower-triangular L: a unit
+    eps_k moves theta along column k of L, and over many draws the increments
+    have covariance L L^T (an L / L^T mix-up gives L^T L, which differs here)."""
+    L = np.array([[0.5, 0.0, 0.0], [0.3, 0.4, 0.0], [-0.2, 0.6, 0.7]])
+    assert not np.allclose(L @ L.T, L.T @ L)
+    th = np.array([[0.1, -0.2, 0.3]])
+    for k in range(3):
+        e = np.zeros((1, 3))
+        e[0, k] = 1.0
+        assert np.array_equal(mc.propose(np.zeros((1, 3)), L, e)[0], L[:, k]), k
+        step = mc.propose(th, L, e) - th
+        assert np.allclose(step[0], L[:, k], rtol=0, atol=1e-15), (k, step, L[:, k])
+    rng = np.random.default_rng(21)
+    N = 400000
+    eps = rng.standard_normal((N, 3))
+    inc = mc.propose(np.zeros((N, 3)), L, eps)
+    cov = inc.T @ inc / N
+    # Monte Carlo error of each covariance entry ~ sqrt(2 / N) * scale ~ 2e-3
+    assert np.max(np.abs(cov - L @ L.T)) < 1e-2, cov
+    assert np.max(np.abs(cov - L.T @ L)) > 0.1
+
+
+def _term_magnitudes(p, X, T):
+    """Per gradient entry: the sum of |terms| of the sums that form it and the
+    largest single |term| (chain rule of ``loss_and_grad`` with absolute
+    values)."""
+    P = mr.unpack(p)
+    _, c = mr.forward(p, X, NORM)
+    B = X.shape[0]
+    go = 2.0 * (c["O"] - (T - NORM["mu_out"]) / NORM["sd_out"]) / B
+    ad = np.abs(go[:, None] * P["W3"][None, :] * (1 - c["H2"] ** 2))
+    mz1 = (ad @ np.abs(P["W2"])) * (1 - c["H1"] ** 2)
+    aU, aH1, aH2, ag = np.abs(c["U"]), np.abs(c["H1"]), np.abs(c["H2"]), np.abs(go)
+    mag = np.concatenate([(mz1.T @ aU).ravel(), mz1.sum(0), (ad.T @ aH1).ravel(), ad.sum(0),
+                          aH2.T @ ag, [ag.sum()]])
+    return mag
+
+
+def test_bf16_operand_gradient_stays_within_the_rounding_bound():
+    """With the operands of the two 128-wide products rounded to BF16, every
+    gradient entry moves by at most a few BF16 unit roundoffs of the summed
+    term magnitudes (first-order propagation of relative 2^-8 perturbations
+    of h1 and dz2 through two products), and does move (the rounding is
+    applied)."""
+    rng = np.random.default_rng(8)
+    p = mr.bf16_round(mr.init_params(8) + 0.05 * rng.standard_normal(mr.NPARAM))
+    X = rng.normal(size=(50, 3))
+    T = rng.normal(3.0, 4.0, size=50)
+    l0, g0 = mr.loss_and_grad(p, X, T, NORM)
+    l1, g1 = mr.loss_and_grad(p, X, T, NORM, bf16_products=True)
+    mag = _term_magnitudes(p, X, T)
+    d = np.abs(g1 - g0)
+    assert np.all(d <= 6 * 2.0 ** -8 * mag + 1e-15), np.max(d / (mag + 1e-300))
+    assert np.max(d / (mag + 1e-300)) > 2.0 ** -14
+    assert abs(l1 - l0) <= 4 * 2.0 ** -8 * max(l0, 1e-12)
+    # the default is the exact chain rule
+    assert np.array_equal(mr.loss_and_grad(p, X, T, NORM, bf16_products=False)[1], g0)
