@@ -339,6 +339,24 @@ hodlr_status hodlr_mlp_train_step_dev(float *d_master, uint16_t *d_wbf16, float 
                                       const double *d_logtheta, const double *d_target,
                                       const int32_t *d_index, int32_t batch, void *d_work,
                                       size_t work_bytes, float *d_loss, void *stream);
+/* The training step above without a workspace argument, for callers that
+ * cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc): the per-tile gradient slots live in a
+ * fixed array of the library in device memory (one per GPU, held until the
+ * process ends; 4 * 17154 * ceil(HODLR_MLP_NOALLOC_MAX_BATCH / 32) bytes, about
+ * 8.4 MiB).  batch must be <= HODLR_MLP_NOALLOC_MAX_BATCH (EINVAL otherwise).
+ * The call allocates nothing; every slot it reads is written earlier in the
+ * same call.  Calls on one GPU share that array, so calls that overlap in time
+ * on one GPU (different streams or threads) race and give wrong results;
+ * serialize them.  Results equal hodlr_mlp_train_step_dev's.  The first call
+ * on a device looks up the array's device address (EDEVICE if that fails). */
+#define HODLR_MLP_NOALLOC_MAX_BATCH 4096
+hodlr_status hodlr_mlp_train_step_noalloc_dev(float *d_master, uint16_t *d_wbf16, float *d_m,
+                                              float *d_v, int32_t step, float lr,
+                                              const hodlr_mlp_norm *norm,
+                                              const double *d_logtheta, const double *d_target,
+                                              const int32_t *d_index, int32_t batch,
+                                              float *d_loss, void *stream);
 /* `epochs` passes over n training pairs in minibatches of `batch` (the last
  * one of an epoch may be smaller), epoch e visiting rows in the order
  * d_perm[e*n .. e*n+n-1]; Adam step numbers start at step0.  d_loss_hist

@@ -21,7 +21,7 @@ __all__ = [
     "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
     "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
-    "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
+    "mlp_train_step_noalloc_dev", "MLP_NOALLOC_MAX_BATCH", "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
     "gp_sample_dev", "Tune", "plan_tuned_create", "autotune", "tune_lookup",
 ]
 
@@ -37,9 +37,10 @@ EXPORTED = [
     "hodlr_mlp_forward_dev", "hodlr_mlp_grad_dev", "hodlr_mlp_train_step_dev",
     "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
     "hodlr_sampler_workspace_size", "gp_sample_dev", "hodlr_plan_tuned_create", "hodlr_autotune",
-    "hodlr_tune_lookup", "hodlr_profile_select", "hodlr_predict",
+    "hodlr_tune_lookup", "hodlr_profile_select", "hodlr_predict", "hodlr_mlp_train_step_noalloc_dev",
 ]
 MLP_NPARAM = 17153
+MLP_NOALLOC_MAX_BATCH = 4096
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhodlrgp.so")
@@ -206,6 +207,9 @@ def lib():
     L.hodlr_mlp_train_step_dev.restype = st
     L.hodlr_mlp_train_step_dev.argtypes = [vp, vp, vp, vp, i32, f32, nrm, vp, vp, vp, i32, vp,
                                            ctypes.c_size_t, vp, vp]
+    L.hodlr_mlp_train_step_noalloc_dev.restype = st
+    L.hodlr_mlp_train_step_noalloc_dev.argtypes = [vp, vp, vp, vp, i32, f32, nrm, vp, vp, vp, i32,
+                                                   vp, vp]
     L.hodlr_mlp_fit_dev.restype = st
     L.hodlr_mlp_fit_dev.argtypes = [vp, vp, vp, vp, i32, f32, nrm, vp, vp, i32, vp, i32, i32, vp,
                                     ctypes.c_size_t, vp, vp]
@@ -534,6 +538,16 @@ def mlp_train_step_dev(d_master, d_wbf16, d_m, d_v, step: int, lr: float, norm: 
                                           _ptr(d_logtheta), _ptr(d_target), _ptr(d_index),
                                           int(batch), _ptr(work), int(work_bytes), _ptr(d_loss),
                                           _stream(stream)))
+
+
+def mlp_train_step_noalloc_dev(d_master, d_wbf16, d_m, d_v, step: int, lr: float, norm: MlpNorm,
+                               d_logtheta, d_target, batch: int, d_loss=None, stream=None,
+                               d_index=None):
+    _check(lib().hodlr_mlp_train_step_noalloc_dev(_ptr(d_master), _ptr(d_wbf16), _ptr(d_m),
+                                                  _ptr(d_v), int(step), float(lr),
+                                                  ctypes.byref(norm), _ptr(d_logtheta),
+                                                  _ptr(d_target), _ptr(d_index), int(batch),
+                                                  _ptr(d_loss), _stream(stream)))
 
 
 def mlp_fit_dev(d_master, d_wbf16, d_m, d_v, step0: int, lr: float, norm: MlpNorm, d_logtheta,

@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include <string>
 
@@ -358,6 +359,38 @@ hodlr_status grad_pass(const uint16_t *wb, const hodlr_mlp_norm *norm, const dou
     return launch_status();
 }
 
+// ----------------------------------------------- allocation-free train step
+// Per-tile gradient slots for callers that cannot allocate: a fixed array in
+// device memory, one copy per GPU for the life of the process.  In host code
+// the array's name only stands for it; kernels receive the device address
+// that hipGetSymbolAddress returns, taken once per device (with that device
+// current) on the entry point's first call there.
+constexpr int NOALLOC_MAX_BATCH = HODLR_MLP_NOALLOC_MAX_BATCH;
+constexpr size_t NOALLOC_FLOATS = (size_t)((NOALLOC_MAX_BATCH + TS - 1) / TS) * (NPARAM + 1);
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+hodlr_status scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return hodlr::report(HODLR_EDEVICE, "no current device for the network scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hodlr::report(HODLR_EDEVICE, std::string("address of the network scratch: ") +
+                                                    hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HODLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -432,6 +465,24 @@ hodlr_status hodlr_mlp_train_step_dev(float *d_master, uint16_t *d_wbf16, float 
                        (const float *)d_work, ntiles(batch), (int)batch, d_master, d_wbf16, d_m,
                        d_v, 1, (int)step, lr, (float *)nullptr, d_loss);
     return launch_status();
+}
+
+hodlr_status hodlr_mlp_train_step_noalloc_dev(float *d_master, uint16_t *d_wbf16, float *d_m,
+                                              float *d_v, int32_t step, float lr,
+                                              const hodlr_mlp_norm *norm,
+                                              const double *d_logtheta, const double *d_target,
+                                              const int32_t *d_index, int32_t batch,
+                                              float *d_loss, void *stream)
+{
+    if (batch < 1 || batch > NOALLOC_MAX_BATCH)
+        return bad("batch must be in [1, HODLR_MLP_NOALLOC_MAX_BATCH]");
+    void *work = nullptr;
+    if (hodlr_status st = scratch_address(&work))
+        return st;
+    // every slot the update kernel reads is written by this call's tile kernel
+    return hodlr_mlp_train_step_dev(d_master, d_wbf16, d_m, d_v, step, lr, norm, d_logtheta,
+                                    d_target, d_index, batch, work,
+                                    sizeof(float) * NOALLOC_FLOATS, d_loss, stream);
 }
 
 hodlr_status hodlr_mlp_fit_dev(float *d_master, uint16_t *d_wbf16, float *d_m, float *d_v,
