@@ -155,7 +155,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--n", type=int, default=None,
+                    help="problem size (default: 2^20; 2^22 for se2d)")
+    ap.add_argument("--max-rank", type=int, default=None, help="rank cap (se2d; default 64)")
+    ap.add_argument("--leaf", type=int, default=None, help="leaf size (se2d; default 256)")
     ap.add_argument("--workload", default="matern1d",
                     choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d",
                              "predict"],
@@ -175,6 +178,8 @@ def main():
                          "(matern1d, batched_theta, ragged)")
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
+    if args.n is None and args.workload != "se2d":
+        args.n = 1 << 20
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each GPU would own a subtree; only the top levels would exchange "
@@ -568,76 +573,117 @@ def bench_learned(args, torch, H, wl, dev):
 
 
 def bench_se2d(args, torch, H, wl, dev):
-    """The 2-D configuration: SE l = 0.05, sigma^2 = 1e-2, ranks capped at 64,
-    points ~ U([0,s]^2) at the density of n = 2^22 on the unit square (n from
-    --n, default 2^20), k-d ordered, leaf 128.  Timed: the device likelihood
-    (factor + log det + one solve through the factor).  Once, untimed in the
-    rate: the refined solve of the host entry point (mixed form: refinement
-    against the exact FP64 product to 1e-10) with its residual and time."""
-    n = args.n
+    """The 2-D configuration: n = 2^22 points ~ U([0,1]^2) (smaller --n keeps
+    the density on a sub-square), k-d ordered, SE a = 1, l = 0.05,
+    sigma^2 = 1e-2, leaf 256, off-diagonal ranks capped at --max-rank (64 as
+    configured; a larger cap is the measured-cap variant), tolerance 1e-10.
+    Timed: the device likelihood (compression, factorization, log det and one
+    solve through the factor) with the ordered points resident in HBM.
+    Untimed, beside it: the relative residual ||y - C z|| / ||y|| of the
+    factor's solve z with C applied exactly (one O(n^2) FP64 product on the
+    GPU, whose time is the cost of one refinement step), and for the level
+    products on FP64 MFMA their achieved rate against the matrix peak."""
+    n = args.n or (1 << 22)
+    cap = args.max_rank if args.max_rank is not None else 64
+    leaf = args.leaf or 256
     p = wl.se2d(n)
-    leaf = 128
     mixed = args.precision == "mixed"
     prec = H.MIXED if mixed else H.FP64
+    t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, leaf)
-    xs, ys = p.x[perm], p.y[perm]
-    plan = H.Plan(n, 2, leaf, H.Opts(max_rank=64, precision=prec))
+    t_order = time.perf_counter() - t0
+    xs = np.ascontiguousarray(p.x[perm])
+    ys = np.ascontiguousarray(p.y[perm])
+    plan = H.Plan(n, 2, leaf, H.Opts(max_rank=cap, precision=prec))
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
-    d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
+    d_y = torch.from_numpy(ys).to(dev)
     work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     out = torch.zeros(8, dtype=torch.float64, device=dev)
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
 
     def step():
         H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
-                        plan.workspace_bytes, None, out)
+                        plan.workspace_bytes, stream, out, z)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    config = {"workload": "se2d_n%d_leaf%d_cap%d%s" % (n, leaf, cap, "_mixed" if mixed else ""),
+              "n": n, "dim": 2, "kernel": "se", "theta": list(p.theta), "sigma2": p.sigma2,
+              "side": p.meta["side"], "leaf": leaf, "max_rank": cap, "tol": p.tol,
+              "precision": args.precision, "workspace_bytes": plan.workspace_bytes}
+    res = {"metric": "GP log-likelihoods/s, 2-D SE (n=2^22 unit square at full size)",
+           "unit": "likelihoods/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64", "data": "synthetic",
+           "config": config, "ordering_s": t_order}
+    try:
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    except H.HodlrError as e:
+        # the configured cap can be too coarse for this kernel and noise level:
+        # the library then reports a coupling matrix that is not positive
+        res.update({"value": None, "ms_per_step": None, "status": e.name, "error": str(e)})
+        print(json.dumps(res), flush=True)
+        return
     loglik, logdet, quad = out[:3].cpu().tolist()
+    info = plan.info()
     # per-stage breakdown in a pass of its own (every launch timed)
     H.profile_select(None)
     H.profile_enable(True)
-    for _ in range(args.steps):
-        step()
+    step()
     torch.cuda.synchronize()
-    breakdown = H.profile_read()
+    stages = {k: v for k, v in H.profile_read().items() if v[1] > 0}
     H.profile_enable(False)
+    # exact residual of the factor's solve
+    cz = torch.empty_like(z)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    f = H.hodlr_build(xs, p.kernel, p.theta, p.sigma2, leaf, p.tol,
-                      H.Opts(max_rank=64, precision=prec, presorted=1, max_refine=40))
-    t_build = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    refined = {}
-    try:
-        f.solve(ys)
-        refined["status"] = "OK"
-    except H.HodlrError as e:
-        refined["status"] = e.name
-    refined["seconds"] = time.perf_counter() - t2
-    info = f.info()
-    f.free()
-    refined.update({"refine_steps": info["refine_steps"],
-                    "relative_residual": info["refine_residual"],
-                    "build_seconds": t_build})
-    res = {"metric": "GP log-likelihoods/s, 2-D SE (ranks capped at 64)",
-           "value": args.steps / el, "unit": "likelihoods/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64", "data": "synthetic",
-           "config": {"workload": "se2d_n%d_leaf128_cap64%s" % (n, "_mixed" if mixed else ""),
-                      "n": n, "dim": 2, "kernel": "se", "l": 0.05, "sigma2": 1e-2,
-                      "side": p.meta["side"], "leaf": leaf, "max_rank": 64, "tol": p.tol,
-                      "precision": args.precision},
-           "ranks": {"rank_max": info["rank_max"], "capped_blocks": info["capped_blocks"]},
-           "stage_ms_per_step": {k: v[0] / args.steps for k, v in breakdown.items() if v[1] > 0},
-           "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
-           "refined_solve": refined if mixed else None}
+    H.hodlr_matvec_dev(n, 2, d_x, p.kernel, p.theta, p.sigma2, z, cz, stream)
+    torch.cuda.synchronize()
+    t_mv = time.perf_counter() - t1
+    resid = float(torch.linalg.vector_norm(d_y - cz) / torch.linalg.vector_norm(d_y))
+    L = info["levels"]
+    r = [0] + [int(v) for v in info["rank_max"][:L]]
+    cnt = [1]
+    for j in range(1, L + 1):
+        cnt.append(cnt[-1] + r[j])
+    leaf_sizes = np.diff(np.linspace(0, n, (1 << L) + 1).round()).astype(int)
+    model = kernel_model(n, leaf_sizes, r, cnt, esz=4 if mixed else 8)
+    mfma = {}
+    for k in ("level_reduce", "level_update", "leaf_factor"):
+        if k in stages and k in model:
+            fl, by = model[k]
+            ms = stages[k][0]
+            ach = fl / (ms / 1e3) / 1e12
+            mfma[k] = {"achieved": ach, "frac": ach / PEAK["alu_fp64"], "ms": ms,
+                       "launches": stages[k][1], "flops": fl, "bytes": by}
+    dom = max(("level_reduce", "level_update", "leaf_factor"),
+              key=lambda k: mfma[k]["ms"] if k in mfma else -1.0)
+    roofline = None
+    if dom in mfma:
+        d = mfma[dom]
+        roofline = {"bound": "mfma", "achieved": d["achieved"], "peak": PEAK["alu_fp64"],
+                    "unit": "TFLOP/s", "frac": d["frac"], "traffic": None, "kernel": dom,
+                    "dtype": "fp64", "avg_launch_ms": d["ms"] / d["launches"],
+                    "algorithmic_per_call": {"flops": d["flops"] / d["launches"],
+                                             "bytes": d["bytes"] / d["launches"]}}
+    res.update({"value": args.steps / el, "ms_per_step": el / args.steps * 1e3, "status": "OK",
+                "ranks": {"rank_max": info["rank_max"], "rank_mean": info["rank_mean"],
+                          "capped_blocks": info["capped_blocks"]},
+                "roofline": roofline, "mfma_level_kernels": mfma,
+                "stage_ms_per_step": {k: v[0] for k, v in stages.items()},
+                "stage_launches_per_step": {k: v[1] for k, v in stages.items()},
+                "result": {"loglik": loglik, "logdet": logdet, "quad": quad},
+                "oracle_check": {"relative_residual": resid, "exact_product_seconds": t_mv,
+                                 "note": "||y - C z|| / ||y|| for the factor's unrefined solve "
+                                         "z, C applied entry by entry in FP64 on the GPU "
+                                         "(hodlr_matvec_dev); no dense oracle exists at this "
+                                         "size"}})
     print(json.dumps(res), flush=True)
 
 

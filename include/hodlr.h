@@ -75,8 +75,10 @@ typedef enum {
 enum { HODLR_FP64 = 0, HODLR_MIXED = 1 };
 
 typedef struct {
-    int32_t max_rank;    /* per off-diagonal block rank cap (default 64); a hit cap is
-                            counted in hodlr_info, not an error                       */
+    int32_t max_rank;    /* per off-diagonal block rank cap in [0, 512] (default 64); a
+                            hit cap is counted in hodlr_info, not an error.  Levels
+                            whose rank is above 64 keep their coupling matrices in
+                            device memory instead of LDS (slower node solves)        */
     int32_t precision;   /* HODLR_FP64 (default) or HODLR_MIXED: the applied bases
                             W~ = (block inverses) W and the solve vector stored in
                             FP32 (updates computed in FP64 registers, rounded on
@@ -203,7 +205,7 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
                                hodlr_plan *out);
 void hodlr_plan_destroy(hodlr_plan p);
 
-/* Launch shape chosen by the autotuner: the leaf size (any leaf <= 128) and
+/* Launch shape chosen by the autotuner: the leaf size (any leaf <= 256) and
  * the level stage's tiles, rows per chunk (256, 512 or 1024), columns per
  * reduction step (4 or 8) and columns per reduction work-group (8 or 64).  The method's result does not depend on the tiles;
  * the leaf size changes the tree (and so the approximation) within the
@@ -240,6 +242,12 @@ hodlr_status hodlr_tune_lookup(int64_t n, int32_t dim, hodlr_kernel k, int32_t p
 
 /* Bytes of device workspace one gp_loglik_dev call needs (256-byte aligned).*/
 hodlr_status hodlr_plan_workspace_size(hodlr_plan p, size_t *bytes);
+
+/* The plan's tree (n, dim, levels, largest leaf; device_bytes = workspace plus
+ * tables) and the block ranks of the last gp_loglik_dev call on it that
+ * completed (per-depth maximum and mean, capped count; zeros before the
+ * first).  Errors: EINVAL (NULL).                                            */
+hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out);
 
 /* Log-likelihood with every input already resident on the device.
  * d_x: tree-ordered points, coordinate-major (d_x[d*n + i]); d_y: n doubles

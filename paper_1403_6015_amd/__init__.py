@@ -38,6 +38,7 @@ EXPORTED = [
     "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
     "hodlr_sampler_workspace_size", "gp_sample_dev", "hodlr_plan_tuned_create", "hodlr_autotune",
     "hodlr_tune_lookup", "hodlr_profile_select", "hodlr_predict", "hodlr_mlp_train_step_noalloc_dev",
+    "hodlr_plan_info",
 ]
 MLP_NPARAM = 17153
 MLP_NOALLOC_MAX_BATCH = 4096
@@ -170,6 +171,8 @@ def lib():
                             ctypes.c_double, ctypes.POINTER(Opts), dp, dp, dp]
     L.hodlr_info.restype = st
     L.hodlr_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.hodlr_plan_info.restype = st
+    L.hodlr_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.hodlr_free.restype = None
     L.hodlr_free.argtypes = [vp]
     L.hodlr_plan_create.restype = st
@@ -394,15 +397,19 @@ def gp_loglik(x, y, kernel: int, theta, sigma2: float, leaf: int, tol: float,
     return ll.value, ld.value, q.value
 
 
-def hodlr_info(f: Factor) -> dict:
-    I = Info()
-    _check(lib().hodlr_info(f.handle, ctypes.byref(I)))
+def _info_dict(I) -> dict:
     L = I.levels
     return {"n": I.n, "dim": I.dim, "levels": L, "leaf_max": I.leaf_max,
             "max_rank_used": I.max_rank_used, "capped_blocks": I.capped_blocks,
             "rank_max": list(I.rank_max[:L]), "rank_mean": list(I.rank_mean[:L]),
             "device_bytes": I.device_bytes, "precision": I.precision,
             "refine_steps": I.refine_steps, "refine_residual": I.refine_residual}
+
+
+def hodlr_info(f: Factor) -> dict:
+    I = Info()
+    _check(lib().hodlr_info(f.handle, ctypes.byref(I)))
+    return _info_dict(I)
 
 
 def hodlr_free(f: Factor):
@@ -434,6 +441,13 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def info(self) -> dict:
+        """hodlr_plan_info: the tree and the ranks of the last completed
+        gp_loglik_dev call on this plan."""
+        I = Info()
+        _check(lib().hodlr_plan_info(self._h, ctypes.byref(I)))
+        return _info_dict(I)
 
     def batch_workspace_bytes(self, nitems: int) -> int:
         sz = ctypes.c_size_t()

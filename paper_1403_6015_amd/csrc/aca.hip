@@ -128,7 +128,9 @@ struct SmallArgs {
     int *status;        // per node AcaDone
 };
 
-template <int TH, int MAXS>
+// RB bounds the rank (LDS arrays); a plan with max_rank <= RMAX_LDS uses the
+// narrow variant, whose LDS footprint keeps more work-groups per CU
+template <int TH, int MAXS, int RB>
 __global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
 {
     const AcaArgs &A = S.a;
@@ -141,8 +143,8 @@ __global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
     double *__restrict__ W = A.W;
     __shared__ double rv[4], rs[4], red[4];
     __shared__ int64_t ri[4];
-    __shared__ double sfix[RMAX_ABS];
-    __shared__ double vdot[RMAX_ABS];
+    __shared__ double sfix[RB];
+    __shared__ double vdot[RB];
     __shared__ unsigned char used[MAXS];
     const int64_t full = na < nb ? na : nb;
     const int cap = (int)(A.cap < full ? A.cap : full);
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(TH) void aca_small_kernel(SmallArgs S)
 // every internal node of every batch item (item = blockIdx.z).  Used rows are
 // kept as a list in LDS; the dots with earlier terms re-read the panel
 // entries the same thread wrote.
+template <int RB>
 __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, BatchArgs B, int *rank0,
                                                                int *status0)
 {
@@ -291,9 +294,10 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
     const int64_t col0 = A0.cofa[depth_of_node(h) + 1];
     __shared__ double rv[4], rs[4], red[4];
     __shared__ int64_t ri[4];
-    __shared__ double sfix[RMAX_ABS];
-    __shared__ double vdot[RMAX_ABS];
-    __shared__ int usedl[USED_MAX];
+    constexpr int UM = used_max(RB);
+    __shared__ double sfix[RB];
+    __shared__ double vdot[RB];
+    __shared__ int usedl[UM];
     const int64_t full = na < nb ? na : nb;
     const int cap = (int)(A0.cap < full ? A0.cap : full);
     const bool usercap = A0.cap < full;
@@ -319,13 +323,13 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
             }
         }
         block_argmax<ACA_THREADS / 64>(bv, bi, bs, rv, ri, rs);
-        if (tid == 0 && nused < USED_MAX)
+        if (tid == 0 && nused < UM)
             usedl[nused] = (int)istar;
         ++nused;
         __syncthreads();
         if (bv == 0.0) {
             ++zeros;
-            if (zeros > ZERO_RETRY || nused >= na || nused >= USED_MAX) {
+            if (zeros > ZERO_RETRY || nused >= na || nused >= UM) {
                 done = ACA_EXHAUSTED;
             } else {
                 int64_t c = na - 1;
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
             W[(col0 + k) * n + s + i] = a;
             sq += a * a;
             bool elig = true;
-            for (int q = 0; q < nused && q < USED_MAX; ++q)
+            for (int q = 0; q < nused && q < UM; ++q)
                 elig = elig && (usedl[q] != (int)i);
             if (elig && fabs(a) > bv) {
                 bv = fabs(a);
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_block_kernel(AcaArgs A0, Batc
             done = ACA_CONVERGED;
         else if (k >= cap)
             done = usercap ? ACA_CAPPED : ACA_CONVERGED;
-        else if (nused >= na || nused >= USED_MAX || bv < 0.0)
+        else if (nused >= na || nused >= UM || bv < 0.0)
             done = ACA_EXHAUSTED;
         else
             istar = bi;
@@ -487,8 +491,11 @@ void run_aca_batched(Pipeline &P)
     int *status = wsp<int>(P, P.lay.aca_status);
     {
         ProfScope ps(s, PS_ACA_SMALL);
-        aca_block_kernel<<<dim3((unsigned)p.nint, 1, P.nitems), ACA_THREADS, 0, s>>>(A, P.batch, rank,
-                                                                                 status);
+        const dim3 grid((unsigned)p.nint, 1, P.nitems);
+        if (p.cap <= RMAX_LDS)
+            aca_block_kernel<RMAX_LDS><<<grid, ACA_THREADS, 0, s>>>(A, P.batch, rank, status);
+        else
+            aca_block_kernel<RMAX_ABS><<<grid, ACA_THREADS, 0, s>>>(A, P.batch, rank, status);
     }
     {
         ProfScope ps(s, PS_ACA_MISC);
@@ -676,10 +683,10 @@ __device__ __forceinline__ void residual_terms(const double *__restrict__ W, int
 
 // sdot[wave][l] = this wave's part of sum_g val_g W[l][g] for l < k, RT terms
 // at a time (their loads and wave sums independent of each other)
-template <int EPT>
+template <int EPT, int RB>
 __device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t n, int64_t col0, int k,
                                           const Chunk &ch, int tid, const double (&val)[EPT],
-                                          double (*sdot)[RMAX_ABS + 1])
+                                          double (*sdot)[RB + 1])
 {
     constexpr int RT = terms_per_round<EPT>();
     const int lane = tid & 63, wid = tid >> 6;
@@ -706,7 +713,7 @@ __device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t 
     }
 }
 
-template <bool ROW, int EPT>
+template <bool ROW, int EPT, int RB>
 __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
 {
     const AcaArgs &A = B.a;
@@ -716,11 +723,14 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     __shared__ double rv[4], rs[4];
     __shared__ int64_t ri[4];
-    __shared__ double sfix[RMAX_ABS];
-    __shared__ double dots[RMAX_ABS + 1];
-    __shared__ double sdot[4][RMAX_ABS + 1];
+    // the block's used-row list lives in HBM with room for RMAX_ABS terms; a
+    // block capped at RB needs at most used_max(RB) of its entries
+    constexpr int UM = used_max(RB);
+    __shared__ double sfix[RB];
+    __shared__ double dots[RB + 1];
+    __shared__ double sdot[4][RB + 1];
     __shared__ double sred[ACA_THREADS / 64][RR_REG + 1];
-    __shared__ int sused[USED_MAX];
+    __shared__ int sused[UM];
     BigState t = B.sin[b];
     const int64_t s = A.start[h], e = A.end[h], m = s + (e - s) / 2;
     const int64_t na = m - s, n = A.n;
@@ -752,7 +762,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
                 t.done = ACA_CONVERGED;
             else if (t.k >= t.cap)
                 t.done = t.usercap ? ACA_CAPPED : ACA_CONVERGED;
-            else if (t.nused >= na || t.nused >= USED_MAX || bv < 0.0)
+            else if (t.nused >= na || t.nused >= UM || bv < 0.0)
                 t.done = ACA_EXHAUSTED;
             else
                 t.istar = (int)(bi - s);
@@ -793,7 +803,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
                 }
             }
         }
-        term_dots<EPT>(W, n, col0, k, ch, tid, val, sdot);
+        term_dots<EPT, RB>(W, n, col0, k, ch, tid, val, sdot);
         sq = wave_sum(sq);
         if (lane == 0)
             sdot[wid][k] = sq;
@@ -808,7 +818,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         for (int l = tid; l < k; l += ACA_THREADS)
             rec[4 + l] = (sdot[0][l] + sdot[1][l]) + (sdot[2][l] + sdot[3][l]);
         if (lead && tid == 0) {
-            if (t.nused < USED_MAX)
+            if (t.nused < UM)
                 used[t.nused] = t.istar;
             t.nused += 1;
             t.phase = BP_ROWDONE;
@@ -820,14 +830,14 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     double bv, bs;
     int64_t bi;
     reduce_records(prec, pn, B.pw, t.k, dots, bv, bi, bs, rv, ri, rs, sred);
-    const int nu = t.nused < USED_MAX ? t.nused : USED_MAX;
+    const int nu = t.nused < UM ? t.nused : UM;
     for (int q = tid; q < nu; q += ACA_THREADS)
         sused[q] = used[q];
     __syncthreads();
     if (bv == 0.0) {
         if (lead && tid == 0) {
             t.zeros += 1;
-            if (t.zeros > ZERO_RETRY || t.nused >= na || t.nused >= USED_MAX) {
+            if (t.zeros > ZERO_RETRY || t.nused >= na || t.nused >= UM) {
                 t.done = ACA_EXHAUSTED;
                 atomicAdd(B.ndone, 1);
             } else {
@@ -883,7 +893,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
             }
         }
     }
-    term_dots<EPT>(W, n, col0, k, ch, tid, val, sdot);
+    term_dots<EPT, RB>(W, n, col0, k, ch, tid, val, sdot);
     sq = wave_sum(sq);
     if (lane == 0)
         sdot[wid][k] = sq;
@@ -1093,6 +1103,26 @@ struct SideJoin {
     }
 };
 
+// one pass over the large blocks' chunks, specialized on the chunk length and
+// on the rank bound of the LDS arrays
+template <bool ROW>
+static void big_pass(const Plan &p, int nchunk, hipStream_t s, const BigArgs &B)
+{
+    constexpr int E1 = ACA_CHUNK_1D / ACA_THREADS, EN = ACA_CHUNK_ND / ACA_THREADS;
+    const bool narrow = p.cap <= RMAX_LDS;
+    if (p.aca_chunk == ACA_CHUNK_1D) {
+        if (narrow)
+            aca_big_pass_kernel<ROW, E1, RMAX_LDS><<<nchunk, ACA_THREADS, 0, s>>>(B);
+        else
+            aca_big_pass_kernel<ROW, E1, RMAX_ABS><<<nchunk, ACA_THREADS, 0, s>>>(B);
+    } else {
+        if (narrow)
+            aca_big_pass_kernel<ROW, EN, RMAX_LDS><<<nchunk, ACA_THREADS, 0, s>>>(B);
+        else
+            aca_big_pass_kernel<ROW, EN, RMAX_ABS><<<nchunk, ACA_THREADS, 0, s>>>(B);
+    }
+}
+
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -1165,14 +1195,23 @@ void run_aca(Pipeline &P)
             // blocks with both sides <= ACA_TINY (listed last) run on one wave,
             // with wave-level reductions only
             const int nwide = p.aca_small_wide;
+            const bool narrow = p.cap <= RMAX_LDS;
             if (nwide > 0) {
-                aca_small_kernel<ACA_SMALL_TH, ACA_SMALL><<<(unsigned)nwide, ACA_SMALL_TH, 0, ss>>>(S);
+                if (narrow)
+                    aca_small_kernel<ACA_SMALL_TH, ACA_SMALL, RMAX_LDS>
+                        <<<(unsigned)nwide, ACA_SMALL_TH, 0, ss>>>(S);
+                else
+                    aca_small_kernel<ACA_SMALL_TH, ACA_SMALL, RMAX_ABS>
+                        <<<(unsigned)nwide, ACA_SMALL_TH, 0, ss>>>(S);
                 HIP_TRY(hipGetLastError());
             }
             const int ntiny = (int)p.aca_small.size() - nwide;
             if (ntiny > 0) {
                 S.nodes = p.d_aca_small + nwide;
-                aca_small_kernel<64, ACA_TINY><<<(unsigned)ntiny, 64, 0, ss>>>(S);
+                if (narrow)
+                    aca_small_kernel<64, ACA_TINY, RMAX_LDS><<<(unsigned)ntiny, 64, 0, ss>>>(S);
+                else
+                    aca_small_kernel<64, ACA_TINY, RMAX_ABS><<<(unsigned)ntiny, 64, 0, ss>>>(S);
                 HIP_TRY(hipGetLastError());
             }
         }
@@ -1221,17 +1260,11 @@ void run_aca(Pipeline &P)
         for (; it < max_iter; ++it) {
             {
                 ProfScope ps(s, PS_ACA_ROW);
-                if (p.aca_chunk == ACA_CHUNK_1D)
-                    aca_big_pass_kernel<true, ACA_CHUNK_1D / ACA_THREADS><<<nrow, ACA_THREADS, 0, s>>>(R);
-                else
-                    aca_big_pass_kernel<true, ACA_CHUNK_ND / ACA_THREADS><<<nrow, ACA_THREADS, 0, s>>>(R);
+                big_pass<true>(p, nrow, s, R);
             }
             {
                 ProfScope ps(s, PS_ACA_COL);
-                if (p.aca_chunk == ACA_CHUNK_1D)
-                    aca_big_pass_kernel<false, ACA_CHUNK_1D / ACA_THREADS><<<ncol, ACA_THREADS, 0, s>>>(C);
-                else
-                    aca_big_pass_kernel<false, ACA_CHUNK_ND / ACA_THREADS><<<ncol, ACA_THREADS, 0, s>>>(C);
+                big_pass<false>(p, ncol, s, C);
             }
             HIP_TRY(hipGetLastError());
             // A converged block is counted by the row pass that absorbs its last

@@ -700,11 +700,10 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
         auto p = std::make_unique<hodlr_plan_s>();
         p->opts = o;
         plan_build(p->plan, n, dim, leaf, &o);
-        if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
+        if (p->plan.leafmax > LEAF_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
-        p->reserve_host();
         *out = p.release();
         return HODLR_OK;
     });
@@ -726,11 +725,10 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
         p->opts = o;
         plan_build(p->plan, n, dim, tune->leaf, &o, tune->level_rows, tune->reduce_cols,
                    tune->reduce_group);
-        if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
+        if (p->plan.leafmax > LEAF_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
-        p->reserve_host();
         *out = p.release();
         return HODLR_OK;
     });
@@ -775,8 +773,44 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         if (d_z)
             run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
         raise_status(read_status(P));
+        {
+            std::lock_guard<std::mutex> lk(p->last_mu);
+            p->last_ranks = P.ranks;
+            p->last_capped = P.capped;
+        }
         return HODLR_OK;
     });
+}
+
+hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
+{
+    if (!p || !out)
+        return fail(HODLR_EINVAL, "NULL argument");
+    hodlr_info_t I;
+    std::memset(&I, 0, sizeof(I));
+    I.n = p->plan.n;
+    I.dim = p->plan.dim;
+    I.levels = p->plan.L;
+    I.leaf_max = p->plan.leafmax;
+    I.precision = p->opts.precision;
+    I.device_bytes = (int64_t)p->lay.total + (int64_t)p->plan.dev_tables_bytes;
+    std::lock_guard<std::mutex> lk(p->last_mu);
+    I.capped_blocks = p->last_capped;
+    if (!p->last_ranks.empty())
+        for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS; ++d) {
+            const int64_t h0 = p->plan.first_at(d), h1 = p->plan.first_at(d + 1);
+            int mx = 0;
+            double sum = 0;
+            for (int64_t h = h0; h < h1; ++h) {
+                mx = std::max(mx, p->last_ranks[h]);
+                sum += p->last_ranks[h];
+            }
+            I.rank_max[d] = mx;
+            I.rank_mean[d] = sum / (double)(h1 - h0);
+            I.max_rank_used = std::max(I.max_rank_used, mx);
+        }
+    *out = I;
+    return HODLR_OK;
 }
 
 }  // extern "C"
@@ -809,8 +843,8 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
         if (work_bytes < istride * (size_t)nitems)
             throw Error{HODLR_EINVAL, "workspace too small: need " +
                                           std::to_string(istride * (size_t)nitems) + " bytes"};
-        if (p->plan.leafmax > LEAF_LDS_MAX)
-            throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
+        if (p->plan.leafmax > LEAF_MAX)
+            throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         Pipeline P;
         P.plan = &p->plan;
         P.lay = p->lay;

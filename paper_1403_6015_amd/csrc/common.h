@@ -27,10 +27,13 @@ constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one w
 constexpr int ACA_TINY = 256;     // ... and on a single wave when both sides are <= this
 constexpr int ACA_THREADS = 256;
 constexpr int LVL_ROWS = 512;     // default rows per level work-group
-constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored in LDS
-constexpr int RMAX_ABS = 64;      // upper bound on max_rank (coupling matrices live in LDS)
+constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored wholly in LDS
+constexpr int LEAF_MAX = 256;     // larger leaves (up to this) keep their off-diagonal half in HBM
+constexpr int RMAX_ABS = 512;     // upper bound on max_rank
+constexpr int RMAX_LDS = 64;      // ranks up to this: coupling matrices in LDS, narrow kernels
 // rows a block may try as pivots: every accepted term can follow ZERO_RETRY zero rows
-constexpr int USED_MAX = (RMAX_ABS + 1) * (ZERO_RETRY + 1) + 2;
+constexpr int used_max(int rb) { return (rb + 1) * (ZERO_RETRY + 1) + 2; }
+constexpr int USED_MAX = used_max(RMAX_ABS);
 
 enum AcaDone { ACA_ACTIVE = 0, ACA_CONVERGED = 1, ACA_CAPPED = 2, ACA_EXHAUSTED = 3 };
 
@@ -296,7 +299,7 @@ struct Plan {
 
 // Workspace layout (byte offsets into one device buffer).
 struct Layout {
-    size_t W, Xt, G;
+    size_t W, Xt, G, L21;
     size_t aca_state, aca_used, aca_vdots, aca_part, aca_status;
     size_t rank, leaf_ld, node_ld;
     size_t lvl_part, Tbuf, Sbuf, small;

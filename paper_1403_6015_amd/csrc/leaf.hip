@@ -31,6 +31,7 @@ struct LeafArgs {
     int64_t gstride;
     double *leaf_ld;
     int *status;
+    double *L21;            // leaves above LEAF_LDS_MAX: their off-diagonal factor tiles
     BatchArgs B;
 };
 
@@ -67,16 +68,17 @@ constexpr int LEAF_MW = LEAF_MT / 64;               // its waves
 
 __device__ __forceinline__ int tix(int I, int K) { return I * (I + 1) / 2 + K; }
 
-// acc += op(A) * B, op(A) = A or A^T
-template <bool TA>
+// acc += op(A) * B^T, op(A) = A or A^T, tiles column-major with leading
+// dimension LD (TLD in LDS, 16 for the tiles a large leaf keeps in HBM)
+template <bool TA, int LDA = TLD, int LDB = TLD>
 __device__ __forceinline__ d4 tile_mma(const double *A, const double *B, d4 acc)
 {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         const int k = q + 4 * kb;
-        double a = TA ? A[r * TLD + k] : A[k * TLD + r];
-        double b = B[k * TLD + r];
+        double a = TA ? A[r * LDA + k] : A[k * LDA + r];
+        double b = B[k * LDB + r];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     return acc;
@@ -195,14 +197,14 @@ __device__ __forceinline__ bool diag_factor(double *T, double *diag, double *g, 
 // acc += op(A) * B with A in LDS (op = identity or transpose) and B a tile
 // held in registers in the MFMA result layout (element t = row q + 4t),
 // which is exactly the B-operand layout of the K-slice t.  NEG subtracts.
-template <bool TA, bool NEG>
+template <bool TA, bool NEG, int LDA = TLD>
 __device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
 {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         const int k = q + 4 * kb;
-        double a = TA ? A[r * TLD + k] : A[k * TLD + r];
+        double a = TA ? A[r * LDA + k] : A[k * LDA + r];
         if (NEG)
             a = -a;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kb], acc, 0, 0, 0);
@@ -537,6 +539,347 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Leaves of LEAF_LDS_MAX + 1 .. LEAF_MAX points.  Their lower triangle (up to
+// 136 tiles) does not fit one CU's LDS, so the leaf is factored as the 2 x 2
+// block matrix [[C11, .], [C21, C22]], C11 its first 128 rows:
+//   C11 = L11 L11^T in LDS;
+//   L21 = C21 L11^{-T}: each wave evaluates tile rows of C21^T on the fly into
+//         registers, solves them with L11 and stores them in HBM (16 x 16
+//         tiles, column-major), where they stay for the right-hand sides;
+//   S = C22 - L21 L21^T in LDS, then S = L22 L22^T.
+// The right-hand sides go through L11, L21 and L22 (forward), then L22^T,
+// L21^T and L11^T (backward), 16 columns per wave in registers.
+constexpr int L21_TSZ = 256;                      // doubles per HBM tile
+constexpr int L21_TILES = NT_MAX * NT_MAX;        // tiles per leaf
+constexpr size_t L21_LEAF = (size_t)L21_TILES * L21_TSZ;
+
+// Blocked right-looking Cholesky of the nt x nt lower tiles at Gt: wave 0
+// factors the diagonal tiles (with look-ahead), all waves the panels and the
+// trailing tiles.  Tile 0 starts at row and column g0 of the leaf (for the
+// packed store and the diagonal).  Returns wave 0's non-positive-pivot flag.
+__device__ bool factor_tiles(double *Gt, double *diag, double *gout, int g0, int nt, int m)
+{
+    const int tid = threadIdx.x, wid = tid >> 6;
+    const int l = tid & 63, r = l & 15, q = l >> 4;
+    bool bad = false;
+    if (wid == 0)
+        bad = diag_factor(Gt, diag, gout, g0, m);
+    __syncthreads();
+    for (int J = 0; J < nt; ++J) {
+        for (int I = J + 1 + wid; I < nt; I += LEAF_MW) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            double *T = Gt + tix(I, J) * TSZ;
+            acc = tile_mma<false>(T, Gt + tix(J, J) * TSZ, acc);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                T[r * TLD + q + 4 * t] = acc[t];
+        }
+        __syncthreads();
+        if (J + 1 < nt) {
+            if (wid == 0) {
+                double *T = Gt + tix(J + 1, J + 1) * TSZ;
+                const double *P = Gt + tix(J + 1, J) * TSZ;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                acc = tile_mma<false>(P, P, acc);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    T[r * TLD + q + 4 * t] -= acc[t];
+                bad = diag_factor(T, diag + 16 * (J + 1), gout, g0 + 16 * (J + 1), m) || bad;
+            }
+            const int Tn = nt - 1 - J;
+            const int ntask = Tn * (Tn + 1) / 2 - 1;
+            const int n0 = ntask > 8 ? (ntask - 8) / 3 : 0;
+            const int t0 = wid == 0 ? ntask - n0 : wid - 1;
+            const int t1 = wid == 0 ? ntask : ntask - n0;
+            const int ts = wid == 0 ? 1 : LEAF_MW - 1;
+            for (int task = t0; task < t1; task += ts) {
+                int tt = task + 1;   // skip the look-ahead tile (I = K = J+1)
+                int I = 0;
+                while ((I + 1) * (I + 2) / 2 <= tt)
+                    ++I;
+                int K = tt - I * (I + 1) / 2;
+                I += J + 1;
+                K += J + 1;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                acc = tile_mma<false>(Gt + tix(I, J) * TSZ, Gt + tix(K, J) * TSZ, acc);
+                double *T = Gt + tix(I, K) * TSZ;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    T[r * TLD + q + 4 * t] -= acc[t];
+            }
+        }
+        __syncthreads();
+    }
+    return bad;
+}
+
+// C + sigma^2 I on the lower tiles of rows [off, off + mm) of the leaf (tile
+// rows and columns of that range only), identity on the padding
+__device__ void eval_region(double *Gt, const KParams &kp, const double *__restrict__ x, int64_t n,
+                            int64_t s, int off, int mm)
+{
+    const int tid = threadIdx.x;
+    const int nt = (mm + 15) >> 4;
+    const int rr = tid & 15, cc = tid >> 4;
+    double xr[3][NT_MAX], xk[3][NT_MAX];
+#pragma unroll
+    for (int I = 0; I < NT_MAX; ++I) {
+        const int i = 16 * I + rr, k = 16 * I + cc;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xr[d][I] = (d < kp.dim && i < mm) ? x[d * n + s + off + i] : 0.0;
+            xk[d][I] = (d < kp.dim && k < mm) ? x[d * n + s + off + k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int I = 0; I < NT_MAX; ++I) {
+#pragma unroll
+        for (int K = 0; K <= I; ++K) {
+            if (I < nt) {
+                const int i = 16 * I + rr, k = 16 * K + cc;
+                double v;
+                if (i < mm && k < mm && i >= k) {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double t = xr[d][I] - xk[d][K];
+                        r2 += t * t;
+                    }
+                    v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
+                    if (i == k)
+                        v += kp.sigma2 + (kp.noise ? kp.noise[s + off + i] : 0.0);
+                } else {
+                    v = (i == k) ? 1.0 : 0.0;
+                }
+                Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
+            }
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(LEAF_MT, 1) void leaf_factor_big_kernel(LeafArgs A)
+{
+    __shared__ double G1[NTRI * TSZ];   // L11 tiles (diagonal slots: L_JJ^{-1})
+    __shared__ double G2[NTRI * TSZ];   // C22, then S, then L22 tiles
+    __shared__ double s_diag[LEAF_MAX];
+    __shared__ double s_red[LEAF_MW];
+    __shared__ int s_bad;
+    static_assert(LEAF_MAX == 2 * LEAF_LDS_MAX && LEAF_MT == LEAF_MAX, "two halves, a thread per row");
+    const int tid = threadIdx.x, wid = tid >> 6;
+    const int l = tid & 63, r = l & 15, q = l >> 4;
+    const int it = blockIdx.z;   // batch item
+    const KParams kp = item_kp(A.kp, A.B, it);
+    const double *__restrict__ Wsrc = ioff(A.W, A.B, it);
+    PT *__restrict__ Xdst = ioff((PT *)A.Xt, A.B, it);
+    double *leaf_ld = ioff(A.leaf_ld, A.B, it);
+    int *status = ioff(A.status, A.B, it);
+    const double *ysrc = A.y ? A.y + it * A.B.ystride : nullptr;
+    const int64_t b = blockIdx.x;
+    const int64_t h = A.leaf0 + b;
+    const int64_t s = A.start[h];
+    const int m = (int)(A.end[h] - s);
+    const int64_t n = A.n;
+    double *L21 = ioff(A.L21, A.B, it) + b * (int64_t)L21_LEAF;
+    if (m == 0) {
+        if (tid == 0)
+            leaf_ld[b] = 0.0;
+        return;
+    }
+    const int m1 = m < LEAF_LDS_MAX ? m : LEAF_LDS_MAX, m2 = m - m1;
+    const int nt1 = (m1 + 15) >> 4, nt2 = (m2 + 15) >> 4;
+    double *gout = A.G ? A.G + b * A.gstride : nullptr;
+    eval_region(G1, kp, A.x, n, s, 0, m1);
+    if (m2 > 0)
+        eval_region(G2, kp, A.x, n, s, m1, m2);
+    __syncthreads();
+    bool bad = factor_tiles(G1, s_diag, gout, 0, nt1, m);
+    if (m2 > 0) {
+        // L21 = C21 L11^{-T}, one tile row per wave: lane (r, q) holds entry
+        // (16 J + q + 4 t, r) of C21^T, i.e. k(x_k, x_c) with k in the first
+        // half and c = 128 + 16 I2 + r
+        for (int I2 = wid; I2 < nt2; I2 += LEAF_MW) {
+            const int pc = LEAF_LDS_MAX + 16 * I2 + r;
+            const bool cok = pc < m;
+            double xc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                xc[d] = (d < kp.dim && cok) ? A.x[d * n + s + pc] : 0.0;
+            d4 X[NT_MAX];
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 16 * J + q + 4 * t;
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double u = (d < kp.dim ? A.x[d * n + s + k] : 0.0) - xc[d];
+                        r2 += u * u;
+                    }
+                    X[J][t] = cok ? kfun_r2<double>(kp.kind, kp.a2, kp.c, r2) : 0.0;
+                }
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+                fwd_step_rt(J, X, G1, NT_MAX);
+            // tile (I2, J) of L21 is the transpose of register tile J
+            double *dst = L21 + (int64_t)I2 * NT_MAX * L21_TSZ;
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    dst[J * L21_TSZ + (q + 4 * t) * 16 + r] = X[J][t];
+        }
+        __syncthreads();   // L21 written (work-group scope) before it is read
+        // S = C22 - L21 L21^T on the lower tiles of the second half
+        const int ntask = nt2 * (nt2 + 1) / 2;
+        for (int task = wid; task < ntask; task += LEAF_MW) {
+            int I = 0;
+            while ((I + 1) * (I + 2) / 2 <= task)
+                ++I;
+            const int K = task - I * (I + 1) / 2;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+                acc = tile_mma<false, 16, 16>(L21 + (int64_t)(I * NT_MAX + J) * L21_TSZ,
+                                              L21 + (int64_t)(K * NT_MAX + J) * L21_TSZ, acc);
+            double *T = G2 + tix(I, K) * TSZ;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                T[r * TLD + q + 4 * t] -= acc[t];
+        }
+        __syncthreads();
+        bad = factor_tiles(G2, s_diag + LEAF_LDS_MAX, gout, LEAF_LDS_MAX, nt2, m) || bad;
+    }
+    double lgp = tid < m ? log(s_diag[tid]) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        lgp += __shfl_xor(lgp, o, 64);
+    if (l == 0)
+        s_red[wid] = lgp;
+    if (tid == 0)
+        s_bad = 0;
+    __syncthreads();
+    if (bad)
+        s_bad = 1;   // wave 0 of each half's factorization
+    __syncthreads();
+    double lg = 0.0;
+#pragma unroll
+    for (int w = 0; w < LEAF_MW; ++w)
+        lg += s_red[w];
+    if (s_bad || !(lg == lg)) {
+        if (tid == 0) {
+            atomicOr(status, DS_NOTSPD_LEAF);
+            leaf_ld[b] = __builtin_nan("");
+        }
+        return;
+    }
+    if (tid == 0)
+        leaf_ld[b] = 2.0 * lg;
+    if (gout) {   // the off-diagonal parts of the packed factor (diagonal tiles went out above)
+        for (int idx = tid; idx < tri(m); idx += LEAF_MT) {
+            const int i = tri_row(idx), k = idx - tri(i);
+            if (i < LEAF_LDS_MAX) {
+                if ((i >> 4) != (k >> 4))
+                    gout[idx] = G1[tix(i >> 4, k >> 4) * TSZ + (k & 15) * TLD + (i & 15)];
+            } else if (k < LEAF_LDS_MAX) {
+                const int i2 = i - LEAF_LDS_MAX;
+                gout[idx] = L21[(int64_t)((i2 >> 4) * NT_MAX + (k >> 4)) * L21_TSZ + (k & 15) * 16 +
+                                (i2 & 15)];
+            } else {
+                const int i2 = i - LEAF_LDS_MAX, k2 = k - LEAF_LDS_MAX;
+                if ((i2 >> 4) != (k2 >> 4))
+                    gout[idx] = G2[tix(i2 >> 4, k2 >> 4) * TSZ + (k2 & 15) * TLD + (i2 & 15)];
+            }
+        }
+    }
+    // C_lambda^{-1} on the column list, 16 columns per wave
+    const int ngrp = (A.ncols - A.cbeg + 15) / 16;
+    for (int g = wid; g < ngrp; g += LEAF_MW) {
+        const int c0 = A.cbeg + 16 * g;
+        // the tile addresses are the same for every group: recomputed per
+        // group rather than held across the loop (256 of them would spill)
+        const double *Lg = L21;
+        asm volatile("" : "+s"(Lg));
+        d4 X1[NT_MAX], X2[NT_MAX];
+        rhs_load(X1, A, c0, ysrc, Wsrc, s, n, nt1, m1);
+        if (m2 > 0)
+            rhs_load(X2, A, c0, ysrc, Wsrc, s + LEAF_LDS_MAX, n, nt2, m2);
+#pragma unroll
+        for (int J = 0; J < NT_MAX; ++J)
+            if (J < nt1)
+                fwd_step_rt(J, X1, G1, nt1);
+        if (m2 > 0) {
+#pragma unroll
+            for (int I2 = 0; I2 < NT_MAX; ++I2)
+                if (I2 < nt2)
+#pragma unroll
+                    for (int J = 0; J < NT_MAX; ++J)
+                        X2[I2] = tile_mma_rb<false, true, 16>(
+                            Lg + (int64_t)(I2 * NT_MAX + J) * L21_TSZ, X1[J], X2[I2]);
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+                if (J < nt2)
+                    fwd_step_rt(J, X2, G2, nt2);
+            bwd_all(X2, G2, nt2);
+#pragma unroll
+            for (int J = 0; J < NT_MAX; ++J)
+#pragma unroll
+                for (int I2 = 0; I2 < NT_MAX; ++I2)
+                    if (I2 < nt2)
+                        X1[J] = tile_mma_rb<true, true, 16>(
+                            Lg + (int64_t)(I2 * NT_MAX + J) * L21_TSZ, X2[I2], X1[J]);
+        }
+        bwd_all(X1, G1, nt1);
+        rhs_store(X1, A, c0, Xdst, s, n, nt1, m1);
+        if (m2 > 0)
+            rhs_store(X2, A, c0, Xdst, s + LEAF_LDS_MAX, n, nt2, m2);
+    }
+}
+
+// z <- C_lambda^{-1} z with the stored packed factor, for leaves above
+// LEAF_LDS_MAX (the factor does not fit LDS): thread i owns row i; the
+// forward sweep goes by columns of L (one broadcast per step), the backward
+// one by rows of L (contiguous reads).
+template <typename PT>
+__global__ __launch_bounds__(LEAF_MT) void leaf_solve_big_kernel(LeafArgs A, PT *z)
+{
+    __shared__ double zs[LEAF_MAX];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t h = A.leaf0 + b;
+    const int64_t s = A.start[h];
+    const int m = (int)(A.end[h] - s);
+    if (m == 0)
+        return;
+    const double *g = A.G + b * A.gstride;
+    const bool in = tid < m;
+    double v = in ? (double)z[s + tid] : 0.0;
+    const double dii = in ? g[tri(tid) + tid] : 1.0;
+    // L y = z
+    for (int j = 0; j < m; ++j) {
+        if (tid == j)
+            zs[j] = v / dii;
+        __syncthreads();
+        if (tid > j && in)
+            v -= g[tri(tid) + j] * zs[j];
+    }
+    __syncthreads();
+    v = in ? zs[tid] : 0.0;
+    // L^T x = y
+    for (int j = m - 1; j >= 0; --j) {
+        if (tid == j)
+            zs[j] = v / dii;
+        __syncthreads();
+        if (tid < j)
+            v -= g[tri(j) + tid] * zs[j];
+    }
+    __syncthreads();
+    if (in)
+        z[s + tid] = (PT)zs[tid];
+}
+
 // the value lane l (uniform) holds, in every lane
 __device__ __forceinline__ double lane_value(double v, int l)
 {
@@ -704,6 +1047,7 @@ static LeafArgs leaf_args(Pipeline &P)
     A.gstride = (int64_t)p.leafmax * (p.leafmax + 1) / 2;
     A.leaf_ld = wsp<double>(P, P.lay.leaf_ld);
     A.status = wsp<int>(P, P.lay.status);
+    A.L21 = wsp<double>(P, P.lay.L21);
     A.B = P.batch;
     return A;
 }
@@ -711,18 +1055,24 @@ static LeafArgs leaf_args(Pipeline &P)
 void run_leaf_factor(Pipeline &P, const double *y)
 {
     const Plan &p = *P.plan;
-    if (p.leafmax > LEAF_LDS_MAX)
-        throw Error{HODLR_EINVAL, "leaf size above 128 is not supported (the leaf factor is held in LDS)"};
+    if (p.leafmax > LEAF_MAX)
+        throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
     LeafArgs A = leaf_args(P);
     A.y = y;
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
     ProfScope ps(P.stream, PS_LEAF);
     const dim3 grid((unsigned)p.nleaf, 1, P.nitems);
-    if (p.f32())
+    if (p.leafmax > LEAF_LDS_MAX) {
+        if (p.f32())
+            leaf_factor_big_kernel<float><<<grid, LEAF_MT, 0, P.stream>>>(A);
+        else
+            leaf_factor_big_kernel<double><<<grid, LEAF_MT, 0, P.stream>>>(A);
+    } else if (p.f32()) {
         leaf_factor_kernel<float><<<grid, LEAF_MT, 0, P.stream>>>(A);
-    else
+    } else {
         leaf_factor_kernel<double><<<grid, LEAF_MT, 0, P.stream>>>(A);
+    }
     HIP_TRY(hipGetLastError());
 }
 
@@ -730,6 +1080,15 @@ void run_leaf_solve(Pipeline &P, void *z)
 {
     const Plan &p = *P.plan;
     LeafArgs A = leaf_args(P);
+    if (p.leafmax > LEAF_LDS_MAX) {
+        ProfScope ps(P.stream, PS_LEAF_SOLVE);
+        if (p.f32())
+            leaf_solve_big_kernel<float><<<(unsigned)p.nleaf, LEAF_MT, 0, P.stream>>>(A, (float *)z);
+        else
+            leaf_solve_big_kernel<double><<<(unsigned)p.nleaf, LEAF_MT, 0, P.stream>>>(A, (double *)z);
+        HIP_TRY(hipGetLastError());
+        return;
+    }
     static bool attr = false;   // room for the packed factor of a 128-point leaf (66 KB)
     if (!attr) {
         const int most = sizeof(double) * LEAF_LDS_MAX * (LEAF_LDS_MAX + 1) / 2;

@@ -340,7 +340,7 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 #define sN(i, j) sNb[(i) * ldr + (j)]
 #define t1(i, c) t1b[(i) * (LV_CB + 1) + (c)]
 #define t2(i, c) t2b[(i) * (LV_CB + 1) + (c)]
-    __shared__ int piv[RMAX_ABS];
+    __shared__ int piv[RMAX_LDS];
     __shared__ double red[TH / 64];
     __shared__ int sbad;
     const int nch = A.nch[loc], base = A.base[loc];
@@ -555,6 +555,208 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 #undef t1
 #undef t2
 
+// Node solves of levels whose rank is above RMAX_LDS (the LDS path's bound).
+// The node's matrices live in its slot of the small-factor store (HBM),
+//   [N^{-1} (r x r) | P | Q | N, overwritten by its LU | pivots (r)],
+// all row-major.  Factoring: P and Q from T, N = I - Q P, LU with partial
+// pivoting under the LDS path's rules (first largest pivot, rows swapped in
+// place), log det M = log det N (its sign checked as there), and N^{-1} from
+// the triangular solves of the permuted identity, one column per thread.
+// Every call then forms S = M^{-1} T for the columns to update as
+//   u = t2 - Q t1 (into S's top rows), s2 = N^{-1} u, s1 = t1 - P s2,
+// so the solves are products.  T is summed beforehand (level_sum_kernel).
+// Within the work-group, values written to HBM by one thread are read by
+// others only after a barrier (work-group scope acquire/release).
+constexpr int LVW_TH = 256;
+
+__global__ __launch_bounds__(LVW_TH) void level_solve_wide_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
+    const int64_t loc = blockIdx.x;
+    const int64_t h = A.node0 + loc;
+    const int r = A.rank[h];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (r == 0) {
+        if (A.factor && tid == 0)
+            A.node_ld[h] = 0.0;
+        return;
+    }
+    __shared__ int piv[RMAX_ABS];
+    __shared__ double sbv[LVW_TH / 64];
+    __shared__ int sbi[LVW_TH / 64];
+    __shared__ double red[LVW_TH / 64];
+    __shared__ int sneg[LVW_TH / 64];
+    __shared__ int sbad;
+    const int ncnt = A.ncnt, rs = A.rstride, nrhs = A.nrhs;
+    const double *T = A.Tbuf + loc * A.tstride;
+    double *sm = A.small + h * A.sstride;
+    const int64_t rr = (int64_t)r * r;
+    double *Ninv = sm, *P = sm + rr, *Q = sm + 2 * rr, *N = sm + 3 * rr;
+    if (A.factor) {
+        const int cp = nrhs;   // the child panel's columns follow the updated ones
+        for (int64_t idx = tid; idx < rr; idx += LVW_TH) {
+            const int i = (int)(idx / r), j = (int)(idx % r);
+            P[idx] = T[(int64_t)i * ncnt + cp + j];
+            Q[idx] = T[(int64_t)(rs + i) * ncnt + cp + j];
+        }
+        if (tid == 0)
+            sbad = 0;
+        __syncthreads();
+        for (int64_t idx = tid; idx < rr; idx += LVW_TH) {
+            const int i = (int)(idx / r), j = (int)(idx % r);
+            const double *qi = Q + (int64_t)i * r;
+            double a = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < r; ++k)
+                a -= qi[k] * P[(int64_t)k * r + j];
+            N[idx] = a;
+        }
+        __syncthreads();
+        for (int k = 0; k < r; ++k) {
+            // pivot: the first largest |N(i, k)|, i >= k
+            double bv = -1.0;
+            int bi = r;
+            for (int i = k + tid; i < r; i += LVW_TH) {
+                const double v = fabs(N[(int64_t)i * r + k]);
+                if (v > bv) {
+                    bv = v;
+                    bi = i;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                sbv[wid] = bv;
+                sbi[wid] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double best = sbv[0];
+                int p = sbi[0];
+                for (int w = 1; w < LVW_TH / 64; ++w)
+                    if (sbv[w] > best || (sbv[w] == best && sbi[w] < p)) {
+                        best = sbv[w];
+                        p = sbi[w];
+                    }
+                piv[k] = p;
+                if (best == 0.0)
+                    sbad = 1;
+            }
+            __syncthreads();
+            const int p = piv[k];
+            if (p != k)
+                for (int j = tid; j < r; j += LVW_TH) {
+                    const double a = N[(int64_t)k * r + j];
+                    N[(int64_t)k * r + j] = N[(int64_t)p * r + j];
+                    N[(int64_t)p * r + j] = a;
+                }
+            __syncthreads();
+            const double pv = N[(int64_t)k * r + k];
+            for (int i = k + 1 + tid; i < r; i += LVW_TH)
+                if (pv != 0.0)
+                    N[(int64_t)i * r + k] /= pv;
+            __syncthreads();
+            const int tr = r - k - 1;
+            for (int64_t idx = tid; idx < (int64_t)tr * tr; idx += LVW_TH) {
+                const int i = k + 1 + (int)(idx / tr), j = k + 1 + (int)(idx % tr);
+                N[(int64_t)i * r + j] -= N[(int64_t)i * r + k] * N[(int64_t)k * r + j];
+            }
+            __syncthreads();
+        }
+        // log det M = log det(I - QP); it must be positive for an SPD C
+        double lg = 0.0;
+        int neg = 0;
+        for (int i = tid; i < r; i += LVW_TH) {
+            const double u = N[(int64_t)i * r + i];
+            lg += log(fabs(u));
+            neg += (u < 0.0) ? 1 : 0;
+            neg += (piv[i] != i) ? 1 : 0;
+            sm[4 * rr + i] = (double)piv[i];
+        }
+        lg = wave_sum(lg);
+        for (int off = 32; off > 0; off >>= 1)
+            neg += __shfl_xor(neg, off, 64);
+        if (lane == 0) {
+            red[wid] = lg;
+            sneg[wid] = neg;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = red[0];
+            int ng = sneg[0];
+            for (int w = 1; w < LVW_TH / 64; ++w) {
+                v += red[w];
+                ng += sneg[w];
+            }
+            if (sbad || (ng & 1)) {
+                atomicOr(A.status, DS_NOTSPD_NODE);
+                v = __builtin_nan("");
+            }
+            A.node_ld[h] = v;
+        }
+        // N^{-1}: column c solves N x = e_c (rows permuted as in the LU)
+        for (int c = tid; c < r; c += LVW_TH) {
+            for (int i = 0; i < r; ++i)
+                Ninv[(int64_t)i * r + c] = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < r; ++k) {
+                const int p = piv[k];
+                if (p != k) {
+                    const double a = Ninv[(int64_t)k * r + c];
+                    Ninv[(int64_t)k * r + c] = Ninv[(int64_t)p * r + c];
+                    Ninv[(int64_t)p * r + c] = a;
+                }
+            }
+            for (int i = 1; i < r; ++i) {
+                double a = Ninv[(int64_t)i * r + c];
+                for (int k = 0; k < i; ++k)
+                    a -= N[(int64_t)i * r + k] * Ninv[(int64_t)k * r + c];
+                Ninv[(int64_t)i * r + c] = a;
+            }
+            for (int i = r - 1; i >= 0; --i) {
+                double a = Ninv[(int64_t)i * r + c];
+                for (int k = i + 1; k < r; ++k)
+                    a -= N[(int64_t)i * r + k] * Ninv[(int64_t)k * r + c];
+                Ninv[(int64_t)i * r + c] = a / N[(int64_t)i * r + i];
+            }
+        }
+        __syncthreads();
+    }
+    // S = M^{-1} T on the columns to update
+    double *S = A.Sbuf + loc * A.tstride;
+    const int64_t nout = (int64_t)r * nrhs;
+    for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // u = t2 - Q t1
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        const double *qi = Q + (int64_t)i * r;
+        double a = T[(int64_t)(rs + i) * ncnt + c];
+        for (int k = 0; k < r; ++k)
+            a -= qi[k] * T[(int64_t)k * ncnt + c];
+        S[(int64_t)i * nrhs + c] = a;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // s2 = N^{-1} u
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        const double *ni = Ninv + (int64_t)i * r;
+        double a = 0.0;
+        for (int k = 0; k < r; ++k)
+            a += ni[k] * S[(int64_t)k * nrhs + c];
+        S[(int64_t)(rs + i) * nrhs + c] = a;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // s1 = t1 - P s2
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        const double *pi = P + (int64_t)i * r;
+        double a = T[(int64_t)i * ncnt + c];
+        for (int k = 0; k < r; ++k)
+            a -= pi[k] * S[(int64_t)(rs + k) * nrhs + c];
+        S[(int64_t)i * nrhs + c] = a;
+    }
+}
+
 // Wide ranks (panel rank above 8, e.g. 2-D kernels or tight tolerances) on
 // FP64 MFMA (v_mfma_f64_16x16x4; lane l = 16 q + r supplies A[r][q] and
 // B[q][r] of a 16 x 4 by 4 x 16 step and holds D[q + 4 t][r], t < 4).
@@ -579,8 +781,12 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
         return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int lr = lane & 15, lq = lane >> 4;
-    const int ct0 = (blockIdx.y * LVM_NT + wid) * LVM_CPW;   // this wave's first column tile
-    if (ct0 * 16 >= A.ncnt)
+    // blockIdx.y = column block + (column blocks) x rank group: ranks above
+    // 16 MT go to further groups of 16 MT, each re-reading the chunk's X
+    const int ncb = (A.ncnt + 16 * LVM_NT * LVM_CPW - 1) / (16 * LVM_NT * LVM_CPW);
+    const int r0 = 16 * MT * (int)(blockIdx.y / ncb);
+    const int ct0 = ((blockIdx.y % ncb) * LVM_NT + wid) * LVM_CPW;   // this wave's first column tile
+    if (ct0 * 16 >= A.ncnt || r0 >= r)
         return;   // the whole wave; no work-group barrier follows
     const int64_t n = A.n;
     // lanes past the last column or rank read a valid column (the first one)
@@ -597,7 +803,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
     bool wok[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-        const int l = 16 * m + lr;
+        const int l = r0 + 16 * m + lr;
         wok[m] = l < r;
         wcol[m] = A.W + (A.colW + (wok[m] ? l : 0)) * n;
     }
@@ -644,7 +850,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int l = 16 * m + lq + 4 * t;
+                    const int l = r0 + 16 * m + lq + 4 * t;
                     if (l < r)
                         rec[(int64_t)l * A.ncnt + c] = acc[m][j][t];
                 }
@@ -668,7 +874,8 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     const int cbase = blockIdx.y * LVM_UNT * 16;
     if (r == 0 || cbase >= nrhs)
         return;   // the whole work-group
-    __shared__ double sS[RMAX_ABS][LVM_UNT * 16 + 1];
+    constexpr int KS = 4 * MT;   // 4-rank steps per rank chunk
+    __shared__ double sS[4 * KS][LVM_UNT * 16 + 1];
     __shared__ int scol[LVM_UNT * 16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
@@ -676,14 +883,18 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     const int64_t loc = ch.node - A.node0;
     const double *S = A.Sbuf + loc * A.tstride;
     const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
-    constexpr int KS = 4 * MT;   // 4-rank steps
+    for (int cc = tid; cc < LVM_UNT * 16; cc += LV_THREADS)
+        scol[cc] = cbase + cc < nrhs ? A.cols[cbase + cc] : -1;
+    // ranks in chunks of 4 KS (one chunk unless the rank is above 16 MT):
+    // S's slice of the chunk in LDS, X updated once per chunk
+    for (int r0 = 0; r0 < r; r0 += 4 * KS) {
+    if (r0)
+        __syncthreads();   // every wave is done with the previous slice
     for (int idx = tid; idx < 4 * KS * LVM_UNT * 16; idx += LV_THREADS) {
         const int l = idx / (LVM_UNT * 16), cc = idx % (LVM_UNT * 16);
         const int col = cbase + cc;
-        sS[l][cc] = (l < r && col < nrhs) ? S[(int64_t)(rowoff + l) * nrhs + col] : 0.0;
+        sS[l][cc] = (r0 + l < r && col < nrhs) ? S[(int64_t)(rowoff + r0 + l) * nrhs + col] : 0.0;
     }
-    for (int cc = tid; cc < LVM_UNT * 16; cc += LV_THREADS)
-        scol[cc] = cbase + cc < nrhs ? A.cols[cbase + cc] : -1;
     __syncthreads();
     const int64_t nrt = (ch.hi - ch.lo + 15) >> 4;
     for (int64_t rt = wid; rt < nrt; rt += LV_THREADS / 64) {
@@ -694,7 +905,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
         const int64_t is = rok ? ia : ch.lo;
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
-            const int l = 4 * st + lq;
+            const int l = r0 + 4 * st + lq;
             const double wv = (double)Xp[(A.colW + (l < r ? l : 0)) * n + is];
             a[st] = (l < r && rok) ? wv : 0.0;
         }
@@ -722,6 +933,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
                 }
             }
         }
+    }
     }
 }
 
@@ -836,9 +1048,47 @@ static void update_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs
         level_update_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
 }
 
+// levels of rank above RMAX_LDS: the MFMA reduction over rank groups of 64,
+// the record sums, the node solves with matrices in HBM, and the MFMA update
+// over rank chunks of 64
+template <typename PT>
+static void level_launch_wide(Pipeline &P, int d, LevelArgs A)
+{
+    const Plan &p = *P.plan;
+    const unsigned nchunks = (unsigned)p.lvl[d].size();
+    const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
+    const unsigned ngrp = (unsigned)((A.rstride + 63) / 64);
+    const unsigned ncb = (unsigned)((A.ncnt + 16 * LVM_NT * LVM_CPW - 1) / (16 * LVM_NT * LVM_CPW));
+    if (nchunks) {
+        ProfScope ps(P.stream, PS_LVL_REDUCE);
+        level_reduce_mfma_kernel<PT, 4><<<dim3(nchunks, ncb * ngrp, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+    }
+    {
+        ProfScope ps(P.stream, PS_LVL_SOLVE);
+        A.tsum = 1;
+        if (nchunks) {
+            const int most = 2 * A.rstride * A.ncnt;
+            level_sum_kernel<<<dim3(nodes, (most + LV_THREADS - 1) / LV_THREADS, P.nitems), LV_THREADS,
+                               0, P.stream>>>(A);
+        }
+        level_solve_wide_kernel<<<dim3(nodes, 1, P.nitems), LVW_TH, 0, P.stream>>>(A);
+    }
+    if (nchunks && A.nrhs > 0) {
+        ProfScope ps(P.stream, PS_LVL_UPDATE);
+        level_update_mfma_kernel<PT, 4>
+            <<<dim3(nchunks, (A.nrhs + 16 * LVM_UNT - 1) / (16 * LVM_UNT), P.nitems), LV_THREADS, 0,
+               P.stream>>>(A);
+    }
+    HIP_TRY(hipGetLastError());
+}
+
 template <typename PT>
 static void level_launch_t(Pipeline &P, int d, LevelArgs A)
 {
+    if (A.rstride > RMAX_LDS) {
+        level_launch_wide<PT>(P, d, A);
+        return;
+    }
     const Plan &p = *P.plan;
     const unsigned nchunks = (unsigned)p.lvl[d].size();
     const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));

@@ -1,6 +1,8 @@
-// The plan handle of the C ABI (shared by the entry points of api.hip and
-// noalloc.hip), and the argument checks they share.
+// The plan handle of the C ABI and the argument checks its entry points
+// share.
 #pragma once
+
+#include <mutex>
 
 #include "common.h"
 
@@ -26,17 +28,10 @@ struct hodlr_plan_s {
     hodlr::Layout lay;
     hodlr_opts opts;
     std::vector<BatchGraph> graphs;
-    // host vectors of one pipeline, reserved at plan creation and lent to
-    // gp_loglik_dev_noalloc so that its calls do no heap allocation
-    std::vector<int> h_rmax, h_cols, h_cnt, h_ranks, h_ints;
-    void reserve_host()
-    {
-        h_rmax.reserve(plan.L + 2);
-        h_cols.reserve(plan.ncol + 1);
-        h_cnt.reserve(plan.L + 1);
-        h_ranks.reserve(std::max<int64_t>(plan.nint, 1));
-        h_ints.assign(64, 0);
-    }
+    // ranks of the last completed gp_loglik_dev call (hodlr_plan_info)
+    std::mutex last_mu;
+    std::vector<int> last_ranks;
+    int last_capped = 0;
     ~hodlr_plan_s()
     {
         for (auto &g : graphs) {

@@ -130,8 +130,8 @@ void worker(RaggedJob *J)
             Plan plan;
             plan_build(plan, n, dim, J->leaf, &J->opts, tt.level_rows, tt.reduce_cols,
                        tt.reduce_group);
-            if (plan.leafmax > LEAF_LDS_MAX)
-                throw Error{HODLR_EINVAL, "leaf above 128"};
+            if (plan.leafmax > LEAF_MAX)
+                throw Error{HODLR_EINVAL, "leaf above 256"};
             Layout lay = make_layout(plan, false);
             size_t tb = plan_image(plan, image);
             // arena: [workspace | tables | x | y]

@@ -335,6 +335,8 @@ Layout make_layout(const Plan &p, bool store_leaf)
     y.Xt = take(p.panel_bytes() * (size_t)n * (size_t)p.ncol);
     int64_t lm = p.leafmax;
     y.G = take(store_leaf ? sizeof(double) * (size_t)p.nleaf * (size_t)(lm * (lm + 1) / 2) : 8);
+    // leaves above LEAF_LDS_MAX: 8 x 8 tiles of 16 x 16 doubles each for L21
+    y.L21 = take(lm > LEAF_LDS_MAX ? sizeof(double) * (size_t)p.nleaf * 64 * 256 : 8);
     int64_t ni = std::max<int64_t>(p.nint, 1);
     int64_t nb = std::max<int64_t>((int64_t)p.aca_big.size(), 1);
     y.aca_state = take(sizeof(BigState) * 2 * nb);
@@ -357,7 +359,8 @@ Layout make_layout(const Plan &p, bool store_leaf)
     y.lvl_part = take(sizeof(double) * lp);
     y.Tbuf = take(sizeof(double) * tb);
     y.Sbuf = take(sizeof(double) * tb);
-    y.small_stride = 3 * (int64_t)capmax * capmax + capmax;
+    // per node: LU of I - QP, P, Q and pivots; above RMAX_LDS also N^{-1}
+    y.small_stride = (capmax > RMAX_LDS ? 4 : 3) * (int64_t)capmax * capmax + capmax;
     y.small = take(sizeof(double) * ni * y.small_stride);
     y.dot_part = take(sizeof(double) * 1024);
     y.out = take(sizeof(double) * 8);

@@ -62,8 +62,8 @@ double time_config(const double *x, int64_t n, int dim, int k, const double thet
         order_points(x, n, dim, leaf, perm.data());
     Plan plan;
     plan_build(plan, n, dim, leaf, &o, rows, cols, grp);
-    if (plan.leafmax > LEAF_LDS_MAX)
-        throw Error{HODLR_EINVAL, "leaf candidate above 128"};
+    if (plan.leafmax > LEAF_MAX)
+        throw Error{HODLR_EINVAL, "leaf candidate above 256"};
     plan_upload(plan);
     struct Guard {
         Plan &p;
@@ -143,8 +143,8 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
         else
             leaves = {32, 64, 96, 128};
         for (int l : leaves)
-            if (l < 1 || l > LEAF_LDS_MAX)
-                return report(HODLR_EINVAL, "leaf candidates must be in [1, 128]");
+            if (l < 1 || l > LEAF_MAX)
+                return report(HODLR_EINVAL, "leaf candidates must be in [1, 256]");
         prime_level_attributes();
         hipStream_t s = nullptr;
         HIP_TRY(hipStreamCreate(&s));
