@@ -59,6 +59,52 @@ def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     return out
 
 
+def item_model(n, leaf, rank_max, esz=8):
+    """kernel_model for one item of n points with leaf `leaf` and per-depth
+    panel widths rank_max (depth 0 .. L-1), plus the cross approximation's
+    basis writes (8 B x n x sum of widths)."""
+    L = len(rank_max)
+    r = [0] + [int(v) for v in rank_max]
+    cnt = [1]
+    for j in range(1, L + 1):
+        cnt.append(cnt[-1] + r[j])
+    leaf_sizes = np.diff(np.linspace(0, n, (1 << L) + 1).round()).astype(int) if L else [n]
+    model = kernel_model(n, leaf_sizes, r, cnt, esz=esz)
+    model["aca_bases"] = (0.0, 8.0 * n * sum(r[1:]))
+    return model
+
+
+def model_ms(model, items=1):
+    """Sum over stages of max(bytes / 8 TB/s, flops / 78.6 TFLOP/s), in ms."""
+    return items * sum(max(b / (PEAK["hbm"] * 1e9), f / (PEAK["alu_fp64"] * 1e12)) * 1e3
+                       for f, b in model.values())
+
+
+def stage_roofline(model, stages, items=1):
+    """Roofline of the stage with the largest measured time among the modelled
+    ones: algorithmic bytes (HBM-bound) or flops (above the FP64 ridge) per
+    launch over its average launch time."""
+    cand = [k for k in stages if k in model]
+    if not cand:
+        return None
+    k = max(cand, key=lambda s: stages[s][0])
+    ms, launches = stages[k]
+    f, b = (items * v for v in model[k])
+    per_s = ms / 1e3
+    if f / b > PEAK["alu_fp64"] * 1e12 / (PEAK["hbm"] * 1e9):
+        ach = f / per_s / 1e12
+        return {"bound": "mfma" if k in ("leaf_factor", "level_reduce", "level_update") else "alu",
+                "achieved": ach, "peak": PEAK["alu_fp64"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["alu_fp64"], "traffic": None, "kernel": k,
+                "avg_launch_ms": ms / launches,
+                "algorithmic_per_call": {"flops": f / launches, "bytes": b / launches}}
+    ach = b / per_s / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm"], "traffic": None, "kernel": k,
+            "avg_launch_ms": ms / launches,
+            "algorithmic_per_call": {"flops": f / launches, "bytes": b / launches}}
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
@@ -441,6 +487,45 @@ def bench_batched(args, torch, H, wl, dev):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
     o = out.cpu().numpy()
+    ms_step = elapsed / args.steps * 1e3
+    # per-stage times in a pass of its own (stages launched eagerly, every
+    # launch timed), the batch-wide column layout, and the model
+    H.profile_select(None)
+    H.profile_enable(True)
+    with torch.cuda.stream(stream):
+        H.gp_loglik_batch_dev(plan, d_x, H.K_MATERN32, d_p, m, d_y, 0, 1e-10, work, nb, stream,
+                              out, False)
+    torch.cuda.synchronize()
+    stages = {k: v for k, v in H.profile_read().items() if v[1] > 0}
+    H.profile_enable(False)
+    info = plan.info()
+    model = item_model(n, 128, info["rank_max"][:info["levels"]], esz=4 if mixed else 8)
+    pipe_ms = model_ms(model, m)
+    # every item against the exact state-space oracle and against its own
+    # single-likelihood call on the same plan
+    import oracle
+    oracle.build(force=False)
+    splan = H.Plan(n, 1, 128, H.Opts(max_rank=16, precision=prec, presorted=1))
+    sw = torch.empty(splan.workspace_bytes, dtype=torch.uint8, device=dev)
+    so = torch.zeros(8, dtype=torch.float64, device=dev)
+    worst = {"kalman_logdet": 0.0, "kalman_quad": 0.0, "single_logdet": 0.0,
+             "single_loglik": 0.0}
+    t_k = 0.0
+    for i in range(m):
+        a, ell, s2 = th[i]
+        H.gp_loglik_dev(splan, d_x, H.K_MATERN32, (a, ell), s2, d_y, 1e-10, sw,
+                        splan.workspace_bytes, None, so)
+        torch.cuda.synchronize()
+        one = so[:3].cpu().numpy()
+        t1 = time.perf_counter()
+        kf = oracle.kalman_matern32(x[:, 0], y, (a, ell), s2, want_alpha=False)
+        t_k += time.perf_counter() - t1
+        rel = lambda u, v: abs(u - v) / max(abs(v), 1.0)
+        worst["kalman_logdet"] = max(worst["kalman_logdet"], rel(o[i, 1], kf["logdet"]))
+        worst["kalman_quad"] = max(worst["kalman_quad"], rel(o[i, 2], kf["quad"]))
+        worst["single_logdet"] = max(worst["single_logdet"], rel(o[i, 1], one[1]))
+        worst["single_loglik"] = max(worst["single_loglik"], rel(o[i, 0], one[0]))
+    del sw, splan
     res = {"metric": "GP log-likelihoods/s, batched hyperparameters (n=65536 shared series)",
            "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -452,7 +537,22 @@ def bench_batched(args, torch, H, wl, dev):
                       "kernel": "matern32", "leaf": 128, "tol": 1e-10, "max_rank": 16,
                       "graph": True, "precision": args.precision, "tiles": tune.as_dict()},
            "tile_sweep_ms": sweep,
-           "finite_items": int(np.isfinite(o[:, 0]).sum())}
+           "finite_items": int(np.isfinite(o[:, 0]).sum()),
+           "ranks": {"batch_rank_max": info["rank_max"][:info["levels"]],
+                     "capped_blocks": info["capped_blocks"]},
+           "roofline": stage_roofline(model, stages, m),
+           "pipeline_roofline": {"model_ms": pipe_ms, "measured_ms": ms_step,
+                                 "frac": pipe_ms / ms_step,
+                                 "note": "the per-point model of the single likelihood (each "
+                                         "modelled stage at the larger of bytes / 8 TB/s and "
+                                         "flops / 78.6 TFLOP/s, plus the basis writes) for "
+                                         "every item at the batch-wide panel widths"},
+           "stage_ms_per_step": {k: v[0] for k, v in stages.items()},
+           "stage_note": "stage times from an eager (no graph) pass with every launch timed",
+           "oracle_check": {"items": m, "max_rel_err": worst, "kalman_seconds_1core": t_k,
+                            "note": "every item: log det and quadratic form against the exact "
+                                    "Kalman oracle; log det and log-likelihood against the "
+                                    "item's own gp_loglik_dev call (relative to max(|v|, 1))"}}
     print(json.dumps(res), flush=True)
 
 
@@ -490,6 +590,35 @@ def bench_ragged(args, torch, H, wl, dev):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ntot = int(sum(len(x) for x in xs))
+    # untimed: every item against the exact Kalman oracle and against a single
+    # gp_loglik_dev call on its own plan, whose ranks feed the per-point model
+    import oracle
+    oracle.build(force=False)
+    worst = {"kalman_logdet": 0.0, "kalman_quad": 0.0, "single_logdet": 0.0,
+             "single_loglik": 0.0}
+    pipe_ms = 0.0
+    so = torch.zeros(8, dtype=torch.float64, device=dev)
+    for i in range(m):
+        ni = len(xs[i])
+        a, ell, s2 = th[i]
+        kf = oracle.kalman_matern32(xs[i][:, 0], ys[i], (a, ell), s2, want_alpha=False)
+        pl = H.Plan(ni, 1, 128, H.Opts(max_rank=16, precision=prec, presorted=1))
+        wk = torch.empty(pl.workspace_bytes, dtype=torch.uint8, device=dev)
+        dx = torch.from_numpy(np.ascontiguousarray(xs[i][:, 0])).to(dev)
+        dy = torch.from_numpy(np.ascontiguousarray(ys[i])).to(dev)
+        H.gp_loglik_dev(pl, dx, H.K_MATERN32, (a, ell), s2, dy, 1e-10, wk, pl.workspace_bytes,
+                        None, so)
+        torch.cuda.synchronize()
+        one = so[:3].cpu().numpy()
+        inf = pl.info()
+        pipe_ms += model_ms(item_model(ni, 128, inf["rank_max"][:inf["levels"]],
+                                       esz=4 if mixed else 8))
+        rel = lambda u, v: abs(u - v) / max(abs(v), 1.0)
+        worst["kalman_logdet"] = max(worst["kalman_logdet"], rel(o[i, 1], kf["logdet"]))
+        worst["kalman_quad"] = max(worst["kalman_quad"], rel(o[i, 2], kf["quad"]))
+        worst["single_logdet"] = max(worst["single_logdet"], rel(o[i, 1], one[1]))
+        worst["single_loglik"] = max(worst["single_loglik"], rel(o[i, 0], one[0]))
+        del wk, pl
     res = {"metric": "GP log-likelihoods/s, independent series of uneven size",
            "value": args.steps * m / elapsed, "unit": "likelihoods/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -502,7 +631,17 @@ def bench_ragged(args, torch, H, wl, dev):
                       "max_rank": 16, "workers": args.workers, "host_buffers": True,
                       "tiles_per_size_class": {str(k): v for k, v in sorted(tuned.items())}},
            "points_per_s": args.steps * ntot / elapsed,
-           "finite_items": int(np.isfinite(o[:, 0]).sum())}
+           "finite_items": int(np.isfinite(o[:, 0]).sum()),
+           "pipeline_roofline": {"model_ms": pipe_ms, "measured_ms": elapsed / args.steps * 1e3,
+                                 "frac": pipe_ms / (elapsed / args.steps * 1e3),
+                                 "note": "sum over items of the per-point model at each item's "
+                                         "own ranks; the measured time includes the host "
+                                         "transfers, so the fraction is a lower bound"},
+           "oracle_check": {"items": m, "max_rel_err": worst,
+                            "note": "every item: log det and quadratic form against the exact "
+                                    "Kalman oracle; log det and log-likelihood against a single "
+                                    "gp_loglik_dev call on its own plan (relative to "
+                                    "max(|v|, 1))"}}
     print(json.dumps(res), flush=True)
 
 

@@ -244,9 +244,11 @@ hodlr_status hodlr_tune_lookup(int64_t n, int32_t dim, hodlr_kernel k, int32_t p
 hodlr_status hodlr_plan_workspace_size(hodlr_plan p, size_t *bytes);
 
 /* The plan's tree (n, dim, levels, largest leaf; device_bytes = workspace plus
- * tables) and the block ranks of the last gp_loglik_dev call on it that
- * completed (per-depth maximum and mean, capped count; zeros before the
- * first).  Errors: EINVAL (NULL).                                            */
+ * tables) and the block ranks of the last call on it: after gp_loglik_dev
+ * (when it completed) the per-depth maximum and mean and the capped count;
+ * after gp_loglik_batch_dev the per-depth maxima over its items (the column
+ * layout every item was padded to; means 0) and the capped count summed over
+ * items.  Zeros before the first call.  Errors: EINVAL (NULL).               */
 hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out);
 
 /* Log-likelihood with every input already resident on the device.
@@ -455,7 +457,8 @@ hodlr_status hodlr_profile_enable(int32_t on);
  * selects which kinds are timed; default: all.  Timing only the kernel of
  * interest keeps the event overhead out of a throughput measurement.        */
 hodlr_status hodlr_profile_select(uint32_t mask);
-/* Copies the counters accumulated by completed calls.                      */
+/* Copies the counters of every timed launch so far (waits for the events of
+ * launches still in flight).                                               */
 hodlr_status hodlr_profile_read(hodlr_profile_t *out);
 
 #ifdef __cplusplus

@@ -775,6 +775,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         raise_status(read_status(P));
         {
             std::lock_guard<std::mutex> lk(p->last_mu);
+            p->last_rmax = P.rmax;
             p->last_ranks = P.ranks;
             p->last_capped = P.capped;
         }
@@ -796,6 +797,11 @@ hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
     I.device_bytes = (int64_t)p->lay.total + (int64_t)p->plan.dev_tables_bytes;
     std::lock_guard<std::mutex> lk(p->last_mu);
     I.capped_blocks = p->last_capped;
+    for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS && d + 1 < (int)p->last_rmax.size();
+         ++d) {
+        I.rank_max[d] = p->last_rmax[d + 1];
+        I.max_rank_used = std::max(I.max_rank_used, I.rank_max[d]);
+    }
     if (!p->last_ranks.empty())
         for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS; ++d) {
             const int64_t h0 = p->plan.first_at(d), h1 = p->plan.first_at(d + 1);
@@ -862,6 +868,12 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
         HIP_TRY(hipGetLastError());
         run_aca_batched(P);
         make_columns(P);
+        {
+            std::lock_guard<std::mutex> lk(p->last_mu);
+            p->last_rmax = P.rmax;
+            p->last_ranks.clear();
+            p->last_capped = P.capped;
+        }
         const bool graph = use_graph && stream != nullptr;
         if (!graph) {
             run_leaf_factor(P, d_y);

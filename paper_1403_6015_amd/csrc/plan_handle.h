@@ -28,9 +28,11 @@ struct hodlr_plan_s {
     hodlr::Layout lay;
     hodlr_opts opts;
     std::vector<BatchGraph> graphs;
-    // ranks of the last completed gp_loglik_dev call (hodlr_plan_info)
+    // ranks of the last gp_loglik_dev call that completed (per node and per
+    // depth) or of the last batched call's compression (per depth, maxima over
+    // its items) for hodlr_plan_info
     std::mutex last_mu;
-    std::vector<int> last_ranks;
+    std::vector<int> last_ranks, last_rmax;
     int last_capped = 0;
     ~hodlr_plan_s()
     {

@@ -132,6 +132,9 @@ hodlr_status hodlr_profile_read(hodlr_profile_t *out)
     using namespace hodlr;
     if (!out)
         return HODLR_EINVAL;
+    // calls that return without synchronizing (the batched form) leave their
+    // records pending: wait for their events and add them first
+    prof_collect();
     Prof &p = P();
     std::lock_guard<std::mutex> g(p.mu);
     std::memset(out, 0, sizeof(*out));

@@ -103,3 +103,42 @@ def test_failed_item_is_nan_and_others_survive():
     for i in (0, 2, 3):
         ref = oracle.gp_dense(x, y, H.K_SE, th[i, :2], th[i, 2])
         assert abs(o[i, 1] - ref["logdet"]) <= 1e-10 * abs(ref["logdet"])
+
+
+def test_full_size_batch_every_item_against_kalman_and_single_calls():
+    """The batched configuration at full size (256 hyperparameter settings on
+    one n = 65536 series, graph replay): every item's log det and quadratic
+    form against the exact Kalman oracle, and its log det and log-likelihood
+    against a single gp_loglik_dev call with the same hyperparameters (the
+    batch pads every item to the batch-wide panel widths, which adds exact
+    zero columns and changes only the order of roundings)."""
+    import torch
+    n, m = 65536, 256
+    announce("batched theta full size n=%d m=%d graph" % (n, m))
+    c = _setup(n, m)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        res = _run(c, stream, True)
+    assert np.isfinite(res).all()
+    plan = H.Plan(n, 1, 128, H.Opts(max_rank=16, presorted=1))
+    dev = torch.device("cuda:0")
+    w1 = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    o1 = torch.zeros(8, dtype=torch.float64, device=dev)
+    worst_k = worst_s = 0.0
+    for i in range(m):
+        a, ell, s2 = c["th"][i]
+        H.gp_loglik_dev(plan, c["d_x"], H.K_MATERN32, (a, ell), s2, c["d_y"], c["tol"], w1,
+                        plan.workspace_bytes, None, o1)
+        torch.cuda.synchronize()
+        one = o1.cpu().numpy()[:3]
+        kf = oracle.kalman_matern32(c["x"][:, 0], c["y"], (a, ell), s2, want_alpha=False)
+        sc = max(abs(kf["logdet"]), 1.0)
+        ek = abs(res[i, 1] - kf["logdet"]) / sc
+        es = max(abs(res[i, 1] - one[1]) / max(abs(one[1]), 1.0),
+                 abs(res[i, 0] - one[0]) / max(abs(one[0]), 1.0))
+        worst_k, worst_s = max(worst_k, ek), max(worst_s, es)
+        assert ek <= 1e-10, (i, ek)
+        assert abs(res[i, 2] - kf["quad"]) <= 1e-9 * abs(kf["quad"]), i
+        assert es <= 1e-12, (i, es)
+    print("full-size batch: worst log det vs Kalman %.2e, worst vs single call %.2e"
+          % (worst_k, worst_s), flush=True)
