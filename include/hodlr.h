@@ -36,7 +36,12 @@
  *    level products, coupling LU, log-det sums) stays FP64, loaded FP32
  *    values are widened in registers and results rounded on store.  The
  *    host solve recovers full accuracy by iterative refinement against an
- *    exact FP64 matrix-vector product (see hodlr_opts.precision).
+ *    exact FP64 matrix-vector product (see hodlr_opts.precision).  The log
+ *    det is held to a relative error of 1e-8: each mixed likelihood (or
+ *    factor) computes the bound eps_32 * sum over split nodes of
+ *    1 / det M_tau, and one whose bound exceeds 1e-8 max(|log det|, 1) is
+ *    computed again with FP64 panels (counted in hodlr_info.fp64_fallback;
+ *    the workspace sizes of mixed plans leave room for it).
  *  - Thread safety: distinct factors/plans may be used concurrently; one
  *    workspace must not be used by two calls at once.
  */
@@ -108,6 +113,12 @@ typedef struct {
                             refine_tol within max_refine steps; ENOCONV otherwise).
                             0 (default): an FP64 factor is applied once, whose
                             residual is about tol ||K|| / sigma2                      */
+    int32_t mixed_unchecked; /* HODLR_MIXED only.  0 (default): every likelihood or
+                            factor tests its log-det error bound (see Precision at
+                            the top) and is redone with FP64 panels when the bound
+                            misses 1e-8.  The bound is safe but can be loose by 10^3
+                            and more on strongly coupled problems.  1: keep the FP32-
+                            panel result untested (the caller measures its error)  */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one
@@ -130,6 +141,9 @@ typedef struct {
     int32_t precision;
     int32_t refine_steps;                      /* mixed form, last solve           */
     double refine_residual;                    /* mixed form, last solve           */
+    int32_t fp64_fallback;                     /* mixed form: factors (or likelihoods
+                                                  of the last plan call) redone with
+                                                  FP64 panels (see HODLR_MIXED)    */
 } hodlr_info_t;
 
 /* ------------------------------------------------------------------ ordering */
@@ -274,7 +288,10 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
  * factorization fails (non-positive pivot or coupling determinant, or
  * non-positive parameters) gets NaNs and does not stop the batch.
  * Workspace: hodlr_plan_batch_workspace_size(plan, nitems).  The call returns
- * without synchronizing; results are ready when the stream is.             */
+ * without synchronizing (results are ready when the stream is), except for
+ * mixed plans: they synchronize at the end to read each item's log-det error
+ * bound and redo the items that miss the bar with FP64 panels, one at a
+ * time (see Precision above).                                              */
 hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes);
 hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
                                  const double *d_params, int32_t nitems, const double *d_y,

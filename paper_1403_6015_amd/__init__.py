@@ -60,10 +60,10 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p),
-                ("refine", ctypes.c_int32)]
+                ("refine", ctypes.c_int32), ("mixed_unchecked", ctypes.c_int32)]
 
     def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0,
-                 noise=None, refine=0):
+                 noise=None, refine=0, mixed_unchecked=0):
         """noise: optional per-point variances (one per point, caller's order),
         added to sigma2 on the diagonal; the array is kept alive with the
         options."""
@@ -73,7 +73,7 @@ class Opts(ctypes.Structure):
             self._noise = np.ascontiguousarray(np.asarray(noise, dtype=np.float64).ravel())
             ptr = self._noise.ctypes.data
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
-                         int(presorted), ptr, int(refine))
+                         int(presorted), ptr, int(refine), int(mixed_unchecked))
 
 
 class Profile(ctypes.Structure):
@@ -88,7 +88,8 @@ class Info(ctypes.Structure):
                 ("rank_max", ctypes.c_int32 * MAX_LEVELS),
                 ("rank_mean", ctypes.c_double * MAX_LEVELS),
                 ("device_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("refine_steps", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
+                ("refine_steps", ctypes.c_int32), ("refine_residual", ctypes.c_double),
+                ("fp64_fallback", ctypes.c_int32)]
 
 
 class MlpNorm(ctypes.Structure):
@@ -403,7 +404,8 @@ def _info_dict(I) -> dict:
             "max_rank_used": I.max_rank_used, "capped_blocks": I.capped_blocks,
             "rank_max": list(I.rank_max[:L]), "rank_mean": list(I.rank_mean[:L]),
             "device_bytes": I.device_bytes, "precision": I.precision,
-            "refine_steps": I.refine_steps, "refine_residual": I.refine_residual}
+            "refine_steps": I.refine_steps, "refine_residual": I.refine_residual,
+            "fp64_fallback": I.fp64_fallback}
 
 
 def hodlr_info(f: Factor) -> dict:

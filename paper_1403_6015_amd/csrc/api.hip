@@ -49,6 +49,7 @@ hodlr_opts default_opts()
     o.presorted = 0;
     o.noise = nullptr;
     o.refine = 0;
+    o.mixed_unchecked = 0;
     return o;
 }
 
@@ -89,6 +90,8 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "refine_tol must be positive"};
     if (o.refine != 0 && o.refine != 1)
         throw Error{HODLR_EINVAL, "refine must be 0 or 1"};
+    if (o.mixed_unchecked != 0 && o.mixed_unchecked != 1)
+        throw Error{HODLR_EINVAL, "mixed_unchecked must be 0 or 1"};
 }
 
 void check_finite(const double *v, int64_t m, const char *what)
@@ -118,6 +121,16 @@ struct DevBuf {
     }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            if (p)
+                (void)hipFree(p);
+            p = o.p;
+            o.p = nullptr;
+        }
+        return *this;
+    }
     void *release()
     {
         void *q = p;
@@ -198,6 +211,23 @@ void raise_status(int st)
         throw Error{HODLR_ENOTSPD, "a coupling determinant is not positive"};
 }
 
+// The mixed form's log-det bar: relative error at most 1e-8 of max(|log det|, 1).
+// Its FP32 storage of the applied bases W~ perturbs each coupling matrix
+// I - QP by about the FP32 unit roundoff, which its inverse amplifies; the
+// finish kernel writes eps_32 sum_tau 1 / det M_tau, a bound on the log-det
+// error (on seeded problems of the batched hyperparameter box the error was at
+// most a quarter of it).  A likelihood whose bound exceeds the bar is redone
+// with FP64 panels.
+constexpr double MIXED_LOGDET_BAR = 1e-8;
+
+bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item)
+{
+    double bound = 0.0;
+    const char *src = P.ws + (size_t)P.batch.istride * item + P.lay.misc + MISC_BOUND;
+    HIP_TRY(hipMemcpy(&bound, src, sizeof(double), hipMemcpyDeviceToHost));
+    return !(bound <= MIXED_LOGDET_BAR * std::max(std::fabs(logdet), 1.0));
+}
+
 // compression, leaves, levels, finish: everything for one likelihood
 void factor_pipeline(Pipeline &P, const double *d_y, double *d_out)
 {
@@ -235,6 +265,7 @@ struct hodlr_factor_s {
     std::vector<int> rmax, cols, cnt, ranks;
     int capped = 0;
     int device = 0;
+    int fp64_fallback = 0;         // a mixed factor rebuilt with FP64 panels
     int refine_steps = 0;          // largest refinement count of the last solve
     double refine_residual = 0.0;  // largest final relative residual of the last solve
     ~hodlr_factor_s()
@@ -429,6 +460,21 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         double hout[8];
         HIP_TRY(hipMemcpyAsync(hout, d_out, sizeof(double) * 8, hipMemcpyDeviceToHost, P.stream));
         raise_status(read_status(P));
+        if (f->plan.mixed_check && mixed_bound_exceeded(P, hout[1], 0)) {
+            // FP64 panels for this factor (solves still refine, as for mixed)
+            f->plan.precision = HODLR_FP64;
+            f->lay = make_layout(f->plan, true);
+            DevBuf ws64(f->lay.total);
+            ws = std::move(ws64);
+            P.lay = f->lay;
+            P.ws = (char *)ws.p;
+            d_out = wsp<double>(P, P.lay.out);
+            factor_pipeline(P, nullptr, d_out);
+            HIP_TRY(hipMemcpyAsync(hout, d_out, sizeof(double) * 8, hipMemcpyDeviceToHost,
+                                   P.stream));
+            raise_status(read_status(P));
+            f->fp64_fallback = 1;
+        }
         f->logdet = hout[1];
         f->kp = P.kp;
         f->tol = tol;
@@ -667,6 +713,7 @@ hodlr_status hodlr_info(hodlr_factor f, hodlr_info_t *out)
     I.precision = f->opts.precision;
     I.refine_steps = f->refine_steps;
     I.refine_residual = f->refine_residual;
+    I.fp64_fallback = f->fp64_fallback;
     for (int d = 0; d < f->plan.L && d < HODLR_MAX_LEVELS; ++d) {
         int64_t h0 = f->plan.first_at(d), h1 = f->plan.first_at(d + 1);
         int mx = 0;
@@ -704,6 +751,7 @@ hodlr_status hodlr_plan_create(int64_t n, int32_t dim, int32_t leaf, const hodlr
             throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
+        p->make_fp64_shadow();
         *out = p.release();
         return HODLR_OK;
     });
@@ -729,6 +777,7 @@ hodlr_status hodlr_plan_tuned_create(int64_t n, int32_t dim, const hodlr_opts *o
             throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         plan_upload(p->plan);
         p->lay = make_layout(p->plan, false);
+        p->make_fp64_shadow();
         *out = p.release();
         return HODLR_OK;
     });
@@ -746,7 +795,7 @@ hodlr_status hodlr_plan_workspace_size(hodlr_plan p, size_t *bytes)
 {
     if (!p || !bytes)
         return fail(HODLR_EINVAL, "NULL argument");
-    *bytes = p->lay.total;
+    *bytes = p->single_bytes();
     return HODLR_OK;
 }
 
@@ -758,9 +807,9 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         if (!p || !d_x || !d_y || !d_work || !d_out)
             throw Error{HODLR_EINVAL, "NULL argument"};
         check_params(k, theta, sigma2, tol);
-        if (work_bytes < p->lay.total)
-            throw Error{HODLR_EINVAL, "workspace too small: need " + std::to_string(p->lay.total) +
-                                          " bytes"};
+        if (work_bytes < p->single_bytes())
+            throw Error{HODLR_EINVAL, "workspace too small: need " +
+                                          std::to_string(p->single_bytes()) + " bytes"};
         Pipeline P;
         P.plan = &p->plan;
         P.lay = p->lay;
@@ -773,11 +822,27 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         if (d_z)
             run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
         raise_status(read_status(P));
+        int fallback = 0;
+        if (p->plan.mixed_check) {
+            double ld = 0.0;
+            HIP_TRY(hipMemcpy(&ld, d_out + 1, sizeof(double), hipMemcpyDeviceToHost));
+            if (mixed_bound_exceeded(P, ld, 0)) {
+                // the same likelihood with FP64 panels on the same workspace
+                P.plan = &p->plan64;
+                P.lay = p->lay64;
+                factor_pipeline(P, d_y, d_out);
+                if (d_z)
+                    run_widen(P.ws + P.lay.Xt, false, d_z, p->plan.n, P.stream);
+                raise_status(read_status(P));
+                fallback = 1;
+            }
+        }
         {
             std::lock_guard<std::mutex> lk(p->last_mu);
             p->last_rmax = P.rmax;
             p->last_ranks = P.ranks;
             p->last_capped = P.capped;
+            p->last_fallback = fallback;
         }
         return HODLR_OK;
     });
@@ -794,9 +859,10 @@ hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
     I.levels = p->plan.L;
     I.leaf_max = p->plan.leafmax;
     I.precision = p->opts.precision;
-    I.device_bytes = (int64_t)p->lay.total + (int64_t)p->plan.dev_tables_bytes;
+    I.device_bytes = (int64_t)p->single_bytes() + (int64_t)p->plan.dev_tables_bytes;
     std::lock_guard<std::mutex> lk(p->last_mu);
     I.capped_blocks = p->last_capped;
+    I.fp64_fallback = p->last_fallback;
     for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS && d + 1 < (int)p->last_rmax.size();
          ++d) {
         I.rank_max[d] = p->last_rmax[d + 1];
@@ -823,11 +889,113 @@ hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
 
 extern "C" {
 
+// bytes of a batched call's workspace: the items, and for a mixed plan room
+// for one FP64 likelihood at its start (the redo of an item that misses the
+// mixed log-det bar)
+static size_t batch_bytes(hodlr_plan p, int32_t nitems)
+{
+    const size_t b = item_stride(p->lay) * (size_t)nitems;
+    return p->plan.f32() ? std::max(b, p->lay64.total) : b;
+}
+
+// Mixed plans: after the batch, every item whose log-det error bound misses
+// the bar is computed again with FP64 panels on the workspace (in FP64
+// batches when the observations are shared, else one at a time) and its row
+// of d_out replaced (synchronizes the stream).
+static void batch_fp64_redo(hodlr_plan p, const Pipeline &B, const double *d_params, int nitems,
+                            const double *d_y, int64_t y_stride, double *d_out)
+{
+    if (!p->plan.mixed_check)
+        return;
+    std::vector<double> bound(nitems), out(3 * (size_t)nitems), par(3 * (size_t)nitems);
+    HIP_TRY(hipStreamSynchronize(B.stream));
+    HIP_TRY(hipMemcpy2D(bound.data(), sizeof(double), B.ws + B.lay.misc + MISC_BOUND,
+                        (size_t)B.batch.istride, sizeof(double), nitems, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out.data(), d_out, sizeof(double) * out.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(par.data(), d_params, sizeof(double) * par.size(), hipMemcpyDeviceToHost));
+    std::vector<int> flag;
+    for (int i = 0; i < nitems; ++i) {
+        const double ld = out[3 * (size_t)i + 1];
+        if (std::isfinite(ld) && !(bound[i] <= MIXED_LOGDET_BAR * std::max(std::fabs(ld), 1.0)))
+            flag.push_back(i);
+    }
+    const int redo = (int)flag.size();
+    const size_t s64 = item_stride(p->lay64);
+    const size_t room = batch_bytes(p, nitems);
+    // shared observations: the flagged items as FP64 batches (as many as the
+    // workspace holds, their parameters and results after them)
+    size_t k = 0;
+    if (y_stride == 0 && redo > 1)
+        k = std::min<size_t>(redo, (room - 256) / (s64 + 6 * sizeof(double)));
+    for (size_t c0 = 0; k > 1 && c0 < flag.size(); c0 += k) {
+        const size_t kk = std::min(k, flag.size() - c0);
+        double *dpar = (double *)(B.ws + ((kk * s64 + 255) & ~(size_t)255));
+        double *dres = dpar + 3 * kk;
+        std::vector<double> sub(3 * kk), res(3 * kk);
+        for (size_t j = 0; j < kk; ++j)
+            for (int q = 0; q < 3; ++q)
+                sub[3 * j + q] = par[3 * (size_t)flag[c0 + j] + q];
+        HIP_TRY(hipMemcpyAsync(dpar, sub.data(), sizeof(double) * sub.size(), hipMemcpyHostToDevice,
+                               B.stream));
+        Pipeline Q;
+        Q.plan = &p->plan64;
+        Q.lay = p->lay64;
+        Q.ws = B.ws;
+        Q.stream = B.stream;
+        Q.x = B.x;
+        Q.kp = B.kp;
+        Q.tol = B.tol;
+        Q.nitems = (int)kk;
+        Q.batch.istride = (int64_t)s64;
+        Q.batch.params = dpar;
+        Q.batch.ystride = 0;
+        zero_status_kernel<<<(unsigned)kk, 64, 0, Q.stream>>>(wsp<int>(Q, Q.lay.status), Q.batch);
+        HIP_TRY(hipGetLastError());
+        run_aca_batched(Q);
+        make_columns(Q);
+        run_leaf_factor(Q, d_y);
+        run_levels_factor(Q);
+        run_finish(Q, d_y, dres, 3);
+        HIP_TRY(hipMemcpyAsync(res.data(), dres, sizeof(double) * res.size(), hipMemcpyDeviceToHost,
+                               Q.stream));
+        HIP_TRY(hipStreamSynchronize(Q.stream));
+        for (size_t j = 0; j < kk; ++j)
+            for (int q = 0; q < 3; ++q)
+                out[3 * (size_t)flag[c0 + j] + q] = res[3 * j + q];
+    }
+    if (k > 1) {
+        HIP_TRY(hipMemcpy(d_out, out.data(), sizeof(double) * out.size(), hipMemcpyHostToDevice));
+        flag.clear();
+    }
+    for (int i : flag) {
+        Pipeline Q;
+        Q.plan = &p->plan64;
+        Q.lay = p->lay64;
+        Q.ws = B.ws;
+        Q.stream = B.stream;
+        Q.x = B.x;
+        const double th[2] = {par[3 * (size_t)i], par[3 * (size_t)i + 1]};
+        Q.kp = make_kparams(B.kp.kind, p->plan.dim, th, par[3 * (size_t)i + 2]);
+        Q.tol = B.tol;
+        double *o = wsp<double>(Q, Q.lay.out);
+        factor_pipeline(Q, d_y + (size_t)i * y_stride, o);
+        const int st = read_status(Q);
+        const double nan3[3] = {NAN, NAN, NAN};
+        if (st)
+            HIP_TRY(hipMemcpy(d_out + 3 * (size_t)i, nan3, sizeof(nan3), hipMemcpyHostToDevice));
+        else
+            HIP_TRY(hipMemcpy(d_out + 3 * (size_t)i, o, sizeof(double) * 3,
+                              hipMemcpyDeviceToDevice));
+    }
+    std::lock_guard<std::mutex> lk(p->last_mu);
+    p->last_fallback = redo;
+}
+
 hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes)
 {
     if (!p || !bytes || nitems < 1)
         return fail(HODLR_EINVAL, "bad argument");
-    *bytes = item_stride(p->lay) * (size_t)nitems;
+    *bytes = batch_bytes(p, nitems);
     return HODLR_OK;
 }
 
@@ -846,9 +1014,9 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
         if (y_stride < 0)
             throw Error{HODLR_EINVAL, "y_stride must be >= 0"};
         const size_t istride = item_stride(p->lay);
-        if (work_bytes < istride * (size_t)nitems)
+        if (work_bytes < batch_bytes(p, nitems))
             throw Error{HODLR_EINVAL, "workspace too small: need " +
-                                          std::to_string(istride * (size_t)nitems) + " bytes"};
+                                          std::to_string(batch_bytes(p, nitems)) + " bytes"};
         if (p->plan.leafmax > LEAF_MAX)
             throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
         Pipeline P;
@@ -879,6 +1047,7 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
             run_leaf_factor(P, d_y);
             run_levels_factor(P);
             run_finish(P, d_y, d_out, 3);
+            batch_fp64_redo(p, P, d_params, nitems, d_y, y_stride, d_out);
             return HODLR_OK;
         }
         BatchGraph *hit = nullptr;
@@ -931,6 +1100,7 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
             hit = &p->graphs.back();
         }
         HIP_TRY(hipGraphLaunch(hit->exec, P.stream));
+        batch_fp64_redo(p, P, d_params, nitems, d_y, y_stride, d_out);
         return HODLR_OK;
     });
 }

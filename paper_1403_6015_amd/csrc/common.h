@@ -241,6 +241,7 @@ struct Plan {
     double refine_tol = 1e-10;
     int max_refine = 8;
     bool refine = false;       // host solves refine against the exact product (always when mixed)
+    bool mixed_check = false;  // mixed form: test the log-det error bound, redo in FP64 if missed
     int64_t nint = 0;    // internal (split) nodes 2^L - 1
     int64_t nleaf = 1;   // 2^L
     int leafmax = 0;
@@ -296,6 +297,10 @@ struct Plan {
     bool f32() const { return precision == HODLR_MIXED; }
     size_t panel_bytes() const { return f32() ? sizeof(float) : sizeof(double); }
 };
+
+// byte offset in the workspace's misc area of the mixed form's log-det error
+// bound (one double per item, written by the finish kernel)
+constexpr size_t MISC_BOUND = 3072;
 
 // Workspace layout (byte offsets into one device buffer).
 struct Layout {
@@ -404,6 +409,9 @@ void make_columns(Pipeline &P);                                // column list af
 int read_status(Pipeline &P);                                  // synchronizes the stream
 void raise_status(int st);
 void factor_pipeline(Pipeline &P, const double *d_y, double *d_out);
+// mixed form: true if the log-det error bound of batch item `item` (written by
+// the finish kernel) exceeds the 1e-8 bar for this log det (synchronizes)
+bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item);
 int *pinned_scratch();                                         // per-thread pinned ints
 
 template <typename T>

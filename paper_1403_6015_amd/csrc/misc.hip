@@ -52,28 +52,40 @@ __device__ __forceinline__ double strided_sum(const double *v, int64_t cnt)
 __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int64_t nleaf,
                                                      const double *node_ld, int64_t nint,
                                                      const double *dpart, int ndp, int64_t n,
-                                                     double *out, int ostride, BatchArgs B)
+                                                     double *out, int ostride, double *bound,
+                                                     BatchArgs B)
 {
     const int it = blockIdx.z;
     leaf_ld = ioff(leaf_ld, B, it);
     node_ld = ioff(node_ld, B, it);
     dpart = ioff(dpart, B, it);
+    bound = ioff(bound, B, it);
     out += (int64_t)it * ostride;
-    __shared__ double red[3][4];
+    __shared__ double red[4][4];
     double a = strided_sum(leaf_ld, nleaf);
     double b = strided_sum(node_ld, nint);
     double q = strided_sum(dpart, ndp);
+    // the mixed form's log-det error bound: FP32 unit roundoff times the sum
+    // over nodes of 1 / det M_tau (its rounding of W~ perturbs each I - QP by
+    // about the unit roundoff, which the inverse of I - QP amplifies; det M_tau
+    // bounds the smallest eigenvalue of I - QP from above)
+    double e = 0.0;
+    for (int64_t i = threadIdx.x; i < nint; i += 256)
+        e += exp(-node_ld[i]);
     a = wave_sum(a);
     b = wave_sum(b);
     q = wave_sum(q);
+    e = wave_sum(e);
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
         red[0][w] = a;
         red[1][w] = b;
         red[2][w] = q;
+        red[3][w] = e;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        *bound = 0x1p-24 * ((red[3][0] + red[3][1]) + (red[3][2] + red[3][3]));
         double la = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
         double lb = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
         double qq = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
@@ -106,7 +118,7 @@ void run_finish(Pipeline &P, const double *y, double *d_out, int ostride)
     }
     finish_kernel<<<dim3(1, 1, P.nitems), 256, 0, P.stream>>>(
         wsp<double>(P, P.lay.leaf_ld), p.nleaf, wsp<double>(P, P.lay.node_ld), p.nint, dpart, ndp,
-        p.n, d_out, ostride, P.batch);
+        p.n, d_out, ostride, wsp<double>(P, P.lay.misc + MISC_BOUND), P.batch);
     HIP_TRY(hipGetLastError());
 }
 

@@ -2,6 +2,7 @@
 // share.
 #pragma once
 
+#include <algorithm>
 #include <mutex>
 
 #include "common.h"
@@ -27,6 +28,20 @@ struct hodlr_plan_s {
     hodlr::Plan plan;
     hodlr::Layout lay;
     hodlr_opts opts;
+    // mixed plans: the same tree with FP64 panels (sharing the device tables)
+    // for likelihoods whose mixed log-det error bound misses the bar
+    hodlr::Plan plan64;
+    hodlr::Layout lay64;
+    void make_fp64_shadow()
+    {
+        if (!plan.f32())
+            return;
+        plan64 = plan;
+        plan64.precision = HODLR_FP64;
+        lay64 = hodlr::make_layout(plan64, false);
+    }
+    // one likelihood (gp_loglik_dev): room for the FP64 redo of a mixed plan
+    size_t single_bytes() const { return plan.f32() ? std::max(lay.total, lay64.total) : lay.total; }
     std::vector<BatchGraph> graphs;
     // ranks of the last gp_loglik_dev call that completed (per node and per
     // depth) or of the last batched call's compression (per depth, maxima over
@@ -34,6 +49,7 @@ struct hodlr_plan_s {
     std::mutex last_mu;
     std::vector<int> last_ranks, last_rmax;
     int last_capped = 0;
+    int last_fallback = 0;   // likelihoods of the last call redone with FP64 panels
     ~hodlr_plan_s()
     {
         for (auto &g : graphs) {

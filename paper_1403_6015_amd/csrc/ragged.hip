@@ -133,13 +133,21 @@ void worker(RaggedJob *J)
             if (plan.leafmax > LEAF_MAX)
                 throw Error{HODLR_EINVAL, "leaf above 256"};
             Layout lay = make_layout(plan, false);
+            Plan plan64;
+            Layout lay64 = lay;
+            if (plan.f32()) {   // the FP64 redo's layout shares the workspace
+                Plan q = plan;
+                q.precision = HODLR_FP64;
+                lay64 = make_layout(q, false);
+            }
+            const size_t wsz = std::max(lay.total, lay64.total);
             size_t tb = plan_image(plan, image);
             // arena: [workspace | tables | x | y]
-            if (a256(lay.total) + a256(tb) + a256(sizeof(double) * n * dim) +
-                    sizeof(double) * n > J->arena)
+            if (a256(wsz) + a256(tb) + a256(sizeof(double) * n * dim) + sizeof(double) * n >
+                J->arena)
                 throw Error{HODLR_ENOMEM, "item layout exceeds the worker arena"};
             char *ws = arena;
-            char *tables = arena + a256(lay.total);
+            char *tables = arena + a256(wsz);
             double *dx = (double *)(tables + a256(tb));
             double *dy = dx + (size_t)n * dim;
             HIP_TRY(hipMemcpyAsync(tables, image.data(), tb, hipMemcpyHostToDevice, s));
@@ -163,6 +171,17 @@ void worker(RaggedJob *J)
             factor_pipeline(P, dy, d_out);
             HIP_TRY(hipMemcpyAsync(host_out, d_out, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
             int st = read_status(P);   // synchronizes: host buffers above are free again
+            if (!st && plan.mixed_check && mixed_bound_exceeded(P, host_out[1], 0)) {
+                plan64 = plan;   // bound to the uploaded tables
+                plan64.precision = HODLR_FP64;
+                P.plan = &plan64;
+                P.lay = lay64;
+                d_out = wsp<double>(P, lay64.out);
+                factor_pipeline(P, dy, d_out);
+                HIP_TRY(hipMemcpyAsync(host_out, d_out, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                                       s));
+                st = read_status(P);
+            }
             if (st)
                 nan_out(o);
             else
@@ -213,6 +232,7 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
             J.opts.presorted = 0;
             J.opts.noise = nullptr;
             J.opts.refine = 0;
+            J.opts.mixed_unchecked = 0;
         }
         if (J.opts.max_rank < 0 || J.opts.max_rank > RMAX_ABS ||
             (J.opts.precision != HODLR_FP64 && J.opts.precision != HODLR_MIXED))
@@ -232,6 +252,7 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
         plan_build(big, nmax, dim, leaf, &J.opts, 256, 4, 8);
         std::vector<char> img;
         size_t tb = plan_image(big, img);
+        big.precision = HODLR_FP64;   // room for an FP64 redo of a mixed item
         Layout lay = make_layout(big, false);
         J.arena = a256(lay.total) + a256(tb) + 2 * a256(sizeof(double) * nmax * (dim + 1)) + 4096;
         if (hipGetDevice(&J.device) != hipSuccess)

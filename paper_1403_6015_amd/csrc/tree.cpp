@@ -93,6 +93,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
     p.refine_tol = (opts && opts->refine_tol > 0) ? opts->refine_tol : 1e-10;
     p.max_refine = opts ? opts->max_refine : 8;   // checked >= 0 by the entry points
     p.refine = p.precision == HODLR_MIXED || (opts && opts->refine);
+    p.mixed_check = p.precision == HODLR_MIXED && !(opts && opts->mixed_unchecked);
     const int L = p.L;
     const int64_t nn = ((int64_t)2 << L) - 1;
     p.nint = ((int64_t)1 << L) - 1;

@@ -131,6 +131,7 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
             o.presorted = 0;
             o.noise = nullptr;
             o.refine = 0;
+            o.mixed_unchecked = 0;
         }
         if (o.max_rank < 0 || o.max_rank > RMAX_ABS ||
             (o.precision != HODLR_FP64 && o.precision != HODLR_MIXED))

@@ -101,6 +101,13 @@ def test_mixed_device_form_logdet_and_unrefined_quad():
     assert abs(o[2] - kf["quad"]) <= 1e-6 * abs(kf["quad"])
     o64, *_ = _dev_call(p, H.Opts(max_rank=16))
     assert abs(o64[1] - kf["logdet"]) <= 1e-10 * abs(kf["logdet"])
+    # unchecked: the FP32-panel result itself (no bound test, no FP64 redo)
+    ou, plan, *_ = _dev_call(p, _mixed(max_rank=16, mixed_unchecked=1))
+    eu = abs(ou[1] - kf["logdet"]) / abs(kf["logdet"])
+    print("mixed dev unchecked logdet rel %.3e" % eu)
+    assert plan.info()["fp64_fallback"] == 0
+    assert eu <= 1e-8
+    assert abs(ou[2] - kf["quad"]) <= 1e-6 * abs(kf["quad"])
 
 
 def test_mixed_batched_items_equal_single_device_calls():
@@ -141,7 +148,7 @@ def test_2d_se_capped_matches_dense_oracle(precision):
     refinement against the exact product (the FP64 factor applied once leaves
     tol ||K|| / sigma^2 ~ 1e-7 here, so the FP64 form is built with
     refine = 1).  The mixed form's log det is held to the 1e-8 mixed-form
-    bar in the test below."""
+    bar (a factor whose error bound misses it is rebuilt with FP64 panels)."""
     p = wl.se2d(4096)
     announce("2-D SE n=%d precision=%d" % (p.n, precision))
     opts = H.Opts(max_rank=64, precision=precision, refine=1)
@@ -154,10 +161,10 @@ def test_2d_se_capped_matches_dense_oracle(precision):
     C = oracle.dense_matrix(p.x, p.kernel, p.theta, p.sigma2)
     res = np.linalg.norm(p.y - C @ z) / np.linalg.norm(p.y)
     rel = abs(ld - ref["logdet"]) / abs(ref["logdet"])
-    print("2-D SE precision %d logdet rel %.3e residual %.3e ranks %s refine steps %d" % (
-        precision, rel, res, info["rank_max"], info["refine_steps"]))
-    if precision == H.FP64:
-        assert rel <= 1e-10
+    print("2-D SE precision %d logdet rel %.3e residual %.3e ranks %s refine steps %d "
+          "fp64 fallback %d" % (precision, rel, res, info["rank_max"], info["refine_steps"],
+                                info["fp64_fallback"]))
+    assert rel <= (1e-10 if precision == H.FP64 else 1e-8)
     assert res <= 1e-10
     assert info["refine_residual"] <= 1e-10
 
@@ -177,3 +184,37 @@ def test_mixed_max_refine_zero_takes_one_step():
     assert e.value.name == "ENOCONV"
     assert info["refine_steps"] <= 0
     assert 0.0 < info["refine_residual"] < 1e-4
+
+
+def test_mixed_batched_full_size_meets_the_logdet_bar():
+    """The batched configuration in the mixed form (256 hyperparameter
+    settings, n = 65536): every item's log det within 1e-8 of the Kalman
+    oracle (relative to max(|log det|, 1)).  Items whose FP32-panel error
+    bound misses the bar are redone with FP64 panels; the count is printed."""
+    import torch
+    n, m = 65536, 256
+    x, y, th = wl.batched_theta(m=m, n=n)
+    announce("mixed batched full size n=%d m=%d" % (n, m))
+    plan = H.Plan(n, 1, 128, _mixed(max_rank=16, presorted=1))
+    nb = plan.batch_workspace_bytes(m)
+    d_x = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    d_y = torch.from_numpy(y).cuda()
+    d_p = torch.from_numpy(np.ascontiguousarray(th)).cuda()
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    out = torch.full((m, 3), np.nan, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        H.gp_loglik_batch_dev(plan, d_x, H.K_MATERN32, d_p, m, d_y, 0, 1e-10, work, nb, stream,
+                              out, True)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    redo = plan.info()["fp64_fallback"]
+    worst = 0.0
+    for i in range(m):
+        a, ell, s2 = th[i]
+        kf = oracle.kalman_matern32(x[:, 0], y, (a, ell), s2, want_alpha=False)
+        e = abs(res[i, 1] - kf["logdet"]) / max(abs(kf["logdet"]), 1.0)
+        worst = max(worst, e)
+        assert e <= 1e-8, (i, e, (a, ell, s2))
+    print("mixed batch: worst log det rel %.2e, %d of %d items redone with FP64 panels"
+          % (worst, redo, m), flush=True)
