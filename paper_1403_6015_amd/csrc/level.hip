@@ -555,6 +555,30 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
 #undef t1
 #undef t2
 
+// a - sum_{k < r} x(k) y(k), the terms subtracted in order of k, with the
+// operand loads of 8 terms issued together (the operands of these node-solve
+// products come from HBM and L2, and one term at a time would wait on every
+// load)
+template <typename FX, typename FY>
+__device__ __forceinline__ double dot_sub(double a, int r, FX x, FY y)
+{
+    int k = 0;
+    for (; k + 8 <= r; k += 8) {
+        double xv[8], yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            xv[u] = x(k + u);
+            yv[u] = y(k + u);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            a -= xv[u] * yv[u];
+    }
+    for (; k < r; ++k)
+        a -= x(k) * y(k);
+    return a;
+}
+
 // Node solves of levels whose rank is above RMAX_LDS (the LDS path's bound).
 // The node's matrices live in its slot of the small-factor store (HBM),
 //   [N^{-1} (r x r) | P | Q | N, overwritten by its LU | pivots (r)],
@@ -605,10 +629,8 @@ __global__ __launch_bounds__(LVW_TH) void level_solve_wide_kernel(LevelArgs A0)
         for (int64_t idx = tid; idx < rr; idx += LVW_TH) {
             const int i = (int)(idx / r), j = (int)(idx % r);
             const double *qi = Q + (int64_t)i * r;
-            double a = (i == j) ? 1.0 : 0.0;
-            for (int k = 0; k < r; ++k)
-                a -= qi[k] * P[(int64_t)k * r + j];
-            N[idx] = a;
+            N[idx] = dot_sub((i == j) ? 1.0 : 0.0, r, [&](int k) { return qi[k]; },
+                             [&](int k) { return P[(int64_t)k * r + j]; });
         }
         __syncthreads();
         for (int k = 0; k < r; ++k) {
@@ -732,28 +754,254 @@ __global__ __launch_bounds__(LVW_TH) void level_solve_wide_kernel(LevelArgs A0)
     for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // u = t2 - Q t1
         const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
         const double *qi = Q + (int64_t)i * r;
-        double a = T[(int64_t)(rs + i) * ncnt + c];
-        for (int k = 0; k < r; ++k)
-            a -= qi[k] * T[(int64_t)k * ncnt + c];
-        S[(int64_t)i * nrhs + c] = a;
+        S[(int64_t)i * nrhs + c] =
+            dot_sub(T[(int64_t)(rs + i) * ncnt + c], r, [&](int k) { return qi[k]; },
+                    [&](int k) { return T[(int64_t)k * ncnt + c]; });
     }
     __syncthreads();
     for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // s2 = N^{-1} u
         const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
         const double *ni = Ninv + (int64_t)i * r;
-        double a = 0.0;
-        for (int k = 0; k < r; ++k)
-            a += ni[k] * S[(int64_t)k * nrhs + c];
-        S[(int64_t)(rs + i) * nrhs + c] = a;
+        S[(int64_t)(rs + i) * nrhs + c] =
+            dot_sub(0.0, r, [&](int k) { return -ni[k]; },
+                    [&](int k) { return S[(int64_t)k * nrhs + c]; });
     }
     __syncthreads();
     for (int64_t idx = tid; idx < nout; idx += LVW_TH) {   // s1 = t1 - P s2
         const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
         const double *pi = P + (int64_t)i * r;
-        double a = T[(int64_t)i * ncnt + c];
-        for (int k = 0; k < r; ++k)
-            a -= pi[k] * S[(int64_t)(rs + k) * nrhs + c];
-        S[(int64_t)i * nrhs + c] = a;
+        S[(int64_t)i * nrhs + c] =
+            dot_sub(T[(int64_t)i * ncnt + c], r, [&](int k) { return pi[k]; },
+                    [&](int k) { return S[(int64_t)(rs + k) * nrhs + c]; });
+    }
+}
+
+// Node solves of levels whose rank is above RMAX_LDS and at most LVG_RMAX,
+// with N in LDS: the same small-factor store as level_solve_wide_kernel
+// ([N^{-1} | P | Q | unused | unused]) and the same products, but N = I - Q P
+// is inverted in place by Gauss-Jordan elimination with partial pivoting
+// (first largest |N(i, k)| over i >= k, rows swapped), on 1024 threads with
+// three barriers per pivot.  Its pivots are those of the LU factorization with
+// the same pivoting, so log det M = sum log |pivot| and the sign of det N is
+// the parity of the negative pivots and the row swaps, checked as on the
+// other paths.  The eliminated array is N^{-1} with permuted columns: column
+// c of N^{-1} is its column sig(c), sig(c) = s_{r-1}(... s_0(c)), s_k the
+// swap of k and the k-th pivot row.
+constexpr int LVG_TH = 1024;
+constexpr int LVG_RMAX = 128;
+
+static_assert(LVG_TH % LVG_RMAX == 0 && LVG_RMAX <= LVG_TH, "thread map of the Gauss-Jordan kernel");
+
+static size_t gj_lds(int rs)
+{
+    return sizeof(double) * ((size_t)rs * (rs + 1) + 3 * (size_t)rs) + sizeof(int) * 2 * (size_t)rs;
+}
+
+__global__ __launch_bounds__(LVG_TH) void level_solve_gj_kernel(LevelArgs A0)
+{
+    const LevelArgs A = item_args(A0);
+    const int64_t loc = blockIdx.x;
+    const int64_t h = A.node0 + loc;
+    const int r = A.rank[h];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // element loops: thread (ti, tj) takes column tj of rows ti, ti + 8, ...
+    constexpr int TI = LVG_TH / LVG_RMAX;
+    const int tj = tid & (LVG_RMAX - 1), ti = tid / LVG_RMAX;
+    if (r == 0) {
+        if (A.factor && tid == 0)
+            A.node_ld[h] = 0.0;
+        return;
+    }
+    extern __shared__ double gsh[];
+    const int ld = r + 1;
+    double *sA = gsh;                       // r x ld, row-major
+    double *rowp = sA + (int64_t)r * ld;    // step k: the pivot row (row p before the swap)
+    double *rowo = rowp + r;                // step k: row k before the swap (moves to row p)
+    double *colk = rowo + r;                // step k: column k after the swap; then the pivots
+    int *piv = (int *)(colk + r);
+    int *sig = piv + r;
+    __shared__ double s_pv[LVG_RMAX], red[LVG_TH / 64];
+    __shared__ int sneg[LVG_TH / 64], s_bad;
+    const int ncnt = A.ncnt, rs = A.rstride, nrhs = A.nrhs;
+    const double *T = A.Tbuf + loc * A.tstride;
+    double *sm = A.small + h * A.sstride;
+    const int64_t rr = (int64_t)r * r;
+    double *Ninv = sm, *P = sm + rr, *Q = sm + 2 * rr;
+    if (A.factor) {
+        const int cp = nrhs;   // the child panel's columns follow the updated ones
+        // P and Q into the store, Q also into sA; then N = I - Q P with
+        // thread (ti, tj) holding rows ti + 8 m of column tj in registers,
+        // Q's entries from LDS (one address per wave) and P's rows from T,
+        // 8 rows per round
+        if (tj < r)
+            for (int i = ti; i < r; i += TI) {
+                const double q = T[(int64_t)(rs + i) * ncnt + cp + tj];
+                P[(int64_t)i * r + tj] = T[(int64_t)i * ncnt + cp + tj];
+                Q[(int64_t)i * r + tj] = q;
+                sA[i * ld + tj] = q;
+            }
+        if (tid == 0)
+            s_bad = 0;
+        __syncthreads();
+        constexpr int NM = LVG_RMAX / TI;
+        double acc[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            acc[m] = (ti + TI * m == tj) ? 1.0 : 0.0;
+        if (tj < r) {
+            for (int k0 = 0; k0 < r; k0 += 8) {
+                double pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    pv[u] = (k0 + u < r) ? T[(int64_t)(k0 + u) * ncnt + cp + tj] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + u < r)
+#pragma unroll
+                        for (int m = 0; m < NM; ++m) {
+                            const int i = ti + TI * m;
+                            if (i < r)
+                                acc[m] -= sA[i * ld + k0 + u] * pv[u];
+                        }
+            }
+        }
+        __syncthreads();   // every read of Q in sA done
+        if (tj < r)
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const int i = ti + TI * m;
+                if (i < r)
+                    sA[i * ld + tj] = acc[m];
+            }
+        __syncthreads();
+        for (int k = 0; k < r; ++k) {
+            if (wid == 0) {   // pivot: the first largest |N(i, k)|, i >= k
+                double bv = -1.0;
+                int bi = r;
+                for (int i = k + lane; i < r; i += 64) {
+                    const double v = fabs(sA[i * ld + k]);
+                    if (v > bv) {
+                        bv = v;
+                        bi = i;
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off, 64);
+                    const int oi = __shfl_xor(bi, off, 64);
+                    if (ov > bv || (ov == bv && oi < bi)) {
+                        bv = ov;
+                        bi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    const int p = bi < r ? bi : k;
+                    piv[k] = p;
+                    const double pv = sA[p * ld + k];
+                    if (!(bv > 0.0))
+                        s_bad = 1;
+                    s_pv[k] = pv != 0.0 ? pv : 1.0;   // flagged above; values stay finite
+                }
+            }
+            __syncthreads();
+            // rows k and p swapped: the pivot row, the row it displaces and
+            // column k as they are after the swap, read before any write
+            const int p = piv[k];
+            if (tid < r) {
+                rowp[tid] = sA[p * ld + tid];
+                rowo[tid] = sA[k * ld + tid];
+                const int src = (tid == k) ? p : (tid == p) ? k : tid;
+                colk[tid] = sA[src * ld + k];
+            }
+            __syncthreads();
+            // the elimination: every entry is written by the thread that
+            // reads it, rows k and p (p != k) from the saved copies
+            const double inv = 1.0 / s_pv[k];
+            if (tj < r) {
+                const double rk = rowp[tj] * inv;
+                for (int i = ti; i < r; i += TI) {
+                    double v;
+                    if (i == k) {
+                        v = (tj == k) ? inv : rk;
+                    } else {
+                        const double old = (i == p) ? rowo[tj] : sA[i * ld + tj];
+                        v = (tj == k) ? -colk[i] * inv : old - colk[i] * rk;
+                    }
+                    sA[i * ld + tj] = v;
+                }
+            }
+            __syncthreads();
+        }
+        // column permutation of the inverse, log det and its sign
+        double lg = 0.0;
+        int neg = 0;
+        if (tid < r) {
+            int v = tid;
+            for (int k = 0; k < r; ++k) {
+                const int pk = piv[k];
+                v = (v == k) ? pk : (v == pk) ? k : v;
+            }
+            sig[tid] = v;
+            lg = log(fabs(s_pv[tid]));
+            neg = (s_pv[tid] < 0.0 ? 1 : 0) + (piv[tid] != tid ? 1 : 0);
+        }
+        lg = wave_sum(lg);
+        for (int off = 32; off > 0; off >>= 1)
+            neg += __shfl_xor(neg, off, 64);
+        if (lane == 0) {
+            red[wid] = lg;
+            sneg[wid] = neg;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = 0.0;
+            int ng = 0;
+            for (int w = 0; w < LVG_TH / 64; ++w) {
+                v += red[w];
+                ng += sneg[w];
+            }
+            if (s_bad || (ng & 1)) {
+                atomicOr(A.status, DS_NOTSPD_NODE);
+                v = __builtin_nan("");
+            }
+            A.node_ld[h] = v;
+        }
+        if (tj < r)
+            for (int i = ti; i < r; i += TI)
+                Ninv[(int64_t)i * r + tj] = sA[i * ld + sig[tj]];
+    }
+    // S = M^{-1} T on the columns to update (N^{-1} from LDS when just
+    // factored, else from the store)
+    double *S = A.Sbuf + loc * A.tstride;
+    const int64_t nout = (int64_t)r * nrhs;
+    for (int64_t idx = tid; idx < nout; idx += LVG_TH) {   // u = t2 - Q t1
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        const double *qi = Q + (int64_t)i * r;
+        S[(int64_t)i * nrhs + c] =
+            dot_sub(T[(int64_t)(rs + i) * ncnt + c], r, [&](int k) { return qi[k]; },
+                    [&](int k) { return T[(int64_t)k * ncnt + c]; });
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < nout; idx += LVG_TH) {   // s2 = N^{-1} u
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        double a;
+        if (A.factor) {
+            const double *ni = sA + i * ld;
+            a = dot_sub(0.0, r, [&](int k) { return -ni[sig[k]]; },
+                        [&](int k) { return S[(int64_t)k * nrhs + c]; });
+        } else {
+            const double *ni = Ninv + (int64_t)i * r;
+            a = dot_sub(0.0, r, [&](int k) { return -ni[k]; },
+                        [&](int k) { return S[(int64_t)k * nrhs + c]; });
+        }
+        S[(int64_t)(rs + i) * nrhs + c] = a;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < nout; idx += LVG_TH) {   // s1 = t1 - P s2
+        const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+        const double *pi = P + (int64_t)i * r;
+        S[(int64_t)i * nrhs + c] =
+            dot_sub(T[(int64_t)i * ncnt + c], r, [&](int k) { return pi[k]; },
+                    [&](int k) { return S[(int64_t)(rs + k) * nrhs + c]; });
     }
 }
 
@@ -761,98 +1009,110 @@ __global__ __launch_bounds__(LVW_TH) void level_solve_wide_kernel(LevelArgs A0)
 // FP64 MFMA (v_mfma_f64_16x16x4; lane l = 16 q + r supplies A[r][q] and
 // B[q][r] of a 16 x 4 by 4 x 16 step and holds D[q + 4 t][r], t < 4).
 typedef double lv_d4 __attribute__((ext_vector_type(4)));
-constexpr int LVM_NT = 4;   // 16-column tiles per work-group (one per wave in the reduction)
-constexpr int LVM_U = 4;    // 4-row steps whose loads are issued together
-constexpr int LVM_CPW = 2;  // column tiles per wave in the reduction
 constexpr int LVM_UNT = 8;  // 16-column tiles per work-group in the update
 
-// T_part[chunk] = W_chunk^T X_chunk: M = ranks (16 per tile, MT tiles: the
-// level's reserved rank rounded up), N = 16 columns per tile, LVM_CPW tiles
-// per wave, K = the chunk's rows.  Every wave takes all rank tiles of its
-// column tiles, so each X column of the chunk is read once and the chunk's W
-// rows by the 4 waves of a work-group (from L1), once per 128 columns.
-template <typename PT, int MT>
-__global__ __launch_bounds__(LV_THREADS) void level_reduce_mfma_kernel(LevelArgs A0)
+// T_part[chunk] = W_chunk^T X_chunk with both operands staged in LDS: the
+// chunk's rows go through 64 at a time, lane = row, so every load of a
+// column-major panel is 512 contiguous bytes; wave w stages columns w, w + 4,
+// ... of this work-group's 64 CPW columns and ranks w, w + 4, ... of its rank
+// group (16 MT ranks).  The next step's loads are issued into registers
+// before the current step's MFMAs (16 steps of 4 rows from LDS), so they are
+// in flight while the matrix cores work.  Wave w owns column tiles w, w + 4;
+// blockIdx.y = column block + (column blocks) x rank group.  The records are
+// those of the other reductions.
+constexpr int RL_ROWS = 64;
+
+template <typename PT, int MT, int CPW>
+__global__ __launch_bounds__(LV_THREADS) void level_reduce_lds_kernel(LevelArgs A0)
 {
+    constexpr int NCOL = 64 * CPW;   // columns per work-group
+    constexpr int NR = 16 * MT;      // ranks per group
+    constexpr int XPT = NCOL / 4, WPT = NR / 4;   // values each lane stages per step
     const LevelArgs A = item_args(A0);
     const Chunk ch = A.chunks[blockIdx.x];
     const int r = A.rank[ch.node];
-    if (r == 0)
-        return;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int ncb = (A.ncnt + NCOL - 1) / NCOL;
+    const int r0 = NR * (int)(blockIdx.y / ncb);
+    const int c0 = NCOL * (int)(blockIdx.y % ncb);
+    if (r == 0 || r0 >= r)
+        return;   // the whole work-group
+    __shared__ double sX[RL_ROWS][NCOL + 1];
+    __shared__ double sW[RL_ROWS][NR + 1];
+    __shared__ int scol[NCOL];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
-    // blockIdx.y = column block + (column blocks) x rank group: ranks above
-    // 16 MT go to further groups of 16 MT, each re-reading the chunk's X
-    const int ncb = (A.ncnt + 16 * LVM_NT * LVM_CPW - 1) / (16 * LVM_NT * LVM_CPW);
-    const int r0 = 16 * MT * (int)(blockIdx.y / ncb);
-    const int ct0 = ((blockIdx.y % ncb) * LVM_NT + wid) * LVM_CPW;   // this wave's first column tile
-    if (ct0 * 16 >= A.ncnt || r0 >= r)
-        return;   // the whole wave; no work-group barrier follows
     const int64_t n = A.n;
-    // lanes past the last column or rank read a valid column (the first one)
-    // and drop the value, so the loads need no branches
-    const PT *xcol[LVM_CPW];
-    bool cok[LVM_CPW];
+    const PT *__restrict__ Xp = (const PT *)A.Xt;
+    const double *__restrict__ Wp = A.W + A.colW * n;
+    // columns past the last one read the first column and store zero
+    for (int c = tid; c < NCOL; c += LV_THREADS)
+        scol[c] = A.cols[c0 + c < A.ncnt ? c0 + c : 0];
+    __syncthreads();
+    double xr[XPT], wr[WPT];
+    auto load = [&](int64_t i0) {
+        const int64_t i = i0 + lane;
+        const bool ok = i < ch.hi;
+        const int64_t is = ok ? i : ch.lo;
 #pragma unroll
-    for (int j = 0; j < LVM_CPW; ++j) {
-        const int c = (ct0 + j) * 16 + lr;
-        cok[j] = c < A.ncnt;
-        xcol[j] = (const PT *)A.Xt + (int64_t)A.cols[cok[j] ? c : 0] * n;
-    }
-    const double *wcol[MT];
-    bool wok[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        const int l = r0 + 16 * m + lr;
-        wok[m] = l < r;
-        wcol[m] = A.W + (A.colW + (wok[m] ? l : 0)) * n;
-    }
-    lv_d4 acc[MT][LVM_CPW];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < LVM_CPW; ++j)
-            acc[m][j] = lv_d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += 4 * LVM_U) {
-        double bv[LVM_CPW][LVM_U], av[MT][LVM_U];
-#pragma unroll
-        for (int u = 0; u < LVM_U; ++u) {
-            const int64_t i = i0 + 4 * u + lq;
-            const bool ok = i < ch.hi;
-            const int64_t is = ok ? i : ch.lo;
-#pragma unroll
-            for (int j = 0; j < LVM_CPW; ++j) {
-                const double xv = (double)xcol[j][is];
-                bv[j][u] = (cok[j] && ok) ? xv : 0.0;
-            }
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const double wv = wcol[m][is];
-                av[m][u] = (wok[m] && ok) ? wv : 0.0;
-            }
+        for (int k = 0; k < XPT; ++k) {
+            const int c = wid + 4 * k;
+            const double v = (double)Xp[(int64_t)scol[c] * n + is];
+            xr[k] = (ok && c0 + c < A.ncnt) ? v : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < LVM_U; ++u)
+        for (int k = 0; k < WPT; ++k) {
+            const int l = r0 + wid + 4 * k;
+            const double v = Wp[(int64_t)(l < r ? l : 0) * n + is];
+            wr[k] = (ok && l < r) ? v : 0.0;
+        }
+    };
+    lv_d4 acc[CPW][MT];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            acc[j][m] = lv_d4{0.0, 0.0, 0.0, 0.0};
+    load(ch.lo);
+    for (int64_t i0 = ch.lo; i0 < ch.hi; i0 += RL_ROWS) {
+        __syncthreads();   // the previous step's operands consumed
+#pragma unroll
+        for (int k = 0; k < XPT; ++k)
+            sX[lane][wid + 4 * k] = xr[k];
+#pragma unroll
+        for (int k = 0; k < WPT; ++k)
+            sW[lane][wid + 4 * k] = wr[k];
+        __syncthreads();
+        if (i0 + RL_ROWS < ch.hi)
+            load(i0 + RL_ROWS);
+#pragma unroll 4
+        for (int ks = 0; ks < RL_ROWS / 4; ++ks) {
+            const int kr = 4 * ks + lq;
+            double a[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m)
+                a[m] = sW[kr][16 * m + lr];
 #pragma unroll
-                for (int j = 0; j < LVM_CPW; ++j)
-                    acc[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m][u], bv[j][u], acc[m][j],
-                                                                     0, 0, 0);
+            for (int j = 0; j < CPW; ++j) {
+                const double b = sX[kr][16 * (wid + 4 * j) + lr];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[j][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b, acc[j][m], 0, 0, 0);
+            }
+        }
     }
-    // lane (lr, lq) holds T[16 m + lq + 4 t][16 (ct0 + j) + lr]
+    // lane (lr, lq) holds T[rank r0 + 16 m + lq + 4 t][column c0 + 16 (wid + 4 j) + lr]
     double *rec = A.part + (int64_t)ch.part * A.rstride * A.ncnt;
 #pragma unroll
-    for (int j = 0; j < LVM_CPW; ++j) {
-        const int c = (ct0 + j) * 16 + lr;
-        if (cok[j]) {
+    for (int j = 0; j < CPW; ++j) {
+        const int c = c0 + 16 * (wid + 4 * j) + lr;
+        if (c < A.ncnt) {
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int l = r0 + 16 * m + lq + 4 * t;
                     if (l < r)
-                        rec[(int64_t)l * A.ncnt + c] = acc[m][j][t];
+                        rec[(int64_t)l * A.ncnt + c] = acc[j][m][t];
                 }
         }
     }
@@ -945,6 +1205,8 @@ static size_t solve_lds(int rs)
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         HIP_TRY(hipFuncSetAttribute((const void *)level_solve_kernel<64>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void *)level_solve_gj_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)gj_lds(LVG_RMAX)));
         attr = true;
     }
     return sizeof(double) * ((size_t)3 * rs * (rs + 1) + (size_t)2 * rs * (LV_CB + 1) + 1);
@@ -1022,17 +1284,26 @@ static void reduce_small_launch(int R, int sr, int cu, dim3 grid, hipStream_t s,
         reduce_small_rows<PT, 8>(sr, cu, grid, s, A);
 }
 
+// the LDS-staged reduction: rank groups of 16 MT (MT = ranks / 16 rounded up,
+// at most 4), 64 or 128 columns per work-group
 template <typename PT>
-static void reduce_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs &A)
+static void reduce_lds_launch(unsigned nchunks, unsigned nitems, hipStream_t s, const LevelArgs &A)
 {
-    if (mt == 1)
-        level_reduce_mfma_kernel<PT, 1><<<grid, LV_THREADS, 0, s>>>(A);
-    else if (mt == 2)
-        level_reduce_mfma_kernel<PT, 2><<<grid, LV_THREADS, 0, s>>>(A);
-    else if (mt == 3)
-        level_reduce_mfma_kernel<PT, 3><<<grid, LV_THREADS, 0, s>>>(A);
-    else
-        level_reduce_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
+    const int mt = std::min(4, (A.rstride + 15) / 16);
+    const int ngrp = (A.rstride + 16 * mt - 1) / (16 * mt);
+    const int cpw = A.ncnt > 64 && mt == 1 ? 2 : 1;   // LDS: at most 75 KB, two groups per CU
+    const unsigned ncb = (unsigned)((A.ncnt + 64 * cpw - 1) / (64 * cpw));
+    const dim3 grid(nchunks, ncb * ngrp, nitems);
+#define RL_LAUNCH(MT, CPW) level_reduce_lds_kernel<PT, MT, CPW><<<grid, LV_THREADS, 0, s>>>(A)
+    if (cpw == 1) {
+        if (mt == 1) RL_LAUNCH(1, 1);
+        else if (mt == 2) RL_LAUNCH(2, 1);
+        else if (mt == 3) RL_LAUNCH(3, 1);
+        else RL_LAUNCH(4, 1);
+    } else {
+        RL_LAUNCH(1, 2);
+    }
+#undef RL_LAUNCH
 }
 
 template <typename PT>
@@ -1049,19 +1320,17 @@ static void update_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs
 }
 
 // levels of rank above RMAX_LDS: the MFMA reduction over rank groups of 64,
-// the record sums, the node solves with matrices in HBM, and the MFMA update
-// over rank chunks of 64
+// the record sums, the node solves (N in LDS up to rank LVG_RMAX, else in
+// HBM), and the MFMA update over rank chunks of 64
 template <typename PT>
 static void level_launch_wide(Pipeline &P, int d, LevelArgs A)
 {
     const Plan &p = *P.plan;
     const unsigned nchunks = (unsigned)p.lvl[d].size();
     const unsigned nodes = (unsigned)(p.first_at(d + 1) - p.first_at(d));
-    const unsigned ngrp = (unsigned)((A.rstride + 63) / 64);
-    const unsigned ncb = (unsigned)((A.ncnt + 16 * LVM_NT * LVM_CPW - 1) / (16 * LVM_NT * LVM_CPW));
     if (nchunks) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
-        level_reduce_mfma_kernel<PT, 4><<<dim3(nchunks, ncb * ngrp, P.nitems), LV_THREADS, 0, P.stream>>>(A);
+        reduce_lds_launch<PT>(nchunks, P.nitems, P.stream, A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);
@@ -1071,7 +1340,12 @@ static void level_launch_wide(Pipeline &P, int d, LevelArgs A)
             level_sum_kernel<<<dim3(nodes, (most + LV_THREADS - 1) / LV_THREADS, P.nitems), LV_THREADS,
                                0, P.stream>>>(A);
         }
-        level_solve_wide_kernel<<<dim3(nodes, 1, P.nitems), LVW_TH, 0, P.stream>>>(A);
+        if (A.rstride <= LVG_RMAX) {
+            (void)solve_lds(1);   // the dynamic LDS limits, once per process
+            level_solve_gj_kernel<<<dim3(nodes, 1, P.nitems), LVG_TH, gj_lds(A.rstride), P.stream>>>(A);
+        } else {
+            level_solve_wide_kernel<<<dim3(nodes, 1, P.nitems), LVW_TH, 0, P.stream>>>(A);
+        }
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
@@ -1101,10 +1375,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
         if (R > 0)
             reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else
-            reduce_mfma_launch<PT>((A.rstride + 15) / 16,
-                                   dim3(nchunks, (A.ncnt + 16 * LVM_NT * LVM_CPW - 1) /
-                                                     (16 * LVM_NT * LVM_CPW), P.nitems),
-                                   P.stream, A);
+            reduce_lds_launch<PT>(nchunks, P.nitems, P.stream, A);
     }
     {
         ProfScope ps(P.stream, PS_LVL_SOLVE);

@@ -90,6 +90,16 @@ def test_2d_se_unit_square_leaf256_uncapped(n):
     assert max(info["rank_max"]) > 128 and info["capped_blocks"] == 0
 
 
+def test_2d_se_node_inverse_in_lds():
+    """2-D SE on the square of side 1/4 (the density-matched n = 2^18 domain)
+    with n = 8192, leaf 256, cap 128: the widest levels have ranks between 65
+    and 128, whose node matrices are inverted in LDS (Gauss-Jordan), in the
+    factorization and in the later solves."""
+    p = wl.se2d(8192, side=0.25)
+    info = _check(p, 256, H.Opts(max_rank=128, refine=1))
+    assert 64 < max(info["rank_max"]) <= 128 and info["capped_blocks"] == 0
+
+
 def test_2d_se_density_matched_leaf256():
     """n = 2^14 points on the sub-square of the n = 2^22 unit square's
     density (side 1/16), leaf 256, cap 128."""
