@@ -208,13 +208,15 @@ def main():
     ap.add_argument("--leaf", type=int, default=None, help="leaf size (se2d; default 256)")
     ap.add_argument("--workload", default="matern1d",
                     choices=["matern1d", "batched_theta", "ragged", "learned", "copy", "se2d",
-                             "predict"],
+                             "predict", "grad"],
                     help="matern1d: one n=2^20 likelihood per step (the benchmark line); "
                          "batched_theta: 256 hyperparameter settings on one shared n=65536 "
                          "series per step, hipGraph replay; ragged: 512 independent series "
                          "with n log-uniform in [1024, 131072] per step; learned: surrogate-"
                          "screened (delayed-acceptance) vs plain Metropolis, 64 walkers, n=2^18; "
-                         "predict: posterior means at --m new inputs through an n=2^20 factor")
+                         "predict: posterior means at --m new inputs through an n=2^20 factor; "
+                         "grad: log-likelihood and its gradient in (a, l, sigma2) at n=2^20 "
+                         "(central differences of 7 likelihoods)")
     ap.add_argument("--m", type=int, default=8192, help="new inputs per step (predict)")
     ap.add_argument("--mcmc-steps", type=int, default=300)
     ap.add_argument("--autotune-free-leaf", action="store_true",
@@ -251,6 +253,8 @@ def main():
         return bench_se2d(args, torch, H, wl, dev)
     if args.workload == "predict":
         return bench_predict(args, torch, H, wl, dev)
+    if args.workload == "grad":
+        return bench_grad(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
@@ -601,6 +605,95 @@ def bench_batched(args, torch, H, wl, dev):
                             "note": "every item: log det and quadratic form against the exact "
                                     "Kalman oracle; log det and log-likelihood against the "
                                     "item's own gp_loglik_dev call (relative to max(|v|, 1))"}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_grad(args, torch, H, wl, dev):
+    """The Matern-3/2 workload of the benchmark line (n = 2^20, leaf 128, tol
+    1e-10): one step = gp_loglik_grad_dev, the log-likelihood and its central
+    difference gradient in (a, l, sigma2) from 7 likelihoods (the two sigma2
+    items on the point's compression).  Checked against the same difference of the exact Kalman
+    likelihood; the single-likelihood time on the same plan is reported for
+    the cost ratio."""
+    p = wl.matern1d(args.n)
+    mixed = args.precision == "mixed"
+    prec = H.MIXED if mixed else H.FP64
+    plan = H.Plan(p.n, 1, p.leaf, H.Opts(max_rank=64, presorted=1, precision=prec))
+    d_x = torch.from_numpy(np.ascontiguousarray(p.x.T)).to(dev)
+    d_y = torch.from_numpy(p.y).to(dev)
+    nb = plan.grad_workspace_bytes
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = torch.zeros(6, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+
+    def step():
+        H.gp_loglik_grad_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, 0.0, work, nb,
+                             stream, out)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        # one likelihood on the same plan and workspace, for the cost ratio
+        o1 = torch.zeros(8, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                            plan.workspace_bytes, stream, o1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                            plan.workspace_bytes, stream, o1)
+        torch.cuda.synchronize()
+        single = time.perf_counter() - t1
+    o = out.cpu().numpy()
+    info = plan.info()
+    model = item_model(p.n, p.leaf, info["rank_max"][:info["levels"]], esz=4 if mixed else 8)
+    ms_step = elapsed / args.steps * 1e3
+    pipe_ms = model_ms(model, 7)
+    import oracle
+    oracle.build(force=False)
+    base = [p.theta[0], p.theta[1], p.sigma2]
+    h = 1e-3 if mixed else 1e-4
+    L0 = oracle.kalman_matern32(p.x[:, 0], p.y, p.theta, p.sigma2, want_alpha=False)["loglik"]
+    errs = []
+    for j in range(3):
+        up, dn = list(base), list(base)
+        up[j] = base[j] * (1.0 + h)
+        dn[j] = base[j] * (1.0 - h)
+        Lu = oracle.kalman_matern32(p.x[:, 0], p.y, up[:2], up[2], want_alpha=False)["loglik"]
+        Ld = oracle.kalman_matern32(p.x[:, 0], p.y, dn[:2], dn[2], want_alpha=False)["loglik"]
+        gk = (Lu - Ld) / (up[j] - dn[j])
+        errs.append({"grad": float(o[3 + j]), "kalman_difference": gk,
+                     "err_over_L_per_p": abs(o[3 + j] - gk) / (abs(L0) / base[j])})
+    res = {"metric": "GP log-likelihood gradients/s (value + dL/d(a, l, sigma2)) at n=2^20",
+           "value": args.steps / elapsed, "unit": "gradients/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 arithmetic, f32 panels" if mixed else "f64", "data": "synthetic",
+           "config": {"workload": "grad_matern32_1d_n%d_leaf%d_tol%g%s"
+                                  % (p.n, p.leaf, p.tol, "_mixed" if mixed else ""),
+                      "n": p.n, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
+                      "leaf": p.leaf, "tol": p.tol, "likelihoods_per_gradient": 7,
+                      "rel_step": h, "precision": args.precision},
+           "single_likelihood_ms": single / args.steps * 1e3,
+           "cost_vs_one_likelihood": ms_step / (single / args.steps * 1e3),
+           "pipeline_roofline": {"model_ms": pipe_ms, "measured_ms": ms_step,
+                                 "frac": pipe_ms / ms_step,
+                                 "note": "the per-point model of one likelihood (each modelled "
+                                         "stage at the larger of bytes / 8 TB/s and flops / "
+                                         "78.6 TFLOP/s) times the 7 likelihoods"},
+           "result": {"loglik": float(o[0]), "grad": [float(v) for v in o[3:6]]},
+           "oracle_check": {"loglik_rel_err_vs_kalman": abs(o[0] - L0) / abs(L0),
+                            "components": errs,
+                            "note": "each component against the same central difference of "
+                                    "the exact Kalman likelihood at the same 7 points, error "
+                                    "relative to |L| / p"}}
     print(json.dumps(res), flush=True)
 
 

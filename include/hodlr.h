@@ -298,6 +298,31 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
                                  int64_t y_stride, double tol, void *d_work, size_t work_bytes,
                                  void *stream, double *d_out, int32_t use_graph);
 
+/* Gradient of the log-likelihood in the hyperparameters (a, l, sigma2) --
+ * what the hyperparameter fits of §2.3 iterate on.  The paper gives no
+ * formula for it; this entry point takes the central difference of the
+ * likelihood the factorization computes,
+ *   dL/dp = (L(p + h_p) - L(p - h_p)) / (2 h_p),  h_p = rel_step * p,
+ * for p = a, l, sigma2: 7 likelihoods (the point and the six shifted ones),
+ * each through the single-likelihood pipeline on the workspace; on FP64
+ * plans the two sigma2 items reuse the point's compression (the off-diagonal
+ * blocks do not depend on sigma2).  The error is O(h^2) from the difference
+ * plus about
+ * eps_L |L| / h from the likelihood's own error eps_L (~1e-13 FP64, ~1e-9
+ * mixed); rel_step <= 0 takes 1e-4 (FP64 plans) or 1e-3 (mixed plans).
+ * Arguments as gp_loglik_dev; sigma2 must be positive (the step below it
+ * must stay a valid noise variance) and rel_step below 0.5.  d_out (device)
+ * receives 6 doubles {loglik, logdet, quad, dL/da, dL/dl, dL/dsigma2}, the
+ * first three at the unshifted point.  Workspace:
+ * hodlr_plan_grad_workspace_size.  The call synchronizes the stream (it
+ * reads the items' status).  Errors: EINVAL, ENOTSPD (any of the 7
+ * factorizations failed), EDEVICE.                                         */
+hodlr_status hodlr_plan_grad_workspace_size(hodlr_plan p, size_t *bytes);
+hodlr_status gp_loglik_grad_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
+                                const double theta[2], double sigma2, const double *d_y,
+                                double tol, double rel_step, void *d_work, size_t work_bytes,
+                                void *stream, double *d_out);
+
 /* Log-likelihoods (Eq. (1), as gp_loglik) of m independent problems of
  * uneven size.  Item i has ns[i] points xs[i] (point-major ns[i]*dim host
  * doubles, caller order), observations ys[i] (ns[i] host doubles) and

@@ -22,7 +22,7 @@ __all__ = [
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
     "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
     "mlp_train_step_noalloc_dev", "MLP_NOALLOC_MAX_BATCH", "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
-    "gp_sample_dev", "Tune", "plan_tuned_create", "autotune", "tune_lookup",
+    "gp_sample_dev", "Tune", "plan_tuned_create", "autotune", "tune_lookup", "gp_loglik_grad_dev",
 ]
 
 K_SE, K_MATERN32, K_EXP, K_CONST, K_IMQ = 0, 1, 2, 3, 4
@@ -38,7 +38,7 @@ EXPORTED = [
     "hodlr_mlp_fit_dev", "hodlr_mh_propose_dev", "hodlr_da_screen_dev", "hodlr_da_accept_dev",
     "hodlr_sampler_workspace_size", "gp_sample_dev", "hodlr_plan_tuned_create", "hodlr_autotune",
     "hodlr_tune_lookup", "hodlr_profile_select", "hodlr_predict", "hodlr_mlp_train_step_noalloc_dev",
-    "hodlr_plan_info",
+    "hodlr_plan_info", "hodlr_plan_grad_workspace_size", "gp_loglik_grad_dev",
 ]
 MLP_NPARAM = 17153
 MLP_NOALLOC_MAX_BATCH = 4096
@@ -192,6 +192,11 @@ def lib():
     L.gp_loglik_batch_dev.restype = st
     L.gp_loglik_batch_dev.argtypes = [vp, vp, ctypes.c_int, vp, i32, vp, i64, ctypes.c_double, vp,
                                       ctypes.c_size_t, vp, vp, i32]
+    L.hodlr_plan_grad_workspace_size.restype = st
+    L.hodlr_plan_grad_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.gp_loglik_grad_dev.restype = st
+    L.gp_loglik_grad_dev.argtypes = [vp, vp, ctypes.c_int, dp, ctypes.c_double, vp, ctypes.c_double,
+                                     ctypes.c_double, vp, ctypes.c_size_t, vp, vp]
     L.gp_loglik_ragged.restype = st
     L.gp_loglik_ragged.argtypes = [i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dp),
                                    ctypes.POINTER(dp), i32, ctypes.c_int, dp, i32, ctypes.c_double,
@@ -456,6 +461,12 @@ class Plan:
         _check(lib().hodlr_plan_batch_workspace_size(self._h, int(nitems), ctypes.byref(sz)))
         return int(sz.value)
 
+    @property
+    def grad_workspace_bytes(self) -> int:
+        sz = ctypes.c_size_t()
+        _check(lib().hodlr_plan_grad_workspace_size(self._h, ctypes.byref(sz)))
+        return int(sz.value)
+
     def destroy(self):
         if self._h:
             lib().hodlr_plan_destroy(self._h)
@@ -487,6 +498,19 @@ def gp_loglik_batch_dev(plan: Plan, d_x, kernel: int, d_params, nitems: int, d_y
     _check(lib().gp_loglik_batch_dev(plan.handle, _ptr(d_x), int(kernel), _ptr(d_params),
                                      int(nitems), _ptr(d_y), int(y_stride), float(tol), _ptr(work),
                                      int(work_bytes), s, _ptr(d_out), 1 if use_graph else 0))
+
+
+def gp_loglik_grad_dev(plan: Plan, d_x, kernel: int, theta, sigma2: float, d_y, tol: float,
+                       rel_step: float, work, work_bytes: int, stream, d_out):
+    """Log-likelihood and its gradient in (a, l, sigma^2) by central
+    differences over one batched call; d_out (device, 6 doubles) receives
+    {loglik, logdet, quad, dL/da, dL/dl, dL/dsigma2}.  rel_step <= 0 takes
+    the library's default."""
+    th = _theta(theta)
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    _check(lib().gp_loglik_grad_dev(plan.handle, _ptr(d_x), int(kernel), _dp(th), float(sigma2),
+                                    _ptr(d_y), float(tol), float(rel_step), _ptr(work),
+                                    int(work_bytes), s, _ptr(d_out)))
 
 
 def gp_loglik_ragged(xs, ys, kernel: int, params, leaf: int, tol: float,

@@ -1105,6 +1105,144 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
     });
 }
 
+// ---------------------------------------------------------------- gradient
+// Central differences of 7 likelihoods: item 0 at the point, items 2q+1 and
+// 2q+2 with parameter q (a, l, sigma2) shifted up and down.  Each item runs
+// the single-likelihood pipeline on the workspace (the batched form, one
+// work-group per block, suits many small items, not the long top blocks of a
+// large n); on FP64 plans the two sigma2 items reuse the point's compression
+// (the off-diagonal blocks do not depend on sigma2) and redo only the
+// leaves, levels and sums.  The divisor is the difference of the two
+// parameter values as stored, so the step's own rounding does not enter.
+constexpr int GRAD_ITEMS = 7;
+constexpr int GRAD_OSTRIDE = 8;   // the finish stage's output row (it writes 5 values)
+
+struct GradPar {
+    double v[3 * GRAD_ITEMS];
+};
+
+__global__ void grad_combine_kernel(GradPar par, const double *res, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    out[0] = res[0];
+    out[1] = res[1];
+    out[2] = res[2];
+    for (int q = 0; q < 3; ++q) {
+        const double up = res[GRAD_OSTRIDE * (2 * q + 1)], dn = res[GRAD_OSTRIDE * (2 * q + 2)];
+        out[3 + q] = (up - dn) / (par.v[3 * (2 * q + 1) + q] - par.v[3 * (2 * q + 2) + q]);
+    }
+}
+
+__global__ void zero_one_status_kernel(int *status)
+{
+    if (threadIdx.x < 4)
+        status[threadIdx.x] = 0;
+}
+
+// the single likelihood's workspace, then (256-byte aligned) the 7 result rows
+static size_t grad_bytes(hodlr_plan p)
+{
+    return ((p->single_bytes() + 255) & ~(size_t)255) + GRAD_OSTRIDE * GRAD_ITEMS * sizeof(double);
+}
+
+hodlr_status hodlr_plan_grad_workspace_size(hodlr_plan p, size_t *bytes)
+{
+    if (!p || !bytes)
+        return fail(HODLR_EINVAL, "bad argument");
+    *bytes = grad_bytes(p);
+    return HODLR_OK;
+}
+
+hodlr_status gp_loglik_grad_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
+                                const double theta[2], double sigma2, const double *d_y,
+                                double tol, double rel_step, void *d_work, size_t work_bytes,
+                                void *stream, double *d_out)
+{
+    return guarded([&]() {
+        if (!p || !d_x || !theta || !d_y || !d_work || !d_out)
+            throw Error{HODLR_EINVAL, "bad argument"};
+        check_params(k, theta, sigma2, tol);
+        if (!(sigma2 > 0.0))
+            throw Error{HODLR_EINVAL, "the gradient needs sigma2 > 0"};
+        if (!(rel_step < 0.5) || std::isnan(rel_step))
+            throw Error{HODLR_EINVAL, "rel_step must be below 0.5"};
+        if (work_bytes < grad_bytes(p))
+            throw Error{HODLR_EINVAL, "workspace too small: need " + std::to_string(grad_bytes(p)) +
+                                          " bytes"};
+        const double h = rel_step > 0.0 ? rel_step : (p->plan.f32() ? 1e-3 : 1e-4);
+        const double base[3] = {theta[0], theta[1], sigma2};
+        GradPar par;
+        for (int i = 0; i < GRAD_ITEMS; ++i)
+            for (int q = 0; q < 3; ++q)
+                par.v[3 * i + q] = base[q];
+        for (int q = 0; q < 3; ++q) {
+            par.v[3 * (2 * q + 1) + q] = base[q] * (1.0 + h);
+            par.v[3 * (2 * q + 2) + q] = base[q] * (1.0 - h);
+        }
+        double *d_res = (double *)((char *)d_work + ((p->single_bytes() + 255) & ~(size_t)255));
+        hipStream_t s = (hipStream_t)stream;
+        Pipeline P0;   // the point's pipeline (its compression serves the sigma2 items)
+        int fallback = 0;
+        // the sigma2 items right after the point, while its compression is
+        // still the one in the workspace
+        static const int order[GRAD_ITEMS] = {0, 5, 6, 1, 2, 3, 4};
+        for (int i : order) {
+            const double th[2] = {par.v[3 * i], par.v[3 * i + 1]};
+            Pipeline P;
+            P.plan = &p->plan;
+            P.lay = p->lay;
+            P.ws = (char *)d_work;
+            P.stream = s;
+            P.x = d_x;
+            P.tol = tol;
+            const bool reuse = i >= 5 && !p->plan.f32();
+            if (reuse) {
+                P = P0;
+                zero_one_status_kernel<<<1, 64, 0, s>>>(wsp<int>(P, P.lay.status));
+                HIP_TRY(hipGetLastError());
+            }
+            P.kp = make_kparams(k, p->plan.dim, th, par.v[3 * i + 2]);
+            double *o = d_res + GRAD_OSTRIDE * i;
+            if (reuse) {
+                run_leaf_factor(P, d_y);
+                run_levels_factor(P);
+                run_finish(P, d_y, o, GRAD_OSTRIDE);
+            } else {
+                factor_pipeline(P, d_y, o);
+            }
+            const int st = read_status(P);
+            if (st)
+                throw Error{HODLR_ENOTSPD,
+                            "factorization " + std::to_string(i) + " of the gradient's 7 failed"};
+            if (p->plan.mixed_check) {
+                double ld = 0.0;
+                HIP_TRY(hipMemcpy(&ld, o + 1, sizeof(double), hipMemcpyDeviceToHost));
+                if (mixed_bound_exceeded(P, ld, 0)) {
+                    P.plan = &p->plan64;
+                    P.lay = p->lay64;
+                    factor_pipeline(P, d_y, o);
+                    raise_status(read_status(P));
+                    ++fallback;
+                }
+            }
+            if (i == 0)
+                P0 = P;
+        }
+        grad_combine_kernel<<<1, 64, 0, s>>>(par, d_res, d_out);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        {
+            std::lock_guard<std::mutex> lk(p->last_mu);
+            p->last_rmax = P0.rmax;
+            p->last_ranks = P0.ranks;
+            p->last_capped = P0.capped;
+            p->last_fallback = fallback;
+        }
+        return HODLR_OK;
+    });
+}
+
 hodlr_status hodlr_matvec_dev(int64_t n, int32_t dim, const double *d_x, hodlr_kernel k,
                               const double theta[2], double sigma2, const double *d_v,
                               double *d_out, void *stream)
