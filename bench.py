@@ -226,6 +226,10 @@ def main():
                     help="mixed: FP32 basis panels, FP64 leaves / coupling LU / log-det sums "
                          "(matern1d, batched_theta, ragged)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--compressor", default="aca", choices=["aca", "sketch"],
+                    help="se2d: compress the off-diagonal blocks by cross approximation "
+                         "(default) or by the randomized two-sided sketch (O(n^2) work; "
+                         "use a moderate --n)")
     args = ap.parse_args()
     if args.n is None and args.workload != "se2d":
         args.n = 1 << 20
@@ -902,7 +906,9 @@ def bench_se2d(args, torch, H, wl, dev):
     t_order = time.perf_counter() - t0
     xs = np.ascontiguousarray(p.x[perm])
     ys = np.ascontiguousarray(p.y[perm])
-    plan = H.Plan(n, 2, leaf, H.Opts(max_rank=cap, precision=prec))
+    sketch = args.compressor == "sketch"
+    comp = H.COMPRESS_SKETCH if sketch else H.COMPRESS_ACA
+    plan = H.Plan(n, 2, leaf, H.Opts(max_rank=cap, precision=prec, compressor=comp))
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
     d_y = torch.from_numpy(ys).to(dev)
     work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
@@ -914,10 +920,12 @@ def bench_se2d(args, torch, H, wl, dev):
         H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
                         plan.workspace_bytes, stream, out, z)
 
-    config = {"workload": "se2d_n%d_leaf%d_cap%d%s" % (n, leaf, cap, "_mixed" if mixed else ""),
+    config = {"workload": "se2d_n%d_leaf%d_cap%d%s%s" % (n, leaf, cap, "_mixed" if mixed else "",
+                                                       "_sketch" if sketch else ""),
               "n": n, "dim": 2, "kernel": "se", "theta": list(p.theta), "sigma2": p.sigma2,
               "side": p.meta["side"], "leaf": leaf, "max_rank": cap, "tol": p.tol,
-              "precision": args.precision, "workspace_bytes": plan.workspace_bytes}
+              "precision": args.precision, "compressor": args.compressor,
+              "workspace_bytes": plan.workspace_bytes}
     res = {"metric": "GP log-likelihoods/s, 2-D SE (n=2^22 unit square at full size)",
            "unit": "likelihoods/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -980,7 +988,50 @@ def bench_se2d(args, torch, H, wl, dev):
                     "dtype": "fp64", "avg_launch_ms": d["ms"] / d["launches"],
                     "algorithmic_per_call": {"flops": d["flops"] / d["launches"],
                                              "bytes": d["bytes"] / d["launches"]}}
+    sketch_info = None
+    if sketch:
+        # the sketch stage on FP64 MFMA: per node, A X and A^T Y (2 m nb (s + s')
+        # flops) and the partial cores (2 m s' s), with the widths the library uses
+        fl = 0.0
+        sizes = [n]
+        for d in range(L):
+            nxt = []
+            for sz in sizes:
+                m_, nb_ = sz // 2, sz - sz // 2
+                s_ = min(cap + 16, m_, nb_)
+                sp_ = min(s_ + 8, m_) if s_ > 0 else 0
+                fl += 2.0 * m_ * nb_ * (s_ + sp_) + 2.0 * m_ * sp_ * s_
+                nxt += [m_, nb_]
+            sizes = nxt
+        ms_sk = stages.get("sketch", (float("nan"), 0))[0]
+        ach = fl / (ms_sk / 1e3) / 1e12
+        sketch_info = {"flops": fl, "ms": ms_sk, "achieved_tflops": ach,
+                       "frac": ach / PEAK["alu_fp64"], "launches": stages.get("sketch", (0, 0))[1],
+                       "note": "the sketch products' flops over the sketch kernels' summed "
+                               "event time, against the FP64 matrix peak"}
+        # the same likelihood with cross approximation, untimed, for comparison
+        aplan = H.Plan(n, 2, leaf, H.Opts(max_rank=cap, precision=prec))
+        aw = torch.empty(aplan.workspace_bytes, dtype=torch.uint8, device=dev)
+        ao = torch.zeros(8, dtype=torch.float64, device=dev)
+        try:
+            H.gp_loglik_dev(aplan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, aw,
+                            aplan.workspace_bytes, stream, ao)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(args.steps):
+                H.gp_loglik_dev(aplan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, aw,
+                                aplan.workspace_bytes, stream, ao)
+            torch.cuda.synchronize()
+            aco = ao[:3].cpu().tolist()
+            sketch_info["aca_same_problem"] = {
+                "ms_per_likelihood": (time.perf_counter() - t2) / args.steps * 1e3,
+                "logdet": aco[1], "logdet_rel_diff": abs(aco[1] - logdet) / abs(logdet),
+                "rank_max": aplan.info()["rank_max"][:L]}
+        except H.HodlrError as e:
+            sketch_info["aca_same_problem"] = {"status": e.name}
+        del aw, aplan
     res.update({"value": args.steps / el, "ms_per_step": el / args.steps * 1e3, "status": "OK",
+                "sketch": sketch_info,
                 "ranks": {"rank_max": info["rank_max"], "rank_mean": info["rank_mean"],
                           "capped_blocks": info["capped_blocks"]},
                 "roofline": roofline, "mfma_level_kernels": mfma,

@@ -78,6 +78,7 @@ typedef enum {
 } hodlr_kernel;
 
 enum { HODLR_FP64 = 0, HODLR_MIXED = 1 };
+enum { HODLR_COMPRESS_ACA = 0, HODLR_COMPRESS_SKETCH = 1 };
 
 typedef struct {
     int32_t max_rank;    /* per off-diagonal block rank cap in [0, 512] (default 64); a
@@ -119,6 +120,22 @@ typedef struct {
                             misses 1e-8.  The bound is safe but can be loose by 10^3
                             and more on strongly coupled problems.  1: keep the FP32-
                             panel result untested (the caller measures its error)  */
+    int32_t compressor;  /* How the off-diagonal blocks K(alpha, beta) are compressed
+                            (§3.1 lists both kinds).  HODLR_COMPRESS_ACA (default):
+                            adaptive cross approximation, O(r^2 (m + n)) work per
+                            block.  HODLR_COMPRESS_SKETCH: a randomized two-sided
+                            sketch (generalized Nystrom): random-sign matrices X and
+                            Y of s = min(max_rank + 16, m, n) and s + 8 columns,
+                            A X and A^T Y evaluated entry by entry (every entry of
+                            every block twice: O(n^2) work in all), the core
+                            Y^T A X factored by a Jacobi SVD and its pseudo-inverse
+                            truncated at tol / 10 of its largest singular value.  It
+                            needs no pivoting heuristic, so it also holds where
+                            cross approximation can stall, at the price of the
+                            quadratic work (moderate n).  Needs max_rank <= 64;
+                            taken by hodlr_build, gp_loglik, gp_loglik_dev and
+                            gp_loglik_grad_dev (the batched, uneven-size and
+                            autotuning entry points reject it with HODLR_EINVAL)  */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one

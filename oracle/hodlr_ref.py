@@ -15,7 +15,7 @@ list) can be pinned against what the mathematics fixes:
    in D > 1 dimensions the node is sorted along coordinate (depth mod D)
    before the split, ties kept in input order.
 2. Low-rank compression of every off-diagonal block K(alpha, beta) by
-   partially pivoted adaptive cross approximation (§3.1, "approximate
+   (default) partially pivoted adaptive cross approximation (§3.1, "approximate
    partial-pivoted LU" with a sub-sampled error estimate).  Reading of the
    details the paper leaves out: start at the row of alpha next to the split
    (its last row); pivot column = first index of max |residual row|; a zero
@@ -24,7 +24,8 @@ list) can be pinned against what the mathematics fixes:
    ||u_k|| ||v_k|| <= tol ||S_k||_F with the Frobenius norm of the running
    approximation S_k updated incrementally; the next pivot row is the first
    index of max |u_k| over unused rows; at most min(max_rank, |alpha|, |beta|)
-   terms.
+   terms.  Alternatively (compress="sketch") by the randomized two-sided
+   sketch of ``sketch_compress``.
 3. Leaf factor K_L: dense diagonal blocks C_lambda = K(lambda, lambda) +
    sigma^2 I, factored by Cholesky; their inverses applied to the rows of
    every off-diagonal basis that covers the leaf (§3.2 pseudo-code; §3.3).
@@ -165,6 +166,69 @@ def aca(row, col, m: int, nb: int, tol: float, max_rank: int):
 
 
 # ------------------------------------------------------------ factorization
+# ---------------------------------------------------- randomized compression
+# Second compressor of §3.1's list of algebraic low-rank methods: a two-sided
+# randomized sketch (generalized Nystrom).  For A = K(alpha, beta) (m x nb):
+#   X (nb x s) and Y (m x s') random signs, s = min(cap + 16, m, nb),
+#   s' = min(s + 8, m);  AX, Y^T A and the core C = Y^T A X;
+#   A ~ AX C^+ Y^T A with the pseudo-inverse truncated to the k singular
+#   values of C above SKETCH_CUT * tol * sigma_1(C) (capped when k > cap):
+#   U = AX Q_k S_k^{-1/2},  V = (Y^T A)^T P_k S_k^{-1/2}  (C = P S Q^T).
+# Readings (the paper names randomized methods without fixing one): signs
+# from SplitMix64 of a per-entry key, the oversampling 16 / 8, and the cut
+# at tol / 10, which kept ||A - U V^T||_F <= tol ||A||_F on the tested 2-D
+# squared-exponential blocks where a cut at tol did not.
+SKETCH_OVER_X = 16
+SKETCH_OVER_Y = 8
+SKETCH_CUT = 0.1
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(key: int) -> int:
+    """SplitMix64's output for state `key` (Steele, Lea, Flood 2014; Vigna's
+    public-domain reference): the state advances by the golden-ratio
+    increment, then two xor-shift-multiply rounds and a final xor-shift."""
+    z = (key + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def sketch_signs(node: int, side: int, nrows: int, ns: int) -> np.ndarray:
+    """(nrows x ns) matrix of +-1: entry (i, j) is -1 when bit j mod 64 of
+    splitmix64(((2 node + side) << 40) | (i << 1) | (j >> 6)) is set.
+    side 0: X over beta's points, 1: Y over alpha's points; node = heap index."""
+    out = np.empty((nrows, ns), dtype=np.float64)
+    for i in range(nrows):
+        words = [splitmix64(((2 * node + side) << 40) | (i << 1) | b) for b in range((ns + 63) // 64)]
+        for j in range(ns):
+            out[i, j] = -1.0 if (words[j >> 6] >> (j & 63)) & 1 else 1.0
+    return out
+
+
+def sketch_compress(A: np.ndarray, depth: int, idx: int, tol: float, cap: int):
+    """Returns (U, V, capped) for block A of the depth-`depth` node number
+    `idx` (heap index 2^depth - 1 + idx)."""
+    m, nb = A.shape
+    h = (1 << depth) - 1 + idx
+    s = min(cap + SKETCH_OVER_X, m, nb)
+    if s <= 0 or cap <= 0:
+        return np.zeros((m, 0)), np.zeros((nb, 0)), False
+    sp = min(s + SKETCH_OVER_Y, m)
+    X = sketch_signs(h, 0, nb, s)
+    Y = sketch_signs(h, 1, m, sp)
+    AX = A @ X
+    YA = Y.T @ A
+    C = Y.T @ AX
+    P, S, Qt = np.linalg.svd(C, full_matrices=False)
+    k = int(np.sum(S > SKETCH_CUT * tol * S[0])) if S.size and S[0] > 0 else 0
+    capped = k > cap
+    k = min(k, cap)
+    U = AX @ (Qt[:k].T / np.sqrt(S[:k]))
+    V = YA.T @ (P[:, :k] / np.sqrt(S[:k]))
+    return U, V, capped
+
+
 class HodlrRef:
     """Plain FP64 HODLR factorization of C = sigma^2 I + K on ordered points."""
 
@@ -203,6 +267,10 @@ class HodlrRef:
                     U, V, cap = aca(lambda ii: kernel_block(self.kind, xa[ii:ii + 1], xb, a, ell)[0],
                                     lambda jj: kernel_block(self.kind, xa, xb[jj:jj + 1], a, ell)[:, 0],
                                     m - s, e - m, self.tol, self.max_rank)
+                    self.capped += int(cap)
+                elif method == "sketch":
+                    A = kernel_block(self.kind, xa, xb, a, ell)
+                    U, V, cap = sketch_compress(A, d, i, self.tol, self.max_rank)
                     self.capped += int(cap)
                 else:   # truncated SVD (optimal rank, used only in tests)
                     A = kernel_block(self.kind, xa, xb, a, ell)

@@ -18,7 +18,7 @@ __all__ = [
     "hodlr_build", "hodlr_logdet", "hodlr_solve", "hodlr_predict", "gp_loglik", "hodlr_info",
     "hodlr_free",
     "gp_loglik_dev", "hodlr_matvec_dev", "K_SE", "K_MATERN32", "K_EXP", "K_CONST", "K_IMQ",
-    "FP64", "MIXED", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
+    "FP64", "MIXED", "COMPRESS_ACA", "COMPRESS_SKETCH", "EXPORTED", "profile_enable", "profile_read", "gp_loglik_batch_dev",
     "gp_loglik_ragged", "MlpNorm", "SamplerCfg", "SamplerStats", "MLP_NPARAM",
     "mlp_workspace_size", "mlp_cast_dev", "mlp_forward_dev", "mlp_grad_dev", "mlp_train_step_dev",
     "mlp_train_step_noalloc_dev", "MLP_NOALLOC_MAX_BATCH", "mlp_fit_dev", "mh_propose_dev", "da_screen_dev", "da_accept_dev", "sampler_workspace_size",
@@ -27,6 +27,7 @@ __all__ = [
 
 K_SE, K_MATERN32, K_EXP, K_CONST, K_IMQ = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
+COMPRESS_ACA, COMPRESS_SKETCH = 0, 1
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOCONV"}
 EXPORTED = [
     "hodlr_order", "hodlr_num_levels", "hodlr_build", "hodlr_logdet", "hodlr_solve",
@@ -60,10 +61,11 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p),
-                ("refine", ctypes.c_int32), ("mixed_unchecked", ctypes.c_int32)]
+                ("refine", ctypes.c_int32), ("mixed_unchecked", ctypes.c_int32),
+                ("compressor", ctypes.c_int32)]
 
     def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0,
-                 noise=None, refine=0, mixed_unchecked=0):
+                 noise=None, refine=0, mixed_unchecked=0, compressor=0):
         """noise: optional per-point variances (one per point, caller's order),
         added to sigma2 on the diagonal; the array is kept alive with the
         options."""
@@ -73,7 +75,7 @@ class Opts(ctypes.Structure):
             self._noise = np.ascontiguousarray(np.asarray(noise, dtype=np.float64).ravel())
             ptr = self._noise.ctypes.data
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
-                         int(presorted), ptr, int(refine), int(mixed_unchecked))
+                         int(presorted), ptr, int(refine), int(mixed_unchecked), int(compressor))
 
 
 class Profile(ctypes.Structure):

@@ -1123,6 +1123,11 @@ static void big_pass(const Plan &p, int nchunk, hipStream_t s, const BigArgs &B)
     }
 }
 
+void run_sketch_levels(Pipeline &P, int *rank, int *status);   // sketch.hip
+
+// The compression stage: adaptive cross approximation, or (plans made with
+// HODLR_COMPRESS_SKETCH) the randomized sketch; both end with the rank
+// statistics on the host and the panels' padding columns zeroed.
 void run_aca(Pipeline &P)
 {
     const Plan &p = *P.plan;
@@ -1171,6 +1176,19 @@ void run_aca(Pipeline &P)
         pipeline_init_kernel<<<(unsigned)std::max<int64_t>(nb, 1), 256, 0, s>>>(ia);
     }
     HIP_TRY(hipGetLastError());
+    if (p.compressor == HODLR_COMPRESS_SKETCH) {
+        run_sketch_levels(P, rank, status);
+        read_rank_stats(P, rank, status, d_rmax, d_capped, nullptr, pinned);
+        for (int j = 0; j <= p.L + 1 && j < 48; ++j)
+            P.rmax[j] = pinned[j];
+        P.capped = pinned[48];
+        ProfScope ps(s, PS_ACA_MISC);
+        if (!p.pad_chunks.empty())
+            aca_pad_kernel<<<(unsigned)p.pad_chunks.size(), 256, 0, s>>>(A.W, p.n, p.d_pad_chunks,
+                                                                          rank, d_rmax, d_cofa);
+        HIP_TRY(hipGetLastError());
+        return;
+    }
     const int nbig = (int)p.aca_big.size();
     // small blocks: the whole loop per work-group.  When there are large
     // blocks too, they run on the side stream, alongside the large blocks'

@@ -50,6 +50,7 @@ hodlr_opts default_opts()
     o.noise = nullptr;
     o.refine = 0;
     o.mixed_unchecked = 0;
+    o.compressor = HODLR_COMPRESS_ACA;
     return o;
 }
 
@@ -92,6 +93,11 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "refine must be 0 or 1"};
     if (o.mixed_unchecked != 0 && o.mixed_unchecked != 1)
         throw Error{HODLR_EINVAL, "mixed_unchecked must be 0 or 1"};
+    if (o.compressor != HODLR_COMPRESS_ACA && o.compressor != HODLR_COMPRESS_SKETCH)
+        throw Error{HODLR_EINVAL, "unknown compressor"};
+    if (o.compressor == HODLR_COMPRESS_SKETCH && o.max_rank > SK_CAP_MAX)
+        throw Error{HODLR_EINVAL, "the sketch compressor needs max_rank <= " +
+                                      std::to_string(SK_CAP_MAX)};
 }
 
 void check_finite(const double *v, int64_t m, const char *what)
@@ -1019,6 +1025,8 @@ hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k
                                           std::to_string(batch_bytes(p, nitems)) + " bytes"};
         if (p->plan.leafmax > LEAF_MAX)
             throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
+        if (p->plan.compressor != HODLR_COMPRESS_ACA)
+            throw Error{HODLR_EINVAL, "the batched form compresses by cross approximation only"};
         Pipeline P;
         P.plan = &p->plan;
         P.lay = p->lay;

@@ -26,6 +26,13 @@ constexpr int ACA_CHUNK_ND = 512;
 constexpr int ACA_SMALL = 2048;   // blocks with both sides <= this run in one work-group
 constexpr int ACA_TINY = 256;     // ... and on a single wave when both sides are <= this
 constexpr int ACA_THREADS = 256;
+// sketch compressor: oversampling of X (beyond the cap) and of Y (beyond X),
+// the largest cap, and the sketch widths it implies
+constexpr int SK_OVER_X = 16, SK_OVER_Y = 8;
+constexpr int SK_CAP_MAX = 64;
+constexpr int SK_SMAX = SK_CAP_MAX + SK_OVER_X;    // 80 columns of X
+constexpr int SK_SPMAX = SK_SMAX + SK_OVER_Y;      // 88 columns of Y
+constexpr int SK_ROWS = 64;                        // rows per sketch work-group
 constexpr int LVL_ROWS = 512;     // default rows per level work-group
 constexpr int LEAF_LDS_MAX = 128; // leaves up to this size are factored wholly in LDS
 constexpr int LEAF_MAX = 256;     // larger leaves (up to this) keep their off-diagonal half in HBM
@@ -242,6 +249,13 @@ struct Plan {
     int max_refine = 8;
     bool refine = false;       // host solves refine against the exact product (always when mixed)
     bool mixed_check = false;  // mixed form: test the log-det error bound, redo in FP64 if missed
+    int compressor = HODLR_COMPRESS_ACA;
+    // sketch compressor tables, per depth d: 64-row chunks of both children of
+    // every depth-d node (alpha chunks of a node first; an alpha chunk's part
+    // is its partial-core slot, contiguous per node), and per node the first
+    // alpha slot and the alpha chunk count
+    std::vector<std::vector<Chunk>> sk;
+    std::vector<std::vector<int>> sk_abase, sk_acnt;
     int64_t nint = 0;    // internal (split) nodes 2^L - 1
     int64_t nleaf = 1;   // 2^L
     int leafmax = 0;
@@ -270,7 +284,7 @@ struct Plan {
     // offsets of the device tables inside their image
     struct TableOffsets {
         size_t start, end, ar, ac, pc, nr, nc, rb, cb, bg, sm, ri, ci;
-        std::vector<size_t> l, ln, lb;
+        std::vector<size_t> l, ln, lb, k, ka, kc;
     } tbl;
     // device copies of the tables
     void *dev_tables = nullptr;
@@ -282,6 +296,8 @@ struct Plan {
         *d_aca_rowidx = nullptr, *d_aca_colidx = nullptr;
     std::vector<Chunk *> d_lvl;
     std::vector<int *> d_lvl_nch, d_lvl_base;
+    std::vector<Chunk *> d_sk;
+    std::vector<int *> d_sk_abase, d_sk_acnt;
     int device = 0;
 
     int depth_of(int64_t h) const
@@ -309,6 +325,7 @@ struct Layout {
     size_t rank, leaf_ld, node_ld;
     size_t lvl_part, Tbuf, Sbuf, small;
     size_t dot_part, out, status, cols, misc;
+    size_t sk_buf, sk_part, sk_core, sk_fac;   // sketch compressor (8 bytes otherwise)
     size_t total;
     int64_t small_stride;   // doubles per internal node in the small-factor store
     int64_t T_stride;       // doubles per node in Tbuf/Sbuf
@@ -357,7 +374,7 @@ struct Pipeline {
 // Optional HIP-event timing of every launch, per kernel kind (tracing aid).
 enum ProfStage {
     PS_ACA_ROW = 0, PS_ACA_COL, PS_ACA_SMALL, PS_ACA_MISC, PS_LEAF, PS_LEAF_SOLVE, PS_LVL_REDUCE, PS_LVL_SOLVE,
-    PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_PREDICT, PS_COUNT
+    PS_LVL_UPDATE, PS_FINISH, PS_MATVEC, PS_PREDICT, PS_SKETCH, PS_SKETCH_CORE, PS_COUNT
 };
 bool prof_on(int stage);
 void prof_suspend(bool on);   // no event recording (e.g. while a stream is captured)

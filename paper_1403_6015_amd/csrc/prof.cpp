@@ -31,7 +31,8 @@ Prof &P()
 const char *kNames[PS_COUNT] = {"aca_row_pass", "aca_col_pass", "aca_small", "aca_misc",
                                 "leaf_factor",
                                 "leaf_solve",   "level_reduce", "level_solve", "level_update",
-                                "finish",       "matvec",      "predict"};
+                                "finish",       "matvec",      "predict",
+                                "sketch",       "sketch_core"};
 
 hipEvent_t take(Prof &p)
 {

@@ -212,6 +212,8 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
             return report(HODLR_EINVAL, "bad shared argument");
         if (opts && opts->noise)
             return report(HODLR_EINVAL, "per-point noise is taken by hodlr_build and gp_loglik only");
+        if (opts && opts->compressor != HODLR_COMPRESS_ACA)
+            return report(HODLR_EINVAL, "the uneven-size form compresses by cross approximation only");
         RaggedJob J;
         J.m = m;
         J.ns = ns;
@@ -233,6 +235,7 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
             J.opts.noise = nullptr;
             J.opts.refine = 0;
             J.opts.mixed_unchecked = 0;
+            J.opts.compressor = HODLR_COMPRESS_ACA;
         }
         if (J.opts.max_rank < 0 || J.opts.max_rank > RMAX_ABS ||
             (J.opts.precision != HODLR_FP64 && J.opts.precision != HODLR_MIXED))

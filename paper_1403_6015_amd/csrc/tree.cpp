@@ -94,6 +94,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
     p.max_refine = opts ? opts->max_refine : 8;   // checked >= 0 by the entry points
     p.refine = p.precision == HODLR_MIXED || (opts && opts->refine);
     p.mixed_check = p.precision == HODLR_MIXED && !(opts && opts->mixed_unchecked);
+    p.compressor = opts ? opts->compressor : HODLR_COMPRESS_ACA;
     const int L = p.L;
     const int64_t nn = ((int64_t)2 << L) - 1;
     p.nint = ((int64_t)1 << L) - 1;
@@ -197,6 +198,24 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
             p.lvl_nch[d].push_back(slot - p.lvl_base[d].back());
         }
     }
+    // sketch compressor tables
+    p.sk.assign(p.compressor == HODLR_COMPRESS_SKETCH ? L : 0, {});
+    p.sk_abase.assign(p.sk.size(), {});
+    p.sk_acnt.assign(p.sk.size(), {});
+    for (int d = 0; d < (int)p.sk.size(); ++d) {
+        int aslot = 0;
+        for (int64_t h = p.first_at(d); h < p.first_at(d + 1); ++h) {
+            int64_t s = p.start[h], e = p.end[h], m = s + (e - s) / 2;
+            p.sk_abase[d].push_back(aslot);
+            int bslot = 0;
+            make_chunks((int)h, 0, s, m, SK_ROWS, p.sk[d], aslot);
+            p.sk_acnt[d].push_back(aslot - p.sk_abase[d].back());
+            const size_t b0 = p.sk[d].size();
+            make_chunks((int)h, 1, m, e, SK_ROWS, p.sk[d], bslot);
+            for (size_t c = b0; c < p.sk[d].size(); ++c)
+                p.sk[d][c].part = -1;
+        }
+    }
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -236,6 +255,15 @@ size_t plan_image(Plan &p, std::vector<char> &host)
         o.ln[d] = take(sizeof(int) * p.lvl_nch[d].size());
         o.lb[d] = take(sizeof(int) * p.lvl_base[d].size());
     }
+    const int LK = (int)p.sk.size();
+    o.k.assign(LK, 0);
+    o.ka.assign(LK, 0);
+    o.kc.assign(LK, 0);
+    for (int d = 0; d < LK; ++d) {
+        o.k[d] = take(sizeof(Chunk) * std::max<size_t>(1, p.sk[d].size()));
+        o.ka[d] = take(sizeof(int) * p.sk_abase[d].size());
+        o.kc[d] = take(sizeof(int) * p.sk_acnt[d].size());
+    }
     host.assign(off, 0);
     auto put = [&](size_t at, const void *src, size_t bytes) {
         if (bytes)
@@ -258,6 +286,11 @@ size_t plan_image(Plan &p, std::vector<char> &host)
         put(o.l[d], p.lvl[d].data(), sizeof(Chunk) * p.lvl[d].size());
         put(o.ln[d], p.lvl_nch[d].data(), sizeof(int) * p.lvl_nch[d].size());
         put(o.lb[d], p.lvl_base[d].data(), sizeof(int) * p.lvl_base[d].size());
+    }
+    for (int d = 0; d < LK; ++d) {
+        put(o.k[d], p.sk[d].data(), sizeof(Chunk) * p.sk[d].size());
+        put(o.ka[d], p.sk_abase[d].data(), sizeof(int) * p.sk_abase[d].size());
+        put(o.kc[d], p.sk_acnt[d].data(), sizeof(int) * p.sk_acnt[d].size());
     }
     return off;
 }
@@ -285,6 +318,15 @@ void plan_bind(Plan &p, char *b)
         p.d_lvl[d] = (Chunk *)(b + o.l[d]);
         p.d_lvl_nch[d] = (int *)(b + o.ln[d]);
         p.d_lvl_base[d] = (int *)(b + o.lb[d]);
+    }
+    const int LK = (int)p.sk.size();
+    p.d_sk.resize(LK);
+    p.d_sk_abase.resize(LK);
+    p.d_sk_acnt.resize(LK);
+    for (int d = 0; d < LK; ++d) {
+        p.d_sk[d] = (Chunk *)(b + o.k[d]);
+        p.d_sk_abase[d] = (int *)(b + o.ka[d]);
+        p.d_sk_acnt[d] = (int *)(b + o.kc[d]);
     }
 }
 
@@ -368,6 +410,21 @@ Layout make_layout(const Plan &p, bool store_leaf)
     y.status = take(sizeof(int) * 4);
     y.cols = take(sizeof(int) * p.ncol);
     y.misc = take(4096);
+    // sketch compressor: one level's sketches (n rows), its partial cores (one
+    // per alpha chunk), its cores and its factor maps (one per node)
+    size_t skp = 1, skn = 1;
+    for (int d = 0; d < (int)p.sk.size(); ++d) {
+        size_t na = 0;
+        for (int c : p.sk_acnt[d])
+            na += (size_t)c;
+        skp = std::max(skp, na);
+        skn = std::max<size_t>(skn, (size_t)(p.first_at(d + 1) - p.first_at(d)));
+    }
+    const bool sk = !p.sk.empty();
+    y.sk_buf = take(sk ? sizeof(double) * (size_t)n * SK_SPMAX : 8);
+    y.sk_part = take(sk ? sizeof(double) * skp * SK_SPMAX * SK_SMAX : 8);
+    y.sk_core = take(sk ? sizeof(double) * skn * SK_SPMAX * SK_SMAX : 8);
+    y.sk_fac = take(sk ? sizeof(double) * skn * (SK_SMAX + SK_SPMAX) * SK_CAP_MAX : 8);
     y.total = off;
     return y;
 }

@@ -132,7 +132,10 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
             o.noise = nullptr;
             o.refine = 0;
             o.mixed_unchecked = 0;
+            o.compressor = HODLR_COMPRESS_ACA;
         }
+        if (o.compressor != HODLR_COMPRESS_ACA)
+            return report(HODLR_EINVAL, "the autotuner times cross approximation only");
         if (o.max_rank < 0 || o.max_rank > RMAX_ABS ||
             (o.precision != HODLR_FP64 && o.precision != HODLR_MIXED))
             return report(HODLR_EINVAL, "unsupported options");

@@ -79,6 +79,11 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(H.HodlrError) as ei:
         H.gp_loglik(p.x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, H.Opts(max_rank=100000))
     assert ei.value.name == "EINVAL"
+    # the sketch compressor's cap, and an unknown compressor
+    for o in (H.Opts(max_rank=65, compressor=H.COMPRESS_SKETCH), H.Opts(compressor=2)):
+        with pytest.raises(H.HodlrError) as ei:
+            H.gp_loglik(p.x, p.y, p.kernel, p.theta, p.sigma2, p.leaf, p.tol, o)
+        assert ei.value.name == "EINVAL"
 
 
 def test_per_point_noise_is_validated():
