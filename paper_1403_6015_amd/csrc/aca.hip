@@ -25,6 +25,8 @@
 //     so state only moves across launch boundaries (double-buffered).
 #include "common.h"
 
+#include <cstring>
+
 namespace hodlr {
 
 // work-group size of the small-block path for blocks with a side above
@@ -925,9 +927,18 @@ __global__ void aca_big_finish_kernel(const BigState *st, const int *bnode, int 
     status[bnode[b]] = st[b].done;
 }
 
-// ranks, per-depth maxima and the capped count: one work-group, LDS atomics
+// ranks, per-depth maxima and the capped count: one work-group.  Depth d's
+// nodes are the heap range [2^d - 1, 2^(d+1) - 1); each thread keeps one
+// maximum per depth in a register (the depth loop is unrolled, so no load
+// waits on another depth's), then one wave reduction and one LDS atomic per
+// wave and depth.  rmax[48] receives the capped count and rmax[49] the
+// finished large-block count (ndone, when given), so that one copy of 64
+// ints carries every statistic.
+constexpr int STATS_DEPTHS = 46;   // depths 0 .. 45 (plans have at most 62 levels; ranks
+                                   // beyond depth 45 would need more than 2^46 points)
+
 __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const int *status,
-                                                        int64_t nint, int *rmax, int *capped)
+                                                        int64_t nint, int *rmax, const int *ndone)
 {
     __shared__ int smax[64];
     __shared__ int scap;
@@ -936,30 +947,40 @@ __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const i
     if (threadIdx.x == 0)
         scap = 0;
     __syncthreads();
-    // nodes of depth d are the heap range [2^d - 1, 2^(d+1) - 1): a register
-    // maximum per depth, then one LDS atomic per wave
+    int m[STATS_DEPTHS];
     int mycap = 0;
-    for (int d = 0; d < 62; ++d) {
+#pragma unroll
+    for (int d = 0; d < STATS_DEPTHS; ++d) {
+        m[d] = 0;
         const int64_t h0 = ((int64_t)1 << d) - 1;
-        if (h0 >= nint)
-            break;
         const int64_t h1 = std::min<int64_t>(nint, ((int64_t)2 << d) - 1);
-        int m = 0;
+#pragma unroll 4
         for (int64_t h = h0 + threadIdx.x; h < h1; h += 256) {
-            m = std::max(m, rank[h]);
+            m[d] = std::max(m[d], rank[h]);
             mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
         }
-        for (int off = 32; off > 0; off >>= 1)
-            m = std::max(m, __shfl_xor(m, off, 64));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(&smax[d + 1], m);
     }
-    atomicAdd(&scap, mycap);
+#pragma unroll
+    for (int d = 0; d < STATS_DEPTHS; ++d) {
+        if (((int64_t)1 << d) - 1 >= nint)
+            break;
+        int v = m[d];
+        for (int off = 32; off > 0; off >>= 1)
+            v = std::max(v, __shfl_xor(v, off, 64));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax(&smax[d + 1], v);
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        mycap += __shfl_xor(mycap, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd(&scap, mycap);
     __syncthreads();
-    if (threadIdx.x < 64)
+    if (threadIdx.x < 48)
         rmax[threadIdx.x] = smax[threadIdx.x];
-    if (threadIdx.x == 0)
-        *capped = scap;
+    if (threadIdx.x == 48)
+        rmax[48] = scap;
+    if (threadIdx.x == 49)
+        rmax[49] = ndone ? *ndone : 0;
 }
 
 // zero columns [rank, rmax) of the panel on the rows of each chunk's block
@@ -993,6 +1014,70 @@ int *pinned_scratch()
     return buf.p;
 }
 
+// Wait for the stream by polling an event recorded on it (one per host
+// thread and device): the rank statistics sit on the likelihood's critical
+// path, and a blocking synchronization wakes the thread tens of microseconds
+// after the copies end.
+void host_wait(hipStream_t s)
+{
+    struct Ev {
+        hipEvent_t e[16] = {};
+        ~Ev()
+        {
+            for (hipEvent_t x : e)
+                if (x)
+                    (void)hipEventDestroy(x);
+        }
+    };
+    thread_local Ev ev;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) {
+        HIP_TRY(hipStreamSynchronize(s));
+        return;
+    }
+    if (!ev.e[dev])
+        HIP_TRY(hipEventCreateWithFlags(&ev.e[dev], hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev.e[dev], s));
+    for (;;) {
+        const hipError_t q = hipEventQuery(ev.e[dev]);
+        if (q == hipSuccess)
+            break;
+        if (q != hipErrorNotReady)
+            HIP_TRY(q);
+    }
+}
+
+// A growable pinned int buffer per host thread and slot (0: the per-node ranks
+// read back after compression, 1: the column list uploaded before the
+// leaves), so those copies go straight between device and host memory.  A
+// slot is rewritten only after the stream has been synchronized since its
+// last copy (each compression ends with a synchronization).
+int *pinned_ints(size_t n, int slot)
+{
+    struct Buf {
+        int *p[2] = {nullptr, nullptr};
+        size_t cap[2] = {0, 0};
+        ~Buf()
+        {
+            for (int i = 0; i < 2; ++i)
+                if (p[i])
+                    (void)hipHostFree(p[i]);
+        }
+    };
+    thread_local Buf buf;
+    if (buf.cap[slot] < n) {
+        if (buf.p[slot])
+            HIP_TRY(hipHostFree(buf.p[slot]));
+        buf.p[slot] = nullptr;
+        buf.cap[slot] = 0;
+        const size_t want = std::max<size_t>(n, 4096);
+        HIP_TRY(hipHostMalloc((void **)&buf.p[slot], want * sizeof(int), hipHostMallocDefault));
+        buf.cap[slot] = want;
+    }
+    return buf.p[slot];
+}
+
 // rank statistics of all blocks and their copies to the host (one
 // synchronization): rmax in pinned[0..L+1], the capped count in pinned[48],
 // the finished large-block count (if d_ndone is given) in pinned[49]
@@ -1001,17 +1086,17 @@ static void read_rank_stats(Pipeline &P, const int *rank, const int *status, int
 {
     const Plan &p = *P.plan;
     hipStream_t s = P.stream;
+    (void)d_capped;   // the capped count travels in d_rmax[48]
     {
         ProfScope ps(s, PS_ACA_MISC);
-        aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_capped);
+        aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, d_ndone);
     }
     HIP_TRY(hipGetLastError());
-    if (d_ndone)
-        HIP_TRY(hipMemcpyAsync(pinned + 49, d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * (p.L + 2), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(pinned + 48, d_capped, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(P.ranks.data(), rank, sizeof(int) * p.nint, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpyAsync(pinned, d_rmax, sizeof(int) * 64, hipMemcpyDeviceToHost, s));
+    int *hr = pinned_ints((size_t)p.nint, 0);
+    HIP_TRY(hipMemcpyAsync(hr, rank, sizeof(int) * p.nint, hipMemcpyDeviceToHost, s));
+    host_wait(s);
+    std::memcpy(P.ranks.data(), hr, sizeof(int) * p.nint);
 }
 
 // Per-call initialization in one launch instead of a memset or copy each:

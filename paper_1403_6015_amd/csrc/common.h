@@ -430,6 +430,8 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out);
 // the finish kernel) exceeds the 1e-8 bar for this log det (synchronizes)
 bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item);
 int *pinned_scratch();                                         // per-thread pinned ints
+int *pinned_ints(size_t n, int slot);                          // per-thread growable pinned ints
+void host_wait(hipStream_t s);                                 // poll the stream to completion
 
 template <typename T>
 inline T *wsp(const Pipeline &P, size_t off)
