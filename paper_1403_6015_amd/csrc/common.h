@@ -281,6 +281,7 @@ struct Plan {
     std::vector<std::vector<Chunk>> lvl;
     std::vector<std::vector<int>> lvl_nch;   // per depth, per node: chunks (both sides)
     std::vector<std::vector<int>> lvl_base;  // per depth, per node: first partial slot
+    std::vector<int> lvl_maxlen;             // per depth: rows of the longest chunk
     // offsets of the device tables inside their image
     struct TableOffsets {
         size_t start, end, ar, ac, pc, nr, nc, rb, cb, bg, sm, ri, ci;

@@ -78,8 +78,34 @@ struct LevelArgs {
     int cgrp;          // columns per work-group of the small-rank reduction
     int rows;          // rows per chunk (a node's chunks: its alpha rows, then its beta rows)
     int tsum;          // 1: T was summed from the records by level_sum_kernel
+    // records written by the fused pass of the level below (nullable): node
+    // loc's alpha records are the chunks of its alpha child in that level's
+    // table ([cbase[2 loc], + cnch[2 loc])), its beta records those of its beta
+    // child, right after them
+    const int *cbase, *cnch;
+    // the fused pass (update of this level, records of the level above):
+    // that level's panel column, rank stride and record columns (= nrhs)
+    int64_t colWp;
+    int rstride_p;
     BatchArgs B;
 };
+
+// a node's record ranges: alpha [base, base + na), beta [base + na, base + nch)
+__device__ __forceinline__ void node_records(const LevelArgs &A, int64_t loc, int &base, int &na,
+                                             int &nch)
+{
+    if (A.cbase) {
+        base = A.cbase[2 * loc];
+        na = A.cnch[2 * loc];
+        nch = na + A.cnch[2 * loc + 1];
+        return;
+    }
+    nch = A.nch[loc];
+    base = A.base[loc];
+    const int64_t ns = A.chunks[base].lo, ne = A.chunks[base + nch - 1].hi;
+    const int64_t alen = (ne - ns) / 2;
+    na = (int)((alen + A.rows - 1) / A.rows);
+}
 
 // this work-group's batch item: offset every per-item pointer
 __device__ __forceinline__ LevelArgs item_args(LevelArgs A)
@@ -277,6 +303,256 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_small_kernel(LevelArg
     }
 }
 
+// Cross-lane moves for the butterfly sums of the fused pass (values in
+// registers, no LDS): DPP within a row of 16 lanes, the lane-swap
+// instructions across rows and across the two halves of the wave.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// lanes L and L ^ M (M = 32 or 16): L with bit M clear returns a(L) +
+// a(L ^ M), L with the bit set b(L) + b(L ^ M)
+template <int M>
+__device__ __forceinline__ double swap_sum(double a, double b)
+{
+    const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    unsigned lo0 = (unsigned)x, hi0 = (unsigned)(x >> 32), lo1 = (unsigned)y, hi1 = (unsigned)(y >> 32);
+    if constexpr (M == 32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo0, lo1, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi0, hi1, false, false);
+        lo0 = l[0], lo1 = l[1], hi0 = h[0], hi1 = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo0, lo1, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi0, hi1, false, false);
+        lo0 = l[0], lo1 = l[1], hi0 = h[0], hi1 = h[1];
+    }
+    return __longlong_as_double(((long long)hi0 << 32) | lo0) +
+           __longlong_as_double(((long long)hi1 << 32) | lo1);
+}
+
+// DPP patterns pairing each lane with one whose bit M differs (M <= 8):
+// row mirror (i <-> 15 - i), half-row mirror (i <-> 7 - i), quad swaps
+template <int M>
+__device__ __forceinline__ double pair_move(double v)
+{
+    if constexpr (M == 8)
+        return dpp64<0x140>(v);
+    else if constexpr (M == 4)
+        return dpp64<0x141>(v);
+    else if constexpr (M == 2)
+        return dpp64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    else
+        return dpp64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+}
+
+// One halving step of the butterfly over v[0, 2H): the pairing of step M
+// joins lanes that hold the same outputs and disjoint sets of summed lanes;
+// a lane keeps the upper half if its bit M is set.
+template <int M, int H>
+__device__ __forceinline__ void halve(double *v, int lane)
+{
+    if constexpr (M >= 16) {
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+            v[j] = swap_sum<M>(v[j], v[j + H]);
+    } else {
+        const bool up = (lane & M) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const double send = up ? v[j] : v[j + H];
+            const double keep = up ? v[j + H] : v[j];
+            v[j] = keep + pair_move<M>(send);
+        }
+    }
+}
+
+// sums of NO values per lane over the 64 lanes: afterwards v[0] of lane l is
+// output l / (64 / NO), complete in every lane
+template <int NO>
+__device__ __forceinline__ double wave_sums(double *v, int lane)
+{
+    static_assert(NO == 16 || NO == 32, "outputs per wave");
+    halve<32, NO / 2>(v, lane);
+    halve<16, NO / 4>(v, lane);
+    halve<8, NO / 8>(v, lane);
+    halve<4, NO / 16>(v, lane);
+    if constexpr (NO == 32)
+        halve<2, 1>(v, lane);
+    double a = v[0];
+    // the lanes sharing an output: a quad (NO = 16) or a pair (NO = 32)
+    if constexpr (NO == 16)
+        a += pair_move<2>(a);
+    a += pair_move<1>(a);
+    return a;
+}
+
+// Fused pass for small ranks: the update of level d (X -= W~ S on the
+// chunk's rows) and the reduction records of level d-1 on the same rows
+// (W_{d-1}^T X over the chunk, of the updated X as stored), so that X is read
+// once for both.  The columns updated at level d are exactly those level d-1
+// reduces (its child panel is level d's last updated panel).  One work-group
+// per level-d chunk, as many waves as the level's longest chunk needs (at
+// most 8), RW rows per lane (row lo + 64 RW w + lane + 64 t of wave w; lanes
+// past the chunk read its last row and contribute nothing), CU columns at a
+// time with the next group's loads issued before this group's arithmetic.
+// A group's CU x RP products are summed across the wave in registers
+// (wave_sums) and left in LDS per wave and group; after the last group one
+// barrier, then the work-group sums the waves.  The record of chunk q holds
+// level d-1's rows l < rank(parent) at A.part + q rstride_p nrhs; the level
+// above finds a node's records through its children's chunk ranges.
+constexpr int LVF_MAXW = 8;
+constexpr int LVF_CU = 4;
+
+template <typename PT, int R, int RP, int RW>
+__global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0)
+{
+    constexpr int CU = LVF_CU;
+    const LevelArgs A = item_args(A0);
+    PT *__restrict__ Xp = (PT *)A.Xt;
+    const double *__restrict__ Wp = A.W;
+    const Chunk ch = A.chunks[blockIdx.x];
+    const int r = A.rank[ch.node];
+    const int rp = A.rank[(ch.node - 1) / 2];
+    if (r == 0 && rp == 0)
+        return;
+    const int64_t n = A.n;
+    const int nrhs = A.nrhs;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    constexpr int NO = CU * RP;
+    constexpr int G = 64 / NO;   // lanes holding each output after the butterfly
+    const int ngrp = (nrhs + CU - 1) / CU;
+    extern __shared__ double sdyn[];
+    double *sS = sdyn;                 // R x nrhs
+    double *wsum = sdyn + R * nrhs;    // [group][wave][NO]: the waves' sums
+    int *scol = (int *)(wsum + (int64_t)ngrp * nw * NO);   // the column list
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+        scol[c] = A.cols[c];
+    const int64_t loc = ch.node - A.node0;
+    const double *S = A.Sbuf + loc * A.tstride;
+    const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
+    for (int idx = threadIdx.x; idx < R * nrhs; idx += blockDim.x) {
+        const int l = idx / nrhs, c = idx % nrhs;
+        sS[idx] = (l < r) ? S[(int64_t)(rowoff + l) * nrhs + c] : 0.0;
+    }
+    int64_t rowi[RW];
+    bool ok[RW];
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+        const int64_t i = ch.lo + 64 * RW * wid + lane + 64 * t;
+        ok[t] = i < ch.hi;
+        rowi[t] = ok[t] ? i : ch.hi - 1;
+    }
+    // panel columns past a node's rank are read at its last column (or the
+    // panel's first) and zeroed.  Every load is issued before the first
+    // value is pinned in a register (the empty asm), so that the zeroing
+    // selects do not turn into one branch and one wait per load.
+    double wt[RW][R], wp[RW][RP];
+#pragma unroll
+    for (int l = 0; l < R; ++l) {
+        const int64_t col = A.colW + (l < r ? l : (r > 0 ? r - 1 : 0));
+#pragma unroll
+        for (int t = 0; t < RW; ++t)
+            wt[t][l] = (double)Xp[col * n + rowi[t]];
+    }
+#pragma unroll
+    for (int l = 0; l < RP; ++l) {
+        const int64_t col = A.colWp + (l < rp ? l : (rp > 0 ? rp - 1 : 0));
+#pragma unroll
+        for (int t = 0; t < RW; ++t)
+            wp[t][l] = Wp[col * n + rowi[t]];
+    }
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+#pragma unroll
+        for (int l = 0; l < R; ++l) {
+            asm volatile("" : "+v"(wt[t][l]));
+            wt[t][l] = (ok[t] && l < r) ? wt[t][l] : 0.0;
+        }
+#pragma unroll
+        for (int l = 0; l < RP; ++l) {
+            asm volatile("" : "+v"(wp[t][l]));
+            wp[t][l] = (ok[t] && l < rp) ? wp[t][l] : 0.0;
+        }
+    }
+    auto load = [&](int c0, PT *xc[CU], PT x[RW][CU]) {
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            xc[u] = Xp + (int64_t)scol[c0 + u < nrhs ? c0 + u : nrhs - 1] * n;
+#pragma unroll
+        for (int t = 0; t < RW; ++t)
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                x[t][u] = xc[u][rowi[t]];
+    };
+    __syncthreads();   // S and the column list staged
+    PT *xc[CU], *xcn[CU];
+    PT x[RW][CU], xn[RW][CU];
+    if (ngrp > 0)
+        load(0, xc, x);
+    for (int g = 0; g < ngrp; ++g) {
+        const int c0 = g * CU;
+        if (g + 1 < ngrp)
+            load(c0 + CU, xcn, xn);
+        double v[NO];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            double sv[R];
+#pragma unroll
+            for (int l = 0; l < R; ++l)
+                sv[l] = c0 + u < nrhs ? sS[l * nrhs + c0 + u] : 0.0;
+#pragma unroll
+            for (int l = 0; l < RP; ++l)
+                v[u * RP + l] = 0.0;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                double a = (double)x[t][u];
+#pragma unroll
+                for (int l = 0; l < R; ++l)
+                    a -= wt[t][l] * sv[l];
+                const PT st = (PT)a;
+                if (r > 0 && ok[t] && c0 + u < nrhs)
+                    xc[u][rowi[t]] = st;
+                const double xs = (double)st;
+#pragma unroll
+                for (int l = 0; l < RP; ++l)
+                    v[u * RP + l] += wp[t][l] * xs;
+            }
+        }
+        if (rp > 0) {
+            const double a = wave_sums<NO>(v, lane);
+            if ((lane % G) == 0)
+                wsum[((int64_t)g * nw + wid) * NO + lane / G] = a;
+        }
+        if (g + 1 < ngrp) {
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                xc[u] = xcn[u];
+#pragma unroll
+            for (int t = 0; t < RW; ++t)
+#pragma unroll
+                for (int u = 0; u < CU; ++u)
+                    x[t][u] = xn[t][u];
+        }
+    }
+    if (rp == 0)
+        return;   // uniform over the work-group
+    __syncthreads();
+    double *rec = A.part + (int64_t)ch.part * A.rstride_p * nrhs;
+    for (int idx = threadIdx.x; idx < rp * nrhs; idx += blockDim.x) {
+        const int l = idx / nrhs, c = idx % nrhs;
+        const int g = c / CU, o = (c % CU) * RP + l;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w)
+            s += wsum[((int64_t)g * nw + w) * NO + o];
+        rec[(int64_t)l * nrhs + c] = s;
+    }
+}
+
 // T of every node of a level with few nodes: one thread per output, summing
 // the node's chunk records of that side in chunk order (four partial sums).
 // The node solve would otherwise sum a top-level node's many records in one
@@ -291,10 +567,8 @@ __global__ __launch_bounds__(LV_THREADS) void level_sum_kernel(LevelArgs A0)
     const int o = blockIdx.y * LV_THREADS + threadIdx.x;
     if (r == 0 || o >= 2 * r * ncnt)
         return;
-    const int nch = A.nch[loc], base = A.base[loc];
-    const int64_t ns = A.chunks[base].lo, ne = A.chunks[base + nch - 1].hi;
-    const int64_t alen = (ne - ns) / 2;
-    const int na = (int)((alen + A.rows - 1) / A.rows);
+    int base, na, nch;
+    node_records(A, loc, base, na, nch);
     const int row2 = o / ncnt, c = o % ncnt;
     const int side = row2 < r ? 1 : 0;
     const int l = row2 < r ? row2 : row2 - r;
@@ -343,7 +617,6 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     __shared__ int piv[RMAX_LDS];
     __shared__ double red[TH / 64];
     __shared__ int sbad;
-    const int nch = A.nch[loc], base = A.base[loc];
     const int ncnt = A.ncnt, rs = A.rstride;
     double *T = A.Tbuf + loc * A.tstride;
     // T rows [0, rs): beta side (top); [rs, 2 rs): alpha side (bottom)
@@ -352,9 +625,8 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
         // node's records; groups stay inside one wave for the final sum.
         // The node's records are its alpha chunks, then its beta chunks, so
         // each side is one contiguous range (na = alpha chunks).
-        const int64_t ns = A.chunks[base].lo, ne = A.chunks[base + nch - 1].hi;
-        const int64_t alen = (ne - ns) / 2;
-        const int na = (int)((alen + A.rows - 1) / A.rows);
+        int base, na, nch;
+        node_records(A, loc, base, na, nch);
         const int nout = 2 * r * ncnt;
         int G = 1;
         while (G < 64 && G * 2 * nout <= TH && G < nch)
@@ -1253,6 +1525,9 @@ static LevelArgs level_args(Pipeline &P, int d)
     A.cgrp = p.red_grp;
     A.rows = p.lvl_rows;
     A.tsum = 0;
+    A.cbase = A.cnch = nullptr;
+    A.colWp = 0;
+    A.rstride_p = 0;
     return A;
 }
 
@@ -1319,6 +1594,57 @@ static void update_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs
         level_update_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
 }
 
+template <typename PT, int R, int RP>
+static void fused_rows(int rw, dim3 grid, int th, size_t lds, hipStream_t s, const LevelArgs &A)
+{
+    if (rw == 1)
+        level_fused_kernel<PT, R, RP, 1><<<grid, th, lds, s>>>(A);
+    else
+        level_fused_kernel<PT, R, RP, 2><<<grid, th, lds, s>>>(A);
+}
+
+// LDS of the fused pass: S (R x nrhs), the waves' sums of every column
+// group (LVF_CU columns, RP rows each) and the column list
+static size_t fused_lds(int nrhs, int R, int RP)
+{
+    const size_t groups = (size_t)(nrhs + LVF_CU - 1) / LVF_CU;
+    return sizeof(double) * ((size_t)R * nrhs + groups * LVF_MAXW * LVF_CU * RP) +
+           sizeof(int) * (size_t)nrhs;
+}
+
+// the fused update + parent records: ranks classed as 4 (1..4) or 8 (5..8);
+// one row per lane for 256-row chunks, else two, and as many waves as the
+// level's longest chunk needs
+template <typename PT>
+static void fused_launch(Pipeline &P, int d, unsigned nchunks, const LevelArgs &A)
+{
+    const int R = A.rstride <= 4 ? 4 : 8, RP = A.rstride_p <= 4 ? 4 : 8;
+    const int rw = P.plan->lvl_rows <= 256 ? 1 : 2;
+    const size_t lds = fused_lds(A.nrhs, R, RP);
+    const dim3 grid(nchunks, 1, P.nitems);
+    const int nw = std::min(LVF_MAXW, (P.plan->lvl_maxlen[d] + 64 * rw - 1) / (64 * rw));
+    const int th = 64 * std::max(nw, 1);
+    if (R == 4 && RP == 4)
+        fused_rows<PT, 4, 4>(rw, grid, th, lds, P.stream, A);
+    else if (R == 4)
+        fused_rows<PT, 4, 8>(rw, grid, th, lds, P.stream, A);
+    else if (RP == 4)
+        fused_rows<PT, 8, 4>(rw, grid, th, lds, P.stream, A);
+    else
+        fused_rows<PT, 8, 8>(rw, grid, th, lds, P.stream, A);
+}
+
+// whether level d's update also writes level d-1's reduction records: both
+// levels of the small-rank kind with S in LDS
+static bool fuse_levels(const Pipeline &P, int d)
+{
+    const Plan &p = *P.plan;
+    if (d < 1 || p.lvl[d].empty() || P.cnt[d] <= 0)
+        return false;
+    const int r = P.rmax[d + 1], rp = P.rmax[d];
+    return r > 0 && r <= 8 && rp > 0 && rp <= 8 && fused_lds(P.cnt[d], 8, 8) <= 64 * 1024;
+}
+
 // levels of rank above RMAX_LDS: the MFMA reduction over rank groups of 64,
 // the record sums, the node solves (N in LDS up to rank LVG_RMAX, else in
 // HBM), and the MFMA update over rank chunks of 64
@@ -1357,7 +1683,7 @@ static void level_launch_wide(Pipeline &P, int d, LevelArgs A)
 }
 
 template <typename PT>
-static void level_launch_t(Pipeline &P, int d, LevelArgs A)
+static void level_launch_t(Pipeline &P, int d, LevelArgs A, bool fuse_up)
 {
     if (A.rstride > RMAX_LDS) {
         level_launch_wide<PT>(P, d, A);
@@ -1369,7 +1695,7 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     const int R = A.rstride <= 2 ? 2 : A.rstride <= 4 ? 4 : A.rstride <= 8 ? 8 : 0;
     const size_t sbytes = sizeof(double) * (size_t)R * A.nrhs;
     const bool small_upd = R > 0 && sbytes <= 48 * 1024;
-    if (nchunks) {
+    if (nchunks && !A.cbase) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
         const dim3 grid(nchunks, (A.ncnt + p.red_grp - 1) / p.red_grp, P.nitems);
         if (R > 0)
@@ -1398,7 +1724,9 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     }
     if (nchunks && A.nrhs > 0) {
         ProfScope ps(P.stream, PS_LVL_UPDATE);
-        if (small_upd && R == 2)
+        if (fuse_up)
+            fused_launch<PT>(P, d, nchunks, A);
+        else if (small_upd && R == 2)
             level_update_small_kernel<PT, 2><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
         else if (small_upd && R == 4)
             level_update_small_kernel<PT, 4><<<dim3(nchunks, 1, P.nitems), LV_THREADS, sbytes, P.stream>>>(A, 0);
@@ -1412,17 +1740,18 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A)
     HIP_TRY(hipGetLastError());
 }
 
-static void level_launch(Pipeline &P, int d, LevelArgs A)
+static void level_launch(Pipeline &P, int d, LevelArgs A, bool fuse_up = false)
 {
     if (P.plan->f32())
-        level_launch_t<float>(P, d, A);
+        level_launch_t<float>(P, d, A, fuse_up);
     else
-        level_launch_t<double>(P, d, A);
+        level_launch_t<double>(P, d, A, fuse_up);
 }
 
 void run_levels_factor(Pipeline &P)
 {
     const Plan &p = *P.plan;
+    bool below = false;   // level d+1's update wrote this level's records
     for (int d = p.L - 1; d >= 0; --d) {
         LevelArgs A = level_args(P, d);
         A.factor = 1;
@@ -1435,9 +1764,20 @@ void run_levels_factor(Pipeline &P)
             ProfScope ps(P.stream, PS_LVL_SOLVE);
             launch_solve(P, A, nodes);
             HIP_TRY(hipGetLastError());
+            below = false;
             continue;
         }
-        level_launch(P, d, A);
+        if (below) {
+            A.cbase = p.d_lvl_base[d + 1];
+            A.cnch = p.d_lvl_nch[d + 1];
+        }
+        const bool fuse = fuse_levels(P, d);
+        if (fuse) {
+            A.colWp = p.cofa[d];
+            A.rstride_p = P.rmax[d];
+        }
+        level_launch(P, d, A, fuse);
+        below = fuse;
     }
 }
 

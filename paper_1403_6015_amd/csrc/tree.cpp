@@ -198,6 +198,10 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
             p.lvl_nch[d].push_back(slot - p.lvl_base[d].back());
         }
     }
+    p.lvl_maxlen.assign(L, 0);
+    for (int d = 0; d < L; ++d)
+        for (const Chunk &c : p.lvl[d])
+            p.lvl_maxlen[d] = std::max(p.lvl_maxlen[d], (int)(c.hi - c.lo));
     // sketch compressor tables
     p.sk.assign(p.compressor == HODLR_COMPRESS_SKETCH ? L : 0, {});
     p.sk_abase.assign(p.sk.size(), {});
@@ -396,6 +400,9 @@ Layout make_layout(const Plan &p, bool store_leaf)
         int64_t cntc = p.cofa[d + 2];           // columns 0 .. end of panel d+1
         int64_t r = p.capj[d + 1];
         lp = std::max<int64_t>(lp, (int64_t)p.lvl[d].size() * r * cntc);
+        // records of level d-1 written by level d's fused update
+        if (d > 0)
+            lp = std::max<int64_t>(lp, (int64_t)p.lvl[d].size() * p.capj[d] * p.cofa[d + 1]);
         tb = std::max<int64_t>(tb, (p.first_at(d + 1) - p.first_at(d)) * 2 * r * cntc);
     }
     y.lvl_part_cap = lp;
