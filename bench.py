@@ -39,7 +39,10 @@ def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     leaf_sizes: sizes of the leaves; r[j]: columns of the depth-j panel
     (j = 1..L); cnt[d] = 1 + sum_{j<=d} r[j] (columns still updated at depth d
     plus the right-hand side).  Bytes count each panel operand moved once
-    (esz bytes per entry: 8 in the FP64 form, 4 in the mixed form).
+    (esz bytes per entry: 8 in the FP64 form, 4 in the mixed form).  Where
+    depth d's update is fused with depth d-1's reduction (small ranks), the
+    update also reads the depth-(d-1) basis and that reduction reads nothing
+    of its own.
     """
     L = len(cnt) - 1
     m = np.asarray(leaf_sizes, dtype=np.float64)
@@ -49,12 +52,26 @@ def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     byts = esz * n * (2 * cnt[L])
     out["leaf_factor"] = (flops, byts)
     fr = br = fu = bu = 0.0
+
+    def fused(d):
+        # depth d's update also writes depth d-1's reduction records (both
+        # panels of rank 1..8 and the pass's LDS within 64 KB)
+        if d < 1 or d >= L or not (0 < r[d + 1] <= 8 and 0 < r[d] <= 8):
+            return False
+        c = cnt[d]
+        return 8 * (8 * c + ((c + 3) // 4) * 8 * 4 * 8) + 4 * c <= 65536
+
     for d in range(L):
         rr = r[d + 1]
-        fr += 2.0 * rr * cnt[d + 1] * n
-        br += esz * n * (cnt[d + 1] + rr)
+        if rr > 0 and not fused(d + 1):
+            fr += 2.0 * rr * cnt[d + 1] * n
+            br += esz * n * (cnt[d + 1] + rr)
         fu += 2.0 * rr * cnt[d] * n
         bu += esz * n * (2 * cnt[d] + rr)
+        if fused(d):
+            # the parent's basis (FP64) against the updated columns
+            fu += 2.0 * r[d] * cnt[d] * n
+            bu += 8.0 * n * r[d]
     out["level_reduce"] = (fr, br)
     out["level_update"] = (fu, bu)
     return out

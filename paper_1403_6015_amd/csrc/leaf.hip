@@ -328,69 +328,109 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     }
     const int nt = (m + 15) >> 4;
     double *gout = A.G ? A.G + b * A.gstride : nullptr;
-    // C = K + sigma^2 I on the lower tiles, identity on the padding.  With
-    // 256 threads every thread owns the same element (rr, cc) of each tile,
-    // so it needs only 8 row and 8 column points.
-    static_assert(LEAF_MT == 256, "one tile element per thread");
-    const int rr = tid & 15, cc = tid >> 4;
-    double xr[3][NT_MAX], xk[3][NT_MAX];
-#pragma unroll
-    for (int I = 0; I < NT_MAX; ++I) {
-        int i = 16 * I + rr, k = 16 * I + cc;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            xr[d][I] = (d < kp.dim && i < m) ? A.x[d * n + s + i] : 0.0;
-            xk[d][I] = (d < kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
-        }
-    }
+    // C_lambda^{-1} is applied to the column list in groups of 16 columns, one
+    // group per wave, held in registers.  Groups 0..2 belong to waves 1..3
+    // from the start: their loads are in flight during the evaluation (issued
+    // after the evaluation's own global loads have returned: the wait on
+    // those would otherwise include them), and their forward substitution
+    // runs inside the factorization (step J once L_JJ^{-1} and column J of L
+    // exist), in the time those waves would otherwise wait for wave 0's
+    // serial diagonal factorizations; only the backward substitution is left
+    // after it.
+    const int ngrp = (A.ncols - A.cbeg + 15) / 16;
+    const int pg = wid - 1;
+    const bool piped = wid > 0 && pg < ngrp;
+    d4 X[NT_MAX];
+    bool bad = false;   // wave 0 only
     // Separable form for 1-D exponential-family kernels on an ascending leaf:
     // for x_i >= x_k, exp(-c (x_i - x_k)) = E_i F_k with E_i = exp(-c (x_i -
-    // x_0)) and F_k = exp(c (x_k - x_0)), x_0 the leaf's first point, so a
-    // thread takes 16 exponentials instead of one exponential and one square
+    // x_0)) and F_k = exp(c (x_k - x_0)), x_0 the leaf's first point, so the
+    // leaf takes 2 m exponentials instead of one exponential and one square
     // root per entry.  Used when the leaf is checked to be in ascending order
     // and c times its span is below 500 (every factor far inside the FP64
     // range); the entries then differ from direct evaluation by a few units
     // in the last place, and the diagonal is exactly a^2 + sigma^2 (plus the
-    // point's own variance when per-point noise is given).
+    // point's own variance when per-point noise is given).  E, F and the
+    // points pass through LDS words the tiles never use (the 17th entry of
+    // each tile column); every thread then holds the factors of its 8 rows
+    // and 8 columns, and an entry of a tile below the diagonal block row
+    // costs three multiplies and a subtraction.
     const bool sep_kind = kp.dim == 1 && (kp.kind == HODLR_K_MATERN32 || kp.kind == HODLR_K_EXP);
-    const int unsorted = (sep_kind && tid + 1 < m && A.x[s + tid + 1] < A.x[s + tid]) ? 1 : 0;
-    const int any_unsorted = __syncthreads_or(unsorted);
-    const double x0 = A.x[s];
-    const bool sep = sep_kind && !any_unsorted && kp.c * (A.x[s + m - 1] - x0) < 500.0;
-    // Entries above the diagonal of a diagonal tile are never read by the
-    // factorization (it works on the lower triangle) and are left zero.
-    if (sep) {
-        double E[NT_MAX], F[NT_MAX];
+    bool sep = false;
+    if (sep_kind) {
+        static_assert(3 * LEAF_LDS_MAX <= NTRI * 16, "padding words for E, F and the points");
+        auto pad = [&](int j) -> double & { return Gt[(j >> 4) * TSZ + (j & 15) * TLD + 16]; };
+        const int i = tid & (LEAF_LDS_MAX - 1);
+        const double x0 = A.x[s], xl = A.x[s + m - 1];
+        const double xi = i < m ? A.x[s + i] : 0.0;
+        const double xn = tid + 1 < m ? A.x[s + tid + 1] : 0.0;   // tid + 1 < m implies tid < 128
+        const int unsorted = (tid + 1 < m && xn < xi) ? 1 : 0;
+        sep = !__syncthreads_or(unsorted) && kp.c * (xl - x0) < 500.0;
+        if (sep) {
+            if (i < m) {
+                pad(tid) = exp((tid < LEAF_LDS_MAX ? -kp.c : kp.c) * (xi - x0));   // E then F
+                if (tid < LEAF_LDS_MAX)
+                    pad(2 * LEAF_LDS_MAX + i) = xi;
+            }
+            __syncthreads();
+            static_assert(LEAF_MT == 256, "one tile element per thread");
+            const int rr = tid & 15, cc = tid >> 4;
+            double aE[NT_MAX], xr1[NT_MAX], Fc[NT_MAX], xc1[NT_MAX];
 #pragma unroll
-        for (int I = 0; I < NT_MAX; ++I) {
-            E[I] = (16 * I + rr < m) ? exp(-kp.c * (xr[0][I] - x0)) : 0.0;
-            F[I] = (16 * I + cc < m) ? exp(kp.c * (xk[0][I] - x0)) : 0.0;
-        }
+            for (int I = 0; I < NT_MAX; ++I) {
+                const int ic = min(16 * I + rr, m - 1), kc = min(16 * I + cc, m - 1);
+                aE[I] = kp.a2 * pad(ic);
+                xr1[I] = pad(2 * LEAF_LDS_MAX + ic);
+                Fc[I] = pad(LEAF_LDS_MAX + kc);
+                xc1[I] = pad(2 * LEAF_LDS_MAX + kc);
+            }
+            const bool matern = kp.kind == HODLR_K_MATERN32;
+            const double dg = kp.a2 + kp.sigma2;
 #pragma unroll
-        for (int I = 0; I < NT_MAX; ++I) {
+            for (int I = 0; I < NT_MAX; ++I) {
 #pragma unroll
-            for (int K = 0; K <= I; ++K) {
-                if (I < nt) {
-                    const int i = 16 * I + rr, k = 16 * K + cc;
-                    double v;
-                    if (i < m && k < m) {
-                        if (i > k) {
-                            const double e = E[I] * F[K];
-                            v = kp.kind == HODLR_K_MATERN32
-                                    ? kp.a2 * (1.0 + kp.c * (xr[0][I] - xk[0][K])) * e
-                                    : kp.a2 * e;
+                for (int K = 0; K <= I; ++K) {
+                    if (I < nt) {
+                        double v;
+                        if (K < I && 16 * I + 15 < m) {
+                            // below the diagonal block row, every row inside the leaf
+                            const double e = aE[I] * Fc[K];
+                            v = matern ? e * (1.0 + kp.c * (xr1[I] - xc1[K])) : e;
                         } else {
-                            v = (i == k) ? kp.a2 + kp.sigma2 + (kp.noise ? kp.noise[s + i] : 0.0)
-                                         : 0.0;
+                            const int ii = 16 * I + rr, k = 16 * K + cc;
+                            if (ii < m && k < m) {
+                                const double e = aE[I] * Fc[K];
+                                const double off = matern ? e * (1.0 + kp.c * (xr1[I] - xc1[K])) : e;
+                                v = ii > k ? off
+                                           : (ii == k ? dg + (kp.noise ? kp.noise[s + ii] : 0.0) : 0.0);
+                            } else {
+                                v = (ii == k) ? 1.0 : 0.0;
+                            }
                         }
-                    } else {
-                        v = (i == k) ? 1.0 : 0.0;
+                        Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
                     }
-                    Gt[tix(I, K) * TSZ + cc * TLD + rr] = v;
                 }
             }
         }
-    } else {
+    }
+    if (!sep) {
+        // C = K + sigma^2 I on the lower tiles, identity on the padding.
+        // With 256 threads every thread owns the same element (rr, cc) of
+        // each tile, so it needs only 8 row and 8 column points.
+        static_assert(LEAF_MT == 256, "one tile element per thread");
+        const int rr = tid & 15, cc = tid >> 4;
+        double xr[3][NT_MAX], xk[3][NT_MAX];
+#pragma unroll
+        for (int I = 0; I < NT_MAX; ++I) {
+            int i = 16 * I + rr, k = 16 * I + cc;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                xr[d][I] = (d < kp.dim && i < m) ? A.x[d * n + s + i] : 0.0;
+                xk[d][I] = (d < kp.dim && k < m) ? A.x[d * n + s + k] : 0.0;
+            }
+        }
+        // entries above the diagonal of a diagonal tile are never read by
+        // the factorization (it works on the lower triangle) and are left zero
 #pragma unroll
         for (int I = 0; I < NT_MAX; ++I) {
 #pragma unroll
@@ -417,19 +457,8 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         }
     }
     __syncthreads();
-    // C_lambda^{-1} is applied to the column list in groups of 16 columns, one
-    // group per wave, held in registers.  Groups 0..2 belong to waves 1..3
-    // from the start: their forward substitution runs inside the
-    // factorization (step J once L_JJ^{-1} and column J of L exist), in the
-    // time those waves would otherwise wait for wave 0's serial diagonal
-    // factorizations; only the backward substitution is left after it.
-    const int ngrp = (A.ncols - A.cbeg + 15) / 16;
-    const int pg = wid - 1;
-    const bool piped = wid > 0 && pg < ngrp;
-    d4 X[NT_MAX];
     if (piped)
         rhs_load(X, A, A.cbeg + 16 * pg, ysrc, Wsrc, s, n, nt, m);
-    bool bad = false;   // wave 0 only
     if (wid == 0)
         bad = diag_factor(Gt, s_diag, gout, 0, m);
     __syncthreads();

@@ -408,36 +408,46 @@ __device__ __forceinline__ double wave_sums(double *v, int lane)
 constexpr int LVF_MAXW = 8;
 constexpr int LVF_CU = 4;
 
-template <typename PT, int R, int RP, int RW>
+//
+// With UPD false the same pass only reduces, for the level's own records
+// (the deepest level, whose reduction no finer update can carry): no update,
+// W of the chunk's own node against the A.ncnt reduced columns, records laid
+// out as the small-rank reduction's.
+template <typename PT, int R, int RP, int RW, bool UPD>
 __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0)
 {
     constexpr int CU = LVF_CU;
+    constexpr int RU = UPD ? R : 1;   // update ranks held (none without the update)
     const LevelArgs A = item_args(A0);
     PT *__restrict__ Xp = (PT *)A.Xt;
     const double *__restrict__ Wp = A.W;
     const Chunk ch = A.chunks[blockIdx.x];
-    const int r = A.rank[ch.node];
-    const int rp = A.rank[(ch.node - 1) / 2];
+    const int r = UPD ? A.rank[ch.node] : 0;
+    const int rp = UPD ? A.rank[(ch.node - 1) / 2] : A.rank[ch.node];
     if (r == 0 && rp == 0)
         return;
     const int64_t n = A.n;
-    const int nrhs = A.nrhs;
+    const int nrhs = UPD ? A.nrhs : A.ncnt;   // columns updated and reduced
+    const int64_t colp = UPD ? A.colWp : A.colW;
+    const int rsp = UPD ? A.rstride_p : A.rstride;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     constexpr int NO = CU * RP;
     constexpr int G = 64 / NO;   // lanes holding each output after the butterfly
     const int ngrp = (nrhs + CU - 1) / CU;
     extern __shared__ double sdyn[];
-    double *sS = sdyn;                 // R x nrhs
-    double *wsum = sdyn + R * nrhs;    // [group][wave][NO]: the waves' sums
+    double *sS = sdyn;                                 // R x nrhs (with the update)
+    double *wsum = sdyn + (UPD ? R * nrhs : 0);        // [group][wave][NO]: the waves' sums
     int *scol = (int *)(wsum + (int64_t)ngrp * nw * NO);   // the column list
     for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
         scol[c] = A.cols[c];
     const int64_t loc = ch.node - A.node0;
     const double *S = A.Sbuf + loc * A.tstride;
     const int rowoff = ch.side ? A.rstride : 0;   // alpha uses S_top, beta S_bottom
-    for (int idx = threadIdx.x; idx < R * nrhs; idx += blockDim.x) {
-        const int l = idx / nrhs, c = idx % nrhs;
-        sS[idx] = (l < r) ? S[(int64_t)(rowoff + l) * nrhs + c] : 0.0;
+    if (UPD) {
+        for (int idx = threadIdx.x; idx < R * nrhs; idx += blockDim.x) {
+            const int l = idx / nrhs, c = idx % nrhs;
+            sS[idx] = (l < r) ? S[(int64_t)(rowoff + l) * nrhs + c] : 0.0;
+        }
     }
     int64_t rowi[RW];
     bool ok[RW];
@@ -451,17 +461,17 @@ __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0
     // panel's first) and zeroed.  Every load is issued before the first
     // value is pinned in a register (the empty asm), so that the zeroing
     // selects do not turn into one branch and one wait per load.
-    double wt[RW][R], wp[RW][RP];
+    double wt[RW][RU], wp[RW][RP];
 #pragma unroll
-    for (int l = 0; l < R; ++l) {
+    for (int l = 0; l < RU; ++l) {
         const int64_t col = A.colW + (l < r ? l : (r > 0 ? r - 1 : 0));
 #pragma unroll
         for (int t = 0; t < RW; ++t)
-            wt[t][l] = (double)Xp[col * n + rowi[t]];
+            wt[t][l] = UPD ? (double)Xp[col * n + rowi[t]] : 0.0;
     }
 #pragma unroll
     for (int l = 0; l < RP; ++l) {
-        const int64_t col = A.colWp + (l < rp ? l : (rp > 0 ? rp - 1 : 0));
+        const int64_t col = colp + (l < rp ? l : (rp > 0 ? rp - 1 : 0));
 #pragma unroll
         for (int t = 0; t < RW; ++t)
             wp[t][l] = Wp[col * n + rowi[t]];
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0
 #pragma unroll
     for (int t = 0; t < RW; ++t) {
 #pragma unroll
-        for (int l = 0; l < R; ++l) {
+        for (int l = 0; l < RU; ++l) {
             asm volatile("" : "+v"(wt[t][l]));
             wt[t][l] = (ok[t] && l < r) ? wt[t][l] : 0.0;
         }
@@ -501,23 +511,26 @@ __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0
         double v[NO];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
-            double sv[R];
+            double sv[RU];
 #pragma unroll
-            for (int l = 0; l < R; ++l)
-                sv[l] = c0 + u < nrhs ? sS[l * nrhs + c0 + u] : 0.0;
+            for (int l = 0; l < RU; ++l)
+                sv[l] = UPD && c0 + u < nrhs ? sS[l * nrhs + c0 + u] : 0.0;
 #pragma unroll
             for (int l = 0; l < RP; ++l)
                 v[u * RP + l] = 0.0;
 #pragma unroll
             for (int t = 0; t < RW; ++t) {
-                double a = (double)x[t][u];
+                double xs = (double)x[t][u];
+                if constexpr (UPD) {
+                    double a = xs;
 #pragma unroll
-                for (int l = 0; l < R; ++l)
-                    a -= wt[t][l] * sv[l];
-                const PT st = (PT)a;
-                if (r > 0 && ok[t] && c0 + u < nrhs)
-                    xc[u][rowi[t]] = st;
-                const double xs = (double)st;
+                    for (int l = 0; l < R; ++l)
+                        a -= wt[t][l] * sv[l];
+                    const PT st = (PT)a;
+                    if (r > 0 && ok[t] && c0 + u < nrhs)
+                        xc[u][rowi[t]] = st;
+                    xs = (double)st;
+                }
 #pragma unroll
                 for (int l = 0; l < RP; ++l)
                     v[u * RP + l] += wp[t][l] * xs;
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0
     if (rp == 0)
         return;   // uniform over the work-group
     __syncthreads();
-    double *rec = A.part + (int64_t)ch.part * A.rstride_p * nrhs;
+    double *rec = A.part + (int64_t)ch.part * rsp * nrhs;
     for (int idx = threadIdx.x; idx < rp * nrhs; idx += blockDim.x) {
         const int l = idx / nrhs, c = idx % nrhs;
         const int g = c / CU, o = (c % CU) * RP + l;
@@ -1594,13 +1607,13 @@ static void update_mfma_launch(int mt, dim3 grid, hipStream_t s, const LevelArgs
         level_update_mfma_kernel<PT, 4><<<grid, LV_THREADS, 0, s>>>(A);
 }
 
-template <typename PT, int R, int RP>
+template <typename PT, int R, int RP, bool UPD>
 static void fused_rows(int rw, dim3 grid, int th, size_t lds, hipStream_t s, const LevelArgs &A)
 {
     if (rw == 1)
-        level_fused_kernel<PT, R, RP, 1><<<grid, th, lds, s>>>(A);
+        level_fused_kernel<PT, R, RP, 1, UPD><<<grid, th, lds, s>>>(A);
     else
-        level_fused_kernel<PT, R, RP, 2><<<grid, th, lds, s>>>(A);
+        level_fused_kernel<PT, R, RP, 2, UPD><<<grid, th, lds, s>>>(A);
 }
 
 // LDS of the fused pass: S (R x nrhs), the waves' sums of every column
@@ -1625,13 +1638,27 @@ static void fused_launch(Pipeline &P, int d, unsigned nchunks, const LevelArgs &
     const int nw = std::min(LVF_MAXW, (P.plan->lvl_maxlen[d] + 64 * rw - 1) / (64 * rw));
     const int th = 64 * std::max(nw, 1);
     if (R == 4 && RP == 4)
-        fused_rows<PT, 4, 4>(rw, grid, th, lds, P.stream, A);
+        fused_rows<PT, 4, 4, true>(rw, grid, th, lds, P.stream, A);
     else if (R == 4)
-        fused_rows<PT, 4, 8>(rw, grid, th, lds, P.stream, A);
+        fused_rows<PT, 4, 8, true>(rw, grid, th, lds, P.stream, A);
     else if (RP == 4)
-        fused_rows<PT, 8, 4>(rw, grid, th, lds, P.stream, A);
+        fused_rows<PT, 8, 4, true>(rw, grid, th, lds, P.stream, A);
     else
-        fused_rows<PT, 8, 8>(rw, grid, th, lds, P.stream, A);
+        fused_rows<PT, 8, 8, true>(rw, grid, th, lds, P.stream, A);
+}
+
+// the same pass as a plain reduction (the level's own records, A.ncnt columns)
+template <typename PT>
+static void fused_reduce_launch(Pipeline &P, int d, unsigned nchunks, const LevelArgs &A)
+{
+    const int rw = P.plan->lvl_rows <= 256 ? 1 : 2;
+    const dim3 grid(nchunks, 1, P.nitems);
+    const int nw = std::min(LVF_MAXW, (P.plan->lvl_maxlen[d] + 64 * rw - 1) / (64 * rw));
+    const int th = 64 * std::max(nw, 1);
+    if (A.rstride <= 4)
+        fused_rows<PT, 4, 4, false>(rw, grid, th, fused_lds(A.ncnt, 0, 4), P.stream, A);
+    else
+        fused_rows<PT, 4, 8, false>(rw, grid, th, fused_lds(A.ncnt, 0, 8), P.stream, A);
 }
 
 // whether level d's update also writes level d-1's reduction records: both
@@ -1698,7 +1725,9 @@ static void level_launch_t(Pipeline &P, int d, LevelArgs A, bool fuse_up)
     if (nchunks && !A.cbase) {
         ProfScope ps(P.stream, PS_LVL_REDUCE);
         const dim3 grid(nchunks, (A.ncnt + p.red_grp - 1) / p.red_grp, P.nitems);
-        if (R > 0)
+        if (R > 0 && A.factor && fused_lds(A.ncnt, 0, 8) <= 64 * 1024)
+            fused_reduce_launch<PT>(P, d, nchunks, A);
+        else if (R > 0)
             reduce_small_launch<PT>(R, p.lvl_rows / 64, p.red_cols, grid, P.stream, A);
         else
             reduce_lds_launch<PT>(nchunks, P.nitems, P.stream, A);
