@@ -243,6 +243,10 @@ def main():
                     help="mixed: FP32 basis panels, FP64 leaves / coupling LU / log-det sums "
                          "(matern1d, batched_theta, ragged)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-speculate", action="store_true",
+                    help="matern1d: every call waits for its compression's rank statistics "
+                         "(default: calls after the first assume the previous call's panel "
+                         "widths and step count, checked on the device, redone on a miss)")
     ap.add_argument("--compressor", default="aca", choices=["aca", "sketch"],
                     help="se2d: compress the off-diagonal blocks by cross approximation "
                          "(default) or by the randomized two-sided sketch (O(n^2) work; "
@@ -284,7 +288,8 @@ def main():
     ys = p.y[perm]
     mixed = args.precision == "mixed"
     prec = H.MIXED if mixed else H.FP64
-    opts = H.Opts(max_rank=64, precision=prec)
+    spec = 0 if args.no_speculate else 1
+    opts = H.Opts(max_rank=64, precision=prec, speculate=spec)
     # tiles from the autotuner at the workload's leaf size (untimed); the tuner
     # is also run with the leaf size free, for information
     t0 = time.perf_counter()
@@ -399,10 +404,12 @@ def main():
                    "n": p.n,
                    "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
                    "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": args.precision,
+                   "speculate": spec,
                    "levels": L, "rank_max": r[1:], "level_rows": tune.level_rows,
                    "reduce_cols": tune.reduce_cols, "reduce_group": tune.reduce_group},
         "roofline": roofline,
         "pipeline_roofline": pipeline,
+        "speculated_last_call": plan.info()["speculated"],
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "stage_launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
         "stage_note": "stage times from a separate pass with every launch timed; the timed "
@@ -426,7 +433,8 @@ def main():
         otune, _ = H.autotune(xs, ys, p.kernel, p.theta, p.sigma2, p.tol, otopts,
                               leaf_cands=[p.leaf], reps=2)
         oplan = H.Plan(p.n, p.dim, p.leaf,
-                       H.Opts(max_rank=64, precision=other, mixed_unchecked=unchecked), tune=otune)
+                       H.Opts(max_rank=64, precision=other, mixed_unchecked=unchecked,
+                              speculate=spec), tune=otune)
         owork = torch.empty(oplan.workspace_bytes, dtype=torch.uint8, device=dev)
         oout = torch.zeros(8, dtype=torch.float64, device=dev)
 

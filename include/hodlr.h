@@ -136,6 +136,19 @@ typedef struct {
                             taken by hodlr_build, gp_loglik, gp_loglik_dev and
                             gp_loglik_grad_dev (the batched, uneven-size and
                             autotuning entry points reject it with HODLR_EINVAL)  */
+    int32_t speculate;   /* gp_loglik_dev with cross approximation only.  0 (default):
+                            after the compression the call waits for the block ranks
+                            to lay out the panel columns.  1: a call on a plan whose
+                            previous gp_loglik_dev completed assumes that call's
+                            panel widths and large-block step count and runs on
+                            without waiting; a device check after the compression
+                            compares the actual ranks and convergence with them,
+                            and a call whose ranks exceed a width or whose blocks
+                            did not converge is redone the ordinary way (same
+                            results; when every rank fits but some width shrank,
+                            the padding columns change the rounding of the coupling
+                            solves at the 1e-15 level).  Meant for repeated
+                            likelihoods of nearby hyperparameters on one plan     */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one
@@ -161,6 +174,9 @@ typedef struct {
     int32_t fp64_fallback;                     /* mixed form: factors (or likelihoods
                                                   of the last plan call) redone with
                                                   FP64 panels (see HODLR_MIXED)    */
+    int32_t speculated;                        /* plans: 1 if the last gp_loglik_dev
+                                                  ran on the assumed panel widths
+                                                  without a redo (hodlr_opts.speculate) */
 } hodlr_info_t;
 
 /* ------------------------------------------------------------------ ordering */

@@ -1056,11 +1056,11 @@ void host_wait(hipStream_t s)
 int *pinned_ints(size_t n, int slot)
 {
     struct Buf {
-        int *p[2] = {nullptr, nullptr};
-        size_t cap[2] = {0, 0};
+        int *p[3] = {nullptr, nullptr, nullptr};
+        size_t cap[3] = {0, 0, 0};
         ~Buf()
         {
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 3; ++i)
                 if (p[i])
                     (void)hipHostFree(p[i]);
         }
@@ -1097,6 +1097,53 @@ static void read_rank_stats(Pipeline &P, const int *rank, const int *status, int
     HIP_TRY(hipMemcpyAsync(hr, rank, sizeof(int) * p.nint, hipMemcpyDeviceToHost, s));
     host_wait(s);
     std::memcpy(P.ranks.data(), hr, sizeof(int) * p.nint);
+}
+
+// After a speculative compression (no host wait): the rank statistics of
+// aca_stats_kernel (rmax[j] = largest rank at depth j - 1, rmax[48] capped,
+// rmax[49] converged large blocks) against the panel widths the call assumed
+// (w, per depth index as rmax) and the large-block count.  The actual
+// statistics are kept in save[0, 64) for the host.  On a miss (a rank above
+// its width, or a large block still running) the status word records it and
+// every block's rank is clamped to its depth's width, so that the rest of the
+// pipeline stays inside its buffers; the call is then redone by the host.
+// rmax[0 .. L+1] finally holds the assumed widths, as the padding kernel
+// expects.
+struct SpecArgs {
+    int *rank;
+    int64_t nint;
+    int *rmax, *save;
+    int *status;
+    int active;   // large blocks that must have converged
+    int L;
+    int w[64];
+};
+
+__global__ __launch_bounds__(256) void spec_check_kernel(SpecArgs a)
+{
+    __shared__ int miss;
+    if (threadIdx.x == 0)
+        miss = (a.active > 0 && a.rmax[49] < a.active) ? 1 : 0;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int v = a.rmax[threadIdx.x];
+        a.save[threadIdx.x] = v;
+        if ((int)threadIdx.x <= a.L + 1 && v > a.w[threadIdx.x])
+            miss = 1;   // every writer stores the same value
+    }
+    __syncthreads();
+    if (miss) {
+        for (int64_t h = threadIdx.x; h < a.nint; h += blockDim.x) {
+            int d = 0;
+            while (((int64_t)2 << d) - 1 <= h)
+                ++d;
+            a.rank[h] = min(a.rank[h], a.w[d + 1]);
+        }
+        if (threadIdx.x == 0)
+            atomicOr(a.status, DS_SPEC_MISS);
+    }
+    if ((int)threadIdx.x <= a.L + 1 && threadIdx.x < 48)
+        a.rmax[threadIdx.x] = a.w[threadIdx.x];
 }
 
 // Per-call initialization in one launch instead of a memset or copy each:
@@ -1261,6 +1308,11 @@ void run_aca(Pipeline &P)
         pipeline_init_kernel<<<(unsigned)std::max<int64_t>(nb, 1), 256, 0, s>>>(ia);
     }
     HIP_TRY(hipGetLastError());
+    // speculation: the previous call's widths and large-block step count
+    const int hint = __atomic_load_n(&p.aca_iters, __ATOMIC_RELAXED);
+    const bool spec = P.spec && (int)P.spec->size() == p.L + 2 && p.L + 2 <= 48 &&
+                      p.compressor == HODLR_COMPRESS_ACA && (p.aca_big.empty() || hint > 0);
+    P.spec_run = spec;
     if (p.compressor == HODLR_COMPRESS_SKETCH) {
         run_sketch_levels(P, rank, status);
         read_rank_stats(P, rank, status, d_rmax, d_capped, nullptr, pinned);
@@ -1358,7 +1410,6 @@ void run_aca(Pipeline &P)
         C.pout = crec;
         const int nrow = (int)p.aca_row.size(), ncol = (int)p.aca_col.size();
         const int max_iter = (p.cap + 1) * (ZERO_RETRY + 2) + 4;
-        const int hint = __atomic_load_n(&p.aca_iters, __ATOMIC_RELAXED);
         int it = 0;
         for (; it < max_iter; ++it) {
             {
@@ -1370,6 +1421,17 @@ void run_aca(Pipeline &P)
                 big_pass<false>(p, ncol, s, C);
             }
             HIP_TRY(hipGetLastError());
+            if (spec) {
+                // the previous call's step count, no poll: the device check
+                // below tells whether every block converged
+                if (it + 1 < hint)
+                    continue;
+                join.wait();
+                ProfScope ps(s, PS_ACA_MISC);
+                aca_big_finish_kernel<<<(nbig + 255) / 256, 256, 0, s>>>(st0, p.d_aca_big, nbig, rank,
+                                                                         status);
+                break;
+            }
             // A converged block is counted by the row pass that absorbs its last
             // column.  Poll from the step where the previous call on this plan
             // finished (else every other step from the third on); a poll that
@@ -1391,13 +1453,36 @@ void run_aca(Pipeline &P)
         }
         if (it >= max_iter)
             throw Error{HODLR_EDEVICE, "cross approximation did not terminate"};
-        __atomic_store_n(&p.aca_iters, it + 1, __ATOMIC_RELAXED);
-    } else {
+        if (!spec)
+            __atomic_store_n(&p.aca_iters, it + 1, __ATOMIC_RELAXED);
+    } else if (!spec) {
         read_rank_stats(P, rank, status, d_rmax, d_capped, nullptr, pinned);
     }
-    for (int j = 0; j <= p.L + 1 && j < 48; ++j)
-        P.rmax[j] = pinned[j];
-    P.capped = pinned[48];
+    if (spec) {
+        join.wait();
+        SpecArgs sa{};
+        sa.rank = rank;
+        sa.nint = p.nint;
+        sa.rmax = d_rmax;
+        sa.save = wsp<int>(P, P.lay.misc + MISC_SPEC);
+        sa.status = wsp<int>(P, P.lay.status);
+        sa.active = nbig > 0 ? p.aca_big_active : 0;
+        sa.L = p.L;
+        for (int j = 0; j <= p.L + 1; ++j)
+            sa.w[j] = (*P.spec)[j];
+        {
+            ProfScope ps(s, PS_ACA_MISC);
+            aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, nbig > 0 ? d_ndone : nullptr);
+            spec_check_kernel<<<1, 256, 0, s>>>(sa);
+        }
+        HIP_TRY(hipGetLastError());
+        P.rmax.assign(P.spec->begin(), P.spec->end());
+        P.capped = 0;   // read with the call's status
+    } else {
+        for (int j = 0; j <= p.L + 1 && j < 48; ++j)
+            P.rmax[j] = pinned[j];
+        P.capped = pinned[48];
+    }
     // zero the padding columns of every block below its panel's maximum rank
     ProfScope ps(s, PS_ACA_MISC);
     if (!p.pad_chunks.empty())

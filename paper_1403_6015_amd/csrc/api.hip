@@ -51,6 +51,7 @@ hodlr_opts default_opts()
     o.refine = 0;
     o.mixed_unchecked = 0;
     o.compressor = HODLR_COMPRESS_ACA;
+    o.speculate = 0;
     return o;
 }
 
@@ -95,6 +96,8 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "mixed_unchecked must be 0 or 1"};
     if (o.compressor != HODLR_COMPRESS_ACA && o.compressor != HODLR_COMPRESS_SKETCH)
         throw Error{HODLR_EINVAL, "unknown compressor"};
+    if (o.speculate != 0 && o.speculate != 1)
+        throw Error{HODLR_EINVAL, "speculate must be 0 or 1"};
     if (o.compressor == HODLR_COMPRESS_SKETCH && o.max_rank > SK_CAP_MAX)
         throw Error{HODLR_EINVAL, "the sketch compressor needs max_rank <= " +
                                       std::to_string(SK_CAP_MAX)};
@@ -826,10 +829,45 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         P.x = d_x;
         P.kp = make_kparams(k, p->plan.dim, theta, sigma2);
         P.tol = tol;
+        std::vector<int> spec;
+        if (p->opts.speculate) {
+            std::lock_guard<std::mutex> lk(p->last_mu);
+            spec = p->spec_rmax;
+        }
+        if (!spec.empty())
+            P.spec = &spec;
         factor_pipeline(P, d_y, d_out);
         if (d_z)
             run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
-        raise_status(read_status(P));
+        int st = 0;
+        std::vector<int> actual;   // per depth index, of this call's compression
+        if (P.spec_run) {
+            // the actual rank statistics and ranks come back with the status
+            int *hs = pinned_ints(64, 2);
+            int *hr = pinned_ints((size_t)p->plan.nint, 0);
+            HIP_TRY(hipMemcpyAsync(hs, wsp<int>(P, P.lay.misc + MISC_SPEC), sizeof(int) * 64,
+                                   hipMemcpyDeviceToHost, P.stream));
+            HIP_TRY(hipMemcpyAsync(hr, wsp<int>(P, P.lay.rank), sizeof(int) * p->plan.nint,
+                                   hipMemcpyDeviceToHost, P.stream));
+            st = read_status(P);
+            if (st & DS_SPEC_MISS) {
+                // the assumed widths or step count did not hold: the ordinary way
+                P.spec = nullptr;
+                factor_pipeline(P, d_y, d_out);
+                if (d_z)
+                    run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
+                st = read_status(P);
+                actual = P.rmax;
+            } else {
+                actual.assign(hs, hs + p->plan.L + 2);
+                P.capped = hs[48];
+                std::memcpy(P.ranks.data(), hr, sizeof(int) * p->plan.nint);
+            }
+        } else {
+            st = read_status(P);
+            actual = P.rmax;
+        }
+        raise_status(st);
         int fallback = 0;
         if (p->plan.mixed_check) {
             double ld = 0.0;
@@ -838,6 +876,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
                 // the same likelihood with FP64 panels on the same workspace
                 P.plan = &p->plan64;
                 P.lay = p->lay64;
+                P.spec = nullptr;
                 factor_pipeline(P, d_y, d_out);
                 if (d_z)
                     run_widen(P.ws + P.lay.Xt, false, d_z, p->plan.n, P.stream);
@@ -847,10 +886,14 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         }
         {
             std::lock_guard<std::mutex> lk(p->last_mu);
-            p->last_rmax = P.rmax;
+            if (fallback)
+                actual = P.rmax;   // the FP64 redo's own compression
+            p->last_rmax = actual;
             p->last_ranks = P.ranks;
             p->last_capped = P.capped;
             p->last_fallback = fallback;
+            p->spec_rmax = actual;
+            p->last_spec = P.spec_run && !(st & DS_SPEC_MISS) && !fallback ? 1 : 0;
         }
         return HODLR_OK;
     });
@@ -871,6 +914,7 @@ hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
     std::lock_guard<std::mutex> lk(p->last_mu);
     I.capped_blocks = p->last_capped;
     I.fp64_fallback = p->last_fallback;
+    I.speculated = p->last_spec;
     for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS && d + 1 < (int)p->last_rmax.size();
          ++d) {
         I.rank_max[d] = p->last_rmax[d + 1];

@@ -231,7 +231,7 @@ struct Error {
     } while (0)
 
 // Status bits written by kernels into the workspace.
-enum DevStatus { DS_NOTSPD_LEAF = 1, DS_NOTSPD_NODE = 2, DS_NONFINITE = 4 };
+enum DevStatus { DS_NOTSPD_LEAF = 1, DS_NOTSPD_NODE = 2, DS_NONFINITE = 4, DS_SPEC_MISS = 8 };
 
 // ----------------------------------------------------------- the plan
 // Tree, per-depth column layout and launch tables for one (n, dim, leaf, cap).
@@ -318,6 +318,7 @@ struct Plan {
 // byte offset in the workspace's misc area of the mixed form's log-det error
 // bound (one double per item, written by the finish kernel)
 constexpr size_t MISC_BOUND = 3072;
+constexpr size_t MISC_SPEC = 2048;   // 64 ints: a speculative call's actual rank statistics
 
 // Workspace layout (byte offsets into one device buffer).
 struct Layout {
@@ -369,6 +370,11 @@ struct Pipeline {
     std::vector<int> cnt;     // cnt[d] = 1 + sum_{j<=d} rmax[j]
     int capped = 0;
     std::vector<int> ranks;   // per internal node
+    // speculation (gp_loglik_dev): panel widths per depth index (as rmax) to
+    // assume instead of waiting for the compression's statistics; spec_run
+    // tells whether the compression actually ran that way
+    const std::vector<int> *spec = nullptr;
+    bool spec_run = false;
 };
 
 // ------------------------------------------------------------ profiling
@@ -431,7 +437,7 @@ void factor_pipeline(Pipeline &P, const double *d_y, double *d_out);
 // the finish kernel) exceeds the 1e-8 bar for this log det (synchronizes)
 bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item);
 int *pinned_scratch();                                         // per-thread pinned ints
-int *pinned_ints(size_t n, int slot);                          // per-thread growable pinned ints
+int *pinned_ints(size_t n, int slot);   // per-thread growable pinned ints, slots 0-2 (0: ranks, 1: column list, 2: statistics)
 void host_wait(hipStream_t s);                                 // poll the stream to completion
 
 template <typename T>

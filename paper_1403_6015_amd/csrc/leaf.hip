@@ -84,6 +84,88 @@ __device__ __forceinline__ d4 tile_mma(const double *A, const double *B, d4 acc)
     return acc;
 }
 
+// T1 -= A1 B1^T and (TWO) T2 -= A2 B2^T, tiles in LDS (column-major, leading
+// dimension TLD): every LDS read of both products is issued before the first
+// MFMA, the products run interleaved from the tiles' own values (negated A
+// operand), and T1, T2 are written back.
+template <bool TWO>
+__device__ __forceinline__ void tile_sub2(double *T1, const double *A1, const double *B1, double *T2,
+                                          const double *A2, const double *B2)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    d4 c1, c2 = {0.0, 0.0, 0.0, 0.0};
+    double a1[4], b1[4], a2[4], b2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        c1[t] = T1[r * TLD + q + 4 * t];
+        if (TWO)
+            c2[t] = T2[r * TLD + q + 4 * t];
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int k = q + 4 * kb;
+        a1[kb] = -A1[k * TLD + r];
+        b1[kb] = B1[k * TLD + r];
+        if (TWO) {
+            a2[kb] = -A2[k * TLD + r];
+            b2[kb] = B2[k * TLD + r];
+        }
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kb], b1[kb], c1, 0, 0, 0);
+        if (TWO)
+            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kb], b2[kb], c2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        T1[r * TLD + q + 4 * t] = c1[t];
+        if (TWO)
+            T2[r * TLD + q + 4 * t] = c2[t];
+    }
+}
+
+// T1 = T1 D^T and (TWO) T2 = T2 D^T with one D (the panel of a block column)
+template <bool TWO>
+__device__ __forceinline__ void tile_panel2(double *T1, double *T2, const double *D)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    d4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
+    double a1[4], a2[4], b[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int k = q + 4 * kb;
+        a1[kb] = T1[k * TLD + r];
+        if (TWO)
+            a2[kb] = T2[k * TLD + r];
+        b[kb] = D[k * TLD + r];
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kb], b[kb], c1, 0, 0, 0);
+        if (TWO)
+            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kb], b[kb], c2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        T1[r * TLD + q + 4 * t] = c1[t];
+        if (TWO)
+            T2[r * TLD + q + 4 * t] = c2[t];
+    }
+}
+
+// (I, K) of trailing task `task` at step J: tiles J < K <= I in packed order,
+// the look-ahead tile (J+1, J+1) skipped
+__device__ __forceinline__ void trail_tile(int task, int J, int &I, int &K)
+{
+    const int tt = task + 1;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= tt)
+        ++i;
+    K = tt - i * (i + 1) / 2 + J + 1;
+    I = i + J + 1;
+}
+
 // Lane K of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
 // In the diagonal-tile wave the four rows hold identical copies, so every lane
 // receives lane K's value, and it arrives in a VGPR: read-lanes would route
@@ -215,40 +297,52 @@ __device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
 // Step J of the forward substitution L y = x on 16 columns held in registers
 // (row tile I of the group in X[I], MFMA result layout): y_J = L_JJ^{-1} x_J,
 // then x_I -= L_IJ y_J for I > J.  Gt holds L_JJ^{-1} in the diagonal slots.
-template <int J>
+// FULL: all NT_MAX row tiles present, so the tile updates carry no run-time
+// condition and their LDS reads can be issued ahead of the products.
+template <int J, bool FULL>
 __device__ __forceinline__ void fwd_step(d4 (&X)[NT_MAX], const double *Gt, int nt)
 {
     const d4 z = {0.0, 0.0, 0.0, 0.0};
     X[J] = tile_mma_rb<false, false>(Gt + tix(J, J) * TSZ, X[J], z);
 #pragma unroll
     for (int I = J + 1; I < NT_MAX; ++I)
-        if (I < nt)
+        if (FULL || I < nt)
             X[I] = tile_mma_rb<false, true>(Gt + tix(I, J) * TSZ, X[J], X[I]);
 }
 
 // the same for a run-time J (uniform): a switch, so that X stays in registers
-__device__ __forceinline__ void fwd_step_rt(int J, d4 (&X)[NT_MAX], const double *Gt, int nt)
+template <bool FULL>
+__device__ __forceinline__ void fwd_step_sw(int J, d4 (&X)[NT_MAX], const double *Gt, int nt)
 {
     static_assert(NT_MAX == 8, "one case per row tile");
     switch (J) {
-    case 0: fwd_step<0>(X, Gt, nt); break;
-    case 1: fwd_step<1>(X, Gt, nt); break;
-    case 2: fwd_step<2>(X, Gt, nt); break;
-    case 3: fwd_step<3>(X, Gt, nt); break;
-    case 4: fwd_step<4>(X, Gt, nt); break;
-    case 5: fwd_step<5>(X, Gt, nt); break;
-    case 6: fwd_step<6>(X, Gt, nt); break;
-    case 7: fwd_step<7>(X, Gt, nt); break;
+    case 0: fwd_step<0, FULL>(X, Gt, nt); break;
+    case 1: fwd_step<1, FULL>(X, Gt, nt); break;
+    case 2: fwd_step<2, FULL>(X, Gt, nt); break;
+    case 3: fwd_step<3, FULL>(X, Gt, nt); break;
+    case 4: fwd_step<4, FULL>(X, Gt, nt); break;
+    case 5: fwd_step<5, FULL>(X, Gt, nt); break;
+    case 6: fwd_step<6, FULL>(X, Gt, nt); break;
+    case 7: fwd_step<7, FULL>(X, Gt, nt); break;
     default: break;
     }
 }
 
+__device__ __forceinline__ void fwd_step_rt(int J, d4 (&X)[NT_MAX], const double *Gt, int nt)
+{
+    if (nt == NT_MAX)
+        fwd_step_sw<true>(J, X, Gt, nt);
+    else
+        fwd_step_sw<false>(J, X, Gt, nt);
+}
+
 // backward substitution L^T z = y on the same register tiles
-__device__ __forceinline__ void bwd_all(d4 (&X)[NT_MAX], const double *Gt, int nt)
+template <bool FULL>
+__device__ __forceinline__ void bwd_all_t(d4 (&X)[NT_MAX], const double *Gt, int nt)
 {
 #pragma unroll
     for (int J = NT_MAX - 1; J >= 0; --J) {
-        if (J < nt) {
+        if (FULL || J < nt) {
             const d4 z = {0.0, 0.0, 0.0, 0.0};
             X[J] = tile_mma_rb<true, false>(Gt + tix(J, J) * TSZ, X[J], z);
 #pragma unroll
@@ -258,9 +352,21 @@ __device__ __forceinline__ void bwd_all(d4 (&X)[NT_MAX], const double *Gt, int n
     }
 }
 
+__device__ __forceinline__ void bwd_all(d4 (&X)[NT_MAX], const double *Gt, int nt)
+{
+    if (nt == NT_MAX)
+        bwd_all_t<true>(X, Gt, nt);
+    else
+        bwd_all_t<false>(X, Gt, nt);
+}
+
 // columns [c0, c0 + 16) of the list (column 0 = the right-hand side y,
 // others basis columns of W) on the leaf's rows into register tiles, lane
-// (r, q) holding column c0 + r, rows 16 I + q + 4 t; missing entries are 0
+// (r, q) holding column c0 + r, rows 16 I + q + 4 t; missing entries are 0.
+// A full leaf (every row inside) loads without conditions: lanes past the
+// group read column 0 of W at the leaf's rows and zero the values after all
+// loads are issued (an empty asm pins them, so that the zeroing stays a
+// select and not one branch per load).
 __device__ __forceinline__ void rhs_load(d4 (&X)[NT_MAX], const LeafArgs &A, int c0,
                                          const double *ysrc, const double *Wsrc, int64_t s,
                                          int64_t n, int nt, int m)
@@ -271,6 +377,24 @@ __device__ __forceinline__ void rhs_load(d4 (&X)[NT_MAX], const LeafArgs &A, int
     if (r < nb) {
         const int col = A.cols[c0 + r];
         src = (col == 0) ? ysrc + s : Wsrc + (int64_t)col * n + s;
+    }
+    if (m == 16 * NT_MAX) {
+        const double *p = src ? src : Wsrc + s;
+#pragma unroll
+        for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                X[I][t] = p[16 * I + q + 4 * t];
+        if (nb < 16) {
+#pragma unroll
+            for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    asm volatile("" : "+v"(X[I][t]));
+                    X[I][t] = src ? X[I][t] : 0.0;
+                }
+        }
+        return;
     }
 #pragma unroll
     for (int I = 0; I < NT_MAX; ++I)
@@ -463,14 +587,15 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
         bad = diag_factor(Gt, s_diag, gout, 0, m);
     __syncthreads();
     for (int J = 0; J < nt; ++J) {
-        // panel: L_IJ = C_IJ L_JJ^{-T}
-        for (int I = J + 1 + wid; I < nt; I += LEAF_MW) {
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            double *T = Gt + tix(I, J) * TSZ;
-            acc = tile_mma<false>(T, Gt + tix(J, J) * TSZ, acc);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                T[r * TLD + q + 4 * t] = acc[t];
+        // panel: L_IJ = C_IJ L_JJ^{-T}, two tiles per wave at most (8 row tiles)
+        {
+            static_assert(NT_MAX <= 1 + 2 * LEAF_MW, "panel tiles per wave");
+            const int I1 = J + 1 + wid, I2 = I1 + LEAF_MW;
+            const double *D = Gt + tix(J, J) * TSZ;
+            if (I2 < nt)
+                tile_panel2<true>(Gt + tix(I1, J) * TSZ, Gt + tix(I2, J) * TSZ, D);
+            else if (I1 < nt)
+                tile_panel2<false>(Gt + tix(I1, J) * TSZ, nullptr, D);
         }
         __syncthreads();
         if (J + 1 < nt) {
@@ -496,20 +621,19 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
             const int t0 = wid == 0 ? ntask - n0 : wid - 1;
             const int t1 = wid == 0 ? ntask : ntask - n0;
             const int ts = wid == 0 ? 1 : LEAF_MW - 1;
-            for (int task = t0; task < t1; task += ts) {
-                int tt = task + 1;   // skip the look-ahead tile (I = K = J+1)
-                int I = 0;
-                while ((I + 1) * (I + 2) / 2 <= tt)
-                    ++I;
-                int K = tt - I * (I + 1) / 2;
-                I += J + 1;
-                K += J + 1;
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-                acc = tile_mma<false>(Gt + tix(I, J) * TSZ, Gt + tix(K, J) * TSZ, acc);
-                double *T = Gt + tix(I, K) * TSZ;
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    T[r * TLD + q + 4 * t] -= acc[t];
+            // two tasks at a time, their products interleaved
+            for (int task = t0; task < t1; task += 2 * ts) {
+                int I1, K1;
+                trail_tile(task, J, I1, K1);
+                if (task + ts < t1) {
+                    int I2, K2;
+                    trail_tile(task + ts, J, I2, K2);
+                    tile_sub2<true>(Gt + tix(I1, K1) * TSZ, Gt + tix(I1, J) * TSZ, Gt + tix(K1, J) * TSZ,
+                                    Gt + tix(I2, K2) * TSZ, Gt + tix(I2, J) * TSZ, Gt + tix(K2, J) * TSZ);
+                } else {
+                    tile_sub2<false>(Gt + tix(I1, K1) * TSZ, Gt + tix(I1, J) * TSZ, Gt + tix(K1, J) * TSZ,
+                                     nullptr, nullptr, nullptr);
+                }
             }
         }
         if (piped)

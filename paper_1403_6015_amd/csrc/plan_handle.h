@@ -50,6 +50,10 @@ struct hodlr_plan_s {
     std::vector<int> last_ranks, last_rmax;
     int last_capped = 0;
     int last_fallback = 0;   // likelihoods of the last call redone with FP64 panels
+    // panel widths per depth index of the last completed gp_loglik_dev (the
+    // widths a speculative call assumes); empty before the first
+    std::vector<int> spec_rmax;
+    int last_spec = 0;       // 1: the last gp_loglik_dev ran speculatively without a redo
     ~hodlr_plan_s()
     {
         for (auto &g : graphs) {
