@@ -940,6 +940,11 @@ constexpr int STATS_DEPTHS = 46;   // depths 0 .. 45 (plans have at most 62 leve
 __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const int *status,
                                                         int64_t nint, int *rmax, const int *ndone)
 {
+    // one flat pass: thread t reads blocks t + 256 u in rounds of 16, all of
+    // a round's loads issued together (indices clamped, the tail masked
+    // afterwards); its running maximum goes to the depth's LDS slot whenever
+    // the depth changes (blocks in heap order, depth nondecreasing)
+    constexpr int U = 16;
     __shared__ int smax[64];
     __shared__ int scap;
     if (threadIdx.x < 64)
@@ -947,29 +952,34 @@ __global__ __launch_bounds__(256) void aca_stats_kernel(const int *rank, const i
     if (threadIdx.x == 0)
         scap = 0;
     __syncthreads();
-    int m[STATS_DEPTHS];
-    int mycap = 0;
+    int mycap = 0, cd = -1, cm = 0;
+    for (int64_t h0 = threadIdx.x; h0 < nint; h0 += 256 * U) {
+        int rv[U], sv[U];
 #pragma unroll
-    for (int d = 0; d < STATS_DEPTHS; ++d) {
-        m[d] = 0;
-        const int64_t h0 = ((int64_t)1 << d) - 1;
-        const int64_t h1 = std::min<int64_t>(nint, ((int64_t)2 << d) - 1);
-#pragma unroll 4
-        for (int64_t h = h0 + threadIdx.x; h < h1; h += 256) {
-            m[d] = std::max(m[d], rank[h]);
-            mycap += (status[h] == ACA_CAPPED) ? 1 : 0;
+        for (int u = 0; u < U; ++u) {
+            const int64_t h = std::min<int64_t>(h0 + 256 * u, nint - 1);
+            rv[u] = rank[h];
+            sv[u] = status[h];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            asm volatile("" : "+v"(rv[u]), "+v"(sv[u]));
+            const int64_t h = h0 + 256 * u;
+            if (h < nint) {
+                const int d = 63 - __clzll((unsigned long long)(h + 1));
+                if (d != cd) {
+                    if (cd >= 0 && cd < STATS_DEPTHS)
+                        atomicMax(&smax[cd + 1], cm);
+                    cd = d;
+                    cm = 0;
+                }
+                cm = std::max(cm, rv[u]);
+                mycap += (sv[u] == ACA_CAPPED) ? 1 : 0;
+            }
         }
     }
-#pragma unroll
-    for (int d = 0; d < STATS_DEPTHS; ++d) {
-        if (((int64_t)1 << d) - 1 >= nint)
-            break;
-        int v = m[d];
-        for (int off = 32; off > 0; off >>= 1)
-            v = std::max(v, __shfl_xor(v, off, 64));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(&smax[d + 1], v);
-    }
+    if (cd >= 0 && cd < STATS_DEPTHS)
+        atomicMax(&smax[cd + 1], cm);
     for (int off = 32; off > 0; off >>= 1)
         mycap += __shfl_xor(mycap, off, 64);
     if ((threadIdx.x & 63) == 0)
@@ -1117,6 +1127,8 @@ struct SpecArgs {
     int active;   // large blocks that must have converged
     int L;
     int w[64];
+    const int64_t *cofa;   // panel column offsets (device)
+    int *cols;             // the column list the assumed widths give
 };
 
 __global__ __launch_bounds__(256) void spec_check_kernel(SpecArgs a)
@@ -1144,6 +1156,21 @@ __global__ __launch_bounds__(256) void spec_check_kernel(SpecArgs a)
     }
     if ((int)threadIdx.x <= a.L + 1 && threadIdx.x < 48)
         a.rmax[threadIdx.x] = a.w[threadIdx.x];
+    // column list: 0, then depth j's panel columns cofa[j] .. cofa[j] + w[j] - 1
+    // (the same list the host builds from the widths)
+    __shared__ int start[64];
+    if (threadIdx.x == 0) {
+        int c = 1;
+        for (int j = 1; j <= a.L; ++j) {
+            start[j] = c;
+            c += a.w[j];
+        }
+        a.cols[0] = 0;
+    }
+    __syncthreads();
+    for (int j = 1; j <= a.L; ++j)
+        for (int c = threadIdx.x; c < a.w[j]; c += blockDim.x)
+            a.cols[start[j] + c] = (int)(a.cofa[j] + c);
 }
 
 // Per-call initialization in one launch instead of a memset or copy each:
@@ -1470,6 +1497,8 @@ void run_aca(Pipeline &P)
         sa.L = p.L;
         for (int j = 0; j <= p.L + 1; ++j)
             sa.w[j] = (*P.spec)[j];
+        sa.cofa = d_cofa;
+        sa.cols = wsp<int>(P, P.lay.cols);
         {
             ProfScope ps(s, PS_ACA_MISC);
             aca_stats_kernel<<<1, 256, 0, s>>>(rank, status, p.nint, d_rmax, nbig > 0 ? d_ndone : nullptr);

@@ -198,6 +198,8 @@ void make_columns(Pipeline &P)
             P.cols.push_back((int)(p.cofa[j] + c));
         P.cnt[j] = (int)P.cols.size();
     }
+    if (P.spec_run)
+        return;   // the speculation check wrote the same list on the device
     int *hc = pinned_ints(P.cols.size(), 1);
     std::memcpy(hc, P.cols.data(), sizeof(int) * P.cols.size());
     HIP_TRY(hipMemcpyAsync(wsp<int>(P, P.lay.cols), hc, sizeof(int) * P.cols.size(),
