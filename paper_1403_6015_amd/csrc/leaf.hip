@@ -84,6 +84,10 @@ __device__ __forceinline__ d4 tile_mma(const double *A, const double *B, d4 acc)
     return acc;
 }
 
+// The FP64 MFMA's last operand carries negate modifiers for A, B and C (bits
+// 0-2) on this target; NEG_A gives acc - A B in one instruction.
+constexpr int MFMA_NEG_A = 1;
+
 // T1 -= A1 B1^T and (TWO) T2 -= A2 B2^T, tiles in LDS (column-major, leading
 // dimension TLD): every LDS read of both products is issued before the first
 // MFMA, the products run interleaved from the tiles' own values (negated A
@@ -104,18 +108,19 @@ __device__ __forceinline__ void tile_sub2(double *T1, const double *A1, const do
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         const int k = q + 4 * kb;
-        a1[kb] = -A1[k * TLD + r];
+        a1[kb] = A1[k * TLD + r];
         b1[kb] = B1[k * TLD + r];
         if (TWO) {
-            a2[kb] = -A2[k * TLD + r];
+            a2[kb] = A2[k * TLD + r];
             b2[kb] = B2[k * TLD + r];
         }
     }
+    // last argument 1: the instruction negates its A operand
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
-        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kb], b1[kb], c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kb], b1[kb], c1, 0, 0, MFMA_NEG_A);
         if (TWO)
-            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kb], b2[kb], c2, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kb], b2[kb], c2, 0, 0, MFMA_NEG_A);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -286,12 +291,113 @@ __device__ __forceinline__ d4 tile_mma_rb(const double *A, const d4 B, d4 acc)
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         const int k = q + 4 * kb;
-        double a = TA ? A[r * LDA + k] : A[k * LDA + r];
-        if (NEG)
-            a = -a;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kb], acc, 0, 0, 0);
+        const double a = TA ? A[r * LDA + k] : A[k * LDA + r];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kb], acc, 0, 0, NEG ? MFMA_NEG_A : 0);
     }
     return acc;
+}
+
+// The A operands of a tile for the four K-slices (op = identity or
+// transpose), and the product with them already in registers: loading the
+// next tile's operands before the current tile's four MFMAs keeps the LDS
+// latency off the chain of dependent products.
+template <bool TA>
+__device__ __forceinline__ void tile_a(const double *A, double (&a)[4])
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int k = q + 4 * kb;
+        a[kb] = TA ? A[r * TLD + k] : A[k * TLD + r];
+    }
+}
+
+template <bool NEG>
+__device__ __forceinline__ d4 mma_a(const double (&a)[4], const d4 B, d4 acc)
+{
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb], B[kb], acc, 0, 0, NEG ? MFMA_NEG_A : 0);
+    return acc;
+}
+
+// Step J of the forward substitution on a full leaf, operands one tile ahead:
+// X[J] = L_JJ^{-1} X[J], then X[I] -= L_IJ X[J] for I > J.
+template <int J>
+__device__ __forceinline__ void fwd_step_full(d4 (&X)[NT_MAX], const double *Gt)
+{
+    double a[4], an[4];
+    tile_a<false>(Gt + tix(J, J) * TSZ, a);
+    if constexpr (J + 1 < NT_MAX)
+        tile_a<false>(Gt + tix(J + 1, J) * TSZ, an);
+    const d4 z = {0.0, 0.0, 0.0, 0.0};
+    X[J] = mma_a<false>(a, X[J], z);
+#pragma unroll
+    for (int I = J + 1; I < NT_MAX; ++I) {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+            a[kb] = an[kb];
+        if (I + 1 < NT_MAX)
+            tile_a<false>(Gt + tix(I + 1, J) * TSZ, an);
+        X[I] = mma_a<true>(a, X[J], X[I]);
+    }
+}
+
+// The backward substitution L^T z = y on a full leaf as one flat sequence of
+// 36 tile products (for J = 7 .. 0: the diagonal block, then the blocks
+// (J, I), I < J), each tile's operands loaded one product ahead.
+__host__ __device__ constexpr int bwd_J(int t)
+{
+    int J = NT_MAX - 1;
+    while (t > J) {
+        t -= J + 1;
+        --J;
+    }
+    return J;
+}
+__host__ __device__ constexpr int bwd_I(int t)   // -1: the diagonal block
+{
+    int J = NT_MAX - 1;
+    while (t > J) {
+        t -= J + 1;
+        --J;
+    }
+    return t - 1;
+}
+
+template <int T>
+__device__ __forceinline__ void bwd_task(d4 (&X)[NT_MAX], const double *Gt, double (&a)[4],
+                                         double (&an)[4])
+{
+    constexpr int NTASK = NT_MAX * (NT_MAX + 1) / 2;
+    constexpr int J = bwd_J(T), I = bwd_I(T);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+        a[kb] = an[kb];
+    if constexpr (T + 1 < NTASK) {
+        constexpr int J1 = bwd_J(T + 1), I1 = bwd_I(T + 1);
+        tile_a<true>(Gt + tix(J1, I1 < 0 ? J1 : I1) * TSZ, an);
+    }
+    if constexpr (I < 0) {
+        const d4 z = {0.0, 0.0, 0.0, 0.0};
+        X[J] = mma_a<false>(a, X[J], z);
+    } else {
+        X[I] = mma_a<true>(a, X[J], X[I]);
+    }
+}
+
+template <int... T>
+__device__ __forceinline__ void bwd_tasks(d4 (&X)[NT_MAX], const double *Gt, double (&a)[4],
+                                          double (&an)[4], std::integer_sequence<int, T...>)
+{
+    (bwd_task<T>(X, Gt, a, an), ...);
+}
+
+__device__ __forceinline__ void bwd_all_full(d4 (&X)[NT_MAX], const double *Gt)
+{
+    double a[4], an[4];
+    tile_a<true>(Gt + tix(NT_MAX - 1, NT_MAX - 1) * TSZ, an);
+    bwd_tasks(X, Gt, a, an, std::make_integer_sequence<int, NT_MAX * (NT_MAX + 1) / 2>{});
 }
 
 // Step J of the forward substitution L y = x on 16 columns held in registers
@@ -330,10 +436,22 @@ __device__ __forceinline__ void fwd_step_sw(int J, d4 (&X)[NT_MAX], const double
 
 __device__ __forceinline__ void fwd_step_rt(int J, d4 (&X)[NT_MAX], const double *Gt, int nt)
 {
-    if (nt == NT_MAX)
-        fwd_step_sw<true>(J, X, Gt, nt);
-    else
+    if (nt == NT_MAX) {
+        static_assert(NT_MAX == 8, "one case per row tile");
+        switch (J) {
+        case 0: fwd_step_full<0>(X, Gt); break;
+        case 1: fwd_step_full<1>(X, Gt); break;
+        case 2: fwd_step_full<2>(X, Gt); break;
+        case 3: fwd_step_full<3>(X, Gt); break;
+        case 4: fwd_step_full<4>(X, Gt); break;
+        case 5: fwd_step_full<5>(X, Gt); break;
+        case 6: fwd_step_full<6>(X, Gt); break;
+        case 7: fwd_step_full<7>(X, Gt); break;
+        default: break;
+        }
+    } else {
         fwd_step_sw<false>(J, X, Gt, nt);
+    }
 }
 
 // backward substitution L^T z = y on the same register tiles
@@ -355,7 +473,7 @@ __device__ __forceinline__ void bwd_all_t(d4 (&X)[NT_MAX], const double *Gt, int
 __device__ __forceinline__ void bwd_all(d4 (&X)[NT_MAX], const double *Gt, int nt)
 {
     if (nt == NT_MAX)
-        bwd_all_t<true>(X, Gt, nt);
+        bwd_all_full(X, Gt);
     else
         bwd_all_t<false>(X, Gt, nt);
 }
@@ -413,6 +531,14 @@ __device__ __forceinline__ void rhs_store(const d4 (&X)[NT_MAX], const LeafArgs 
     const int nb = min(16, A.ncols - c0);
     if (r < nb) {
         PT *dst = Xdst + (int64_t)A.cols[c0 + r] * n + s;
+        if (m == 16 * NT_MAX) {   // full leaf: every row inside
+#pragma unroll
+            for (int I = 0; I < NT_MAX; ++I)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    dst[16 * I + q + 4 * t] = (PT)X[I][t];
+            return;
+        }
 #pragma unroll
         for (int I = 0; I < NT_MAX; ++I)
 #pragma unroll
@@ -431,7 +557,9 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
     __shared__ double s_diag[LEAF_LDS_MAX];   // diagonal of the factor
     __shared__ double s_red[LEAF_MW];
     __shared__ int s_bad;
-    const int tid = threadIdx.x, wid = tid >> 6;
+    // the wave index is uniform in a wave: in a scalar register, the loops and
+    // branches on it are scalar too
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63, r = l & 15, q = l >> 4;
     const int it = blockIdx.z;   // batch item
     const KParams kp = item_kp(A.kp, A.B, it);
@@ -520,6 +648,13 @@ __global__ __launch_bounds__(LEAF_MT, 2) void leaf_factor_kernel(LeafArgs A)
                             // below the diagonal block row, every row inside the leaf
                             const double e = aE[I] * Fc[K];
                             v = matern ? e * (1.0 + kp.c * (xr1[I] - xc1[K])) : e;
+                        } else if (K == I && 16 * I + 15 < m) {
+                            // a diagonal block inside the leaf: selects only
+                            const int ii = 16 * I + rr, k = 16 * K + cc;
+                            const double e = aE[I] * Fc[K];
+                            const double off = matern ? e * (1.0 + kp.c * (xr1[I] - xc1[K])) : e;
+                            const double nz = kp.noise ? kp.noise[s + ii] : 0.0;
+                            v = ii > k ? off : (ii == k ? dg + nz : 0.0);
                         } else {
                             const int ii = 16 * I + rr, k = 16 * K + cc;
                             if (ii < m && k < m) {
@@ -713,7 +848,9 @@ constexpr size_t L21_LEAF = (size_t)L21_TILES * L21_TSZ;
 // packed store and the diagonal).  Returns wave 0's non-positive-pivot flag.
 __device__ bool factor_tiles(double *Gt, double *diag, double *gout, int g0, int nt, int m)
 {
-    const int tid = threadIdx.x, wid = tid >> 6;
+    // the wave index is uniform in a wave: in a scalar register, the loops and
+    // branches on it are scalar too
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63, r = l & 15, q = l >> 4;
     bool bad = false;
     if (wid == 0)
@@ -820,7 +957,9 @@ __global__ __launch_bounds__(LEAF_MT, 1) void leaf_factor_big_kernel(LeafArgs A)
     __shared__ double s_red[LEAF_MW];
     __shared__ int s_bad;
     static_assert(LEAF_MAX == 2 * LEAF_LDS_MAX && LEAF_MT == LEAF_MAX, "two halves, a thread per row");
-    const int tid = threadIdx.x, wid = tid >> 6;
+    // the wave index is uniform in a wave: in a scalar register, the loops and
+    // branches on it are scalar too
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63, r = l & 15, q = l >> 4;
     const int it = blockIdx.z;   // batch item
     const KParams kp = item_kp(A.kp, A.B, it);
