@@ -68,7 +68,7 @@ template <int NW>
 __device__ void block_argmax(double &v, int64_t &i, double &sgn, double *rv, int64_t *ri,
                              double *rs)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     wave_argmax_signed(v, i, sgn);
     if (lane == 0) {
         rv[wid] = v;
@@ -92,7 +92,7 @@ template <int NW>
 __device__ double block_sum(double v, double *red)
 {
     static_assert(NW == 2 || NW == 4, "two or four waves");
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     v = wave_sum(v);
     if (lane == 0)
         red[wid] = v;
@@ -573,7 +573,7 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
                                double &bv, int64_t &bi, double &bs, double *rv, int64_t *ri,
                                double *rs, double (*sred)[RR_REG + 1])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kr = k < RR_REG ? k : RR_REG;
     double acc[RR_REG + 1];
 #pragma unroll
@@ -691,7 +691,7 @@ __device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t 
                                           double (*sdot)[RB + 1])
 {
     constexpr int RT = terms_per_round<EPT>();
-    const int lane = tid & 63, wid = tid >> 6;
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int l0 = 0; l0 < k; l0 += RT) {
         double d[RT];
 #pragma unroll
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     const Chunk ch = B.chunks[blockIdx.x];
     const int b = B.cidx[blockIdx.x];
     const int64_t h = B.bnode[b];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     __shared__ double rv[4], rs[4];
     __shared__ int64_t ri[4];
     // the block's used-row list lives in HBM with room for RMAX_ABS terms; a

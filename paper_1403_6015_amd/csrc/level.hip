@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64 * LVF_MAXW) void level_fused_kernel(LevelArgs A0
     const int nrhs = UPD ? A.nrhs : A.ncnt;   // columns updated and reduced
     const int64_t colp = UPD ? A.colWp : A.colW;
     const int rsp = UPD ? A.rstride_p : A.rstride;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     constexpr int NO = CU * RP;
     constexpr int G = 64 / NO;   // lanes holding each output after the butterfly
     const int ngrp = (nrhs + CU - 1) / CU;
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(TH) void level_solve_kernel(LevelArgs A0)
     const int64_t loc = blockIdx.x;
     const int64_t h = A.node0 + loc;
     const int r = A.rank[h];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     // with gridDim.y > 1 (levels whose T is summed beforehand) every
     // work-group of a node factors M and solves every gridDim.y-th batch of
     // columns; the first one records the factors
@@ -884,7 +884,7 @@ __global__ __launch_bounds__(LVW_TH) void level_solve_wide_kernel(LevelArgs A0)
     const int64_t loc = blockIdx.x;
     const int64_t h = A.node0 + loc;
     const int r = A.rank[h];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (r == 0) {
         if (A.factor && tid == 0)
             A.node_ld[h] = 0.0;
@@ -1088,7 +1088,7 @@ __global__ __launch_bounds__(LVG_TH) void level_solve_gj_kernel(LevelArgs A0)
     const int64_t loc = blockIdx.x;
     const int64_t h = A.node0 + loc;
     const int r = A.rank[h];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     // element loops: thread (ti, tj) takes column tj of rows ti, ti + 8, ...
     constexpr int TI = LVG_TH / LVG_RMAX;
     const int tj = tid & (LVG_RMAX - 1), ti = tid / LVG_RMAX;
@@ -1324,7 +1324,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_reduce_lds_kernel(LevelArgs 
     __shared__ double sX[RL_ROWS][NCOL + 1];
     __shared__ double sW[RL_ROWS][NR + 1];
     __shared__ int scol[NCOL];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lq = lane >> 4;
     const int64_t n = A.n;
     const PT *__restrict__ Xp = (const PT *)A.Xt;
@@ -1422,7 +1422,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
     constexpr int KS = 4 * MT;   // 4-rank steps per rank chunk
     __shared__ double sS[4 * KS][LVM_UNT * 16 + 1];
     __shared__ int scol[LVM_UNT * 16];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lq = lane >> 4;
     const int64_t n = A.n;
     const int64_t loc = ch.node - A.node0;

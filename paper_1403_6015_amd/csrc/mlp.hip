@@ -84,7 +84,7 @@ __global__ __launch_bounds__(THREADS) void mlp_tile_kernel(
 {
     extern __shared__ __align__(16) char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int s0 = blockIdx.x * TS;
 
     // stage W2 (and its transpose for the backward pass)

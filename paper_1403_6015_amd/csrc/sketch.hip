@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchArgs S)
     const int side = ch.side;
     const int nsamp = side ? sp : s;
     const int64_t c_lo = side ? lo : mid, c_hi = side ? mid : hi;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, r = lane & 15, q = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6), r = lane & 15, q = lane >> 4;
     const int64_t n = S.n;
     const int64_t wr0 = ch.lo + 16 * wid;
     const int64_t gi = wr0 + r;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(SK_SVD_TH) void sk_svd_kernel(SketchArgs S)
     int64_t lo, mid, hi;
     int s, sp;
     sk_sizes(S, h, lo, mid, hi, s, sp);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int NW = SK_SVD_TH / 64;
     if (s == 0) {
         if (tid == 0) {
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void sk_form_kernel(SketchArgs S)
     if (s == 0 || k == 0)
         return;   // the whole work-group
     __shared__ double sS[SK_ROWS][SK_SPMAX + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nsamp = ch.side ? sp : s;
     const int64_t n = S.n;
     for (int e = tid; e < SK_ROWS * nsamp; e += 256) {
