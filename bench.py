@@ -129,7 +129,9 @@ def measured_traffic(kernel: str):
     none or the kernel's source changed since the counters were taken."""
     import hashlib
     files = {"leaf_factor": ("profiles/leaf_factor_traffic_matern32_n2p20.md",
-                             "paper_1403_6015_amd/csrc/leaf.hip")}
+                             "paper_1403_6015_amd/csrc/leaf.hip"),
+             "level_update": ("profiles/level_update_traffic_matern32_n2p20.md",
+                              "paper_1403_6015_amd/csrc/level.hip")}
     if kernel not in files:
         return None
     summary, src = (os.path.join(ROOT, f) for f in files[kernel])
@@ -243,6 +245,9 @@ def main():
                     help="mixed: FP32 basis panels, FP64 leaves / coupling LU / log-det sums "
                          "(matern1d, batched_theta, ragged)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="matern1d: only warmup + steps likelihoods on a plan with the library's "
+                         "default tiles (no autotuning, no other legs); for counter profiles")
     ap.add_argument("--no-speculate", action="store_true",
                     help="matern1d: every call waits for its compression's rank statistics "
                          "(default: calls after the first assume the previous call's panel "
@@ -281,6 +286,8 @@ def main():
     if args.workload == "grad":
         return bench_grad(args, torch, H, wl, dev)
     p = wl.matern1d(args.n)
+    if args.profile_run:
+        return profile_run(args, torch, H, p, dev)
     t0 = time.perf_counter()
     perm = H.hodlr_order(p.x, p.leaf)
     t_order = time.perf_counter() - t0
@@ -374,8 +381,10 @@ def main():
         else:
             ach = byts / per_call_s / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-                        "frac": ach / PEAK["hbm"], "traffic": None, "kernel": dom,
-                        "avg_launch_ms": dom_ms / dom_launches,
+                        "frac": ach / PEAK["hbm"],
+                        "traffic": None if mixed else measured_traffic(dom),
+                        "traffic_unit": "HBM bytes per likelihood (the stage's launches)",
+                        "kernel": dom, "avg_launch_ms": dom_ms / dom_launches,
                         "algorithmic_per_call": {"flops": flops, "bytes": byts}}
 
     # whole-pipeline model: each modelled stage at the larger of its HBM time
@@ -1155,6 +1164,36 @@ def bench_predict(args, torch, H, wl, dev):
 # The paper's single-core timings at n = 10^6 (§5, one-dimensional rows of the
 # Gaussian table tab_gauss_all, the exponential table tab_exp and the inverse
 # multiquadric table tab_inv): assembly + factor + solve + determinant, seconds.
+def profile_run(args, torch, H, p, dev):
+    """The benchmark's likelihood, warmup + steps calls on one plan with the
+    default tiles (512 rows per level chunk), nothing else: the command the
+    counter profiles run, so that every dispatch of a kernel belongs to one of
+    these calls."""
+    perm = H.hodlr_order(p.x, p.leaf)
+    xs, ys = p.x[perm], p.y[perm]
+    spec = 0 if args.no_speculate else 1
+    plan = H.Plan(p.n, p.dim, p.leaf, H.Opts(max_rank=64, presorted=1, speculate=spec))
+    d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
+    d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
+    work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+    z = torch.empty(p.n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                        plan.workspace_bytes, None, out, z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        H.gp_loglik_dev(plan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, work,
+                        plan.workspace_bytes, None, out, z)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"profile_run": "matern32_1d_n%d_leaf%d" % (p.n, p.leaf),
+                      "calls": args.warmup + args.steps, "ms_per_call": el / args.steps * 1e3,
+                      "logdet": float(out[1].item()), "speculated": plan.info()["speculated"]}),
+          flush=True)
+
+
 def bench_copy(args, torch, dev):
     """Calibration for the HBM byte counters: a plain elementwise copy of
     2^28 doubles (2 GiB read, 2 GiB written per launch), one launch per step."""
