@@ -583,13 +583,19 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
     bs = 0.0;
     bi = INT64_MAX;
     for (int c = tid; c < nrec; c += ACA_THREADS) {
+        // a record's words all issued together: slots past the k terms are
+        // read at slot 4 (always present) and dropped, so no load waits
+        // behind a branch
         const double *r = rec + (int64_t)c * pw;
+        double rr[RR_REG];
+#pragma unroll
+        for (int l = 0; l < RR_REG; ++l)
+            rr[l] = r[4 + (l < kr ? l : 0)];
         const double v = r[0], di = r[1], sv = r[3];
         acc[RR_REG] += r[2];
 #pragma unroll
         for (int l = 0; l < RR_REG; ++l)
-            if (l < kr)
-                acc[l] += r[4 + l];
+            acc[l] += l < kr ? rr[l] : 0.0;
         const int64_t i = di < 0.0 ? INT64_MAX : (int64_t)di;
         if (better(v, i, bv, bi)) {
             bv = v;
@@ -627,10 +633,13 @@ __device__ void reduce_records(const double *rec, int nrec, int pw, int k, doubl
             a[j] = 0.0;
         for (int c = tid; c < nrec; c += ACA_THREADS) {
             const double *r = rec + (int64_t)c * pw + 4 + l0;
+            double rr[RR_REG];
 #pragma unroll
             for (int j = 0; j < RR_REG; ++j)
-                if (j < kl)
-                    a[j] += r[j];
+                rr[j] = r[j < kl ? j : 0];
+#pragma unroll
+            for (int j = 0; j < RR_REG; ++j)
+                a[j] += j < kl ? rr[j] : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < RR_REG; ++j)
@@ -666,13 +675,26 @@ __device__ __forceinline__ void residual_terms(const double *__restrict__ W, int
 {
     constexpr int RT = terms_per_round<EPT>();
     for (int l0 = 0; l0 < k; l0 += RT) {
+        // every load of the round issued unconditionally (term index and row
+        // clamped into the block's written entries), the dropped ones zeroed
+        // after: a conditional load would wait in its own branch
         double w[RT][EPT];
 #pragma unroll
         for (int u = 0; u < RT; ++u)
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
                 const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-                w[u][q] = (l0 + u < k && g < ch.hi) ? W[(col0 + l0 + u) * n + g] : 0.0;
+                const int64_t gc = g < ch.hi ? g : ch.hi - 1;
+                const int lu = l0 + u < k ? l0 + u : k - 1;
+                w[u][q] = W[(col0 + lu) * n + gc];
+            }
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+                asm volatile("" : "+v"(w[u][q]));
+                w[u][q] = (l0 + u < k && g < ch.hi) ? w[u][q] : 0.0;
             }
 #pragma unroll
         for (int u = 0; u < RT; ++u)
@@ -699,9 +721,12 @@ __device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t 
             d[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
+                // clamped and unconditional; val is 0 past the chunk, and a
+                // term past k is never stored
                 const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-                if (l0 + u < k && g < ch.hi)
-                    d[u] += val[q] * W[(col0 + l0 + u) * n + g];
+                const int64_t gc = g < ch.hi ? g : ch.hi - 1;
+                const int lu = l0 + u < k ? l0 + u : k - 1;
+                d[u] += val[q] * W[(col0 + lu) * n + gc];
             }
         }
 #pragma unroll
@@ -712,6 +737,77 @@ __device__ __forceinline__ void term_dots(const double *__restrict__ W, int64_t 
             for (int u = 0; u < RT; ++u)
                 if (l0 + u < k)
                     sdot[wid][l0 + u] = d[u];
+    }
+}
+
+// Kernel entries K(fix, g) for the thread's EPT rows g = lo + tid + 256 q of
+// the chunk (0 past it), the same values as kentry: every coordinate load is
+// issued (rows clamped into the chunk) before the first entry is formed, so
+// the rows do not take one memory round trip each.
+template <int EPT>
+__device__ __forceinline__ void chunk_entries(const KParams &kp, const double *__restrict__ x,
+                                              int64_t n, int64_t fix, const Chunk &ch, int tid,
+                                              double (&val)[EPT])
+{
+    if (kp.dim == 1) {
+        const double xf = x[fix];
+        double xg[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+            xg[q] = x[g < ch.hi ? g : ch.hi - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+            asm volatile("" : "+v"(xg[q]));
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+            const double t = xg[q] - xf;
+            const double v = kfun_r2<double>(kp.kind, kp.a2, kp.c, 0.0 + t * t);
+            val[q] = g < ch.hi ? v : 0.0;
+        }
+        return;
+    }
+    if constexpr (EPT > 2) {
+        // plans give 2048-entry chunks (EPT 8) to 1-D points only; any other
+        // case takes the entries one by one, keeping these registers free
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+            const double v = kentry(kp, x, n, fix, g < ch.hi ? g : ch.hi - 1);
+            val[q] = g < ch.hi ? v : 0.0;
+        }
+        return;
+    }
+    double xf[3], xg[EPT][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        xf[d] = x[(d < kp.dim ? d : 0) * n + fix];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+        const int64_t gc = g < ch.hi ? g : ch.hi - 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            xg[q][d] = x[(d < kp.dim ? d : 0) * n + gc];
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            asm volatile("" : "+v"(xg[q][d]));
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
+        double r2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double t = xg[q][d] - xf[d];
+            r2 += d < kp.dim ? t * t : 0.0;
+        }
+        const double v = kfun_r2<double>(kp.kind, kp.a2, kp.c, r2);
+        val[q] = g < ch.hi ? v : 0.0;
     }
 }
 
@@ -785,11 +881,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
         double val[EPT];
         double bv = -1.0, bs = 0.0, sq = 0.0;
         int64_t bi = INT64_MAX;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-            val[q] = (g < ch.hi) ? kentry(A.kp, A.x, n, fix, g) : 0.0;
-        }
+        chunk_entries<EPT>(A.kp, A.x, n, fix, ch, tid, val);
         residual_terms<EPT>(W, n, col0, k, sfix, ch, tid, val);
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
@@ -870,11 +962,7 @@ __global__ __launch_bounds__(ACA_THREADS) void aca_big_pass_kernel(BigArgs B)
     double val[EPT];
     double cv = -1.0, cs = 0.0, sq = 0.0;
     int64_t ci = INT64_MAX;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        int64_t g = ch.lo + tid + (int64_t)q * ACA_THREADS;
-        val[q] = (g < ch.hi) ? kentry(A.kp, A.x, n, g, fix) : 0.0;
-    }
+    chunk_entries<EPT>(A.kp, A.x, n, fix, ch, tid, val);
     residual_terms<EPT>(W, n, col0, k, sfix, ch, tid, val);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {

@@ -123,13 +123,18 @@ __device__ __forceinline__ T kfun_r2(int kind, T a2, T c, T r2)
 
 // Squared distance between ordered points i and j; coordinates are
 // coordinate-major (x[d*n + i]).
+// dim is 1, 2 or 3 (checked at every entry point).  All coordinate loads are
+// issued without a condition (dimensions past dim read coordinate 0 and add
+// nothing), so none waits in a branch of its own; the sum is the same.
 __device__ __forceinline__ double dist2(const double *__restrict__ x, int64_t n, int dim, int64_t i,
                                         int64_t j)
 {
     double r2 = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        double t = x[d * n + i] - x[d * n + j];
-        r2 += t * t;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = (d < dim ? d : 0) * n;
+        const double t = x[o + i] - x[o + j];
+        r2 += d < dim ? t * t : 0.0;
     }
     return r2;
 }
