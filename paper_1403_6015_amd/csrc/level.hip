@@ -1462,21 +1462,26 @@ __global__ __launch_bounds__(LV_THREADS) void level_update_mfma_kernel(LevelArgs
             // results lie along rows: lane (lr, lq) holds row i0 + lr of
             // columns cbase + 16 j + lq + 4 t, and each load or store of X
             // covers 16 consecutive rows of 4 columns
+            // the tile's X values loaded first and without a condition (a
+            // column past the list reads column 0, a row past the chunk its
+            // first row; neither is stored), so the four loads are in flight
+            // during the products instead of each waiting in a branch
+            int cl[4];
+            double xv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                cl[t] = scol[16 * j + lq + 4 * t];
+                xv[t] = (double)Xp[(int64_t)(cl[t] >= 0 ? cl[t] : 0) * n + is];
+            }
             lv_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int st = 0; st < KS; ++st)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sS[4 * st + lq][16 * j + lr], a[st], acc,
                                                            0, 0, 0);
-            if (rok) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int col = scol[16 * j + lq + 4 * t];
-                    if (col >= 0) {
-                        PT *px = Xp + (int64_t)col * n + ia;
-                        *px = (PT)((double)*px - acc[t]);
-                    }
-                }
-            }
+            for (int t = 0; t < 4; ++t)
+                if (rok && cl[t] >= 0)
+                    Xp[(int64_t)cl[t] * n + ia] = (PT)(xv[t] - acc[t]);
         }
     }
     }
