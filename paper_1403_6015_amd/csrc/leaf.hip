@@ -190,13 +190,31 @@ __device__ __forceinline__ double row_bcast(double v)
 //   y[J] = w[J] rr, w[k] -= L[k][J] y[J]   for k > J   (substitution step).
 // Only the pivot's reciprocal square root is serial; the 2 (15 - J) updates
 // are independent of each other.
+// acc += (lane K's src, broadcast to its 16-lane row) * mul in one
+// instruction: the FP64 FMA with a DPP row_newbcast operand.  The same
+// product and rounding as an FMA after a separate broadcast, one instruction
+// instead of two.  Volatile, so the sequence keeps its order: NOP puts the two
+// wait states a DPP read needs after a vector write of its source (the
+// source of a step's first update is computed just before it).
+template <int K, bool NOP>
+__device__ __forceinline__ void fmac_bcast(double &acc, double src, double mul)
+{
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc) : "v"(src), "v"(mul), "i"(K));
+    else
+        asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc) : "v"(src), "v"(mul), "i"(K));
+}
+
 template <int J, int K>
-__device__ __forceinline__ void pivot_update(double (&a)[16], double (&x)[16], double lij, double yj)
+__device__ __forceinline__ void pivot_update(double (&a)[16], double (&x)[16], double lij, double nlij,
+                                             double nyj)
 {
     if constexpr (K > J) {
-        const double lkj = row_bcast<K>(lij);
-        a[K] -= lij * lkj;
-        x[K] -= lkj * yj;
+        // a[K] -= lij L[K][J] and x[K] -= L[K][J] yj, L[K][J] = lane K's lij
+        fmac_bcast<K, K == J + 1>(a[K], lij, nlij);
+        fmac_bcast<K, false>(x[K], lij, nyj);
     }
 }
 
@@ -204,7 +222,11 @@ template <int J, int... K>
 __device__ __forceinline__ void pivot_updates(double (&a)[16], double (&x)[16], double lij, double yj,
                                               std::integer_sequence<int, K...>)
 {
-    (pivot_update<J, K>(a, x, lij, yj), ...);
+    const double nlij = -lij, nyj = -yj;
+    (pivot_update<J, K>(a, x, lij, nlij, nyj), ...);
+    // two wait states before the next step's broadcast of a value written
+    // by this step's last update
+    asm volatile("s_nop 1");
 }
 
 template <int J>
