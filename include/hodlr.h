@@ -38,10 +38,14 @@
  *    host solve recovers full accuracy by iterative refinement against an
  *    exact FP64 matrix-vector product (see hodlr_opts.precision).  The log
  *    det is held to a relative error of 1e-8: each mixed likelihood (or
- *    factor) computes the bound eps_32 * sum over split nodes of
- *    1 / det M_tau, and one whose bound exceeds 1e-8 max(|log det|, 1) is
- *    computed again with FP64 panels (counted in hodlr_info.fp64_fallback;
- *    the workspace sizes of mixed plans leave room for it).
+ *    factor) computes the error estimate 4 eps_32 sqrt(sum over split nodes
+ *    of det M_tau^-2) (the FP32 rounding of W~, amplified at most by
+ *    1 / det M_tau at each node, the nodes' independent roundings adding as
+ *    a root sum of squares), and one whose estimate exceeds
+ *    1e-8 max(|log det|, 1) is computed again with FP64 panels (counted in
+ *    hodlr_info.fp64_fallback; the workspace sizes of mixed plans leave room
+ *    for it).  The estimate is calibrated, not proven: on seeded settings of
+ *    the 1-D hyperparameter box the error stayed below a third of it.
  *  - Thread safety: distinct factors/plans may be used concurrently; one
  *    workspace must not be used by two calls at once.
  */
@@ -115,11 +119,10 @@ typedef struct {
                             0 (default): an FP64 factor is applied once, whose
                             residual is about tol ||K|| / sigma2                      */
     int32_t mixed_unchecked; /* HODLR_MIXED only.  0 (default): every likelihood or
-                            factor tests its log-det error bound (see Precision at
-                            the top) and is redone with FP64 panels when the bound
-                            misses 1e-8.  The bound is safe but can be loose by 10^3
-                            and more on strongly coupled problems.  1: keep the FP32-
-                            panel result untested (the caller measures its error)  */
+                            factor tests its log-det error estimate (see Precision
+                            at the top) and is redone with FP64 panels when the
+                            estimate misses 1e-8.  1: keep the FP32-panel result
+                            untested (the caller measures its error)               */
     int32_t compressor;  /* How the off-diagonal blocks K(alpha, beta) are compressed
                             (§3.1 lists both kinds).  HODLR_COMPRESS_ACA (default):
                             adaptive cross approximation, O(r^2 (m + n)) work per
@@ -323,7 +326,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
  * Workspace: hodlr_plan_batch_workspace_size(plan, nitems).  The call returns
  * without synchronizing (results are ready when the stream is), except for
  * mixed plans: they synchronize at the end to read each item's log-det error
- * bound and redo the items that miss the bar with FP64 panels, one at a
+ * estimate and redo the items that miss the bar with FP64 panels, one at a
  * time (see Precision above).                                              */
 hodlr_status hodlr_plan_batch_workspace_size(hodlr_plan p, int32_t nitems, size_t *bytes);
 hodlr_status gp_loglik_batch_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,

@@ -39,6 +39,11 @@ list) can be pinned against what the mathematics fixes:
    determinant theorem and multiplicativity of det over the factor list).
 6. C^{-1} y applies the inverse factors leaves first (§3.2, the inverse of
    the factor list).
+
+``panel32=True`` rounds every stored value of the applied bases W~ to FP32
+(after the leaf solves and after each level's update) and keeps all
+arithmetic in FP64: the storage precision of the mixed form, whose log-det
+error this makes measurable on the CPU.  Not part of the paper's method.
 """
 from __future__ import annotations
 
@@ -233,7 +238,8 @@ class HodlrRef:
     """Plain FP64 HODLR factorization of C = sigma^2 I + K on ordered points."""
 
     def __init__(self, x, kind, theta, sigma2, leaf, tol, max_rank=64, presorted=False,
-                 compress="aca"):
+                 compress="aca", panel32=False):
+        self.panel32 = bool(panel32)
         x = np.asarray(x, dtype=np.float64)
         if x.ndim == 1:
             x = x.reshape(-1, 1)
@@ -299,7 +305,7 @@ class HodlrRef:
                 for li, (ls, le) in enumerate(self.nodes[L]):
                     if ls >= s and le <= e and le > ls:
                         blk = self.Wt[d][j][ls - s:le - s]
-                        self.Wt[d][j][ls - s:le - s] = self._leaf_solve(li, blk)
+                        self.Wt[d][j][ls - s:le - s] = self._store(self._leaf_solve(li, blk))
         # levels, from the leaves' parents up to the root
         self.M = [None] * L
         self.node_logdet = [None] * L
@@ -329,8 +335,12 @@ class HodlrRef:
                     Xb = X[mid - as_:e - as_]
                     if r:
                         S = np.linalg.solve(Mt, np.vstack([Wb.T @ Xb, Wa.T @ Xa]))
-                        X[s - as_:mid - as_] = Xa - Ta @ S[:r]
-                        X[mid - as_:e - as_] = Xb - Tb @ S[r:]
+                        X[s - as_:mid - as_] = self._store(Xa - Ta @ S[:r])
+                        X[mid - as_:e - as_] = self._store(Xb - Tb @ S[r:])
+
+    def _store(self, A):
+        """A value of W~ as stored: FP64, or rounded to FP32 with panel32."""
+        return A.astype(np.float32).astype(np.float64) if self.panel32 else A
 
     def _leaf_solve(self, li, B):
         G = self.G[li]

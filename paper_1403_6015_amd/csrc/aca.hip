@@ -1148,17 +1148,19 @@ void host_wait(hipStream_t s)
 
 // A growable pinned int buffer per host thread and slot (0: the per-node ranks
 // read back after compression, 1: the column list uploaded before the
-// leaves), so those copies go straight between device and host memory.  A
-// slot is rewritten only after the stream has been synchronized since its
-// last copy (each compression ends with a synchronization).
+// leaves, 2: a speculative call's rank statistics, 3: values read back with
+// the status at the end of a call), so those copies go straight between
+// device and host memory.  A slot is rewritten only after the stream has been
+// synchronized since its last copy (each compression, and each read of the
+// status, ends with a synchronization).
 int *pinned_ints(size_t n, int slot)
 {
     struct Buf {
-        int *p[3] = {nullptr, nullptr, nullptr};
-        size_t cap[3] = {0, 0, 0};
+        int *p[4] = {nullptr, nullptr, nullptr, nullptr};
+        size_t cap[4] = {0, 0, 0, 0};
         ~Buf()
         {
-            for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 4; ++i)
                 if (p[i])
                     (void)hipHostFree(p[i]);
         }

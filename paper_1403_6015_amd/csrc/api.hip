@@ -226,19 +226,37 @@ void raise_status(int st)
 
 // The mixed form's log-det bar: relative error at most 1e-8 of max(|log det|, 1).
 // Its FP32 storage of the applied bases W~ perturbs each coupling matrix
-// I - QP by about the FP32 unit roundoff, which its inverse amplifies; the
-// finish kernel writes eps_32 sum_tau 1 / det M_tau, a bound on the log-det
-// error (on seeded problems of the batched hyperparameter box the error was at
-// most a quarter of it).  A likelihood whose bound exceeds the bar is redone
-// with FP64 panels.
+// I - QP by about the FP32 unit roundoff u, which its inverse amplifies by at
+// most 1 / det M_tau; the finish kernel writes the estimate
+// 4 u sqrt(sum_tau det M_tau^-2) of the log-det error (independent roundings
+// at the nodes add as a root sum of squares; on seeded problems of the batched
+// hyperparameter box the error stayed below a third of it).  A likelihood
+// whose estimate exceeds the bar is redone with FP64 panels.
 constexpr double MIXED_LOGDET_BAR = 1e-8;
 
-bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item)
+bool mixed_estimate_exceeds(double estimate, double logdet)
 {
-    double bound = 0.0;
+    return !(estimate <= MIXED_LOGDET_BAR * std::max(std::fabs(logdet), 1.0));
+}
+
+// Enqueues on P's stream the copies of a mixed likelihood's log det (d_out[1])
+// and error estimate into this thread's pinned slot 3: {log det, estimate},
+// valid after the stream's next synchronization (the read of the status).
+double *queue_mixed_check(const Pipeline &P, const double *d_out)
+{
+    double *hv = (double *)pinned_ints(4, 3);
+    HIP_TRY(hipMemcpyAsync(hv, d_out + 1, sizeof(double), hipMemcpyDeviceToHost, P.stream));
+    HIP_TRY(hipMemcpyAsync(hv + 1, wsp<double>(P, P.lay.misc + MISC_BOUND), sizeof(double),
+                           hipMemcpyDeviceToHost, P.stream));
+    return hv;
+}
+
+bool mixed_estimate_missed(const Pipeline &P, double logdet, int item)
+{
+    double est = 0.0;
     const char *src = P.ws + (size_t)P.batch.istride * item + P.lay.misc + MISC_BOUND;
-    HIP_TRY(hipMemcpy(&bound, src, sizeof(double), hipMemcpyDeviceToHost));
-    return !(bound <= MIXED_LOGDET_BAR * std::max(std::fabs(logdet), 1.0));
+    HIP_TRY(hipMemcpy(&est, src, sizeof(double), hipMemcpyDeviceToHost));
+    return mixed_estimate_exceeds(est, logdet);
 }
 
 // compression, leaves, levels, finish: everything for one likelihood
@@ -473,7 +491,7 @@ hodlr_status hodlr_build(const double *x, int64_t n, int32_t dim, hodlr_kernel k
         double hout[8];
         HIP_TRY(hipMemcpyAsync(hout, d_out, sizeof(double) * 8, hipMemcpyDeviceToHost, P.stream));
         raise_status(read_status(P));
-        if (f->plan.mixed_check && mixed_bound_exceeded(P, hout[1], 0)) {
+        if (f->plan.mixed_check && mixed_estimate_missed(P, hout[1], 0)) {
             // FP64 panels for this factor (solves still refine, as for mixed)
             f->plan.precision = HODLR_FP64;
             f->lay = make_layout(f->plan, true);
@@ -841,6 +859,13 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         factor_pipeline(P, d_y, d_out);
         if (d_z)
             run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
+        // a mixed plan's log det and error estimate come back with the status
+        double *hv = nullptr;
+        auto status = [&]() {
+            if (p->plan.mixed_check)
+                hv = queue_mixed_check(P, d_out);
+            return read_status(P);
+        };
         int st = 0;
         std::vector<int> actual;   // per depth index, of this call's compression
         if (P.spec_run) {
@@ -851,14 +876,14 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
                                    hipMemcpyDeviceToHost, P.stream));
             HIP_TRY(hipMemcpyAsync(hr, wsp<int>(P, P.lay.rank), sizeof(int) * p->plan.nint,
                                    hipMemcpyDeviceToHost, P.stream));
-            st = read_status(P);
+            st = status();
             if (st & DS_SPEC_MISS) {
                 // the assumed widths or step count did not hold: the ordinary way
                 P.spec = nullptr;
                 factor_pipeline(P, d_y, d_out);
                 if (d_z)
                     run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
-                st = read_status(P);
+                st = status();
                 actual = P.rmax;
             } else {
                 actual.assign(hs, hs + p->plan.L + 2);
@@ -866,15 +891,13 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
                 std::memcpy(P.ranks.data(), hr, sizeof(int) * p->plan.nint);
             }
         } else {
-            st = read_status(P);
+            st = status();
             actual = P.rmax;
         }
         raise_status(st);
         int fallback = 0;
-        if (p->plan.mixed_check) {
-            double ld = 0.0;
-            HIP_TRY(hipMemcpy(&ld, d_out + 1, sizeof(double), hipMemcpyDeviceToHost));
-            if (mixed_bound_exceeded(P, ld, 0)) {
+        if (hv) {
+            if (mixed_estimate_exceeds(hv[1], hv[0])) {
                 // the same likelihood with FP64 panels on the same workspace
                 P.plan = &p->plan64;
                 P.lay = p->lay64;
@@ -952,7 +975,7 @@ static size_t batch_bytes(hodlr_plan p, int32_t nitems)
     return p->plan.f32() ? std::max(b, p->lay64.total) : b;
 }
 
-// Mixed plans: after the batch, every item whose log-det error bound misses
+// Mixed plans: after the batch, every item whose log-det error estimate misses
 // the bar is computed again with FP64 panels on the workspace (in FP64
 // batches when the observations are shared, else one at a time) and its row
 // of d_out replaced (synchronizes the stream).
@@ -970,7 +993,7 @@ static void batch_fp64_redo(hodlr_plan p, const Pipeline &B, const double *d_par
     std::vector<int> flag;
     for (int i = 0; i < nitems; ++i) {
         const double ld = out[3 * (size_t)i + 1];
-        if (std::isfinite(ld) && !(bound[i] <= MIXED_LOGDET_BAR * std::max(std::fabs(ld), 1.0)))
+        if (std::isfinite(ld) && mixed_estimate_exceeds(bound[i], ld))
             flag.push_back(i);
     }
     const int redo = (int)flag.size();
@@ -1267,14 +1290,13 @@ hodlr_status gp_loglik_grad_dev(hodlr_plan p, const double *d_x, hodlr_kernel k,
             } else {
                 factor_pipeline(P, d_y, o);
             }
+            const double *hv = p->plan.mixed_check ? queue_mixed_check(P, o) : nullptr;
             const int st = read_status(P);
             if (st)
                 throw Error{HODLR_ENOTSPD,
                             "factorization " + std::to_string(i) + " of the gradient's 7 failed"};
-            if (p->plan.mixed_check) {
-                double ld = 0.0;
-                HIP_TRY(hipMemcpy(&ld, o + 1, sizeof(double), hipMemcpyDeviceToHost));
-                if (mixed_bound_exceeded(P, ld, 0)) {
+            if (hv) {
+                if (mixed_estimate_exceeds(hv[1], hv[0])) {
                     P.plan = &p->plan64;
                     P.lay = p->lay64;
                     factor_pipeline(P, d_y, o);

@@ -321,7 +321,7 @@ struct Plan {
 };
 
 // byte offset in the workspace's misc area of the mixed form's log-det error
-// bound (one double per item, written by the finish kernel)
+// estimate (one double per item, written by the finish kernel)
 constexpr size_t MISC_BOUND = 3072;
 constexpr size_t MISC_SPEC = 2048;   // 64 ints: a speculative call's actual rank statistics
 
@@ -440,9 +440,11 @@ void raise_status(int st);
 void factor_pipeline(Pipeline &P, const double *d_y, double *d_out);
 // mixed form: true if the log-det error bound of batch item `item` (written by
 // the finish kernel) exceeds the 1e-8 bar for this log det (synchronizes)
-bool mixed_bound_exceeded(const Pipeline &P, double logdet, int item);
+bool mixed_estimate_missed(const Pipeline &P, double logdet, int item);
+bool mixed_estimate_exceeds(double estimate, double logdet);
+double *queue_mixed_check(const Pipeline &P, const double *d_out);
 int *pinned_scratch();                                         // per-thread pinned ints
-int *pinned_ints(size_t n, int slot);   // per-thread growable pinned ints, slots 0-2 (0: ranks, 1: column list, 2: statistics)
+int *pinned_ints(size_t n, int slot);   // per-thread growable pinned ints, slots 0-3 (0: ranks, 1: column list, 2: statistics, 3: end-of-call values)
 void host_wait(hipStream_t s);                                 // poll the stream to completion
 
 template <typename T>

@@ -170,8 +170,9 @@ void worker(RaggedJob *J)
             double *d_out = wsp<double>(P, lay.out);
             factor_pipeline(P, dy, d_out);
             HIP_TRY(hipMemcpyAsync(host_out, d_out, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+            const double *hv = plan.mixed_check ? queue_mixed_check(P, d_out) : nullptr;
             int st = read_status(P);   // synchronizes: host buffers above are free again
-            if (!st && plan.mixed_check && mixed_bound_exceeded(P, host_out[1], 0)) {
+            if (!st && hv && mixed_estimate_exceeds(hv[1], hv[0])) {
                 plan64 = plan;   // bound to the uploaded tables
                 plan64.precision = HODLR_FP64;
                 P.plan = &plan64;
