@@ -152,6 +152,17 @@ typedef struct {
                             the padding columns change the rounding of the coupling
                             solves at the 1e-15 level).  Meant for repeated
                             likelihoods of nearby hyperparameters on one plan     */
+    int32_t level_form;  /* How a likelihood (a call given a right-hand side y) runs
+                            the levels.  0 (default): projected when it fits (panel
+                            columns <= 128, widths <= 32 per depth, each level's
+                            coupling solve within 60 KB of LDS): the bases'
+                            projections G = Z^T K^{-1} Z (Z: y and the bases on a
+                            node's rows) go up the tree and C^{-1} y comes down it,
+                            with the same coupling matrices and determinants as the
+                            level-by-level factorization (§3.2, §4) and O(n r)
+                            panel traffic instead of O(n r L^2).  1: always the
+                            level-by-level updates of every applied basis.  A kept
+                            factor (hodlr_build) always takes the latter          */
 } hodlr_opts;          /* pass NULL for all defaults */
 
 typedef struct hodlr_factor_s *hodlr_factor;   /* opaque; factors fixed after build; one
@@ -180,6 +191,9 @@ typedef struct {
     int32_t speculated;                        /* plans: 1 if the last gp_loglik_dev
                                                   ran on the assumed panel widths
                                                   without a redo (hodlr_opts.speculate) */
+    int32_t projected;                         /* plans: 1 if the last gp_loglik_dev
+                                                  ran the projected levels
+                                                  (hodlr_opts.level_form)          */
 } hodlr_info_t;
 
 /* ------------------------------------------------------------------ ordering */

@@ -62,10 +62,12 @@ class Opts(ctypes.Structure):
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("presorted", ctypes.c_int32), ("noise", ctypes.c_void_p),
                 ("refine", ctypes.c_int32), ("mixed_unchecked", ctypes.c_int32),
-                ("compressor", ctypes.c_int32), ("speculate", ctypes.c_int32)]
+                ("compressor", ctypes.c_int32), ("speculate", ctypes.c_int32),
+                ("level_form", ctypes.c_int32)]
 
     def __init__(self, max_rank=64, precision=FP64, refine_tol=1e-10, max_refine=8, presorted=0,
-                 noise=None, refine=0, mixed_unchecked=0, compressor=0, speculate=0):
+                 noise=None, refine=0, mixed_unchecked=0, compressor=0, speculate=0,
+                 level_form=0):
         """noise: optional per-point variances (one per point, caller's order),
         added to sigma2 on the diagonal; the array is kept alive with the
         options."""
@@ -76,7 +78,7 @@ class Opts(ctypes.Structure):
             ptr = self._noise.ctypes.data
         super().__init__(int(max_rank), int(precision), float(refine_tol), int(max_refine),
                          int(presorted), ptr, int(refine), int(mixed_unchecked), int(compressor),
-                         int(speculate))
+                         int(speculate), int(level_form))
 
 
 class Profile(ctypes.Structure):
@@ -92,7 +94,8 @@ class Info(ctypes.Structure):
                 ("rank_mean", ctypes.c_double * MAX_LEVELS),
                 ("device_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("refine_residual", ctypes.c_double),
-                ("fp64_fallback", ctypes.c_int32), ("speculated", ctypes.c_int32)]
+                ("fp64_fallback", ctypes.c_int32), ("speculated", ctypes.c_int32),
+                ("projected", ctypes.c_int32)]
 
 
 class MlpNorm(ctypes.Structure):
@@ -413,7 +416,8 @@ def _info_dict(I) -> dict:
             "rank_max": list(I.rank_max[:L]), "rank_mean": list(I.rank_mean[:L]),
             "device_bytes": I.device_bytes, "precision": I.precision,
             "refine_steps": I.refine_steps, "refine_residual": I.refine_residual,
-            "fp64_fallback": I.fp64_fallback, "speculated": I.speculated}
+            "fp64_fallback": I.fp64_fallback, "speculated": I.speculated,
+            "projected": I.projected}
 
 
 def hodlr_info(f: Factor) -> dict:

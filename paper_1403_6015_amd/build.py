@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhodlrgp.so")
 SOURCES = ["tree.cpp", "prof.cpp", "aca.hip", "leaf.hip", "level.hip", "misc.hip", "api.hip", "ragged.hip",
-           "mlp.hip", "sampler.hip", "tune.cpp", "predict.hip", "sketch.hip"]
+           "mlp.hip", "sampler.hip", "tune.cpp", "predict.hip", "sketch.hip", "proj.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

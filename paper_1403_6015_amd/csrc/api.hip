@@ -52,6 +52,7 @@ hodlr_opts default_opts()
     o.mixed_unchecked = 0;
     o.compressor = HODLR_COMPRESS_ACA;
     o.speculate = 0;
+    o.level_form = 0;
     return o;
 }
 
@@ -98,6 +99,8 @@ void check_opts(const hodlr_opts &o)
         throw Error{HODLR_EINVAL, "unknown compressor"};
     if (o.speculate != 0 && o.speculate != 1)
         throw Error{HODLR_EINVAL, "speculate must be 0 or 1"};
+    if (o.level_form != 0 && o.level_form != 1)
+        throw Error{HODLR_EINVAL, "level_form must be 0 or 1"};
     if (o.compressor == HODLR_COMPRESS_SKETCH && o.max_rank > SK_CAP_MAX)
         throw Error{HODLR_EINVAL, "the sketch compressor needs max_rank <= " +
                                       std::to_string(SK_CAP_MAX)};
@@ -919,6 +922,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
             p->last_fallback = fallback;
             p->spec_rmax = actual;
             p->last_spec = P.spec_run && !(st & DS_SPEC_MISS) && !fallback ? 1 : 0;
+            p->last_proj = P.proj_run ? 1 : 0;
         }
         return HODLR_OK;
     });
@@ -940,6 +944,7 @@ hodlr_status hodlr_plan_info(hodlr_plan p, hodlr_info_t *out)
     I.capped_blocks = p->last_capped;
     I.fp64_fallback = p->last_fallback;
     I.speculated = p->last_spec;
+    I.projected = p->last_proj;
     for (int d = 0; d < p->plan.L && d < HODLR_MAX_LEVELS && d + 1 < (int)p->last_rmax.size();
          ++d) {
         I.rank_max[d] = p->last_rmax[d + 1];

@@ -255,6 +255,7 @@ struct Plan {
     bool refine = false;       // host solves refine against the exact product (always when mixed)
     bool mixed_check = false;  // mixed form: test the log-det error bound, redo in FP64 if missed
     int compressor = HODLR_COMPRESS_ACA;
+    int level_form = 0;        // 0: projected levels for a likelihood when they fit; 1: never
     // sketch compressor tables, per depth d: 64-row chunks of both children of
     // every depth-d node (alpha chunks of a node first; an alpha chunk's part
     // is its partial-core slot, contiguous per node), and per node the first
@@ -380,6 +381,8 @@ struct Pipeline {
     // tells whether the compression actually ran that way
     const std::vector<int> *spec = nullptr;
     bool spec_run = false;
+    const double *rhs = nullptr;   // the right-hand side the leaf factor was given
+    bool proj_run = false;         // the last run_levels_factor took the projected form
 };
 
 // ------------------------------------------------------------ profiling
@@ -414,6 +417,11 @@ void run_aca(Pipeline &P);                                   // fills W panels, 
 void run_aca_batched(Pipeline &P);                           // every block of every item
 void run_leaf_factor(Pipeline &P, const double *y);          // leaves: G, log-dets, Xt
 void run_levels_factor(Pipeline &P);                         // coupling matrices, Xt, z
+// projected levels (log det and C^{-1} y from the bases' projections)
+constexpr int PJ_MMAX = 128;   // panel columns (y and the bases of all depths)
+constexpr int PJ_WMAX = 32;    // columns of one depth
+bool proj_fits(const Pipeline &P);
+void run_levels_projected(Pipeline &P);
 void run_solve(Pipeline &P, double *z);                      // z := C^{-1} z using a built factor
 void run_finish(Pipeline &P, const double *y, double *d_out, int ostride = 8);  // log det, quad, loglik
 // refinement helpers (misc.hip); z is the panel-typed solve vector

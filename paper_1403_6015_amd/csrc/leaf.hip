@@ -1373,6 +1373,7 @@ void run_leaf_factor(Pipeline &P, const double *y)
         throw Error{HODLR_EINVAL, "leaf size above 256 is not supported"};
     LeafArgs A = leaf_args(P);
     A.y = y;
+    P.rhs = y;
     A.cbeg = y ? 0 : 1;
     A.ncols = P.cnt[p.L];
     ProfScope ps(P.stream, PS_LEAF);

@@ -1784,6 +1784,11 @@ static void level_launch(Pipeline &P, int d, LevelArgs A, bool fuse_up = false)
 
 void run_levels_factor(Pipeline &P)
 {
+    P.proj_run = proj_fits(P);
+    if (P.proj_run) {
+        run_levels_projected(P);
+        return;
+    }
     const Plan &p = *P.plan;
     bool below = false;   // level d+1's update wrote this level's records
     for (int d = p.L - 1; d >= 0; --d) {

@@ -53,6 +53,7 @@ struct hodlr_plan_s {
     // panel widths per depth index of the last completed gp_loglik_dev (the
     // widths a speculative call assumes); empty before the first
     std::vector<int> spec_rmax;
+    int last_proj = 0;       // 1: the last gp_loglik_dev ran the projected levels
     int last_spec = 0;       // 1: the last gp_loglik_dev ran speculatively without a redo
     ~hodlr_plan_s()
     {

@@ -238,9 +238,11 @@ extern "C" hodlr_status gp_loglik_ragged(int32_t m, const int64_t *ns, const dou
             J.opts.mixed_unchecked = 0;
             J.opts.compressor = HODLR_COMPRESS_ACA;
             J.opts.speculate = 0;
+            J.opts.level_form = 0;
         }
         if (J.opts.max_rank < 0 || J.opts.max_rank > RMAX_ABS ||
-            (J.opts.precision != HODLR_FP64 && J.opts.precision != HODLR_MIXED))
+            (J.opts.precision != HODLR_FP64 && J.opts.precision != HODLR_MIXED) ||
+            (J.opts.level_form != 0 && J.opts.level_form != 1))
             return report(HODLR_EINVAL, "unsupported options");
         J.out = out;
         J.order.resize(m);

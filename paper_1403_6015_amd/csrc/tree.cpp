@@ -95,6 +95,7 @@ void plan_build(Plan &p, int64_t n, int dim, int leaf, const hodlr_opts *opts, i
     p.refine = p.precision == HODLR_MIXED || (opts && opts->refine);
     p.mixed_check = p.precision == HODLR_MIXED && !(opts && opts->mixed_unchecked);
     p.compressor = opts ? opts->compressor : HODLR_COMPRESS_ACA;
+    p.level_form = opts ? opts->level_form : 0;
     const int L = p.L;
     const int64_t nn = ((int64_t)2 << L) - 1;
     p.nint = ((int64_t)1 << L) - 1;

@@ -134,6 +134,7 @@ hodlr_status hodlr_autotune(const double *x, int64_t n, int32_t dim, hodlr_kerne
             o.mixed_unchecked = 0;
             o.compressor = HODLR_COMPRESS_ACA;
             o.speculate = 0;
+            o.level_form = 0;
         }
         if (o.compressor != HODLR_COMPRESS_ACA)
             return report(HODLR_EINVAL, "the autotuner times cross approximation only");
