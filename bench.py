@@ -33,8 +33,14 @@ PEAK = {"hbm": 8000.0, "alu_fp64": 78.6, "alu_fp32": 157.3,   # GB/s, TFLOP/s, T
         "bf16_mfma": 2500.0}                                   # TFLOP/s, dense
 
 
-def kernel_model(n, leaf_sizes, r, cnt, esz=8):
+def kernel_model(n, leaf_sizes, r, cnt, esz=8, projected=False):
     """Algorithmic FLOPs and HBM bytes per call for each kernel kind.
+
+    projected: the likelihood's projected level form, whose stages are the leaf
+    projection G = Z^T Xt (level_reduce: W and Xt read once, the leaves' G
+    written), the upward coupling solves (level_solve: the children's G read,
+    the parent's G and S written) and the downward pass (level_update: S read,
+    Xt read once, C^{-1} y written).
 
     leaf_sizes: sizes of the leaves; r[j]: columns of the depth-j panel
     (j = 1..L); cnt[d] = 1 + sum_{j<=d} r[j] (columns still updated at depth d
@@ -51,6 +57,19 @@ def kernel_model(n, leaf_sizes, r, cnt, esz=8):
     flops = float(np.sum(m ** 3 / 3.0 + 2.0 * m * m * cnt[L]))
     byts = esz * n * (2 * cnt[L])
     out["leaf_factor"] = (flops, byts)
+    if projected:
+        mL = cnt[L]
+        nleaf = len(leaf_sizes)
+        out["level_reduce"] = (2.0 * mL * mL * n, (esz + 8.0) * n * mL + 8.0 * nleaf * mL * mL)
+        fs = bs = sb = 0.0
+        for d in range(L):
+            nodes, m, w = 1 << d, cnt[d], r[d + 1]
+            fs += nodes * (2.0 * w ** 3 + 6.0 * w * w * m + 4.0 * w * m * m)
+            bs += 8.0 * (2 * nodes * cnt[d + 1] ** 2 + nodes * m * m + nodes * 2 * w * m)
+            sb += 8.0 * nodes * 2 * w * m
+        out["level_solve"] = (fs, bs)
+        out["level_update"] = (2.0 * n * mL, esz * n * (mL + 1) + sb)
+        return out
     fr = br = fu = bu = 0.0
 
     def fused(d):
@@ -358,7 +377,8 @@ def main():
         cnt.append(cnt[-1] + r[j])
     nl = 1 << L
     leaf_sizes = np.diff(np.linspace(0, p.n, nl + 1).round()).astype(int) if L else [p.n]
-    model = kernel_model(p.n, leaf_sizes, r, cnt, esz=4 if mixed else 8)
+    projected = bool(plan.info()["projected"])
+    model = kernel_model(p.n, leaf_sizes, r, cnt, esz=4 if mixed else 8, projected=projected)
 
     dom_ms, dom_launches = prof[dom]
     roofline = None
@@ -414,6 +434,7 @@ def main():
                    "dim": 1, "kernel": "matern32", "theta": list(p.theta), "sigma2": p.sigma2,
                    "leaf": p.leaf, "tol": p.tol, "max_rank": 64, "precision": args.precision,
                    "speculate": spec,
+                   "level_form": "projected" if projected else "level-by-level",
                    "levels": L, "rank_max": r[1:], "level_rows": tune.level_rows,
                    "reduce_cols": tune.reduce_cols, "reduce_group": tune.reduce_group},
         "roofline": roofline,
@@ -446,10 +467,11 @@ def main():
                               speculate=spec), tune=otune)
         owork = torch.empty(oplan.workspace_bytes, dtype=torch.uint8, device=dev)
         oout = torch.zeros(8, dtype=torch.float64, device=dev)
+        oz = torch.empty(p.n, dtype=torch.float64, device=dev)
 
         def ostep():
             H.gp_loglik_dev(oplan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, owork,
-                            oplan.workspace_bytes, stream, oout, None)
+                            oplan.workspace_bytes, stream, oout, oz)
 
         for _ in range(args.warmup):
             ostep()
@@ -465,6 +487,30 @@ def main():
                 "result": {"loglik": o_ll, "logdet": o_ld, "quad": o_q},
                 "tiles": otune.as_dict(), "fp64_fallback": oplan.info()["fp64_fallback"]}
 
+    # the same precision with the level-by-level updates (level_form = 1), for
+    # comparison with the projected levels the default takes
+    lplan = H.Plan(p.n, p.dim, p.leaf, H.Opts(max_rank=64, precision=prec, speculate=spec,
+                                              level_form=1), tune=tune)
+    lwork = torch.empty(lplan.workspace_bytes, dtype=torch.uint8, device=dev)
+    lout = torch.zeros(8, dtype=torch.float64, device=dev)
+    lz = torch.empty(p.n, dtype=torch.float64, device=dev)
+
+    def lstep():
+        H.gp_loglik_dev(lplan, d_x, p.kernel, p.theta, p.sigma2, d_y, p.tol, lwork,
+                        lplan.workspace_bytes, stream, lout, lz)
+
+    for _ in range(args.warmup):
+        lstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lstep()
+    torch.cuda.synchronize()
+    lel = time.perf_counter() - t0
+    res["level_by_level"] = {"value": args.steps / lel, "unit": "likelihoods/s",
+                             "ms_per_step": lel / args.steps * 1e3,
+                             "logdet": lout[1].item(), "quad": lout[2].item()}
+    del lwork
     res["other_precision"] = time_other(0)
     if other == H.MIXED:
         res["other_precision"]["mode"] = "checked (default)"

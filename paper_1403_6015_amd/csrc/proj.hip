@@ -112,6 +112,101 @@ __global__ __launch_bounds__(256) void proj_leaf_kernel(ProjArgs A)
         }
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// The same product on FP64 MFMA for at most 16 TM <= 64 columns, one wave per
+// leaf.  Chunks of 16 rows go through LDS: each column's 16 rows are one
+// coalesced 128-byte load (the next chunk's loads are issued before this
+// chunk's products), and lane (r, q) takes row 4 u + q of column 16 T + r of
+// Z and of Xt from LDS as the A and B operands of the 16 x 16 x 4 product;
+// tile (T, U) accumulates G[16 T + q + 4 t][16 U + r] in element t.
+constexpr int PJ_MLD = 65;   // LDS row length of the staged chunks
+template <typename PT, int TM>
+__global__ __launch_bounds__(64) void proj_leaf_mfma_kernel(ProjArgs A)
+{
+    constexpr int NV = (16 * 16 * TM + 63) / 64;   // staged values per lane and operand
+    const int it = blockIdx.z;
+    const int64_t h = A.node0 + blockIdx.x;
+    const int64_t s = A.start[h], e = A.end[h];
+    const int64_t n = A.n;
+    const double *W = ioff(A.W, A.B, it);
+    const PT *X = (const PT *)ioff(A.Xt, A.B, it);
+    const double *y = A.y + it * A.B.ystride;
+    const int m = A.m;
+    const int l = threadIdx.x, r = l & 15, q = l >> 4;
+    __shared__ double zs[16 * PJ_MLD], xs[16 * PJ_MLD];
+    // the staged values of this lane: row r of columns k = q + 4 j (value
+    // l + 64 j of the chunk); columns past m read column 0 and are zeroed, and
+    // Z's column 0 (lane q = 0, j = 0) is y
+    int64_t off[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int k = q + 4 * j;
+        off[j] = (int64_t)A.cols[k < m ? k : 0] * n;
+    }
+    const double *z0 = q == 0 ? y : W + off[0];
+    double zv[NV], xv[NV];
+    auto load = [&](int64_t r0) {
+        const int64_t row = r0 + r;
+        const int64_t rc = row < e ? row : e - 1;   // clamped: loads never wait on a branch
+        zv[0] = z0[rc];
+        xv[0] = (double)X[off[0] + rc];
+#pragma unroll
+        for (int j = 1; j < NV; ++j) {
+            zv[j] = W[off[j] + rc];
+            xv[j] = (double)X[off[j] + rc];
+        }
+    };
+    d4 acc[TM][TM];
+#pragma unroll
+    for (int T = 0; T < TM; ++T)
+#pragma unroll
+        for (int U = 0; U < TM; ++U)
+            acc[T][U] = d4{0.0, 0.0, 0.0, 0.0};
+    if (s < e)
+        load(s);
+    for (int64_t r0 = s; r0 < e; r0 += 16) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int k = q + 4 * j;
+            asm volatile("" : "+v"(zv[j]), "+v"(xv[j]));
+            const bool in = k < m && r0 + r < e;
+            zs[r * PJ_MLD + k] = in ? zv[j] : 0.0;
+            xs[r * PJ_MLD + k] = in ? xv[j] : 0.0;
+        }
+        __syncthreads();
+        if (r0 + 16 < e)
+            load(r0 + 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double za[TM], xb[TM];
+#pragma unroll
+            for (int T = 0; T < TM; ++T) {
+                za[T] = zs[(4 * u + q) * PJ_MLD + 16 * T + r];
+                xb[T] = xs[(4 * u + q) * PJ_MLD + 16 * T + r];
+            }
+#pragma unroll
+            for (int T = 0; T < TM; ++T)
+#pragma unroll
+                for (int U = 0; U < TM; ++U)
+                    acc[T][U] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[T], xb[U], acc[T][U],
+                                                                     0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double *G = ioff(A.Gout, A.B, it) + (int64_t)blockIdx.x * m * m;
+#pragma unroll
+    for (int T = 0; T < TM; ++T)
+#pragma unroll
+        for (int U = 0; U < TM; ++U)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = 16 * T + q + 4 * t, j = 16 * U + r;
+                if (i < m && j < m)
+                    G[(int64_t)i * m + j] = acc[T][U][t];
+            }
+}
+
 // One level upwards: one wave per node of depth d (see the file comment).
 // Dynamic LDS: P, Q, N (w x w), R1/S1 and R2/S2 (w x m), G_alpha[A, D] and
 // G_beta[A, D] (m x w).
@@ -298,6 +393,13 @@ __global__ __launch_bounds__(64) void proj_down_kernel(ProjArgs A, ProjDown D)
 template <typename PT>
 void leaf_launch(int mb, dim3 g, hipStream_t s, const ProjArgs &A)
 {
+    switch (mb) {
+    case 1: proj_leaf_mfma_kernel<PT, 1><<<g, 64, 0, s>>>(A); return;
+    case 2: proj_leaf_mfma_kernel<PT, 2><<<g, 64, 0, s>>>(A); return;
+    case 3: proj_leaf_mfma_kernel<PT, 3><<<g, 64, 0, s>>>(A); return;
+    case 4: proj_leaf_mfma_kernel<PT, 4><<<g, 64, 0, s>>>(A); return;
+    default: break;
+    }
     switch (mb) {
     case 1: proj_leaf_kernel<PT, 1><<<g, 256, 0, s>>>(A); break;
     case 2: proj_leaf_kernel<PT, 2><<<g, 256, 0, s>>>(A); break;
