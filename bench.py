@@ -148,9 +148,7 @@ def measured_traffic(kernel: str):
     none or the kernel's source changed since the counters were taken."""
     import hashlib
     files = {"leaf_factor": ("profiles/leaf_factor_traffic_matern32_n2p20.md",
-                             "paper_1403_6015_amd/csrc/leaf.hip"),
-             "level_update": ("profiles/level_update_traffic_matern32_n2p20.md",
-                              "paper_1403_6015_amd/csrc/level.hip")}
+                             "paper_1403_6015_amd/csrc/leaf.hip")}
     if kernel not in files:
         return None
     summary, src = (os.path.join(ROOT, f) for f in files[kernel])
