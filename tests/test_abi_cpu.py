@@ -105,3 +105,42 @@ def test_per_point_noise_is_validated():
         H.Plan(64, 1, 16, H.Opts(noise=np.zeros(64)))
     assert ei.value.name == "EINVAL"
 
+
+
+# C struct <-> ctypes mirror of the binding: sizes and every field's offset
+_STRUCTS = [("hodlr_opts", "Opts"), ("hodlr_info_t", "Info"), ("hodlr_tune_t", "Tune"),
+            ("hodlr_mlp_norm", "MlpNorm"), ("hodlr_sampler_cfg", "SamplerCfg"),
+            ("hodlr_sampler_stats", "SamplerStats"), ("hodlr_profile_t", "Profile")]
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Compiles a C program against include/hodlr.h that prints sizeof and
+    offsetof of every field the binding declares, and compares them with the
+    ctypes structures (a mismatch would pass wrong options to the library)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hodlr.h"', "int main(void) {"]
+    for cname, pname in _STRUCTS:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in getattr(H, pname)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, pname in _STRUCTS:
+        cls = getattr(H, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
