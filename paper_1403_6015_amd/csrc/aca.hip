@@ -1148,8 +1148,8 @@ void host_wait(hipStream_t s)
 
 // A growable pinned int buffer per host thread and slot (0: the per-node ranks
 // read back after compression, 1: the column list uploaded before the
-// leaves, 2: a speculative call's rank statistics, 3: values read back with
-// the status at the end of a call), so those copies go straight between
+// leaves, 2: a speculative call's rank statistics, 3: values read back at
+// the end of a call, the status word at int 8), so those copies go straight between
 // device and host memory.  A slot is rewritten only after the stream has been
 // synchronized since its last copy (each compression, and each read of the
 // status, ends with a synchronization).

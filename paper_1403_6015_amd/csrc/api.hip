@@ -209,14 +209,17 @@ void make_columns(Pipeline &P)
                            hipMemcpyHostToDevice, P.stream));
 }
 
+// The status word through this thread's pinned slot 3 (ints 8 on; the mixed
+// check's values take ints 0-3), the stream polled to completion: a plain
+// synchronization wakes the host tens of microseconds later.
 int read_status(Pipeline &P)
 {
-    int st = 0;
-    HIP_TRY(hipMemcpyAsync(&st, wsp<int>(P, P.lay.status), sizeof(int), hipMemcpyDeviceToHost,
+    int *hs = pinned_ints(16, 3) + 8;
+    HIP_TRY(hipMemcpyAsync(hs, wsp<int>(P, P.lay.status), sizeof(int), hipMemcpyDeviceToHost,
                            P.stream));
-    HIP_TRY(hipStreamSynchronize(P.stream));
+    host_wait(P.stream);
     prof_collect();
-    return st;
+    return *hs;
 }
 
 void raise_status(int st)
@@ -240,6 +243,42 @@ constexpr double MIXED_LOGDET_BAR = 1e-8;
 bool mixed_estimate_exceeds(double estimate, double logdet)
 {
     return !(estimate <= MIXED_LOGDET_BAR * std::max(std::fabs(logdet), 1.0));
+}
+
+// The end of a likelihood call: the status word, and when asked a speculative
+// call's rank statistics and ranks and a mixed call's log det and error
+// estimate, written by one kernel straight into this thread's pinned buffers
+// (device addresses of the same memory) instead of one copy each.
+struct EndArgs {
+    const int *status = nullptr, *stats = nullptr, *ranks = nullptr;
+    int64_t nint = 0;
+    const double *ld = nullptr, *est = nullptr;
+    int *h_status = nullptr, *h_stats = nullptr, *h_ranks = nullptr;
+    double *h_vals = nullptr;
+};
+
+__global__ __launch_bounds__(256) void end_read_kernel(EndArgs E)
+{
+    for (int64_t i = threadIdx.x; i < E.nint; i += 256)
+        E.h_ranks[i] = E.ranks[i];
+    if (E.stats)
+        for (int i = threadIdx.x; i < 64; i += 256)
+            E.h_stats[i] = E.stats[i];
+    if (threadIdx.x == 0) {
+        *E.h_status = *E.status;
+        if (E.ld) {
+            E.h_vals[0] = *E.ld;
+            E.h_vals[1] = *E.est;
+        }
+    }
+}
+
+template <typename T>
+T *device_alias(T *host)
+{
+    void *d = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&d, (void *)host, 0));
+    return (T *)d;
 }
 
 // Enqueues on P's stream the copies of a mixed likelihood's log det (d_out[1])
@@ -862,31 +901,47 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
         factor_pipeline(P, d_y, d_out);
         if (d_z)
             run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
-        // a mixed plan's log det and error estimate come back with the status
+        // the status, with a mixed plan's log det and error estimate and (after
+        // a speculative compression) the actual rank statistics and ranks
         double *hv = nullptr;
-        auto status = [&]() {
-            if (p->plan.mixed_check)
-                hv = queue_mixed_check(P, d_out);
-            return read_status(P);
+        int *hs = nullptr, *hr = nullptr;
+        auto status = [&](bool spec_reads) {
+            int *h8 = pinned_ints(16, 3);   // ints 0-3: the mixed values; int 8: status
+            EndArgs E;
+            E.status = wsp<int>(P, P.lay.status);
+            E.h_status = device_alias(h8 + 8);
+            if (p->plan.mixed_check) {
+                hv = (double *)h8;
+                E.ld = d_out + 1;
+                E.est = wsp<double>(P, P.lay.misc + MISC_BOUND);
+                E.h_vals = device_alias(hv);
+            }
+            if (spec_reads) {
+                hs = pinned_ints(64, 2);
+                hr = pinned_ints((size_t)p->plan.nint, 0);
+                E.stats = wsp<int>(P, P.lay.misc + MISC_SPEC);
+                E.h_stats = device_alias(hs);
+                E.ranks = wsp<int>(P, P.lay.rank);
+                E.nint = p->plan.nint;
+                E.h_ranks = device_alias(hr);
+            }
+            end_read_kernel<<<1, 256, 0, P.stream>>>(E);
+            HIP_TRY(hipGetLastError());
+            host_wait(P.stream);
+            prof_collect();
+            return h8[8];
         };
         int st = 0;
         std::vector<int> actual;   // per depth index, of this call's compression
         if (P.spec_run) {
-            // the actual rank statistics and ranks come back with the status
-            int *hs = pinned_ints(64, 2);
-            int *hr = pinned_ints((size_t)p->plan.nint, 0);
-            HIP_TRY(hipMemcpyAsync(hs, wsp<int>(P, P.lay.misc + MISC_SPEC), sizeof(int) * 64,
-                                   hipMemcpyDeviceToHost, P.stream));
-            HIP_TRY(hipMemcpyAsync(hr, wsp<int>(P, P.lay.rank), sizeof(int) * p->plan.nint,
-                                   hipMemcpyDeviceToHost, P.stream));
-            st = status();
+            st = status(true);
             if (st & DS_SPEC_MISS) {
                 // the assumed widths or step count did not hold: the ordinary way
                 P.spec = nullptr;
                 factor_pipeline(P, d_y, d_out);
                 if (d_z)
                     run_widen(P.ws + P.lay.Xt, p->plan.f32(), d_z, p->plan.n, P.stream);
-                st = status();
+                st = status(false);
                 actual = P.rmax;
             } else {
                 actual.assign(hs, hs + p->plan.L + 2);
@@ -894,7 +949,7 @@ hodlr_status gp_loglik_dev(hodlr_plan p, const double *d_x, hodlr_kernel k, cons
                 std::memcpy(P.ranks.data(), hr, sizeof(int) * p->plan.nint);
             }
         } else {
-            st = status();
+            st = status(false);
             actual = P.rmax;
         }
         raise_status(st);
