@@ -36,25 +36,40 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
         part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// one work-group: fixed-order sums, so repeated calls agree bit for bit
-// this thread's share (stride 256) of v[0, cnt), as four independent sums
-// so that several loads are in flight
-__device__ __forceinline__ double strided_sum(const double *v, int64_t cnt)
+// one work-group of FIN_T threads: fixed-order sums, so repeated calls agree
+// bit for bit
+constexpr int FIN_T = 1024;
+
+// this thread's share (stride FIN_T) of v[0, cnt), as four independent sums
+// so that several loads are in flight; with EXP also the sum of exp(-2 v)
+template <bool EXP>
+__device__ __forceinline__ double strided_sum(const double *v, int64_t cnt, double &ex)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double e0 = 0.0, e1 = 0.0;
     int64_t i = threadIdx.x;
-    for (; i + 768 < cnt; i += 1024) {
-        s0 += v[i];
-        s1 += v[i + 256];
-        s2 += v[i + 512];
-        s3 += v[i + 768];
+    for (; i + 3 * FIN_T < cnt; i += 4 * FIN_T) {
+        const double v0 = v[i], v1 = v[i + FIN_T], v2 = v[i + 2 * FIN_T], v3 = v[i + 3 * FIN_T];
+        s0 += v0;
+        s1 += v1;
+        s2 += v2;
+        s3 += v3;
+        if (EXP) {
+            e0 += exp(-2.0 * v0) + exp(-2.0 * v1);
+            e1 += exp(-2.0 * v2) + exp(-2.0 * v3);
+        }
     }
-    for (; i < cnt; i += 256)
-        s0 += v[i];
+    for (; i < cnt; i += FIN_T) {
+        const double v0 = v[i];
+        s0 += v0;
+        if (EXP)
+            e0 += exp(-2.0 * v0);
+    }
+    ex = e0 + e1;
     return (s0 + s1) + (s2 + s3);
 }
 
-__global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int64_t nleaf,
+__global__ __launch_bounds__(FIN_T) void finish_kernel(const double *leaf_ld, int64_t nleaf,
                                                      const double *node_ld, int64_t nint,
                                                      const double *dpart, int ndp, int64_t n,
                                                      double *out, int ostride, double *bound,
@@ -66,19 +81,18 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int6
     dpart = ioff(dpart, B, it);
     bound = ioff(bound, B, it);
     out += (int64_t)it * ostride;
-    __shared__ double red[4][4];
-    double a = strided_sum(leaf_ld, nleaf);
-    double b = strided_sum(node_ld, nint);
-    double q = strided_sum(dpart, ndp);
+    constexpr int NW = FIN_T / 64;
+    __shared__ double red[4][NW];
     // the mixed form's log-det error estimate: the FP32 rounding of W~
     // perturbs each I - QP by about the unit roundoff u, which its inverse
     // amplifies by at most 1 / det M_tau (det M_tau bounds the smallest
     // eigenvalue of I - QP from above); the nodes' errors come from independent
     // roundings and add as a root sum of squares, so the estimate is
     // MIXED_LAMBDA u sqrt(sum_tau det M_tau^-2)
-    double e = 0.0;
-    for (int64_t i = threadIdx.x; i < nint; i += 256)
-        e += exp(-2.0 * node_ld[i]);
+    double e = 0.0, unused = 0.0;
+    double a = strided_sum<false>(leaf_ld, nleaf, unused);
+    double b = strided_sum<true>(node_ld, nint, e);
+    double q = strided_sum<false>(dpart, ndp, unused);
     a = wave_sum(a);
     b = wave_sum(b);
     q = wave_sum(q);
@@ -92,10 +106,19 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *leaf_ld, int6
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        *bound = MIXED_LAMBDA * 0x1p-24 * sqrt((red[3][0] + red[3][1]) + (red[3][2] + red[3][3]));
-        double la = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        double lb = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-        double qq = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+        double t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; w += 2) {
+                s0 += red[k][w];
+                s1 += red[k][w + 1];
+            }
+            t[k] = s0 + s1;
+        }
+        *bound = MIXED_LAMBDA * 0x1p-24 * sqrt(t[3]);
+        const double la = t[0], lb = t[1], qq = t[2];
         double ld = la + lb;
         out[1] = ld;
         out[2] = qq;
@@ -123,7 +146,7 @@ void run_finish(Pipeline &P, const double *y, double *d_out, int ostride)
                                                                 dpart, P.batch);
         ndp = FIN_BLOCKS;
     }
-    finish_kernel<<<dim3(1, 1, P.nitems), 256, 0, P.stream>>>(
+    finish_kernel<<<dim3(1, 1, P.nitems), FIN_T, 0, P.stream>>>(
         wsp<double>(P, P.lay.leaf_ld), p.nleaf, wsp<double>(P, P.lay.node_ld), p.nint, dpart, ndp,
         p.n, d_out, ostride, wsp<double>(P, P.lay.misc + MISC_BOUND), P.batch);
     HIP_TRY(hipGetLastError());
