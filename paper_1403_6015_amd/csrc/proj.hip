@@ -326,12 +326,26 @@ __global__ __launch_bounds__(64) void proj_up_kernel(ProjArgs A)
         S[idx] = s1[idx];
         S[w * m + idx] = s2[idx];
     }
-    for (int idx = lane; idx < m * m; idx += 64) {
-        const int a = idx / m, b = idx % m;
-        double v = Ga[(int64_t)a * mc + b] + Gb[(int64_t)a * mc + b];
-        for (int k = 0; k < w; ++k)
-            v -= ad[a * w + k] * s1[k * m + b] + bd[a * w + k] * s2[k * m + b];
-        Go[idx] = v;
+    // four outputs per lane at a time, their eight loads issued first
+    // (clamped indices, stores masked)
+    const int mm = m * m;
+    for (int idx0 = lane; idx0 < mm; idx0 += 256) {
+        double v[4];
+        int ix[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ix[u] = min(idx0 + 64 * u, mm - 1);
+            const int a = ix[u] / m, b = ix[u] % m;
+            v[u] = Ga[(int64_t)a * mc + b] + Gb[(int64_t)a * mc + b];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int a = ix[u] / m, b = ix[u] % m;
+            for (int k = 0; k < w; ++k)
+                v[u] -= ad[a * w + k] * s1[k * m + b] + bd[a * w + k] * s2[k * m + b];
+            if (idx0 + 64 * u < mm)
+                Go[idx0 + 64 * u] = v[u];
+        }
     }
     if (lane == 0) {
         double *ld = ioff(A.node_ld, A.B, it);
