@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="matern1d: only warmup + steps likelihoods on a plan with the library's "
                          "default tiles (no autotuning, no other legs); for counter profiles")
+    ap.add_argument("--level-by-level", action="store_true",
+                    help="--profile-run only: level-by-level updates (hodlr_opts.level_form = 1) "
+                         "instead of the projected levels")
     ap.add_argument("--no-speculate", action="store_true",
                     help="matern1d: every call waits for its compression's rank statistics "
                          "(default: calls after the first assume the previous call's panel "
@@ -1216,7 +1219,8 @@ def profile_run(args, torch, H, p, dev):
     perm = H.hodlr_order(p.x, p.leaf)
     xs, ys = p.x[perm], p.y[perm]
     spec = 0 if args.no_speculate else 1
-    plan = H.Plan(p.n, p.dim, p.leaf, H.Opts(max_rank=64, presorted=1, speculate=spec))
+    plan = H.Plan(p.n, p.dim, p.leaf, H.Opts(max_rank=64, presorted=1, speculate=spec,
+                                             level_form=1 if args.level_by_level else 0))
     d_x = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
     d_y = torch.from_numpy(np.ascontiguousarray(ys)).to(dev)
     work = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
