@@ -106,7 +106,7 @@ def test_wide_ranks_take_the_level_by_level_form():
     assert np.array_equal(o0, o1) and np.array_equal(z0, z1)
 
 
-def test_batched_items_equal_single_calls():
+def test_batched_items_against_kalman():
     import torch
     n, m = 16384, 6
     x, y, th = wl.batched_theta(m=m, n=n)
