@@ -17,6 +17,8 @@ of the level-by-level factorization.
   against the Kalman oracle.
 * The 1-D Matern-3/2 workload at n = 2^20: projected, log det within 1e-10 and
   the quadratic form within 1e-8 of the Kalman oracle.
+* The smallest trees (a single leaf, one, two and three levels with uneven
+  leaves): both forms against each other and the dense oracle.
 """
 import numpy as np
 import pytest
@@ -148,3 +150,21 @@ def test_option_is_validated():
     with pytest.raises(H.HodlrError) as ei:
         H.Plan(4096, 1, 64, H.Opts(level_form=2))
     assert ei.value.name == "EINVAL"
+
+
+@pytest.mark.parametrize("n", [64, 65, 130, 300])
+def test_smallest_trees(n):
+    """A single leaf (no level: the level-by-level form), one level (the root
+    only) and two or three levels with uneven leaves: both forms against each
+    other and the dense oracle."""
+    p = wl.random_problem(n, 1, wl.K_MATERN32, 707 + n, ell=0.1, sigma2=0.05, leaf=64, tol=1e-12)
+    announce("projected form, smallest trees: n=%d leaf=64" % n)
+    o0, z0, i0 = _dev_call(p, H.Opts(max_rank=64))
+    o1, z1, i1 = _dev_call(p, H.Opts(max_rank=64, level_form=1))
+    print("  levels %d projected %d" % (i0["levels"], i0["projected"]), flush=True)
+    assert i0["projected"] == (1 if i0["levels"] >= 1 else 0)
+    assert _rel(o0[1], o1[1]) <= 1e-12 and _rel(o0[2], o1[2]) <= 1e-10
+    assert np.linalg.norm(z0 - z1) <= 1e-10 * np.linalg.norm(z1)
+    ref = oracle.gp_dense(p.x, p.y, p.kernel, p.theta, p.sigma2)
+    assert _rel(o0[1], ref["logdet"]) <= 1e-10
+    assert _rel(o0[2], ref["quad"]) <= 1e-9
